@@ -1,0 +1,237 @@
+"""Pins of the oracle's tree, interaction lists and whole FMM / Barnes-Hut
+evaluation (Section 3.2, Eq. 12, Eq. 13) against brute force, degenerate cases
+that reduce to the direct sum, coverage invariants and the paper's
+qualitative claims (Section 4)."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2005_12351_amd import workloads as W
+
+
+def _coverage(d, n):
+    """count, for every ordered pair (i, j), how many list entries cover it"""
+    nc = d.level.shape[0]
+    leaf_of = np.full(n, -1)
+    for c in range(nc):
+        if d.nchild[c] == 0:
+            leaf_of[d.first[c]:d.first[c] + d.count[c]] = c
+    cover = np.zeros((n, n), dtype=np.int32)
+
+    def parts(c):
+        return np.arange(d.first[c], d.first[c] + d.count[c])
+
+    for c in range(nc):
+        tg = parts(c)
+        for e in range(d.m2l_ptr[c], d.m2l_ptr[c + 1]):
+            sr = parts(d.m2l_src[e])
+            cover[np.ix_(tg, sr)] += 1
+        for e in range(d.p2p_ptr[c], d.p2p_ptr[c + 1]):
+            sr = parts(d.p2p_src[e])
+            cover[np.ix_(tg, sr)] += 1
+    return cover, leaf_of
+
+
+@pytest.mark.parametrize("kind,n,ncrit,theta", [("uniform", 300, 4, 0.5), ("plummer", 400, 8, 0.6),
+                                                ("uniform", 257, 1, 0.3), ("lattice", 343, 16, 0.5)])
+def test_tree_invariants_and_pair_coverage(orc, kind, n, ncrit, theta):
+    w = W.small_random(100 + n, n, 0, kind)
+    t = orc.Tree(w.pos, ncrit, theta)
+    d = t.dump()
+    n = w.n
+    # keys sorted, permutation is a permutation, stable for equal keys
+    assert np.all(np.diff(d.key.astype(np.uint64)) >= 0)
+    assert np.array_equal(np.sort(d.perm), np.arange(n))
+    same = d.key[1:] == d.key[:-1]
+    assert np.all(d.perm[1:][same] > d.perm[:-1][same])
+    # cells: root, level-major, children partition parents
+    assert d.level[0] == 0 and d.first[0] == 0 and d.count[0] == n
+    assert np.all(np.diff(d.level) >= 0)
+    for c in range(d.level.shape[0]):
+        if d.nchild[c]:
+            kids = range(d.child0[c], d.child0[c] + d.nchild[c])
+            assert d.count[c] > ncrit
+            assert sum(d.count[k] for k in kids) == d.count[c]
+            assert d.first[d.child0[c]] == d.first[c]
+            for k in kids:
+                assert d.parent[k] == c and d.level[k] == d.level[c] + 1
+                assert np.all(d.ix[k] // 2 == d.ix[c])
+        else:
+            assert d.count[c] <= ncrit or d.level[c] == 21
+    # every ordered pair (i, j) is covered exactly once by M2L or P2P lists
+    cover, leaf_of = _coverage(d, n)
+    assert np.all(leaf_of >= 0)
+    # an M2L entry (A -> B) covers the targets of B; L2L carries it to B's descendants
+    nc = d.level.shape[0]
+    full = np.zeros_like(cover)
+    anc_cover = {}
+    for i in range(n):
+        c = leaf_of[i]
+        chain = []
+        while c >= 0:
+            chain.append(c)
+            c = d.parent[c]
+        row = np.zeros(n, dtype=np.int32)
+        for c in chain:
+            for e in range(d.m2l_ptr[c], d.m2l_ptr[c + 1]):
+                a = d.m2l_src[e]
+                row[d.first[a]:d.first[a] + d.count[a]] += 1
+        b = leaf_of[i]
+        for e in range(d.p2p_ptr[b], d.p2p_ptr[b + 1]):
+            a = d.p2p_src[e]
+            row[d.first[a]:d.first[a] + d.count[a]] += 1
+        full[i] = row
+    assert np.all(full == 1)
+    # lists sorted, and M2L only between cells that satisfy Eq. 13 strictly
+    for c in range(nc):
+        seg = d.m2l_src[d.m2l_ptr[c]:d.m2l_ptr[c + 1]]
+        assert np.all(np.diff(seg) > 0)
+
+
+def test_tree_octant_digit_order(orc):
+    """child octant = 4 bx + 2 by + bz (x most significant)."""
+    pos = np.array([[0.1, 0.1, 0.1], [0.9, 0.2, 0.8], [0.2, 0.95, 0.05], [1.0, 1.0, 1.0]])
+    t = orc.Tree(pos, 1, 0.5)
+    d = t.dump()
+    kids = [(tuple(d.ix[c]), list(d.perm[d.first[c]:d.first[c] + d.count[c]]))
+            for c in range(d.child0[0], d.child0[0] + d.nchild[0])]
+    assert kids == [((0, 0, 0), [0]), ((0, 1, 0), [2]), ((1, 0, 1), [1]), ((1, 1, 1), [3])]
+    # top digit of the key is that octant
+    assert [int(k) >> 60 for k in d.key] == [0, 2, 5, 7]
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_fmm_single_leaf_is_direct(orc, order):
+    """N <= ncrit: one leaf, pure P2P, equal to the direct sum to rounding."""
+    w = W.small_random(7, 60, order)
+    t = orc.Tree(w.pos, 64, 0.5)
+    assert t.info()["ncells"] == 1
+    ph, E = t.fmm(order, w.moments, order + 2)
+    pd, Ed = orc.direct(w.pos, order, w.moments)
+    assert np.abs(ph - pd).max() <= 1e-13 * np.abs(pd).max()
+    assert np.abs(E - Ed).max() <= 1e-13 * np.abs(Ed).max()
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_fmm_tiny_theta_is_direct(orc, order):
+    w = W.small_random(8, 200, order)
+    t = orc.Tree(w.pos, 4, 1e-3)
+    assert t.info()["n_m2l"] == 0
+    ph, E = t.fmm(order, w.moments, order + 2)
+    pd, Ed = orc.direct(w.pos, order, w.moments)
+    assert orc.rel_l2(ph, pd) < 1e-13 and orc.rel_l2(E, Ed) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 10])
+@pytest.mark.parametrize("ncrit", [1, 2, 8])
+def test_fmm_tiny_inputs(orc, n, ncrit):
+    for order in (0, 1, 2):
+        w = W.small_random(n * 10 + ncrit, n, order)
+        t = orc.Tree(w.pos, ncrit, 0.3)
+        ph, E = t.fmm(order, w.moments, order + 8)
+        pd, Ed = orc.direct(w.pos, order, w.moments)
+        if n == 1:
+            assert ph[0] == 0.0 and np.all(E == 0.0)
+        else:
+            assert orc.rel_l2(ph, pd) < 1e-3 and orc.rel_l2(E, Ed) < 1e-3
+
+
+def test_fmm_coincident_box_degenerates(orc):
+    """All particles on one line: the root box is still a cube of side W."""
+    pos = np.zeros((50, 3))
+    pos[:, 0] = np.linspace(0, 1, 50)
+    q = np.linspace(-1, 1, 50)
+    t = orc.Tree(pos, 4, 0.5)
+    ph, E = t.fmm(0, q, 8)
+    pd, Ed = orc.direct(pos, 0, q)
+    assert orc.rel_l2(ph, pd) < 1e-3
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_fmm_error_falls_with_p(orc, order):
+    """Figure 3: the error decreases with the expansion order."""
+    w = W.small_random(40 + order, 2500, order, p=4, theta=0.5, ncrit=32)
+    t = orc.Tree(w.pos, w.ncrit, w.theta)
+    pd, Ed = orc.direct(w.pos, order, w.moments)
+    errs = []
+    for p in (order + 2, order + 4, order + 6, order + 8):
+        ph, E = t.fmm(order, w.moments, p)
+        errs.append(orc.rel_l2(ph, pd) + orc.rel_l2(E, Ed))
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[0] / errs[-1] > 10
+
+
+def test_fmm_target_subset_matches_full(orc):
+    w = W.small_random(9, 3000, 1, ncrit=32)
+    t = orc.Tree(w.pos, 32, 0.5)
+    ph, E = t.fmm(1, w.moments, 5)
+    tg = np.array([0, 17, 999, 2998, 1500], dtype=np.int64)
+    ps, Es = t.fmm(1, w.moments, 5, targets=tg)
+    assert np.array_equal(ps, ph[tg]) and np.array_equal(Es, E[tg])
+    pd, Ed = orc.direct(w.pos, 1, w.moments, targets=tg)
+    pa, Ea = orc.direct(w.pos, 1, w.moments)
+    assert np.array_equal(pd, pa[tg]) and np.array_equal(Ed, Ea[tg])
+
+
+def test_oracle_is_thread_count_independent(orc, tmp_path):
+    """Parallel only over targets: bit-identical at 1 and 4 threads."""
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r)\n"
+        "import oracle\n"
+        "from paper_2005_12351_amd import workloads as W\n"
+        "w = W.small_random(3, 4000, 2, ncrit=32)\n"
+        "t = oracle.Tree(w.pos, 32, 0.5)\n"
+        "ph, E = t.fmm(2, w.moments, 6)\n"
+        "pb, Eb = t.bh(2, w.moments, 5, 0.4)\n"
+        "np.save(sys.argv[1], np.concatenate([ph, E.ravel(), pb, Eb.ravel()]))\n"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for nt in ("1", "4"):
+        f = str(tmp_path / f"o{nt}.npy")
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        subprocess.check_call([sys.executable, "-c", code, f], env=env)
+        outs.append(np.load(f))
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ----------------------------------------------------------------- Barnes-Hut
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_bh_converges_to_direct(orc, order):
+    w = W.small_random(60 + order, 2000, order, ncrit=16)
+    t = orc.Tree(w.pos, 16)
+    pd, Ed = orc.direct(w.pos, order, w.moments)
+    errs = []
+    for p in (order + 1, order + 3, order + 5):
+        ph, E = t.bh(order, w.moments, p, 0.4)
+        errs.append(orc.rel_l2(E, Ed))
+    assert errs[0] > errs[1] > errs[2]
+    ph, E = t.bh(order, w.moments, order + 2, 1e-3)   # nothing accepted: direct
+    assert orc.rel_l2(ph, pd) < 1e-13 and orc.rel_l2(E, Ed) < 1e-13
+
+
+def test_bh_p1_dipole_has_large_error_tail(orc):
+    """Section 4: BH with p = 1, s = 1 can be off by more than 100% on
+    individual particles."""
+    w = W.small_random(77, 4000, 1, kind="plummer", ncrit=16)
+    t = orc.Tree(w.pos, 16)
+    _, Ed = orc.direct(w.pos, 1, w.moments)
+    _, E = t.bh(1, w.moments, 1, 0.5)
+    rel = np.linalg.norm(E - Ed, axis=1) / np.linalg.norm(Ed, axis=1)
+    assert rel.max() > 1.0
+
+
+def test_theta_fmm_about_twice_theta_bh(orc):
+    """Section 4: the two acceptance criteria are not equivalent; at the same
+    order the FMM at theta lands between BH at theta/2 and BH at theta (the
+    paper quotes theta_FMM ~ 2 theta_BH for similar error)."""
+    w = W.small_random(78, 5000, 0, ncrit=32)
+    pd, _ = orc.direct(w.pos, 0, w.moments)
+    t = orc.Tree(w.pos, 32, 0.5)
+    for p in (4, 6):
+        ef = orc.rel_l2(t.fmm(0, w.moments, p)[0], pd)
+        eb_half = orc.rel_l2(t.bh(0, w.moments, p, 0.25)[0], pd)
+        eb_full = orc.rel_l2(t.bh(0, w.moments, p, 0.5)[0], pd)
+        assert eb_half < ef < eb_full

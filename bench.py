@@ -1,0 +1,189 @@
+"""Benchmark of the MI355X Cartesian FMM (one JSON line on stdout).
+
+Default workload: 100,000 point dipoles uniform in the unit cube, p = 8,
+theta = 0.5, ncrit = 64, potential + field (the configuration the headline
+metric is quoted on).  One step = upward pass + evaluation (P2M, M2M, M2L,
+L2L, L2P, P2P) with the octree and interaction lists resident, as the metric
+counts particle evaluations per second of N / (t_upward + t_evaluate); the
+tree build (set-up, excluded by the paper's own timings) is reported
+separately.  The headline precision is MIXED (FP32 M2L/P2P, FP64 elsewhere);
+the plain FP64 GPU path is timed on the same tree and reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks (dense, per GPU)
+PEAK_FP32_VALU = 157.3e12
+PEAK_FP64_VALU = 78.6e12
+PEAK_HBM = 8.0e12
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/kernels.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    f = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(f):
+        return None
+    try:
+        d = json.load(open(f))
+        e = d.get(kernel_key)
+        if e and e.get("src_hash") == _src_hash():
+            return e.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error checks")
+    ap.add_argument("--n", type=int, default=0, help="shrink the workload (testing only)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_12351_amd import fmm, workloads as W
+
+    w = W.config(args.config, n_override=args.n or None)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(w.pos).to(dev)
+    mom = torch.from_numpy(w.moments).to(dev)
+    outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
+    ctx = fmm.Context(0)
+    stream = torch.cuda.Stream(device=dev)
+
+    t0 = time.perf_counter()
+    tree = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+    t_build = time.perf_counter() - t0
+    info = tree.info()
+
+    def run(prec, steps, warmup, profile):
+        phi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
+        fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            tree.upward(w.order, mom, w.p, prec)
+            tree.evaluate(outputs, phi, fld)
+        torch.cuda.synchronize()
+        ctx.profile_reset()
+        ctx.profile(profile)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            tree.upward(w.order, mom, w.p, prec)
+            tree.evaluate(outputs, phi, fld)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.profile(False)
+        prof = ctx.profile_read()
+        return dt / steps, prof, (phi, fld), tree.work_counts()
+
+    res = {}
+    for name, prec in (("mixed", fmm.FMM_PREC_MIXED), ("fp64", fmm.FMM_PREC_FP64)):
+        step_s, prof, out, work = run(prec, args.steps, args.warmup, True)
+        res[name] = dict(step_s=step_s, prof=prof, out=(None if out[0] is None else out[0].cpu().numpy(),
+                                                         out[1].cpu().numpy()), work=work)
+
+    m = res["mixed"]
+    prof = m["prof"]
+    kern_ms = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
+    # dominant kernel: M2L (FP32 VALU contraction)
+    m2l_ms = kern_ms.get("m2l", float("nan"))
+    p2p_ms = kern_ms.get("p2p", float("nan"))
+    m2l_flops = m["work"]["m2l_flops"]
+    achieved = m2l_flops / (m2l_ms * 1e-3) if m2l_ms > 0 else None
+    roofline = {"bound": "alu", "kernel": "m2l (FP32)", "achieved": achieved / 1e12 if achieved else None,
+                "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
+                "traffic": _traffic("m2l_c%d_mixed" % args.config),
+                "flops_per_launch": m2l_flops, "avg_launch_ms": m2l_ms,
+                "p2p": {"achieved": m["work"]["p2p_flops"] / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None,
+                        "avg_launch_ms": p2p_ms, "flops_per_launch": m["work"]["p2p_flops"]}}
+    f64 = res["fp64"]
+    f64_m2l = f64["prof"].get("m2l", (float("nan"), 1))
+    f64_m2l_ms = f64_m2l[0] / max(1, f64_m2l[1])
+    value = w.n / m["step_s"]
+    line = {
+        "metric": "FMM particle evals/sec (pot+field), FP32-bulk (MIXED); FP64 GPU path reported beside it",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["step_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (M2L, P2P) + f64 (P2M, M2M, L2L, L2P)", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
+                   "ncrit": w.ncrit, "outputs": w.outputs, "method": "FMM (dual-tree lists)"},
+        "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3,
+                 "m2l_avg_launch_ms": f64_m2l_ms,
+                 "m2l_achieved_tflops": f64["work"]["m2l_flops"] / (f64_m2l_ms * 1e-3) / 1e12 if f64_m2l_ms > 0 else None,
+                 "m2l_frac_fp64_peak": (f64["work"]["m2l_flops"] / (f64_m2l_ms * 1e-3) / PEAK_FP64_VALU) if f64_m2l_ms > 0 else None},
+        "kernel_avg_ms_mixed": kern_ms,
+        "kernel_avg_ms_fp64": {k: v[0] / max(1, v[1]) for k, v in f64["prof"].items()},
+        "tree": {"build_ms": t_build * 1e3, **info},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu:
+        import oracle
+        oracle.lib()
+        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        t0 = time.perf_counter()
+        ot = oracle.Tree(w.pos, w.ncrit, w.theta)
+        tb = time.perf_counter() - t0
+        sample = w.sample if w.sample is not None else np.arange(w.n)
+        full = w.n <= 200_000
+        t0 = time.perf_counter()
+        if full:
+            po, Eo = ot.fmm(w.order, w.moments, w.p)
+            po_s, Eo_s = (po[sample] if po is not None else None), Eo[sample]
+        else:
+            po_s, Eo_s = ot.fmm(w.order, w.moments, w.p, targets=sample)
+        tc = time.perf_counter() - t0
+        nev = w.n if full else len(sample)
+        line["cpu_baseline"] = {"value": nev / tc, "unit": "evals/s", "cores": cores, "kind": "oracle",
+                                "sample": ("full workload, one upward+evaluate of the plain FP64 C oracle (tree "
+                                           "build %.2f s excluded)" % tb) if full else
+                                          ("%d sampled targets of the workload (full upward pass, lists of the "
+                                           "sampled leaves only)" % len(sample)),
+                                "seconds": tc}
+        pd, Ed = oracle.direct(w.pos, w.order, w.moments, targets=sample)
+        errs = {}
+        for name in ("mixed", "fp64"):
+            ph, E = res[name]["out"]
+            e = {"E_vs_direct": oracle.rel_l2(E[sample], Ed), "E_vs_oracle_fmm": oracle.rel_l2(E[sample], Eo_s)}
+            if ph is not None:
+                e["phi_vs_direct"] = oracle.rel_l2(ph[sample], pd)
+                e["phi_vs_oracle_fmm"] = oracle.rel_l2(ph[sample], po_s)
+            errs[name] = e
+        errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64" % len(sample)
+        line["rel_l2_error"] = errs
+    print(json.dumps(line), flush=True)
+    tree.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

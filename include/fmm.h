@@ -1,0 +1,174 @@
+/*
+ * fmm.h -- C ABI of libfmm.so, an MI355X (gfx950) implementation of the
+ * Cartesian Fast Multipole Method and the multipolar Barnes-Hut method of
+ * Pepper & Fangohr, "fmmgen: Automatic Code Generation of Operators for
+ * Cartesian Fast Multipole and Barnes-Hut Methods" (arXiv 2005.12351).
+ *
+ * What is computed (Section 2): the potential phi(x_i) = sum_{j != i} of the
+ * field of point sources of order m (0 monopole, 1 dipole, 2 quadrupole) with
+ * the Coulomb kernel 1/|x_i - x_j| (Eq. 1, no 1/(4 pi) factor), and the field
+ * E = -grad phi.  Physical moments: phi = q/r, phi = mu.r/r^3,
+ * phi = 1/2 sum_ij Q_ij d_i d_j (1/r) with r = x_target - x_source.
+ *
+ * Method (Section 3.2): an adaptive octree split while a cell holds more than
+ * ncrit particles, P2M at the leaves (Eq. 3, Eq. 5), M2M upward (Eq. 4), then
+ *   FMM: dual-tree traversal with the acceptance test (r_A + r_B) < theta R
+ *        (Eq. 13), stored interaction lists, M2L (Eq. 8), L2L, L2P (Eq. 9-10)
+ *        and direct P2P over the near-field lists;
+ *   BH:  per-particle traversal with r_A < theta |x - z_A| (Eq. 12), M2P
+ *        (Eq. 6) for accepted cells and P2P at unaccepted leaves.
+ * Cell radius r = half the cell side; expansion centre = geometric centre.
+ *
+ * Conventions of every entry point:
+ *  - All particle arrays are DEVICE pointers of the context's device, owned
+ *    by the caller, IEEE double, C-contiguous:
+ *      pos      n x 3   (x, y, z)
+ *      moments  n       (order 0: q)
+ *               n x 3   (order 1: mu_x, mu_y, mu_z)
+ *               n x 6   (order 2: Q_xx, Q_xy, Q_xz, Q_yy, Q_yz, Q_zz, symmetric Q)
+ *      phi      n       output potential, caller's particle order
+ *      field    n x 3   output field, caller's particle order
+ *  - Calls are stream-ordered on the context's stream and return before the
+ *    GPU work finishes; inputs must stay valid and outputs untouched until the
+ *    stream is synchronised.  fmm_build_tree is the exception: it reads the
+ *    positions back to the host and returns after the tree is resident.
+ *  - Every entry point returns FMM_OK or an error code; no C++ exception
+ *    crosses the ABI.  Arguments are checked before any GPU work is queued.
+ *    fmm_last_error() returns a thread-local text for the last failure.
+ *  - The library owns fmm_ctx and fmm_tree objects and all device memory they
+ *    hold; free them with the matching *_destroy call.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_ctx fmm_ctx;
+typedef struct fmm_tree fmm_tree;
+
+enum {
+    FMM_OK = 0,
+    FMM_EINVAL = 1,    /* bad argument; nothing was queued */
+    FMM_ENOMEM = 2,    /* device or host allocation failed / over the budget */
+    FMM_EDEVICE = 3,   /* a HIP call failed */
+    FMM_ESTATE = 4,    /* call out of order (e.g. evaluate before upward) */
+    FMM_EBUSY = 5,     /* serving: request not finished yet */
+    FMM_ETIMEOUT = 6   /* serving: wait timed out */
+};
+
+enum { FMM_POT = 1, FMM_FIELD = 2 };               /* output bit mask */
+enum { FMM_METHOD_FMM = 0, FMM_METHOD_BH = 1 };
+enum {
+    FMM_PREC_FP64 = 0,   /* every operator in IEEE double on the GPU */
+    FMM_PREC_MIXED = 1   /* M2L, M2P and P2P in FP32 (P2P compensated),
+                            P2M, M2M, L2L, L2P in FP64 */
+};
+
+#define FMM_P_MAX 10     /* largest expansion order p compiled in */
+
+/* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the
+ * library creates its own).  `hbm_budget_bytes` bounds the device memory the
+ * serving loop admits (0: 80% of the free memory at creation). */
+int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, fmm_ctx **out);
+int fmm_ctx_destroy(fmm_ctx *ctx);
+
+/* Octree, Morton order and (for FMM) interaction lists of n particles
+ * (Section 3.2).  n >= 1, ncrit >= 1, 0 < theta < 1; method FMM_METHOD_FMM or
+ * FMM_METHOD_BH (for BH, theta is the acceptance parameter of Eq. 12 used by
+ * fmm_evaluate).  The root box is the cube of side W = the largest extent of
+ * the positions, with corner at the componentwise minimum. */
+int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double theta,
+                   int method, fmm_tree **out);
+
+/* Upward pass: P2M at the leaves (Eq. 5 with the source tensor
+ * S_n = (-1)^|n| T_n / n! of the physical moment T) and M2M to the root
+ * (Eq. 4), expansion order p.  order in {0,1,2}; order+1 <= p <= FMM_P_MAX
+ * for FMM, order <= p <= FMM_P_MAX for BH.  `moments` must stay valid until
+ * fmm_evaluate has been queued (the near field reads it). */
+int fmm_upward(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int p,
+               int precision);
+
+/* Far field (M2L, L2L, L2P or, for BH, M2P) plus near field (P2P) at every
+ * particle.  `outputs` is a mask of FMM_POT / FMM_FIELD; phi (n) and field
+ * (n x 3) must be non-NULL for the requested outputs.  FMM_ESTATE if
+ * fmm_upward has not run on this tree. */
+int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field);
+
+/* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,
+ * n_m2l_classes, n_m2l_tiles, n_m2l_slots_used (tile lanes x union entries),
+ * device bytes held. */
+int fmm_tree_info(const fmm_tree *tree, int64_t *info);
+
+/* Copy the canonical tree to HOST arrays (any pointer may be NULL), sized by
+ * fmm_tree_info: geom[4] = lo_x, lo_y, lo_z, W; key[n] Morton keys of the
+ * sorted particles; perm[n] input index of sorted particle i; per cell
+ * (level-major, ascending key): level, ix[3] integer cell coordinates,
+ * first, count (sorted particle range), parent (-1 at the root), child0,
+ * nchild; CSR interaction lists per target cell, sources sorted ascending:
+ * m2l_ptr[ncells+1], m2l_src[n_m2l], p2p_ptr[ncells+1], p2p_src[n_p2p]. */
+int fmm_tree_export(const fmm_tree *tree, double *geom, uint64_t *key, int64_t *perm,
+                    int32_t *level, int32_t *ix, int64_t *first, int64_t *count,
+                    int64_t *parent, int64_t *child0, int32_t *nchild, int64_t *m2l_ptr,
+                    int64_t *m2l_src, int64_t *p2p_ptr, int64_t *p2p_src);
+
+int fmm_tree_destroy(fmm_tree *tree);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *fmm_last_error(void);
+
+/* Near field (P2P) on a second stream overlapping the far field (default on).
+ * Off: every kernel runs on the context stream, one after the other, so the
+ * per-kernel timings below measure each kernel alone. */
+int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
+
+/* Per-kernel device timing.  When enabled, every kernel launch is bracketed
+ * by HIP events on the stream it runs on.  fmm_profile_read synchronises and
+ * writes, for up to `cap` kernel kinds, the kind name (static string), the
+ * summed milliseconds and the launch count; returns the number of kinds. */
+int fmm_profile_enable(fmm_ctx *ctx, int on);
+int fmm_profile_reset(fmm_ctx *ctx);
+int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, int64_t *launches, int cap);
+
+/* Algorithmic work of the last fmm_evaluate on a tree (for roofline
+ * accounting): w[0] = M2L list entries, w[1] = M2L FLOPs (2 per
+ * multiply-add of the contraction), w[2] = P2P pairs, w[3] = P2P FLOPs,
+ * w[4] = M2P (cell, particle) pairs, w[5] = M2P FLOPs, w[6] = M2L input
+ * and output bytes, w[7] = P2P input and output bytes. */
+int fmm_work_counts(const fmm_tree *tree, double *w);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching: requests are admitted while their device footprint
+ * fits the context budget and a stream slot is free; admitted requests run
+ * tree build, upward pass and evaluation concurrently on separate HIP
+ * streams and release their memory when done.  The caller owns the request's
+ * buffers (device pointers, as above) until the request completes. */
+typedef struct {
+    const double *pos;       /* n x 3, device */
+    const double *moments;   /* n x {1,3,6}, device */
+    double *phi;             /* n or NULL, device */
+    double *field;           /* n x 3 or NULL, device */
+    int64_t n;
+    int order, p, ncrit, method, precision, outputs;
+    double theta;
+} fmm_request;
+
+enum { FMM_REQ_QUEUED = 0, FMM_REQ_RUNNING = 1, FMM_REQ_DONE = 2, FMM_REQ_FAILED = 3 };
+
+int fmm_serve_start(fmm_ctx *ctx, int max_concurrent);
+int fmm_submit(fmm_ctx *ctx, const fmm_request *req, uint64_t *ticket);
+int fmm_poll(fmm_ctx *ctx, uint64_t ticket, int *state);
+int fmm_wait(fmm_ctx *ctx, uint64_t ticket, double timeout_s);
+/* times in seconds since fmm_serve_start: t[0] submit, t[1] admitted,
+ * t[2] done; bytes[0] = admitted footprint */
+int fmm_request_times(fmm_ctx *ctx, uint64_t ticket, double *t, int64_t *bytes);
+int fmm_serve_stop(fmm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

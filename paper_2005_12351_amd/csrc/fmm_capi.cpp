@@ -1,0 +1,585 @@
+// C ABI of libfmm.so: argument checking, device memory, and the order in
+// which the kernels of the Cartesian FMM / Barnes-Hut method are queued
+// (Pepper & Fangohr, arXiv 2005.12351, Section 3.2).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+
+#include "fmm_internal.h"
+
+static thread_local char g_err[1024];
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+extern "C" const char *fmm_last_error(void) { return g_err; }
+
+#define FAIL(code, ...)          \
+    do {                         \
+        set_error(__VA_ARGS__);  \
+        return code;             \
+    } while (0)
+
+#define HIPCHK(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            FAIL(FMM_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s);
+
+// ------------------------------------------------------------------ profiling
+// events come from a per-context pool so that bracketing every launch costs
+// two hipEventRecord calls and no allocation
+static hipEvent_t pool_event(fmm_ctx *c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(fmm_ctx *c, hipStream_t st, const char *nm) : ctx(c), s(st), name(nm)
+{
+    if (!ctx->profile) return;
+    b = pool_event(ctx);
+    if (b) hipEventRecord(b, s);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!ctx->profile || !b) return;
+    hipEvent_t e = pool_event(ctx);
+    if (!e) return;
+    hipEventRecord(e, s);
+    ctx->prof.push_back(ProfEntry{name, b, e});
+}
+
+extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    ctx->overlap = on != 0;
+    return FMM_OK;
+}
+
+extern "C" int fmm_profile_enable(fmm_ctx *ctx, int on)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    ctx->profile = on != 0;
+    return FMM_OK;
+}
+
+extern "C" int fmm_profile_reset(fmm_ctx *ctx)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    for (auto &e : ctx->prof) {
+        ctx->ev_pool.push_back(e.a);
+        ctx->ev_pool.push_back(e.b);
+    }
+    ctx->prof.clear();
+    return FMM_OK;
+}
+
+extern "C" int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, int64_t *launches, int cap)
+{
+    if (!ctx || cap < 0) FAIL(FMM_EINVAL, "bad arguments");
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<const char *> nm;
+    std::vector<double> tot;
+    std::vector<int64_t> cnt;
+    for (auto &e : ctx->prof) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+        size_t k = 0;
+        while (k < nm.size() && strcmp(nm[k], e.name) != 0) ++k;
+        if (k == nm.size()) {
+            nm.push_back(e.name);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[k] += t;
+        cnt[k] += 1;
+    }
+    const int nk = (int)std::min<size_t>(nm.size(), (size_t)cap);
+    for (int k = 0; k < nk; ++k) {
+        if (names) names[k] = nm[k];
+        if (ms) ms[k] = tot[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    return (int)nm.size();
+}
+
+// ------------------------------------------------------------------ context
+extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, fmm_ctx **out)
+{
+    if (!out) FAIL(FMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) FAIL(FMM_EINVAL, "device %d out of range (have %d)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    fmm_ctx *c = new fmm_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            FAIL(FMM_EDEVICE, "stream creation failed");
+        }
+        c->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        FAIL(FMM_EDEVICE, "stream/event creation failed");
+    }
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+    *out = c;
+    return FMM_OK;
+}
+
+static void tree_release_device(fmm_tree *t)
+{
+    for (void *p : t->allocs) hipFree(p);
+    t->allocs.clear();
+    t->dev_bytes = 0;
+}
+
+extern "C" int fmm_ctx_destroy(fmm_ctx *c)
+{
+    if (!c) return FMM_OK;
+    hipSetDevice(c->device);
+    serve_destroy(c);
+    hipDeviceSynchronize();
+    // trees still alive lose their device memory and become orphans that
+    // only fmm_tree_destroy accepts
+    for (fmm_tree *t : c->trees) {
+        tree_release_device(t);
+        t->ctx = nullptr;
+    }
+    c->trees.clear();
+    for (auto &e : c->prof) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    hipEventDestroy(c->ev_up);
+    hipEventDestroy(c->ev_near);
+    hipStreamDestroy(c->aux);
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    delete c;
+    return FMM_OK;
+}
+
+// ------------------------------------------------------------------ tree
+int tree_alloc(fmm_tree *t, void **p, size_t bytes)
+{
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        FAIL(FMM_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    t->allocs.push_back(*p);
+    t->dev_bytes += bytes;
+    return FMM_OK;
+}
+
+static void tree_free_block(fmm_tree *t, void *p)
+{
+    if (!p) return;
+    auto it = std::find(t->allocs.begin(), t->allocs.end(), p);
+    if (it != t->allocs.end()) t->allocs.erase(it);
+    hipFree(p);
+}
+
+template <typename T>
+static int upload(fmm_tree *t, T **dst, const std::vector<T> &src, hipStream_t s)
+{
+    int rc = tree_alloc(t, (void **)dst, src.size() * sizeof(T));
+    if (rc) return rc;
+    if (!src.empty()) HIPCHK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return FMM_OK;
+}
+
+extern "C" int fmm_tree_destroy(fmm_tree *t)
+{
+    if (!t) return FMM_OK;
+    if (fmm_ctx *c = t->ctx) {
+        hipSetDevice(c->device);
+        hipStreamSynchronize(c->stream);
+        hipStreamSynchronize(c->aux);
+        tree_release_device(t);
+        c->trees.erase(std::remove(c->trees.begin(), c->trees.end(), t), c->trees.end());
+    }
+    delete t;
+    return FMM_OK;
+}
+
+static int mom_width(int order) { return order == 0 ? 1 : (order == 1 ? 3 : 6); }
+
+extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double theta, int method,
+                              fmm_tree **out)
+{
+    if (!ctx || !out) FAIL(FMM_EINVAL, "null context or output");
+    *out = nullptr;
+    if (!pos) FAIL(FMM_EINVAL, "positions are NULL");
+    if (n < 1 || n > (int64_t)INT32_MAX / 4) FAIL(FMM_EINVAL, "n = %lld out of range", (long long)n);
+    if (ncrit < 1) FAIL(FMM_EINVAL, "ncrit = %d must be >= 1", ncrit);
+    if (!(theta > 0.0 && theta < 1.0)) FAIL(FMM_EINVAL, "theta = %g must lie in (0, 1)", theta);
+    if (method != FMM_METHOD_FMM && method != FMM_METHOD_BH) FAIL(FMM_EINVAL, "unknown method %d", method);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+
+    std::vector<double> hpos((size_t)n * 3);
+    HIPCHK(hipMemcpyAsync(hpos.data(), pos, hpos.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (double v : hpos)
+        if (!std::isfinite(v)) FAIL(FMM_EINVAL, "non-finite position");
+
+    fmm_tree *t = new fmm_tree();
+    t->ctx = ctx;
+    t->method = method;
+    t->ncrit = ncrit;
+    t->theta = theta;
+    host_build_tree(hpos.data(), n, ncrit, t->ht);
+    HostTree &h = t->ht;
+    const int64_t nc = h.ncells();
+    if (method == FMM_METHOD_FMM) {
+        host_dual_traversal(h, theta);
+        build_m2l_tiling(h, t->tiling);
+    } else {
+        h.m2l_ptr.assign(nc + 1, 0);
+        h.p2p_ptr.assign(nc + 1, 0);
+    }
+    // leaves, per-particle leaf, non-leaf cells per level, P2P CSR per leaf
+    std::vector<int32_t> leaf_of(n), level_cells(nc);
+    std::vector<DevCell> cells(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+        DevCell d{};
+        d.level = h.level[c];
+        d.ix = h.ix[3 * c];
+        d.iy = h.ix[3 * c + 1];
+        d.iz = h.ix[3 * c + 2];
+        d.first = (int32_t)h.first[c];
+        d.count = (int32_t)h.count[c];
+        d.parent = (int32_t)h.parent[c];
+        d.child0 = (int32_t)h.child0[c];
+        d.nchild = h.nchild[c];
+        cells[c] = d;
+        level_cells[c] = (int32_t)c;
+        if (h.nchild[c] == 0) {
+            t->leaves.push_back((int32_t)c);
+            for (int64_t i = h.first[c]; i < h.first[c] + h.count[c]; ++i) leaf_of[i] = (int32_t)c;
+        }
+    }
+    t->nleaves = (int64_t)t->leaves.size();
+    const int nlev = (int)h.level_ptr.size() - 1;
+    t->level_nonleaf_ptr.assign(nlev + 1, 0);
+    for (int l = 0; l < nlev; ++l) {
+        for (int64_t c = h.level_ptr[l]; c < h.level_ptr[l + 1]; ++c)
+            if (h.nchild[c]) t->level_nonleaf.push_back((int32_t)c);
+        t->level_nonleaf_ptr[l + 1] = (int32_t)t->level_nonleaf.size();
+    }
+    std::vector<int32_t> pptr(t->nleaves + 1, 0), psrc;
+    double p2p_pairs = 0.0;
+    for (int64_t k = 0; k < t->nleaves; ++k) {
+        const int64_t b = t->leaves[k];
+        for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) {
+            psrc.push_back((int32_t)h.p2p_src[e]);
+            p2p_pairs += (double)h.count[b] * (double)h.count[h.p2p_src[e]];
+        }
+        if (h.p2p_ptr[b + 1] > h.p2p_ptr[b]) p2p_pairs -= (double)h.count[b];   // no self pair
+        pptr[k + 1] = (int32_t)psrc.size();
+    }
+    t->work[2] = p2p_pairs;
+    std::vector<double> leaf_cost(t->nleaves, 0.0);
+    for (int64_t k = 0; k < t->nleaves; ++k) {
+        const int64_t b = t->leaves[k];
+        for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) leaf_cost[k] += (double)h.count[h.p2p_src[e]];
+        leaf_cost[k] *= (double)std::max<int64_t>(1, (h.count[b] + 63) / 64) * 64.0;
+    }
+    std::vector<int32_t> p2p_order(t->nleaves);
+    for (int64_t k = 0; k < t->nleaves; ++k) p2p_order[k] = (int32_t)k;
+    std::stable_sort(p2p_order.begin(), p2p_order.end(), [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
+    std::vector<int32_t> perm32(n);
+    for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)h.perm[i];
+
+    int rc = FMM_OK;
+#define UP(dst, vec)                                   \
+    if ((rc = upload(t, &(dst), vec, s)) != FMM_OK) {  \
+        fmm_tree_destroy(t);                           \
+        return rc;                                     \
+    }
+    UP(t->d_cells, cells);
+    UP(t->d_perm, perm32);
+    UP(t->d_leaf_of, leaf_of);
+    UP(t->d_leaves, t->leaves);
+    UP(t->d_nonleaf, t->level_nonleaf);
+    UP(t->d_level_cells, level_cells);
+    UP(t->d_p2p_ptr, pptr);
+    UP(t->d_p2p_src, psrc);
+    UP(t->d_p2p_order, p2p_order);
+    if (method == FMM_METHOD_FMM) {
+        const M2LTiling &tl = t->tiling;
+        UP(t->d_ucls, tl.ucls);
+        UP(t->d_usrc, tl.usrc);
+        UP(t->d_tile_cell, tl.tile_cell);
+        UP(t->d_cls_geom, tl.cls_geom);
+        t->work[0] = (double)tl.pairs;
+    }
+#undef UP
+    if ((rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n)) ||
+        (rc = tree_alloc(t, (void **)&t->d_xi, sizeof(float) * 4 * n))) {
+        fmm_tree_destroy(t);
+        return rc;
+    }
+    hipError_t e = launch_prep_positions(t, pos, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        fmm_tree_destroy(t);
+        FAIL(FMM_EDEVICE, "tree upload failed: %s", hipGetErrorString(e));
+    }
+    ctx->trees.push_back(t);
+    *out = t;
+    return FMM_OK;
+}
+
+// ------------------------------------------------------------------ upward
+static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
+{
+    if (t->d_M64 && t->order == order && t->p == p && t->prec == prec) return FMM_OK;
+    for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32,
+                      (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_D64,
+                      (void **)&t->d_D32, (void **)&t->d_sc64, (void **)&t->d_sc32, (void **)&t->d_work,
+                      (void **)&t->d_tile_chunk0, (void **)&t->d_tile_nchunk, (void **)&t->d_wave_ptr}) {
+        tree_free_block(t, *pp);
+        *pp = nullptr;
+    }
+    t->dtab_p = -1;
+    const int64_t n = t->ht.n, nc = t->ht.ncells();
+    const int nm = nterms(p) - nterms(order - 1), nmp = (nm + 3) / 4 * 4, nl = nterms(p - order);
+    int rc;
+    if ((rc = tree_alloc(t, (void **)&t->d_mom, sizeof(double) * mom_width(order) * n)) ||
+        (rc = tree_alloc(t, (void **)&t->d_mom32, sizeof(float) * 8 * n)) ||
+        (rc = tree_alloc(t, (void **)&t->d_M64, sizeof(double) * (nc + 1) * nmp)) ||
+        (rc = tree_alloc(t, (void **)&t->d_near, sizeof(double) * 4 * n)))
+        return rc;
+    if (prec == FMM_PREC_MIXED && (rc = tree_alloc(t, (void **)&t->d_M32, sizeof(float) * (nc + 1) * nmp))) return rc;
+    if (t->method == FMM_METHOD_FMM) {
+        M2LVariant v;
+        if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, &v)) FAIL(FMM_EINVAL, "no M2L kernel for p=%d s=%d", p, order);
+        const size_t es = prec == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
+        const int nc_ = std::max(1, t->tiling.nclasses);
+        const int scw = (p + 1 + 3) / 4 * 4;
+        // one wave per resident slot of the device
+        int dev = 0, ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+        build_m2l_work(t->tiling, v, ncu * v.occupancy(), t->m2lwork);
+        std::vector<int4> work(t->m2lwork.work.size() / 4);
+        for (size_t k = 0; k < work.size(); ++k)
+            work[k] = make_int4(t->m2lwork.work[4 * k], t->m2lwork.work[4 * k + 1], t->m2lwork.work[4 * k + 2],
+                                t->m2lwork.work[4 * k + 3]);
+        hipStream_t st = t->ctx->stream;
+        if ((rc = upload(t, &t->d_work, work, st)) || (rc = upload(t, &t->d_tile_chunk0, t->m2lwork.chunk0, st)) ||
+            (rc = upload(t, &t->d_tile_nchunk, t->m2lwork.nchunk, st)) ||
+            (rc = upload(t, &t->d_wave_ptr, t->m2lwork.wave_ptr, st)))
+            return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        if ((rc = tree_alloc(t, &t->d_part, es * (size_t)std::max<int64_t>(1, t->m2lwork.nrows) * v.nl_pad)) ||
+            (rc = tree_alloc(t, (void **)&t->d_L64, sizeof(double) * nc * nl)) ||
+            (rc = tree_alloc(t, (void **)&t->d_D64, sizeof(double) * nc_ * v.nd)) ||
+            (rc = tree_alloc(t, (void **)&t->d_D32, sizeof(float) * nc_ * v.nd)) ||
+            (rc = tree_alloc(t, (void **)&t->d_sc64, sizeof(double) * nc_ * scw)) ||
+            (rc = tree_alloc(t, (void **)&t->d_sc32, sizeof(float) * nc_ * scw)))
+            return rc;
+    }
+    hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
+    if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+    t->order = order;
+    t->p = p;
+    t->prec = prec;
+    return FMM_OK;
+}
+
+#define KCHK(expr)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) FAIL(FMM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (order < 0 || order > 2) FAIL(FMM_EINVAL, "source order %d not in {0,1,2}", order);
+    if (!moments) FAIL(FMM_EINVAL, "moments are NULL");
+    if (precision != FMM_PREC_FP64 && precision != FMM_PREC_MIXED) FAIL(FMM_EINVAL, "unknown precision %d", precision);
+    const int pmin = t->method == FMM_METHOD_FMM ? order + 1 : std::max(order, 1);
+    if (p < pmin || p > FMM_P_MAX) FAIL(FMM_EINVAL, "p = %d must lie in [%d, %d]", p, pmin, FMM_P_MAX);
+    HIPCHK(hipSetDevice(ctx->device));
+    t->have_up = 0;
+    int rc = ensure_expansions(t, order, p, precision);
+    if (rc) return rc;
+    hipStream_t s = ctx->stream;
+    t->mom_user = moments;
+    {
+        ProfScope ps(ctx, s, "prep_moments");
+        KCHK(launch_prep_moments(t, s));
+    }
+    {
+        ProfScope ps(ctx, s, "p2m");
+        KCHK(launch_p2m(t, s));
+    }
+    const int nlev = (int)t->ht.level_ptr.size() - 1;
+    for (int l = nlev - 2; l >= 0; --l) {
+        ProfScope ps(ctx, s, "m2m");
+        KCHK(launch_m2m_level(t, l, s));
+    }
+    if (precision == FMM_PREC_MIXED) {
+        ProfScope ps(ctx, s, "m2_fp32");
+        KCHK(launch_to_fp32(t, s));
+    }
+    if (t->method == FMM_METHOD_FMM && t->dtab_p != p) {
+        ProfScope ps(ctx, s, "dtable");
+        KCHK(launch_dtable(t, s));
+        t->dtab_p = p;
+    }
+    KCHK(hipEventRecord(ctx->ev_up, s));
+    t->have_up = 1;
+    return FMM_OK;
+}
+
+// FLOPs per P2P pair as counted in the FP32 kernel (multiply-add = 2,
+// reciprocal square root = 1), potential and field
+static double p2p_flops(int order) { return order == 0 ? 20.0 : (order == 1 ? 32.0 : 58.0); }
+
+extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (outputs <= 0 || (outputs & ~(FMM_POT | FMM_FIELD))) FAIL(FMM_EINVAL, "bad output mask %d", outputs);
+    if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
+    if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
+    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream, a = ctx->overlap ? ctx->aux : ctx->stream;
+    const int s_ = t->order, p = t->p;
+    if (t->method == FMM_METHOD_BH) {
+        ProfScope ps(ctx, s, "bh");
+        KCHK(launch_bh(t, outputs, phi, field, s));
+        return FMM_OK;
+    }
+    // near field on the auxiliary stream, overlapping the far field
+    KCHK(hipStreamWaitEvent(a, ctx->ev_up, 0));
+    {
+        ProfScope ps(ctx, a, "p2p");
+        KCHK(launch_p2p(t, a));
+    }
+    KCHK(hipEventRecord(ctx->ev_near, a));
+    const int64_t nc = t->ht.ncells();
+    const int nl = nterms(p - s_);
+    KCHK(launch_fill(t->d_L64, (size_t)nc * nl, s));
+    {
+        ProfScope ps(ctx, s, "m2l");
+        KCHK(launch_m2l(t, s));
+    }
+    {
+        ProfScope ps(ctx, s, "m2l_combine");
+        KCHK(launch_m2l_combine(t, s));
+    }
+    const int nlev = (int)t->ht.level_ptr.size() - 1;
+    for (int l = 1; l < nlev; ++l) {
+        ProfScope ps(ctx, s, "l2l");
+        KCHK(launch_l2l_level(t, l, s));
+    }
+    KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+    {
+        ProfScope ps(ctx, s, "l2p");
+        KCHK(launch_l2p_final(t, outputs, phi, field, s));
+    }
+    // algorithmic work of this evaluation
+    const double fc = [&] {
+        double f = 0;
+        for (int k = 0; k <= p - s_; ++k) f += (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
+        return f;
+    }();
+    const size_t es = t->prec == FMM_PREC_MIXED ? 4 : 8;
+    t->work[1] = 2.0 * fc * t->work[0];
+    t->work[3] = p2p_flops(s_) * t->work[2];
+    t->work[6] = (double)nc * (double)(nterms(p) - nterms(s_ - 1) + nl) * es;
+    t->work[7] = (double)t->ht.n * (es * (4 + 8) + 32);
+    return FMM_OK;
+}
+
+extern "C" int fmm_work_counts(const fmm_tree *t, double *w)
+{
+    if (!t || !w) FAIL(FMM_EINVAL, "null argument");
+    for (int k = 0; k < 8; ++k) w[k] = t->work[k];
+    return FMM_OK;
+}
+
+extern "C" int fmm_tree_info(const fmm_tree *t, int64_t *info)
+{
+    if (!t || !info) FAIL(FMM_EINVAL, "null argument");
+    const HostTree &h = t->ht;
+    info[0] = h.n;
+    info[1] = h.ncells();
+    info[2] = (int64_t)h.level_ptr.size() - 1;
+    info[3] = t->nleaves;
+    info[4] = h.m2l_ptr.empty() ? 0 : h.m2l_ptr.back();
+    info[5] = h.p2p_ptr.empty() ? 0 : h.p2p_ptr.back();
+    info[6] = t->tiling.nclasses;
+    info[7] = t->tiling.ntiles;
+    info[8] = t->tiling.nentries * kTileW;
+    info[9] = (int64_t)t->dev_bytes;
+    return FMM_OK;
+}
+
+extern "C" int fmm_tree_export(const fmm_tree *t, double *geom, uint64_t *key, int64_t *perm, int32_t *level,
+                               int32_t *ix, int64_t *first, int64_t *count, int64_t *parent, int64_t *child0,
+                               int32_t *nchild, int64_t *m2l_ptr, int64_t *m2l_src, int64_t *p2p_ptr, int64_t *p2p_src)
+{
+    if (!t) FAIL(FMM_EINVAL, "null tree");
+    const HostTree &h = t->ht;
+    auto cp = [](auto *dst, const auto &v) {
+        if (dst && !v.empty()) memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    if (geom) {
+        geom[0] = h.lo[0];
+        geom[1] = h.lo[1];
+        geom[2] = h.lo[2];
+        geom[3] = h.W;
+    }
+    cp(key, h.key);
+    cp(perm, h.perm);
+    cp(level, h.level);
+    cp(ix, h.ix);
+    cp(first, h.first);
+    cp(count, h.count);
+    cp(parent, h.parent);
+    cp(child0, h.child0);
+    cp(nchild, h.nchild);
+    cp(m2l_ptr, h.m2l_ptr);
+    cp(m2l_src, h.m2l_src);
+    cp(p2p_ptr, h.p2p_ptr);
+    cp(p2p_src, h.p2p_src);
+    return FMM_OK;
+}

@@ -1,0 +1,194 @@
+// Internal declarations of libfmm.so (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+// ------------------------------------------------------------------ indexing
+// Coefficients are ordered by total order k, then n_x descending, then n_y
+// descending (the default lexicographic mapping of Section 3.1).
+__host__ __device__ constexpr int nterms(int p) { return p < 0 ? 0 : (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int mindex(int nx, int ny, int nz)
+{
+    return nterms(nx + ny + nz - 1) + (ny + nz) * (ny + nz + 1) / 2 + nz;
+}
+
+constexpr int kMaxLevel = 21;        // 21 bits per axis, 63-bit keys
+constexpr int kTileW = 64;           // targets per M2L tile = wavefront width
+constexpr int kPTable = 12;          // multi-index tables cover orders <= 12
+
+struct MultiIndex { int8_t x, y, z, k; };
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+#define FMM_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return FMM_EDEVICE;                                                    \
+        }                                                                          \
+    } while (0)
+
+// ------------------------------------------------------------------ tree
+struct DevCell {       // 48 bytes, canonical order
+    int32_t level, ix, iy, iz;
+    int32_t first, count, parent, child0;
+    int32_t nchild, pad0, pad1, pad2;
+};
+
+struct HostTree {      // canonical tree built on the host
+    int64_t n = 0;
+    double lo[3] = {0, 0, 0}, W = 1.0, h = 0.0;
+    std::vector<uint64_t> key;
+    std::vector<int64_t> perm;
+    std::vector<int32_t> level, ix;        // ix: 3 per cell
+    std::vector<int64_t> first, count, parent, child0;
+    std::vector<int32_t> nchild;
+    std::vector<int64_t> level_ptr;        // nlevels + 1
+    std::vector<int64_t> m2l_ptr, m2l_src, p2p_ptr, p2p_src;
+    int64_t ncells() const { return (int64_t)level.size(); }
+};
+
+// host tree construction (tree_host.cpp)
+int host_build_tree(const double *pos_host, int64_t n, int ncrit, HostTree &t);
+void host_dual_traversal(HostTree &t, double theta);
+
+// M2L tiling (tree_host.cpp)
+struct M2LTiling {
+    int ntiles = 0, nclasses = 0;
+    int64_t nentries = 0;                  // union entries over all tiles
+    std::vector<int32_t> tile_cell;        // ntiles*64: target cell or -1
+    std::vector<int32_t> tile_uoff;        // ntiles+1: entry range of each tile
+    std::vector<int32_t> ucls;             // nentries: class id
+    std::vector<int32_t> usrc;             // nentries*64: source cell (or zero row)
+    std::vector<double> cls_geom;          // nclasses*4: (z_B - z_A)/r_B, r_A/r_B
+    int64_t pairs = 0;                     // real list entries
+};
+void build_m2l_tiling(const HostTree &t, M2LTiling &out);
+
+// M2L work for one kernel variant: the (tile, output block, entry) units,
+// concatenated, are cut into nwaves pieces of equal cost; a piece that
+// crosses a (tile, block) boundary becomes several items, each with its own
+// 64 partial-result rows
+struct M2LWork {
+    std::vector<int32_t> work;             // nitems*4: tile | block << 24, u0, u1, first row
+    std::vector<int32_t> wave_ptr;         // nwaves+1
+    std::vector<int32_t> chunk0, nchunk;   // per (tile, block): first row set, row-set count
+    int64_t nrows = 0;
+    int nwaves = 0;
+};
+
+// ------------------------------------------------------------------ M2L kernels
+struct M2LArgs {
+    const int4 *work;          // x = tile | block << 24, y/z = entry range, w = first output row
+    const int32_t *ucls, *usrc;
+    const void *D, *sc, *M;
+    void *part;
+    const int32_t *wave_ptr;   // pieces of wave w: work[wave_ptr[w] .. wave_ptr[w+1])
+};
+// generated dispatch (m2l_generated_*.hip)
+typedef hipError_t (*m2l_launch_fn)(const M2LArgs &, int nwaves, hipStream_t);
+struct M2LVariant {
+    m2l_launch_fn launch;
+    int (*occupancy)();        // resident waves per CU
+    int nl_pad, nm_pad, nd, nblocks;
+    int blo[17];               // output blocks: coefficients [blo[b], blo[b+1])
+    int bfma[16];              // multiply-adds per list entry in each block
+};
+bool m2l_lookup(int p, int s, bool fp32, M2LVariant *out);
+void build_m2l_work(const M2LTiling &tl, const M2LVariant &v, int nwaves, M2LWork &out);
+
+// ------------------------------------------------------------------ context
+struct ProfEntry { const char *name; hipEvent_t a, b; };
+
+struct fmm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr, aux = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    bool profile = false;
+    bool overlap = true;                  // P2P on the auxiliary stream
+    std::vector<ProfEntry> prof;
+    std::vector<hipEvent_t> ev_pool;
+    hipEvent_t ev_up = nullptr, ev_near = nullptr;
+    struct Server *server = nullptr;
+    std::vector<struct fmm_tree *> trees;  // live trees; released with the context
+};
+
+struct fmm_tree {
+    fmm_ctx *ctx = nullptr;
+    int method = FMM_METHOD_FMM, ncrit = 0;
+    double theta = 0.5;
+    HostTree ht;
+    int64_t nleaves = 0;
+    std::vector<int32_t> leaves;           // cell index of every leaf
+    std::vector<int32_t> level_nonleaf_ptr, level_nonleaf;  // M2M work per level
+    M2LTiling tiling;
+    // device copies
+    DevCell *d_cells = nullptr;
+    int32_t *d_perm = nullptr, *d_leaf_of = nullptr, *d_leaves = nullptr;
+    int32_t *d_nonleaf = nullptr, *d_level_cells = nullptr;
+    double *d_x = nullptr;                 // sorted positions, SoA x[n] y[n] z[n]
+    float *d_xi = nullptr;                 // FP32 offsets from own leaf centre / leaf radius, 4 per particle
+    int32_t *d_p2p_ptr = nullptr, *d_p2p_src = nullptr;   // per leaf, sources as cell ids
+    int4 *d_work = nullptr;                // per expansion configuration
+    int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_tile_cell = nullptr;
+    int32_t *d_tile_chunk0 = nullptr, *d_tile_nchunk = nullptr;
+    int32_t *d_p2p_order = nullptr;        // leaf ordinals by decreasing near-field cost
+    int32_t *d_wave_ptr = nullptr;
+    M2LWork m2lwork;
+    double *d_cls_geom = nullptr;
+    int32_t *d_bh_leafgroup = nullptr;
+    // per expansion state
+    int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;
+    const double *mom_user = nullptr;
+    double *d_mom = nullptr;               // sorted moments FP64 (w per particle)
+    float *d_mom32 = nullptr;              // sorted moments FP32 (8 per particle)
+    double *d_M64 = nullptr;
+    float *d_M32 = nullptr;
+    void *d_part = nullptr;
+    double *d_L64 = nullptr;
+    double *d_near = nullptr;              // 4 per particle
+    double *d_D64 = nullptr, *d_sc64 = nullptr;
+    float *d_D32 = nullptr, *d_sc32 = nullptr;
+    size_t dev_bytes = 0;
+    std::vector<void *> allocs;
+    double work[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// allocation helper that records the block on the tree
+int tree_alloc(fmm_tree *t, void **p, size_t bytes);
+
+// profiling helper: launch wrapper
+struct ProfScope {
+    fmm_ctx *ctx;
+    hipStream_t s;
+    const char *name;
+    hipEvent_t b = nullptr;
+    ProfScope(fmm_ctx *c, hipStream_t st, const char *nm);
+    ~ProfScope();
+};
+
+// kernels entry points (host launchers), return hipError_t
+hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s);
+hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s);
+hipError_t launch_p2m(fmm_tree *t, hipStream_t s);
+hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s);
+hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s);
+hipError_t launch_dtable(fmm_tree *t, hipStream_t s);
+hipError_t launch_fill(double *p, size_t count, hipStream_t s);
+hipError_t launch_m2l(fmm_tree *t, hipStream_t s);
+hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s);
+hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s);
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
+hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
+
+// serving (serve.cpp)
+int serve_destroy(fmm_ctx *ctx);

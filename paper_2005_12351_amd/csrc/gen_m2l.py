@@ -1,0 +1,267 @@
+"""Writes the unrolled M2L kernels of libfmm.so (a build step).
+
+The multipole-to-local translation (Eq. 8 of Pepper & Fangohr, arXiv
+2005.12351) is, for target cell B and source cell A,
+
+    L_n(B) += sum_{s <= |m| <= p - |n|} M_m(A) D_{n+m}(z_B - z_A),  |n| <= p - s,
+
+with D_k the derivatives of 1/r.  In the normalised form used on the GPU
+(M~_m = M_m / r_A^|m|, L~_n = L_n r_B^(|n|+1), rho = r_A / r_B) it reads
+
+    L~_n(B) += sum_m D_{n+m}((z_B - z_A) / r_B) * rho^|m| * M~_m(A).
+
+Each generated kernel runs one 64-wide wavefront per work item: lane l owns
+the target cell of tile slot l and keeps its local coefficients (or one block
+of them) in registers; the wave walks the tile's translation classes, and at
+each step every lane streams the multipole of its own source while the
+derivative tensor of the class, identical for all lanes, comes through scalar
+loads.  The contraction is written out term by term (one fused multiply-add
+each), so no index arithmetic is left at run time.  The grid has exactly as
+many waves as the device keeps resident; the host cuts the concatenated
+(tile, output block, entry) work into equally expensive pieces per wave, so
+every SIMD finishes together although the blocks differ in work by up to 10x;
+a wave writes its partial sums only where its range crosses a (tile, block)
+boundary.
+
+Usage: python gen_m2l.py OUTDIR  -> OUTDIR/m2l_s{0,1,2}_{f32,f64}.hip
+"""
+import os
+import sys
+
+P_MAX = 10
+TILE = 64
+
+# code-shape options (register blocking and scalar-load pipelining); the
+# defaults are the measured best on gfx950, see DEFAULTS
+DEFAULTS = {"acc32": 128, "m32": 128, "acc64": 64, "m64": 48, "dgroup32": 24, "dgroup64": 10, "pipeline": 1,
+            "depth": 1, "scale_branch": 0}
+
+
+def orders(p):
+    out = []
+    for k in range(p + 1):
+        for nx in range(k, -1, -1):
+            for ny in range(k - nx, -1, -1):
+                out.append((nx, ny, k - nx - ny))
+    return out
+
+
+def nterms(p):
+    return 0 if p < 0 else (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def idx(n):
+    k = sum(n)
+    a = n[1] + n[2]
+    return nterms(k - 1) + a * (a + 1) // 2 + n[2]
+
+
+def pad(x, m):
+    return (x + m - 1) // m * m
+
+
+def split_blocks(p, s, max_acc):
+    """Fewest contiguous n-ranges [a, b) of nearly equal size with at most
+    max_acc accumulators each (every block re-reads the multipole
+    coefficients it needs, so fewer blocks means less gather traffic)."""
+    nl = nterms(p - s)
+    nb = max(1, -(-nl // max_acc))
+    assert nb <= 16, 'at most 16 output blocks'
+    return [(nl * i // nb, nl * (i + 1) // nb) for i in range(nb)]
+
+
+def gen_kernel(p, s, fp32, opt=None):
+    """One kernel per (p, s, precision).  Work split: blockIdx.x = work item
+    (tile, entry range, output row), blockIdx.y = block of output
+    coefficients.  Inside a block the needed multipole coefficients are loaded
+    into registers in chunks; within a chunk the multiply-adds are emitted in
+    bands of equal total derivative order |n| + |m|, so that only one band of
+    the (uniform) derivative tensor is live in scalar registers at a time; an
+    scheduling barrier (not a memory clobber, so the tensor stays eligible
+    for scalar loads) separates the groups so that the compiler cannot hoist
+    every scalar load to the top of the loop."""
+    T = "float" if fp32 else "double"
+    V = "float4" if fp32 else "double2"
+    VW = 4 if fp32 else 2
+    fma = "__builtin_fmaf" if fp32 else "__builtin_fma"
+    suf = "f32" if fp32 else "f64"
+    nm = nterms(p) - nterms(s - 1)
+    nl = nterms(p - s)
+    nmp = pad(nm, 4)
+    nlp = pad(nl, 4)
+    nd = pad(nterms(p), 16)
+    scw = pad(p + 1, 4)
+    opt = dict(DEFAULTS, **(opt or {}))
+    max_acc = opt["acc32"] if fp32 else opt["acc64"]
+    max_m = opt["m32"] if fp32 else opt["m64"]
+    dgroup = opt["dgroup32"] if fp32 else opt["dgroup64"]
+    blocks = split_blocks(p, s, max_acc)
+    ns = orders(p - s)
+    ms = orders(p)[nterms(s - 1):]
+    name = f"m2l_p{p}_s{s}_{suf}"
+    L = []
+    L.append(f"__global__ __launch_bounds__({TILE}) void {name}(M2LArgs a)")
+    L.append("{")
+    L.append("    const int lane = threadIdx.x;")
+    L.append(f"    const {T} *__restrict__ Mb = (const {T} *)a.M;")
+    L.append(f"    const {T} *__restrict__ Db = (const {T} *)a.D;")
+    L.append(f"    const {T} *__restrict__ Sb = (const {T} *)a.sc;")
+    L.append("    // this wave's pieces (equal total cost per wave, fixed by the host)")
+    L.append("    const int p0 = a.wave_ptr[blockIdx.x], p1 = a.wave_ptr[blockIdx.x + 1];")
+    L.append("    for (int item = p0; item < p1; ++item) {")
+    L.append("    const int4 w = a.work[item];")
+    L.append("    const int blk = w.x >> 24;")
+    L.append(f"    {T} *__restrict__ out = ({T} *)a.part + ((size_t)w.w + lane) * {nlp};")
+    for bi, (n0, n1) in enumerate(blocks):
+        kw = "if" if bi == 0 else "else if"
+        L.append(f"    {kw} (blk == {bi}) {{")
+        for i in range(n0, n1):
+            L.append(f"        {T} c{i} = 0;")
+        minord = min(sum(ns[i]) for i in range(n0, n1))
+        need = [j for j, m in enumerate(ms) if sum(m) + minord <= p]
+        # chunks of the needed m, aligned to the vector width
+        chunks, cur = [], []
+        for j in need:
+            if cur and (len(cur) >= max_m and j % VW == 0):
+                chunks.append(cur)
+                cur = []
+            cur.append(j)
+        if cur:
+            chunks.append(cur)
+        L.append("        for (int u = w.y; u < w.z; ++u) {")
+        L.append("            const int cls = a.ucls[u];")
+        L.append(f"            const {T} *__restrict__ D = Db + (size_t)cls * {nd};")
+        L.append(f"            const {T} *__restrict__ sc = Sb + (size_t)cls * {scw};")
+        L.append(f"            const {T} *__restrict__ Mr = Mb + (size_t)a.usrc[(size_t)u * {TILE} + lane] * {nmp};")
+        comps = "xyzw"
+        for ch in chunks:
+            L.append("            {")
+            groups = sorted(set(j // VW for j in ch))
+            for g in groups:
+                L.append(f"                const {V} v{g} = *(const {V} *)(Mr + {g * VW});")
+            if opt["scale_branch"]:
+                # rho = r_A / r_B is 1 for pairs of one level: skip the scaling then
+                for j in ch:
+                    L.append(f"                {T} m{j} = v{j // VW}.{comps[j % VW]};")
+                L.append("                if (sc[1] != 1) {")
+                for j in ch:
+                    L.append(f"                    m{j} *= sc[{sum(ms[j])}];")
+                L.append("                }")
+            else:
+                for j in ch:
+                    L.append(f"                const {T} m{j} = v{j // VW}.{comps[j % VW]} * sc[{sum(ms[j])}];")
+            # multiply-adds of this chunk, ordered by derivative index k = n + m
+            # (bands of equal |k| are contiguous in the coefficient order)
+            terms = []
+            for i in range(n0, n1):
+                n = ns[i]
+                for j in ch:
+                    m = ms[j]
+                    if sum(n) + sum(m) > p:
+                        continue
+                    k = idx((n[0] + m[0], n[1] + m[1], n[2] + m[2]))
+                    terms.append((k, i, j))
+            terms.sort()
+            # groups of at most dgroup distinct k, never spanning two bands
+            groups, cur, curk = [], [], []
+            for k, i, j in terms:
+                band = sum(orders(p)[k])
+                if curk and k != curk[-1] and (len(curk) >= dgroup or sum(orders(p)[curk[-1]]) != band):
+                    groups.append((curk, cur))
+                    cur, curk = [], []
+                if not curk or curk[-1] != k:
+                    curk.append(k)
+                cur.append((k, i, j))
+            if cur:
+                groups.append((curk, cur))
+            D = "d"
+            def loads(gi):
+                ks, _ = groups[gi]
+                return [f"                const {T} {D}{k} = D[{k}];" for k in ks]
+            def fmas(gi):
+                _, ts = groups[gi]
+                return [f"                c{i} = {fma}({D}{k}, m{j}, c{i});" for k, i, j in ts]
+            if opt["pipeline"]:
+                # loads of group g+depth are issued before the multiply-adds of group g
+                dep = opt["depth"]
+                L.append('                __builtin_amdgcn_sched_barrier(0);')
+                for gi in range(min(dep, len(groups))):
+                    L.extend(loads(gi))
+                for gi in range(len(groups)):
+                    L.append('                __builtin_amdgcn_sched_barrier(0);')
+                    if gi + dep < len(groups):
+                        L.extend(loads(gi + dep))
+                    L.extend(fmas(gi))
+            else:
+                for gi in range(len(groups)):
+                    L.append('                __builtin_amdgcn_sched_barrier(0);')
+                    L.extend(loads(gi))
+                    L.extend(fmas(gi))
+            L.append("            }")
+        L.append("        }")
+        for i in range(n0, n1):
+            L.append(f"        out[{i}] = c{i};")
+        L.append("    }")
+    L.append("    }")
+    L.append("}")
+    launcher = f"""
+static hipError_t launch_{name}(const M2LArgs &a, int nwaves, hipStream_t st)
+{{
+    hipLaunchKernelGGL({name}, dim3(nwaves), dim3({TILE}), 0, st, a);
+    return hipGetLastError();
+}}
+
+static int occ_{name}()
+{{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, {name}, {TILE}, 0) != hipSuccess) return 1;
+    return per_cu > 0 ? per_cu : 1;
+}}
+"""
+    fma_per_block = []
+    for (n0, n1) in blocks:
+        fma_per_block.append(sum(nterms(p - sum(ns[i])) - nterms(s - 1) for i in range(n0, n1)))
+    meta = dict(name=name, nl_pad=nlp, nm_pad=nmp, nd=nd, nblocks=len(blocks), scw=scw,
+                blo=[b[0] for b in blocks] + [blocks[-1][1]], bfma=fma_per_block)
+    return "\n".join(L) + "\n" + launcher, meta
+
+
+def gen_file(s, fp32, opt=None):
+    suf = "f32" if fp32 else "f64"
+    parts = ["// Generated by gen_m2l.py; do not edit.", "#include <algorithm>", '#include "fmm_internal.h"', ""]
+    metas = []
+    for p in range(s + 1, P_MAX + 1):
+        code, meta = gen_kernel(p, s, fp32, opt)
+        parts.append(code)
+        metas.append((p, meta))
+    parts.append(f"bool m2l_lookup_s{s}_{suf}(int p, M2LVariant *v)")
+    parts.append("{")
+    parts.append("    switch (p) {")
+    for p, m in metas:
+        blo = ", ".join(str(x) for x in m["blo"] + [0] * (17 - len(m["blo"])))
+        bf = ", ".join(str(x) for x in m["bfma"] + [0] * (16 - len(m["bfma"])))
+        parts.append(f"    case {p}: *v = M2LVariant{{launch_{m['name']}, occ_{m['name']}, {m['nl_pad']}, {m['nm_pad']}, "
+                     f"{m['nd']}, {m['nblocks']}, {{{blo}}}, {{{bf}}}}}; return true;")
+    parts.append("    default: return false;")
+    parts.append("    }")
+    parts.append("}")
+    return "\n".join(parts) + "\n"
+
+
+def main(outdir, opt=None):
+    os.makedirs(outdir, exist_ok=True)
+    written = []
+    for s in (0, 1, 2):
+        for fp32 in (True, False):
+            fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}.hip")
+            txt = gen_file(s, fp32, opt)
+            old = open(fn).read() if os.path.exists(fn) else None
+            if old != txt:
+                with open(fn, "w") as f:
+                    f.write(txt)
+            written.append(fn)
+    return written
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "_build/gen")

@@ -1,0 +1,969 @@
+// GPU kernels of libfmm.so other than the generated M2L contraction:
+// particle/moment preparation, P2M, M2M, the derivative tensor table,
+// M2L partial combination, L2L, P2P and L2P (Pepper & Fangohr, arXiv
+// 2005.12351, Section 2 and Section 3.2).
+//
+// All expansions on the GPU are kept in a dimensionless form:
+//   M~_n(A) = M_n(A) / r_A^|n|,  L~_n(B) = L_n(B) * r_B^(|n|+1),
+// with r the cell radius (half side).  Child and parent centres differ by
+// exactly +-r_child per axis, so M2M and L2L become fixed rational operators
+// per octant and the M2L derivative tensor depends only on the dimensionless
+// pair geometry.  P2M, M2M, L2L, L2P run in FP64.
+#include <cmath>
+
+#include "fmm_internal.h"
+
+// ------------------------------------------------------------------ tables
+struct MITable {
+    MultiIndex v[nterms(kPTable)];
+};
+constexpr MITable make_mi()
+{
+    MITable t{};
+    int i = 0;
+    for (int k = 0; k <= kPTable; ++k)
+        for (int nx = k; nx >= 0; --nx)
+            for (int ny = k - nx; ny >= 0; --ny) t.v[i++] = MultiIndex{(int8_t)nx, (int8_t)ny, (int8_t)(k - nx - ny), (int8_t)k};
+    return t;
+}
+struct HalfTable {
+    double v[kPTable + 2];
+};
+constexpr HalfTable make_half()
+{
+    HalfTable t{};
+    double f = 1.0;
+    for (int a = 0; a <= kPTable + 1; ++a) {
+        if (a > 0) f = f * 0.5 / a;
+        t.v[a] = f;
+    }
+    return t;
+}
+__constant__ MITable k_mi = make_mi();
+__constant__ HalfTable k_half = make_half();   // (1/2)^a / a!
+
+__device__ __forceinline__ double cell_radius(int level, double h) { return ldexp(1.0, kMaxLevel - level) * h; }
+
+// real centre, computed exactly as the canonical definition: lo + c * h
+__device__ __forceinline__ void cell_center(const DevCell &c, const double *lo, double h, double *z)
+{
+    const double r = ldexp(1.0, kMaxLevel - c.level);
+    z[0] = __dadd_rn(lo[0], __dmul_rn((double)(2 * c.ix + 1) * r, h));
+    z[1] = __dadd_rn(lo[1], __dmul_rn((double)(2 * c.iy + 1) * r, h));
+    z[2] = __dadd_rn(lo[2], __dmul_rn((double)(2 * c.iz + 1) * r, h));
+}
+
+struct Geo {
+    double lo[3];
+    double h;
+};
+
+// ------------------------------------------------------------------ fill
+__global__ void fill_kernel(double *p, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+__global__ void zero_ints_kernel(int *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+hipError_t launch_fill(double *p, size_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<size_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_kernel, dim3(g), dim3(256), 0, s, p, count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ particles
+// sorted SoA positions and per-particle FP32 offsets from the own leaf centre
+// in units of the leaf radius
+__global__ void prep_particles_kernel(int n, const double *__restrict__ pos, const int32_t *__restrict__ perm,
+                                      const int32_t *__restrict__ leaf_of, const DevCell *__restrict__ cells, Geo g,
+                                      double *__restrict__ xs, float *__restrict__ xi)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = perm[i];
+    const double x = pos[3 * (size_t)j], y = pos[3 * (size_t)j + 1], z = pos[3 * (size_t)j + 2];
+    xs[i] = x;
+    xs[n + i] = y;
+    xs[2 * (size_t)n + i] = z;
+    const DevCell c = cells[leaf_of[i]];
+    double zc[3];
+    cell_center(c, g.lo, g.h, zc);
+    const double ir = 1.0 / cell_radius(c.level, g.h);
+    float4 v;
+    v.x = (float)((x - zc[0]) * ir);
+    v.y = (float)((y - zc[1]) * ir);
+    v.z = (float)((z - zc[2]) * ir);
+    v.w = 0.f;
+    reinterpret_cast<float4 *>(xi)[i] = v;
+}
+
+hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s)
+{
+    const int n = (int)t->ht.n;
+    Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
+    hipLaunchKernelGGL(prep_particles_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, t->d_perm,
+                       t->d_leaf_of, t->d_cells, g, t->d_x, t->d_xi);
+    return hipGetLastError();
+}
+
+// sorted moments: FP64 (w per particle) and FP32 (8 per particle; for
+// quadrupoles the 6 components and the trace)
+__global__ void prep_moments_kernel(int n, int w, const double *__restrict__ mom, const int32_t *__restrict__ perm,
+                                    double *__restrict__ m64, float *__restrict__ m32)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t j = (size_t)perm[i];
+    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < w; ++k) {
+        const double a = mom[j * w + k];
+        m64[(size_t)i * w + k] = a;
+        v[k] = (float)a;
+    }
+    if (w == 6) v[6] = (float)(mom[j * 6 + 0] + mom[j * 6 + 3] + mom[j * 6 + 5]);
+    float4 *o = reinterpret_cast<float4 *>(m32) + 2 * (size_t)i;
+    o[0] = make_float4(v[0], v[1], v[2], v[3]);
+    o[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s)
+{
+    const int n = (int)t->ht.n;
+    const int w = t->order == 0 ? 1 : (t->order == 1 ? 3 : 6);
+    hipLaunchKernelGGL(prep_moments_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, w, t->mom_user, t->d_perm,
+                       t->d_mom, t->d_mom32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ P2M
+// M~_n = r^-s sum_j sum_{sigma <= n, |sigma| = s} zeta_j^(n-sigma)/(n-sigma)! S_sigma(j)
+// with zeta = (z - x_j)/r and S_sigma = (-1)^s T_sigma / sigma! (Eq. 3, Eq. 5).
+// One workgroup per leaf; a thread owns one or more coefficients n (its
+// multi-index is read once), particles are staged in LDS 64 at a time as
+// per-axis tables zeta^a / a!, so the inner loop touches LDS only.
+constexpr int kP2MThreads = 128;
+constexpr int kAxW = kPTable + 2;   // row of one axis table, padded
+
+struct InvTable {
+    double v[kPTable + 2];
+};
+constexpr InvTable make_inv()
+{
+    InvTable t{};
+    t.v[0] = 1.0;
+    for (int a = 1; a <= kPTable + 1; ++a) t.v[a] = 1.0 / a;
+    return t;
+}
+__constant__ InvTable k_inv = make_inv();   // 1/a
+
+template <int S>
+__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
+                                                          const DevCell *__restrict__ cells, Geo g,
+                                                          const double *__restrict__ xs, int n,
+                                                          const double *__restrict__ mom, double *__restrict__ M)
+{
+    constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
+    __shared__ double pw[64][3][kAxW];
+    __shared__ double sv[64][W];
+    const int c = leaves[blockIdx.x];
+    const DevCell cell = cells[c];
+    double z[3];
+    cell_center(cell, g.lo, g.h, z);
+    const double r = cell_radius(cell.level, g.h);
+    const double ir = 1.0 / r;
+    const double irs = S == 0 ? 1.0 : (S == 1 ? ir : ir * ir);
+    const int n0 = nterms(S - 1), nm = nterms(p) - n0;
+    constexpr int KMAX = (nterms(kPTable) + kP2MThreads - 1) / kP2MThreads;
+    double acc[KMAX];
+    int ix[KMAX], iy[KMAX], iz[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        acc[k] = 0.0;
+        const int i = threadIdx.x + k * kP2MThreads;
+        const MultiIndex nn = k_mi.v[i < nm ? n0 + i : 0];
+        ix[k] = nn.x;
+        iy[k] = nn.y;
+        iz[k] = nn.z;
+    }
+    for (int base = 0; base < cell.count; base += 64) {
+        const int cnt = min(64, cell.count - base);
+        __syncthreads();
+        for (int it = threadIdx.x; it < 3 * cnt; it += kP2MThreads) {
+            // item -> (particle, axis): zeta^a / a! for a = 0..p
+            const int t = it / 3, d = it % 3;
+            const size_t j = (size_t)cell.first + base + t;
+            const double zeta = (z[d] - xs[(size_t)d * n + j]) * ir;
+            double f = 1.0;
+            pw[t][d][0] = 1.0;
+            for (int a = 1; a <= p; ++a) {
+                f = f * zeta * k_inv.v[a];
+                pw[t][d][a] = f;
+            }
+        }
+        if ((int)threadIdx.x < cnt) {
+            const int t = threadIdx.x;
+            const double *m = mom + ((size_t)cell.first + base + t) * W;
+            if (S == 0) {
+                sv[t][0] = m[0];
+            } else if (S == 1) {
+                sv[t][0] = -m[0] * irs;
+                sv[t][1] = -m[1] * irs;
+                sv[t][2] = -m[2] * irs;
+            } else {
+                sv[t][0] = 0.5 * m[0] * irs;   // (2,0,0)
+                sv[t][1] = m[1] * irs;         // (1,1,0)
+                sv[t][2] = m[2] * irs;         // (1,0,1)
+                sv[t][3] = 0.5 * m[3] * irs;   // (0,2,0)
+                sv[t][4] = m[4] * irs;         // (0,1,1)
+                sv[t][5] = 0.5 * m[5] * irs;   // (0,0,2)
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            if ((int)threadIdx.x + k * kP2MThreads >= nm) break;
+            const int ax = ix[k], ay = iy[k], az = iz[k];
+            double a = acc[k];
+            for (int t = 0; t < cnt; ++t) {
+                if (S == 0) {
+                    a = fma(pw[t][0][ax] * pw[t][1][ay], pw[t][2][az] * sv[t][0], a);
+                } else if (S == 1) {
+                    // sigma = e_x, e_y, e_z; a zero table entry stands for a negative index
+                    const double px = pw[t][0][ax], py = pw[t][1][ay], pz = pw[t][2][az];
+                    const double pxm = ax ? pw[t][0][ax - 1] : 0.0, pym = ay ? pw[t][1][ay - 1] : 0.0,
+                                 pzm = az ? pw[t][2][az - 1] : 0.0;
+                    a = fma(pxm * py, pz * sv[t][0], a);
+                    a = fma(px * pym, pz * sv[t][1], a);
+                    a = fma(px * py, pzm * sv[t][2], a);
+                } else {
+                    const double px0 = pw[t][0][ax], py0 = pw[t][1][ay], pz0 = pw[t][2][az];
+                    const double px1 = ax >= 1 ? pw[t][0][ax - 1] : 0.0, py1 = ay >= 1 ? pw[t][1][ay - 1] : 0.0,
+                                 pz1 = az >= 1 ? pw[t][2][az - 1] : 0.0;
+                    const double px2 = ax >= 2 ? pw[t][0][ax - 2] : 0.0, py2 = ay >= 2 ? pw[t][1][ay - 2] : 0.0,
+                                 pz2 = az >= 2 ? pw[t][2][az - 2] : 0.0;
+                    a = fma(px2 * py0, pz0 * sv[t][0], a);
+                    a = fma(px1 * py1, pz0 * sv[t][1], a);
+                    a = fma(px1 * py0, pz1 * sv[t][2], a);
+                    a = fma(px0 * py2, pz0 * sv[t][3], a);
+                    a = fma(px0 * py1, pz1 * sv[t][4], a);
+                    a = fma(px0 * py0, pz2 * sv[t][5], a);
+                }
+            }
+            acc[k] = a;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+        if ((int)threadIdx.x + k * kP2MThreads < nm) M[(size_t)c * nmp + threadIdx.x + k * kP2MThreads] = acc[k];
+}
+
+hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
+{
+    Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
+    const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
+    const dim3 gr((unsigned)t->nleaves), bl(kP2MThreads);
+    if (t->order == 0)
+        hipLaunchKernelGGL(p2m_kernel<0>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
+                           t->d_mom, t->d_M64);
+    else if (t->order == 1)
+        hipLaunchKernelGGL(p2m_kernel<1>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
+                           t->d_mom, t->d_M64);
+    else
+        hipLaunchKernelGGL(p2m_kernel<2>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
+                           t->d_mom, t->d_M64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ M2M
+// M~_n(P) = sum_children 2^-|n| sum_{k <= n} prod_d (-sigma_d)^k_d / k_d! M~_{n-k}(C)
+// (Eq. 4 with new-minus-old centre; the child centre is the parent's plus
+// sigma r_child, and the radii halve).  The triple sum factorises over the
+// axes, so it is applied as three 1-D passes in LDS, all children at once.
+constexpr int kM2MThreads = 256;
+__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
+                                                          const DevCell *__restrict__ cells, double *__restrict__ M)
+{
+    extern __shared__ double sm[];   // X[8][nt], Y[8][nt]
+    const int nt = nterms(p), n0 = nterms(s - 1);
+    double *X = sm, *Y = sm + 8 * nt;
+    __shared__ double inv_fact[kPTable + 2];
+    const int P = parents[blockIdx.x];
+    const DevCell pc = cells[P];
+    const int nch = pc.nchild, kid0 = pc.child0;
+    if (threadIdx.x <= kPTable + 1) {
+        double f = 1.0;
+        for (int a = 1; a <= (int)threadIdx.x; ++a) f *= k_inv.v[a];
+        inv_fact[threadIdx.x] = f;
+    }
+    for (int it = threadIdx.x; it < nch * nt; it += blockDim.x) {
+        const int k = it / nt, i = it % nt;
+        X[k * nt + i] = i < n0 ? 0.0 : M[(size_t)(kid0 + k) * nmp + (i - n0)];
+    }
+    __syncthreads();
+    // pass d: dst_n = sum_{a <= n_d} (-sigma_d)^a / a! src_{n - a e_d}
+    for (int d = 0; d < 3; ++d) {
+        const double *src = d == 1 ? Y : X;
+        double *dst = d == 1 ? X : Y;
+        for (int it = threadIdx.x; it < nch * nt; it += blockDim.x) {
+            const int k = it / nt, i = it % nt;
+            const DevCell cc = cells[kid0 + k];
+            const int bit = d == 0 ? (cc.ix & 1) : (d == 1 ? (cc.iy & 1) : (cc.iz & 1));
+            const double sg = bit ? -1.0 : 1.0;   // -sigma_d
+            const MultiIndex nn = k_mi.v[i];
+            int m[3] = {nn.x, nn.y, nn.z};
+            const int nd = m[d];
+            double acc = 0.0, sp = 1.0;
+            for (int a = 0; a <= nd; ++a) {
+                acc = fma(sp * inv_fact[a], src[k * nt + mindex(m[0], m[1], m[2])], acc);
+                m[d] -= 1;
+                sp *= sg;
+            }
+            dst[k * nt + i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int i = n0 + threadIdx.x; i < nt; i += blockDim.x) {
+        double acc = 0.0;
+        for (int k = 0; k < nch; ++k) acc += Y[k * nt + i];
+        M[(size_t)P * nmp + (i - n0)] = ldexp(acc, -(int)k_mi.v[i].k);
+    }
+}
+
+hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
+{
+    const int a = t->level_nonleaf_ptr[level], b = t->level_nonleaf_ptr[level + 1];
+    if (b <= a) return hipSuccess;
+    const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
+    const size_t lds = (size_t)16 * nterms(t->p) * sizeof(double);
+    hipLaunchKernelGGL(m2m_kernel, dim3(b - a), dim3(kM2MThreads), lds, s, t->p, t->order, nmp, t->d_nonleaf + a,
+                       t->d_cells, t->d_M64);
+    return hipGetLastError();
+}
+
+__global__ void to_fp32_kernel(size_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = (float)a[i];
+}
+
+hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s)
+{
+    const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
+    const size_t n = (size_t)(t->ht.ncells() + 1) * nmp;
+    const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(to_fp32_kernel, dim3(g), dim3(256), 0, s, n, t->d_M64, t->d_M32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ D table
+// Derivatives D_k = d^k (1/r) at every M2L class geometry, |k| <= p, by the
+// Hermite-type recursion on R^(j)_n = d^n f^(j)(u), f(u) = (2u)^-1/2,
+// u = r^2/2:  R^(j)_0 = (-1)^j (2j-1)!! r^-(2j+1),
+//             R^(j)_{m+e_d} = x_d R^(j+1)_m + m_d R^(j+1)_{m-e_d},
+// and D_k = R^(0)_k.  FP64; an FP32 copy feeds the mixed-precision M2L.
+// Also writes the scale row rho^k, k = 0..p.
+__global__ __launch_bounds__(64) void dtable_kernel(int p, int nd, int scw, const double *__restrict__ geom,
+                                                    double *__restrict__ D64, float *__restrict__ D32,
+                                                    double *__restrict__ S64, float *__restrict__ S32)
+{
+    __shared__ double Rall[1820];   // all R^(j) blocks: sum_j nterms(p - j) = C(p+4,4) <= 1820 for p <= 12
+    const int c = blockIdx.x;
+    const double x[3] = {geom[4 * c], geom[4 * c + 1], geom[4 * c + 2]};
+    const double rho = geom[4 * c + 3];
+    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    // offsets of the R^(j) blocks
+    auto off = [&](int j) {
+        int o = 0;
+        for (int q = 0; q < j; ++q) o += nterms(p - q);
+        return o;
+    };
+    if ((int)threadIdx.x <= p) {
+        const int j = threadIdx.x;
+        double v = 1.0 / sqrt(r2);
+        const double ir2 = 1.0 / r2;
+        for (int q = 1; q <= j; ++q) v *= -(2.0 * q - 1.0) * ir2;
+        Rall[off(j)] = v;
+    }
+    __syncthreads();
+    for (int t = 1; t <= p; ++t) {
+        const int per = (t + 1) * (t + 2) / 2;
+        const int items = per * (p - t + 1);
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int j = it / per;
+            const MultiIndex nn = k_mi.v[nterms(t - 1) + it % per];
+            int m[3] = {nn.x, nn.y, nn.z};
+            const int d = nn.x > 0 ? 0 : (nn.y > 0 ? 1 : 2);
+            m[d] -= 1;
+            const double *Rn = Rall + off(j + 1);
+            double v = x[d] * Rn[mindex(m[0], m[1], m[2])];
+            if (m[d] > 0) {
+                int q[3] = {m[0], m[1], m[2]};
+                q[d] -= 1;
+                v = fma((double)m[d], Rn[mindex(q[0], q[1], q[2])], v);
+            }
+            Rall[off(j) + mindex(nn.x, nn.y, nn.z)] = v;
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        const double v = k < nterms(p) ? Rall[k] : 0.0;
+        D64[(size_t)c * nd + k] = v;
+        D32[(size_t)c * nd + k] = (float)v;
+    }
+    for (int k = threadIdx.x; k < scw; k += blockDim.x) {
+        const double v = k <= p ? ldexp(1.0, ilogb(rho) * k) : 0.0;   // rho is a power of two
+        S64[(size_t)c * scw + k] = v;
+        S32[(size_t)c * scw + k] = (float)v;
+    }
+}
+
+hipError_t launch_dtable(fmm_tree *t, hipStream_t s)
+{
+    if (t->tiling.nclasses == 0) return hipSuccess;
+    M2LVariant v;
+    m2l_lookup(t->p, t->order, true, &v);
+    const int scw = (t->p + 1 + 3) / 4 * 4;
+    hipLaunchKernelGGL(dtable_kernel, dim3(t->tiling.nclasses), dim3(64), 0, s, t->p, v.nd, scw, t->d_cls_geom,
+                       t->d_D64, t->d_D32, t->d_sc64, t->d_sc32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ M2L
+hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
+{
+    const M2LWork &wk = t->m2lwork;
+    if (wk.work.empty()) return hipSuccess;
+    const bool f32 = t->prec == FMM_PREC_MIXED;
+    M2LVariant v;
+    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
+    M2LArgs a;
+    a.work = t->d_work;
+    a.ucls = t->d_ucls;
+    a.usrc = t->d_usrc;
+    a.D = f32 ? (const void *)t->d_D32 : (const void *)t->d_D64;
+    a.sc = f32 ? (const void *)t->d_sc32 : (const void *)t->d_sc64;
+    a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
+    a.part = t->d_part;
+    a.wave_ptr = t->d_wave_ptr;
+    return v.launch(a, wk.nwaves, s);
+}
+
+// sum of the chunk partials of every target slot into L~ (FP64); each output
+// block of a tile has its own chunks
+struct BlockBounds {
+    int lo[17];
+    int nb;
+};
+
+template <typename T>
+__global__ void m2l_combine_kernel(int nslots, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ tile_cell,
+                                   const int32_t *__restrict__ chunk0, const int32_t *__restrict__ nchunk,
+                                   const T *__restrict__ part, double *__restrict__ L)
+{
+    const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)nslots * nl) return;
+    const int slot = (int)(id / nl), n = (int)(id % nl);
+    const int cell = tile_cell[slot];
+    if (cell < 0) return;
+    const int tile = slot / kTileW, lane = slot % kTileW;
+    int b = 0;
+    while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
+    double acc = 0.0;
+    const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
+    for (int k = 0; k < nc; ++k) acc += (double)part[((size_t)(c0 + k) * kTileW + lane) * nlp + n];
+    L[(size_t)cell * nl + n] = acc;
+}
+
+hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
+{
+    const M2LTiling &tl = t->tiling;
+    if (tl.ntiles == 0) return hipSuccess;
+    const bool f32 = t->prec == FMM_PREC_MIXED;
+    M2LVariant v;
+    m2l_lookup(t->p, t->order, f32, &v);
+    BlockBounds bb;
+    for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
+    bb.nb = v.nblocks;
+    const int nl = nterms(t->p - t->order);
+    const int nslots = tl.ntiles * kTileW;
+    const size_t tot = (size_t)nslots * nl;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+    if (f32)
+        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
+                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
+    else
+        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
+                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ L2L
+// L~_n(C) += sum_{a: |n+a| <= q} prod_d sigma_d^a_d / a_d! * 2^-(|n+a|+1) L~_{n+a}(P)
+// (Taylor shift of the local expansion by +sigma r_child, in the normalised
+// form).  Applied as three 1-D passes after scaling the parent row.
+__global__ __launch_bounds__(128) void l2l_kernel(int q, const int32_t *__restrict__ cellsl, const DevCell *__restrict__ cells,
+                                                  double *__restrict__ L)
+{
+    __shared__ double X[nterms(kPTable)], Y[nterms(kPTable)];
+    __shared__ double inv_fact[kPTable + 2];
+    const int C = cellsl[blockIdx.x];
+    const DevCell cc = cells[C];
+    const int nl = nterms(q);
+    if (threadIdx.x <= kPTable + 1) {
+        double f = 1.0;
+        for (int a = 1; a <= (int)threadIdx.x; ++a) f *= k_inv.v[a];
+        inv_fact[threadIdx.x] = f;
+    }
+    for (int i = threadIdx.x; i < nl; i += blockDim.x)
+        X[i] = ldexp(L[(size_t)cc.parent * nl + i], -((int)k_mi.v[i].k + 1));
+    __syncthreads();
+    const int bits[3] = {cc.ix & 1, cc.iy & 1, cc.iz & 1};
+    for (int d = 0; d < 3; ++d) {
+        const double *src = d == 1 ? Y : X;
+        double *dst = d == 1 ? X : Y;
+        const double sg = bits[d] ? 1.0 : -1.0;   // sigma_d
+        for (int i = threadIdx.x; i < nl; i += blockDim.x) {
+            const MultiIndex nn = k_mi.v[i];
+            int m[3] = {nn.x, nn.y, nn.z};
+            double acc = 0.0, sp = 1.0;
+            for (int a = 0; a <= q - nn.k; ++a) {
+                acc = fma(sp * inv_fact[a], src[mindex(m[0], m[1], m[2])], acc);
+                m[d] += 1;
+                sp *= sg;
+            }
+            dst[i] = acc;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < nl; i += blockDim.x) L[(size_t)C * nl + i] += Y[i];
+}
+
+hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s)
+{
+    const int a = (int)t->ht.level_ptr[level], b = (int)t->ht.level_ptr[level + 1];
+    if (b <= a) return hipSuccess;
+    hipLaunchKernelGGL(l2l_kernel, dim3(b - a), dim3(128), 0, s, t->p - t->order, t->d_level_cells + a, t->d_cells,
+                       t->d_L64);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ P2P
+// Direct interaction over the near-field lists (Section 3.2): one workgroup
+// per target leaf, lanes = (target, source slice).  MIXED: offsets from the
+// leaf centres in units of the target leaf radius, FP32 arithmetic, FP32
+// sums per source block added into Kahan-compensated accumulators; the result
+// is scaled back to physical units in FP64.  FP64: physical positions, IEEE
+// division and square root.
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v)
+{
+    const float y = v - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int S>
+__device__ __forceinline__ void p2p_pair_f32(float rx, float ry, float rz, float inv, const float4 &m0, const float4 &m1,
+                                             float &ph, float &ex, float &ey, float &ez)
+{
+    const float inv2 = inv * inv;
+    const float inv3 = inv * inv2;
+    if (S == 0) {
+        const float q3 = m0.x * inv3;
+        ph = __builtin_fmaf(m0.x, inv, ph);
+        ex = __builtin_fmaf(q3, rx, ex);
+        ey = __builtin_fmaf(q3, ry, ey);
+        ez = __builtin_fmaf(q3, rz, ez);
+    } else if (S == 1) {
+        const float mr = __builtin_fmaf(m0.x, rx, __builtin_fmaf(m0.y, ry, m0.z * rz));
+        ph = __builtin_fmaf(mr, inv3, ph);
+        const float t1 = 3.0f * mr * inv2;
+        ex = __builtin_fmaf(inv3, __builtin_fmaf(t1, rx, -m0.x), ex);
+        ey = __builtin_fmaf(inv3, __builtin_fmaf(t1, ry, -m0.y), ey);
+        ez = __builtin_fmaf(inv3, __builtin_fmaf(t1, rz, -m0.z), ez);
+    } else {
+        // m0 = (xx, xy, xz, yy), m1 = (yz, zz, tr, -)
+        const float qx = __builtin_fmaf(m0.x, rx, __builtin_fmaf(m0.y, ry, m0.z * rz));
+        const float qy = __builtin_fmaf(m0.y, rx, __builtin_fmaf(m0.w, ry, m1.x * rz));
+        const float qz = __builtin_fmaf(m0.z, rx, __builtin_fmaf(m1.x, ry, m1.y * rz));
+        const float rqr = __builtin_fmaf(rx, qx, __builtin_fmaf(ry, qy, rz * qz));
+        const float inv5 = inv3 * inv2;
+        const float r2 = rx * rx + ry * ry + rz * rz;
+        ph = __builtin_fmaf(0.5f * inv5, __builtin_fmaf(3.0f, rqr, -r2 * m1.z), ph);
+        const float a = __builtin_fmaf(7.5f * rqr, inv2, -1.5f * m1.z);
+        ex = __builtin_fmaf(inv5, __builtin_fmaf(a, rx, -3.0f * qx), ex);
+        ey = __builtin_fmaf(inv5, __builtin_fmaf(a, ry, -3.0f * qy), ey);
+        ez = __builtin_fmaf(inv5, __builtin_fmaf(a, rz, -3.0f * qz), ez);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void p2p_pair_f64(double rx, double ry, double rz, const double *m, double &ph, double &ex,
+                                             double &ey, double &ez)
+{
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double inv = 1.0 / sqrt(r2);
+    const double inv2 = inv * inv;
+    const double inv3 = inv * inv2;
+    if (S == 0) {
+        ph += m[0] * inv;
+        ex += m[0] * rx * inv3;
+        ey += m[0] * ry * inv3;
+        ez += m[0] * rz * inv3;
+    } else if (S == 1) {
+        const double mr = m[0] * rx + m[1] * ry + m[2] * rz;
+        const double inv5 = inv3 * inv2;
+        ph += mr * inv3;
+        ex += (3.0 * mr * rx - r2 * m[0]) * inv5;
+        ey += (3.0 * mr * ry - r2 * m[1]) * inv5;
+        ez += (3.0 * mr * rz - r2 * m[2]) * inv5;
+    } else {
+        const double qx = m[0] * rx + m[1] * ry + m[2] * rz;
+        const double qy = m[1] * rx + m[3] * ry + m[4] * rz;
+        const double qz = m[2] * rx + m[4] * ry + m[5] * rz;
+        const double rqr = rx * qx + ry * qy + rz * qz;
+        const double tr = m[0] + m[3] + m[5];
+        const double inv5 = inv3 * inv2;
+        const double inv7 = inv5 * inv2;
+        ph += 0.5 * (3.0 * rqr - r2 * tr) * inv5;
+        ex += 7.5 * rqr * rx * inv7 - 3.0 * qx * inv5 - 1.5 * tr * rx * inv5;
+        ey += 7.5 * rqr * ry * inv7 - 3.0 * qy * inv5 - 1.5 * tr * ry * inv5;
+        ez += 7.5 * rqr * rz * inv7 - 3.0 * qz * inv5 - 1.5 * tr * rz * inv5;
+    }
+}
+
+struct P2PArgs {
+    const int32_t *leaves, *ptr, *src, *order;
+    const DevCell *cells;
+    const float *xi;        // 4 per particle
+    const float *m32;       // 8 per particle
+    const double *xs;       // SoA
+    const double *m64;
+    double *near;           // 4 per particle
+    int n;
+    double h;
+};
+
+// Lanes of one wave sharing LDS data written by other lanes of the same wave:
+// a wavefront-scope fence around a wave barrier (no workgroup barrier, so the
+// four waves of a workgroup may run different numbers of source leaves).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kP2PWaves = 4;
+
+// One workgroup per target leaf, kP2PWaves waves; wave w takes the source
+// leaves w, w + kP2PWaves, ... of the list, stages them in its own LDS slots
+// (the next leaf is prefetched into registers while the current one is
+// summed), and the waves' compensated partial sums are added in a fixed order
+// at the end.
+template <int S>
+__global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
+{
+    constexpr int NV = S == 0 ? 1 : (S == 1 ? 2 : 3);   // float4 per staged source
+    __shared__ float4 st[kP2PWaves][NV][64];
+    __shared__ double red[kP2PWaves][4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lk = a.order[blockIdx.x];   // workgroups are dispatched in order: heavy leaves first
+    const int b = a.leaves[lk];
+    const DevCell cb = a.cells[b];
+    const double rb = ldexp(1.0, kMaxLevel - cb.level) * a.h;
+    const double sphi = 1.0 / pow(rb, (double)(S + 1)), sfld = sphi / rb;
+    const int e0 = a.ptr[lk], e1 = a.ptr[lk + 1];
+    const float4 *xi4 = reinterpret_cast<const float4 *>(a.xi);
+    const float4 *m4 = reinterpret_cast<const float4 *>(a.m32);
+    for (int t0 = 0; t0 < cb.count; t0 += 64) {
+        const int cs = min(64, cb.count - t0);
+        const int slices = 64 / cs;
+        const int ti = lane % cs, sl = lane / cs;
+        const bool active = sl < slices;
+        const int i = cb.first + t0 + ti;
+        const float4 eta = xi4[i];
+        float ps = 0.f, pc = 0.f, xs_ = 0.f, xc = 0.f, ys = 0.f, yc = 0.f, zs = 0.f, zc = 0.f;
+        // units of work of this wave: (source leaf e, 64-particle chunk s0)
+        int e = e0 + wv, s0 = 0;
+        DevCell ca{};
+        if (e < e1) ca = a.cells[a.src[e]];
+        // prefetch registers for the current unit
+        float4 pre[NV];
+        auto fetch = [&](const DevCell &c, int base) {
+            const int j = c.first + base + lane;
+            if (base + lane < c.count) {
+                pre[0] = xi4[j];
+                if (S >= 1) pre[1] = m4[2 * j];
+                if (S == 2) pre[2] = m4[2 * j + 1];
+                if (S == 0) pre[0].w = m4[2 * j].x;
+            }
+        };
+        if (e < e1) fetch(ca, 0);
+        while (e < e1) {
+            const int A = a.src[e];
+            const int ns = min(64, ca.count - s0);
+            const double rho = ldexp(1.0, cb.level - ca.level);
+            const float frho = (float)rho;
+            // stage the prefetched sources (offsets rescaled to target-leaf units)
+            wave_sync();
+            if (lane < ns) {
+                float4 q = pre[0];
+                q.x *= frho;
+                q.y *= frho;
+                q.z *= frho;
+                st[wv][0][lane] = q;
+                if (S >= 1) st[wv][1][lane] = pre[1];
+                if (S == 2) st[wv][2][lane] = pre[2];
+            }
+            wave_sync();
+            // advance to the next unit and prefetch it while this one is summed
+            int en = e, sn = s0 + 64;
+            DevCell cn = ca;
+            if (sn >= ca.count) {
+                en = e + kP2PWaves;
+                sn = 0;
+                if (en < e1) cn = a.cells[a.src[en]];
+            }
+            if (en < e1) fetch(cn, sn);
+            if (active) {
+                const float dx = (float)((double)(2 * cb.ix + 1) - (double)(2 * ca.ix + 1) * rho);
+                const float dy = (float)((double)(2 * cb.iy + 1) - (double)(2 * ca.iy + 1) * rho);
+                const float dz = (float)((double)(2 * cb.iz + 1) - (double)(2 * ca.iz + 1) * rho);
+                const float tx = eta.x + dx, ty = eta.y + dy, tz = eta.z + dz;
+                float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+                const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (A == b) {
+                    for (int jj = sl; jj < ns; jj += slices) {
+                        const float4 q = st[wv][0][jj];
+                        const float rx = tx - q.x, ry = ty - q.y, rz = tz - q.z;
+                        const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
+                        const float inv = (s0 + jj == t0 + ti) ? 0.f : __builtin_amdgcn_rsqf(r2);
+                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : st[wv][S >= 1 ? 1 : 0][jj];
+                        const float4 m1 = S == 2 ? st[wv][2][jj] : zero4;
+                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
+                    }
+                } else {
+                    for (int jj = sl; jj < ns; jj += slices) {
+                        const float4 q = st[wv][0][jj];
+                        const float rx = tx - q.x, ry = ty - q.y, rz = tz - q.z;
+                        const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
+                        const float inv = __builtin_amdgcn_rsqf(r2);
+                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : st[wv][S >= 1 ? 1 : 0][jj];
+                        const float4 m1 = S == 2 ? st[wv][2][jj] : zero4;
+                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
+                    }
+                }
+                kahan_add(ps, pc, bp);
+                kahan_add(xs_, xc, bx);
+                kahan_add(ys, yc, by);
+                kahan_add(zs, zc, bz);
+            }
+            e = en;
+            s0 = sn;
+            ca = cn;
+        }
+        __syncthreads();
+        red[wv][0][lane] = (double)ps - (double)pc;
+        red[wv][1][lane] = (double)xs_ - (double)xc;
+        red[wv][2][lane] = (double)ys - (double)yc;
+        red[wv][3][lane] = (double)zs - (double)zc;
+        __syncthreads();
+        if (wv == 0 && sl == 0) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int w = 0; w < kP2PWaves; ++w)
+                for (int k = 0; k < slices; ++k)
+                    for (int q = 0; q < 4; ++q) v[q] += red[w][q][lane + k * cs];
+            double *o = a.near + 4 * (size_t)i;
+            o[0] = v[0] * sphi;
+            o[1] = v[1] * sfld;
+            o[2] = v[2] * sfld;
+            o[3] = v[3] * sfld;
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(64) void p2p_f64_kernel(P2PArgs a)
+{
+    constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
+    __shared__ double sx[64], sy[64], sz[64], sm[64][W];
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x;
+    {
+    // workgroups are dispatched in order: leaves with the most work first
+    const int lk = a.order[blockIdx.x];
+    const int b = a.leaves[lk];
+    const DevCell cb = a.cells[b];
+    const size_t n = a.n;
+    for (int t0 = 0; t0 < cb.count; t0 += 64) {
+        const int cs = min(64, cb.count - t0);
+        const int slices = 64 / cs;
+        const int ti = lane % cs, sl = lane / cs;
+        const bool active = sl < slices;
+        const int i = cb.first + t0 + ti;
+        const double xi = a.xs[i], yi = a.xs[n + i], zi = a.xs[2 * n + i];
+        double ph = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int e = a.ptr[lk]; e < a.ptr[lk + 1]; ++e) {
+            const int A = a.src[e];
+            const DevCell ca = a.cells[A];
+            for (int s0 = 0; s0 < ca.count; s0 += 64) {
+                const int ns = min(64, ca.count - s0);
+                __syncthreads();
+                if (lane < ns) {
+                    const size_t j = ca.first + s0 + lane;
+                    sx[lane] = a.xs[j];
+                    sy[lane] = a.xs[n + j];
+                    sz[lane] = a.xs[2 * n + j];
+                    for (int q = 0; q < W; ++q) sm[lane][q] = a.m64[j * W + q];
+                }
+                __syncthreads();
+                if (!active) continue;
+                for (int jj = sl; jj < ns; jj += slices) {
+                    if (A == b && s0 + jj == t0 + ti) continue;
+                    p2p_pair_f64<S>(xi - sx[jj], yi - sy[jj], zi - sz[jj], sm[jj], ph, ex, ey, ez);
+                }
+            }
+        }
+        __syncthreads();
+        red[0][lane] = ph;
+        red[1][lane] = ex;
+        red[2][lane] = ey;
+        red[3][lane] = ez;
+        __syncthreads();
+        if (sl == 0) {
+            double v[4] = {red[0][lane], red[1][lane], red[2][lane], red[3][lane]};
+            for (int k = 1; k < slices; ++k)
+                for (int q = 0; q < 4; ++q) v[q] += red[q][lane + k * cs];
+            double *o = a.near + 4 * (size_t)i;
+            o[0] = v[0];
+            o[1] = v[1];
+            o[2] = v[2];
+            o[3] = v[3];
+        }
+    }
+    }
+}
+
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
+{
+    P2PArgs a;
+    a.leaves = t->d_leaves;
+    a.ptr = t->d_p2p_ptr;
+    a.src = t->d_p2p_src;
+    a.cells = t->d_cells;
+    a.xi = t->d_xi;
+    a.m32 = t->d_mom32;
+    a.xs = t->d_x;
+    a.m64 = t->d_mom;
+    a.near = t->d_near;
+    a.n = (int)t->ht.n;
+    a.h = t->ht.h;
+    a.order = t->d_p2p_order;
+    const dim3 g((unsigned)t->nleaves), b(64), bw(64 * kP2PWaves);
+    if (t->prec == FMM_PREC_MIXED) {
+        if (t->order == 0) hipLaunchKernelGGL(p2p_f32_kernel<0>, g, bw, 0, s, a);
+        else if (t->order == 1) hipLaunchKernelGGL(p2p_f32_kernel<1>, g, bw, 0, s, a);
+        else hipLaunchKernelGGL(p2p_f32_kernel<2>, g, bw, 0, s, a);
+    } else {
+        if (t->order == 0) hipLaunchKernelGGL(p2p_f64_kernel<0>, g, b, 0, s, a);
+        else if (t->order == 1) hipLaunchKernelGGL(p2p_f64_kernel<1>, g, b, 0, s, a);
+        else hipLaunchKernelGGL(p2p_f64_kernel<2>, g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ L2P
+// phi = (1/r) sum_{|n|<=q} eta^n/n! L~_n, E_d = -(1/r^2) sum eta^n/n! L~_{n+e_d}
+// (Eq. 9, Eq. 10 with |k| = 1), eta = (x - z)/r, plus the near field, written
+// to the caller's particle order.  Unrolled for each q = p - s.
+template <int Q>
+__global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ leaves,
+                                                 const DevCell *__restrict__ cells, Geo g, const double *__restrict__ xs,
+                                                 int n, const double *__restrict__ L, const double *__restrict__ near,
+                                                 const int32_t *__restrict__ perm, double *__restrict__ phi,
+                                                 double *__restrict__ field)
+{
+    constexpr int NL = nterms(Q);
+    __shared__ double ls[NL];
+    const int c = leaves[blockIdx.x];
+    const DevCell cell = cells[c];
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) ls[i] = L[(size_t)c * NL + i];
+    __syncthreads();
+    double z[3];
+    cell_center(cell, g.lo, g.h, z);
+    const double r = cell_radius(cell.level, g.h);
+    const double ir = 1.0 / r;
+    for (int k = threadIdx.x; k < cell.count; k += blockDim.x) {
+        const int i = cell.first + k;
+        const double e[3] = {(xs[i] - z[0]) * ir, (xs[n + i] - z[1]) * ir, (xs[2 * (size_t)n + i] - z[2]) * ir};
+        double px[Q + 1], py[Q + 1], pz[Q + 1];
+        px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+        for (int a = 1; a <= Q; ++a) {
+            px[a] = px[a - 1] * e[0] * (1.0 / a);
+            py[a] = py[a - 1] * e[1] * (1.0 / a);
+            pz[a] = pz[a - 1] * e[2] * (1.0 / a);
+        }
+        double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+        for (int nx = 0; nx <= Q; ++nx)
+#pragma unroll
+            for (int ny = 0; ny <= Q - nx; ++ny) {
+                const double pxy = px[nx] * py[ny];
+#pragma unroll
+                for (int nz = 0; nz <= Q - nx - ny; ++nz) {
+                    const double mono = pxy * pz[nz];
+                    ph = fma(mono, ls[mindex(nx, ny, nz)], ph);
+                    if (nx + ny + nz < Q) {
+                        fx = fma(mono, ls[mindex(nx + 1, ny, nz)], fx);
+                        fy = fma(mono, ls[mindex(nx, ny + 1, nz)], fy);
+                        fz = fma(mono, ls[mindex(nx, ny, nz + 1)], fz);
+                    }
+                }
+            }
+        const double *nr = near + 4 * (size_t)i;
+        const size_t o = (size_t)perm[i];
+        if (outputs & FMM_POT) phi[o] = ph * ir + nr[0];
+        if (outputs & FMM_FIELD) {
+            const double ir2 = ir * ir;
+            field[3 * o] = -fx * ir2 + nr[1];
+            field[3 * o + 1] = -fy * ir2 + nr[2];
+            field[3 * o + 2] = -fz * ir2 + nr[3];
+        }
+    }
+}
+
+template <int Q>
+static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
+{
+    Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
+    hipLaunchKernelGGL(l2p_kernel<Q>, dim3((unsigned)t->nleaves), dim3(64), 0, s, outputs, t->d_leaves, t->d_cells, g,
+                       t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm, phi, field);
+}
+
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
+{
+    switch (t->p - t->order) {
+    case 1: l2p_launch<1>(t, outputs, phi, field, s); break;
+    case 2: l2p_launch<2>(t, outputs, phi, field, s); break;
+    case 3: l2p_launch<3>(t, outputs, phi, field, s); break;
+    case 4: l2p_launch<4>(t, outputs, phi, field, s); break;
+    case 5: l2p_launch<5>(t, outputs, phi, field, s); break;
+    case 6: l2p_launch<6>(t, outputs, phi, field, s); break;
+    case 7: l2p_launch<7>(t, outputs, phi, field, s); break;
+    case 8: l2p_launch<8>(t, outputs, phi, field, s); break;
+    case 9: l2p_launch<9>(t, outputs, phi, field, s); break;
+    case 10: l2p_launch<10>(t, outputs, phi, field, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bh(fmm_tree *, int, double *, double *, hipStream_t) { return hipErrorNotSupported; }

@@ -1,0 +1,229 @@
+"""Thin Python binding of libfmm.so (see include/fmm.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory (contiguous float64 tensors on
+the context's device) and streams.  Importing this module loads the library
+and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# FMM_LIBRARY may point at another build of the same library (e.g. a variant
+# with different code-shape options); the default is the in-tree build.
+LIB_PATH = os.environ.get("FMM_LIBRARY") or os.path.join(_HERE, "libfmm.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE, FMM_EBUSY, FMM_ETIMEOUT = range(7)
+FMM_POT, FMM_FIELD = 1, 2
+FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
+FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
+FMM_P_MAX = 10
+FMM_REQ_QUEUED, FMM_REQ_RUNNING, FMM_REQ_DONE, FMM_REQ_FAILED = range(4)
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+
+
+class fmm_request(ctypes.Structure):
+    _fields_ = [("pos", _vp), ("moments", _vp), ("phi", _vp), ("field", _vp), ("n", _i64),
+                ("order", ctypes.c_int), ("p", ctypes.c_int), ("ncrit", ctypes.c_int), ("method", ctypes.c_int),
+                ("precision", ctypes.c_int), ("outputs", ctypes.c_int), ("theta", ctypes.c_double)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+fmm_ctx_create = _sig("fmm_ctx_create", [ctypes.c_int, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)])
+fmm_ctx_destroy = _sig("fmm_ctx_destroy", [_vp])
+fmm_build_tree = _sig("fmm_build_tree", [_vp, _vp, _i64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                         ctypes.POINTER(_vp)])
+fmm_upward = _sig("fmm_upward", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int])
+fmm_evaluate = _sig("fmm_evaluate", [_vp, _vp, ctypes.c_int, _vp, _vp])
+fmm_tree_info = _sig("fmm_tree_info", [_vp, _vp])
+fmm_tree_export = _sig("fmm_tree_export", [_vp] + [_vp] * 14)
+fmm_tree_destroy = _sig("fmm_tree_destroy", [_vp])
+fmm_last_error = _sig("fmm_last_error", [], ctypes.c_char_p)
+fmm_ctx_set_overlap = _sig("fmm_ctx_set_overlap", [_vp, ctypes.c_int])
+fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
+fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
+fmm_profile_read = _sig("fmm_profile_read", [_vp, _vp, _vp, _vp, ctypes.c_int])
+fmm_work_counts = _sig("fmm_work_counts", [_vp, _vp])
+fmm_serve_start = _sig("fmm_serve_start", [_vp, ctypes.c_int])
+fmm_submit = _sig("fmm_submit", [_vp, ctypes.POINTER(fmm_request), ctypes.POINTER(ctypes.c_uint64)])
+fmm_poll = _sig("fmm_poll", [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)])
+fmm_wait = _sig("fmm_wait", [_vp, ctypes.c_uint64, ctypes.c_double])
+fmm_request_times = _sig("fmm_request_times", [_vp, ctypes.c_uint64, _vp, _vp])
+fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
+
+EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_tree_info",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
+            "fmm_request_times", "fmm_serve_stop"]
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what} failed with code {code}: {fmm_last_error().decode(errors='replace')}")
+        self.code = code
+
+
+def _check(rc, what):
+    if rc != FMM_OK:
+        raise FMMError(rc, what)
+
+
+def _dev_f64(t: torch.Tensor, cols: Optional[int], name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous float64")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols) and not (cols == 1 and t.dim() == 1):
+        raise ValueError(f"{name} must have shape (n, {cols})")
+    return t
+
+
+class Context:
+    """A libfmm context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0):
+        self.device = device
+        self.stream = stream
+        h = _vp()
+        s = stream.cuda_stream if stream is not None else None
+        _check(fmm_ctx_create(device, s, budget_bytes, ctypes.byref(h)), "fmm_ctx_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            fmm_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_overlap(self, on: bool = True):
+        _check(fmm_ctx_set_overlap(self.h, int(on)), "fmm_ctx_set_overlap")
+
+    # profiling -------------------------------------------------------
+    def profile(self, on: bool = True):
+        _check(fmm_profile_enable(self.h, int(on)), "fmm_profile_enable")
+
+    def profile_reset(self):
+        _check(fmm_profile_reset(self.h), "fmm_profile_reset")
+
+    def profile_read(self) -> dict:
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int64 * cap)()
+        k = fmm_profile_read(self.h, ctypes.cast(names, _vp), ctypes.cast(ms, _vp), ctypes.cast(cnt, _vp), cap)
+        if k < 0:
+            raise FMMError(k, "fmm_profile_read")
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(k, cap))}
+
+
+class Tree:
+    """Octree + interaction lists resident on the device (fmm_build_tree)."""
+
+    def __init__(self, ctx: Context, pos: torch.Tensor, ncrit: int, theta: float, method: int = FMM_METHOD_FMM):
+        _dev_f64(pos, 3, "pos")
+        self.ctx = ctx
+        self.n = int(pos.shape[0])
+        self.method = method
+        h = _vp()
+        _check(fmm_build_tree(ctx.h, pos.data_ptr(), self.n, int(ncrit), float(theta), int(method), ctypes.byref(h)),
+               "fmm_build_tree")
+        self.h = h
+        self._moments = None
+
+    def close(self):
+        if self.h:
+            fmm_tree_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        a = (ctypes.c_int64 * 10)()
+        _check(fmm_tree_info(self.h, ctypes.cast(a, _vp)), "fmm_tree_info")
+        keys = ["n", "ncells", "nlevels", "nleaves", "n_m2l", "n_p2p", "n_classes", "n_tiles", "m2l_slots", "bytes"]
+        return dict(zip(keys, [int(v) for v in a]))
+
+    def upward(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED):
+        _dev_f64(moments, None, "moments")
+        self._moments = moments       # the near field reads it during evaluate
+        _check(fmm_upward(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision)), "fmm_upward")
+
+    def evaluate(self, outputs: int = FMM_POT | FMM_FIELD, phi: Optional[torch.Tensor] = None,
+                 field: Optional[torch.Tensor] = None):
+        dev = torch.device("cuda", self.ctx.device)
+        if (outputs & FMM_POT) and phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if (outputs & FMM_FIELD) and field is None:
+            field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        _check(fmm_evaluate(self.ctx.h, self.h, int(outputs), phi.data_ptr() if phi is not None else None,
+                            field.data_ptr() if field is not None else None), "fmm_evaluate")
+        return phi, field
+
+    def work_counts(self):
+        a = (ctypes.c_double * 8)()
+        _check(fmm_work_counts(self.h, ctypes.cast(a, _vp)), "fmm_work_counts")
+        keys = ["m2l_pairs", "m2l_flops", "p2p_pairs", "p2p_flops", "m2p_pairs", "m2p_flops", "m2l_bytes",
+                "p2p_bytes"]
+        return dict(zip(keys, list(a)))
+
+    def export(self):
+        import numpy as np
+        inf = self.info()
+        n, nc = inf["n"], inf["ncells"]
+        d = dict(geom=np.zeros(4), key=np.zeros(n, np.uint64), perm=np.zeros(n, np.int64),
+                 level=np.zeros(nc, np.int32), ix=np.zeros((nc, 3), np.int32), first=np.zeros(nc, np.int64),
+                 count=np.zeros(nc, np.int64), parent=np.zeros(nc, np.int64), child0=np.zeros(nc, np.int64),
+                 nchild=np.zeros(nc, np.int32), m2l_ptr=np.zeros(nc + 1, np.int64),
+                 m2l_src=np.zeros(max(1, inf["n_m2l"]), np.int64), p2p_ptr=np.zeros(nc + 1, np.int64),
+                 p2p_src=np.zeros(max(1, inf["n_p2p"]), np.int64))
+        order = ["geom", "key", "perm", "level", "ix", "first", "count", "parent", "child0", "nchild", "m2l_ptr",
+                 "m2l_src", "p2p_ptr", "p2p_src"]
+        _check(fmm_tree_export(self.h, *[d[k].ctypes.data for k in order]), "fmm_tree_export")
+        d["m2l_src"] = d["m2l_src"][: inf["n_m2l"]]
+        d["p2p_src"] = d["p2p_src"][: inf["n_p2p"]]
+        return d
+
+
+def evaluate(pos: torch.Tensor, order: int, moments: torch.Tensor, p: int, theta: float, ncrit: int,
+             outputs: int = FMM_POT | FMM_FIELD, precision: int = FMM_PREC_MIXED, method: int = FMM_METHOD_FMM,
+             ctx: Optional[Context] = None):
+    """One-shot convenience: build, upward, evaluate; returns (phi, field)."""
+    own = ctx is None
+    ctx = ctx or Context(pos.device.index or 0)
+    try:
+        t = Tree(ctx, pos, ncrit, theta, method)
+        t.upward(order, moments, p, precision)
+        out = t.evaluate(outputs)
+        torch.cuda.synchronize(pos.device)
+        t.close()
+        return out
+    finally:
+        if own:
+            ctx.close()

@@ -1,0 +1,131 @@
+"""GPU parity: the C-ABI library on cuda:0 against the CPU oracle on the same
+seeded inputs.  Trees, permutations and interaction lists must be bit-exact;
+the FP64 GPU FMM must match the oracle FMM (same lists, same truncation) to
+rounding; the mixed-precision path to the stated FP32 tolerance."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2005_12351_amd import fmm  # noqa: E402  (fails loudly if libfmm.so is missing)
+from paper_2005_12351_amd import workloads as W  # noqa: E402
+from tests.gpu_helpers import gpu_fmm, rel_l2  # noqa: E402
+
+# FP64 path vs oracle: same tree, lists and truncation; differences come only
+# from the summation order and the normalised (dyadic) form of the operators.
+TOL_FP64 = 1e-10
+# Mixed path vs oracle: FP32 M2L/P2P (unit roundoff 6e-8) summed over a few
+# hundred list entries per target; see the tolerance derivation in the design
+# notes.  Stated per precision and checked here.
+TOL_MIXED = 2e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fmm.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES_TREE = [("uniform", 3000, 32, 0.5), ("plummer", 5000, 16, 0.6), ("lattice", 4096, 64, 0.5),
+              ("uniform", 777, 1, 0.4), ("uniform", 1, 8, 0.5), ("uniform", 2, 1, 0.5)]
+
+
+@pytest.mark.parametrize("kind,n,ncrit,theta", CASES_TREE)
+def test_tree_bit_exact(orc, ctx, kind, n, ncrit, theta):
+    _say(f"[tree] {kind} n={n} ncrit={ncrit} theta={theta}")
+    w = W.small_random(500 + n, n, 0, kind)
+    gt = fmm.Tree(ctx, torch.from_numpy(w.pos).cuda(), ncrit, theta)
+    g = gt.export()
+    o = orc.Tree(w.pos, ncrit, theta).dump()
+    assert np.array_equal(g["geom"][:3], o.lo) and g["geom"][3] == o.W
+    for k in ("key", "perm", "level", "ix", "first", "count", "parent", "child0", "nchild", "m2l_ptr", "m2l_src",
+              "p2p_ptr", "p2p_src"):
+        a = g[k]
+        b = getattr(o, k)
+        assert a.shape == b.shape, k
+        assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
+
+
+PARITY = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2, 10, "lattice", 3375, 64, 0.5),
+          (1, 6, "plummer", 4000, 32, 0.6), (0, 1, "uniform", 1500, 16, 0.5), (2, 3, "plummer", 2500, 8, 0.4),
+          (1, 2, "uniform", 700, 4, 0.3), (0, 10, "plummer", 1200, 8, 0.5)]
+
+
+@pytest.mark.parametrize("order,p,kind,n,ncrit,theta", PARITY)
+def test_fmm_fp64_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
+    _say(f"[fp64] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
+    w = W.small_random(900 + n + order, n, order, kind)
+    ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=fmm.FMM_PREC_FP64)
+    t = orc.Tree(w.pos, ncrit, theta)
+    po, Eo = t.fmm(order, w.moments, p)
+    assert rel_l2(ph, po) < TOL_FP64, rel_l2(ph, po)
+    assert rel_l2(E, Eo) < TOL_FP64, rel_l2(E, Eo)
+
+
+@pytest.mark.parametrize("order,p,kind,n,ncrit,theta", PARITY)
+def test_fmm_mixed_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
+    _say(f"[mixed] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
+    w = W.small_random(900 + n + order, n, order, kind)
+    ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=fmm.FMM_PREC_MIXED)
+    t = orc.Tree(w.pos, ncrit, theta)
+    po, Eo = t.fmm(order, w.moments, p)
+    e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)
+    _say(f"   mixed rel L2 vs oracle FMM: phi {e1:.3e}  E {e2:.3e}")
+    assert e1 < TOL_MIXED and e2 < TOL_MIXED
+
+
+@pytest.mark.parametrize("n,ncrit", [(1, 8), (2, 1), (3, 1), (60, 64), (65, 64), (200, 1)])
+def test_edge_sizes(orc, ctx, n, ncrit):
+    _say(f"[edge] n={n} ncrit={ncrit}")
+    for order in (0, 1, 2):
+        w = W.small_random(31 * n + order, n, order)
+        for prec, tol in ((fmm.FMM_PREC_FP64, TOL_FP64), (fmm.FMM_PREC_MIXED, TOL_MIXED)):
+            ph, E, _ = gpu_fmm(fmm, ctx, w, p=order + 3, theta=0.5, ncrit=ncrit, precision=prec)
+            po, Eo = orc.Tree(w.pos, ncrit, 0.5).fmm(order, w.moments, order + 3)
+            if n == 1:
+                assert ph[0] == 0.0 and np.all(E == 0.0)
+            else:
+                assert rel_l2(ph, po) < tol and rel_l2(E, Eo) < tol
+
+
+def test_outputs_mask_and_determinism(orc, ctx):
+    w = W.small_random(4242, 5000, 1, "plummer")
+    for prec in (fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED):
+        runs, t = gpu_fmm(fmm, ctx, w, p=6, theta=0.5, ncrit=32, precision=prec, reps=2)
+        assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+        ph, E = runs[0]
+        p2, _, _ = gpu_fmm(fmm, ctx, w, p=6, theta=0.5, ncrit=32, precision=prec, outputs=fmm.FMM_POT)
+        _, E2, _ = gpu_fmm(fmm, ctx, w, p=6, theta=0.5, ncrit=32, precision=prec, outputs=fmm.FMM_FIELD)
+        assert np.array_equal(p2, ph) and np.array_equal(E2, E)
+
+
+def test_error_codes(ctx):
+    pos = torch.rand(100, 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Tree(ctx, pos, 0, 0.5)
+    assert e.value.code == fmm.FMM_EINVAL
+    with pytest.raises(fmm.FMMError):
+        fmm.Tree(ctx, pos, 8, 1.5)
+    t = fmm.Tree(ctx, pos, 8, 0.5)
+    with pytest.raises(fmm.FMMError) as e:
+        t.evaluate()
+    assert e.value.code == fmm.FMM_ESTATE
+    q = torch.rand(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(fmm.FMMError):
+        t.upward(0, q, 0)            # p < order + 1
+    with pytest.raises(fmm.FMMError):
+        t.upward(3, q, 4)            # bad order
+    with pytest.raises(fmm.FMMError):
+        t.upward(0, q, fmm.FMM_P_MAX + 1)

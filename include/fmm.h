@@ -126,6 +126,13 @@ const char *fmm_last_error(void);
  * per-kernel timings below measure each kernel alone. */
 int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
 
+/* Replay HIP graphs (default on): the kernel sequence of fmm_upward and of
+ * fmm_evaluate is captured the first time a tree sees a given argument set
+ * (moments / output pointers, order, p, precision) and replayed afterwards,
+ * which removes the per-kernel launch cost.  Graphs are never used while
+ * profiling is enabled.  Off: kernels are launched one by one. */
+int fmm_ctx_set_graphs(fmm_ctx *ctx, int on);
+
 /* Per-kernel device timing.  When enabled, every kernel launch is bracketed
  * by HIP events on the stream it runs on.  fmm_profile_read synchronises and
  * writes, for up to `cap` kernel kinds, the kind name (static string), the

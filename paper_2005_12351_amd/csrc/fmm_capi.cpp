@@ -66,10 +66,55 @@ ProfScope::~ProfScope()
     ctx->prof.push_back(ProfEntry{name, b, e});
 }
 
+static void drop_graphs(fmm_tree *t)
+{
+    for (auto &g : t->graphs) (void)hipGraphExecDestroy(g.exec);
+    t->graphs.clear();
+}
+
 extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
     ctx->overlap = on != 0;
+    for (fmm_tree *t : ctx->trees) drop_graphs(t);
+    return FMM_OK;
+}
+
+extern "C" int fmm_ctx_set_graphs(fmm_ctx *ctx, int on)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    ctx->graphs = on != 0;
+    return FMM_OK;
+}
+
+// Runs `body` (which queues kernels on stream s) either directly or through a
+// cached HIP graph of the same launch sequence.  Graphs are not used while
+// profiling, because the per-kernel events must bracket real launches.
+template <typename F>
+static int run_cached(fmm_ctx *ctx, fmm_tree *t, const int64_t *key, hipStream_t s, F &&body)
+{
+    if (!ctx->graphs || ctx->profile) return body();
+    for (auto &g : t->graphs)
+        if (memcmp(g.key, key, sizeof(g.key)) == 0) {
+            HIPCHK(hipGraphLaunch(g.exec, s));
+            return FMM_OK;
+        }
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = body();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != FMM_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) FAIL(FMM_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    fmm_tree::GraphEntry ge;
+    memcpy(ge.key, key, sizeof(ge.key));
+    e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) FAIL(FMM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    t->graphs.push_back(ge);
+    HIPCHK(hipGraphLaunch(ge.exec, s));
     return FMM_OK;
 }
 
@@ -145,7 +190,8 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
     }
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
         delete c;
         FAIL(FMM_EDEVICE, "stream/event creation failed");
     }
@@ -158,6 +204,7 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
 
 static void tree_release_device(fmm_tree *t)
 {
+    drop_graphs(t);
     for (void *p : t->allocs) hipFree(p);
     t->allocs.clear();
     t->dev_bytes = 0;
@@ -183,6 +230,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     hipEventDestroy(c->ev_up);
     hipEventDestroy(c->ev_near);
+    hipEventDestroy(c->ev_fork);
     hipStreamDestroy(c->aux);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -367,6 +415,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
 {
     if (t->d_M64 && t->order == order && t->p == p && t->prec == prec) return FMM_OK;
+    drop_graphs(t);
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32,
                       (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_D64,
                       (void **)&t->d_D32, (void **)&t->d_sc64, (void **)&t->d_sc32, (void **)&t->d_work,
@@ -418,6 +467,12 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
     t->order = order;
     t->p = p;
     t->prec = prec;
+    if (t->method == FMM_METHOD_FMM) {
+        // derivative tensors of the translation classes depend on p only
+        e = launch_dtable(t, t->ctx->stream);
+        if (e != hipSuccess) FAIL(FMM_EDEVICE, "dtable failed: %s", hipGetErrorString(e));
+        t->dtab_p = p;
+    }
     return FMM_OK;
 }
 
@@ -441,29 +496,29 @@ extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *mo
     if (rc) return rc;
     hipStream_t s = ctx->stream;
     t->mom_user = moments;
-    {
-        ProfScope ps(ctx, s, "prep_moments");
-        KCHK(launch_prep_moments(t, s));
-    }
-    {
-        ProfScope ps(ctx, s, "p2m");
-        KCHK(launch_p2m(t, s));
-    }
-    const int nlev = (int)t->ht.level_ptr.size() - 1;
-    for (int l = nlev - 2; l >= 0; --l) {
-        ProfScope ps(ctx, s, "m2m");
-        KCHK(launch_m2m_level(t, l, s));
-    }
-    if (precision == FMM_PREC_MIXED) {
-        ProfScope ps(ctx, s, "m2_fp32");
-        KCHK(launch_to_fp32(t, s));
-    }
-    if (t->method == FMM_METHOD_FMM && t->dtab_p != p) {
-        ProfScope ps(ctx, s, "dtable");
-        KCHK(launch_dtable(t, s));
-        t->dtab_p = p;
-    }
-    KCHK(hipEventRecord(ctx->ev_up, s));
+    auto body = [&]() -> int {
+        {
+            ProfScope ps(ctx, s, "prep_moments");
+            KCHK(launch_prep_moments(t, s));
+        }
+        {
+            ProfScope ps(ctx, s, "p2m");
+            KCHK(launch_p2m(t, s));
+        }
+        const int nlev = (int)t->ht.level_ptr.size() - 1;
+        for (int l = nlev - 2; l >= 0; --l) {
+            ProfScope ps(ctx, s, "m2m");
+            KCHK(launch_m2m_level(t, l, s));
+        }
+        if (precision == FMM_PREC_MIXED) {
+            ProfScope ps(ctx, s, "m2_fp32");
+            KCHK(launch_to_fp32(t, s));
+        }
+        return FMM_OK;
+    };
+    const int64_t key[6] = {1, order, p, precision, (int64_t)(uintptr_t)moments, 0};
+    rc = run_cached(ctx, t, key, s, body);
+    if (rc) return rc;
     t->have_up = 1;
     return FMM_OK;
 }
@@ -487,34 +542,43 @@ extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi,
         KCHK(launch_bh(t, outputs, phi, field, s));
         return FMM_OK;
     }
-    // near field on the auxiliary stream, overlapping the far field
-    KCHK(hipStreamWaitEvent(a, ctx->ev_up, 0));
-    {
-        ProfScope ps(ctx, a, "p2p");
-        KCHK(launch_p2p(t, a));
-    }
-    KCHK(hipEventRecord(ctx->ev_near, a));
     const int64_t nc = t->ht.ncells();
     const int nl = nterms(p - s_);
-    KCHK(launch_fill(t->d_L64, (size_t)nc * nl, s));
-    {
-        ProfScope ps(ctx, s, "m2l");
-        KCHK(launch_m2l(t, s));
-    }
-    {
-        ProfScope ps(ctx, s, "m2l_combine");
-        KCHK(launch_m2l_combine(t, s));
-    }
-    const int nlev = (int)t->ht.level_ptr.size() - 1;
-    for (int l = 1; l < nlev; ++l) {
-        ProfScope ps(ctx, s, "l2l");
-        KCHK(launch_l2l_level(t, l, s));
-    }
-    KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
-    {
-        ProfScope ps(ctx, s, "l2p");
-        KCHK(launch_l2p_final(t, outputs, phi, field, s));
-    }
+    auto body = [&]() -> int {
+        // near field on the auxiliary stream, overlapping the far field
+        if (a != s) {
+            KCHK(hipEventRecord(ctx->ev_fork, s));
+            KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
+        }
+        {
+            ProfScope ps(ctx, a, "p2p");
+            KCHK(launch_p2p(t, a));
+        }
+        if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
+        KCHK(launch_fill(t->d_L64, (size_t)nc * nl, s));
+        {
+            ProfScope ps(ctx, s, "m2l");
+            KCHK(launch_m2l(t, s));
+        }
+        {
+            ProfScope ps(ctx, s, "m2l_combine");
+            KCHK(launch_m2l_combine(t, s));
+        }
+        const int nlev = (int)t->ht.level_ptr.size() - 1;
+        for (int l = 1; l < nlev; ++l) {
+            ProfScope ps(ctx, s, "l2l");
+            KCHK(launch_l2l_level(t, l, s));
+        }
+        if (a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+        {
+            ProfScope ps(ctx, s, "l2p");
+            KCHK(launch_l2p_final(t, outputs, phi, field, s));
+        }
+        return FMM_OK;
+    };
+    const int64_t key[6] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, ctx->overlap, 0};
+    int rc = run_cached(ctx, t, key, s, body);
+    if (rc) return rc;
     // algorithmic work of this evaluation
     const double fc = [&] {
         double f = 0;

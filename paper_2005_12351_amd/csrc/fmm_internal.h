@@ -114,6 +114,8 @@ struct fmm_ctx {
     size_t budget = 0;
     bool profile = false;
     bool overlap = true;                  // P2P on the auxiliary stream
+    bool graphs = true;                   // replay captured HIP graphs
+    hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;
     hipEvent_t ev_up = nullptr, ev_near = nullptr;
@@ -159,6 +161,12 @@ struct fmm_tree {
     float *d_D32 = nullptr, *d_sc32 = nullptr;
     size_t dev_bytes = 0;
     std::vector<void *> allocs;
+    // captured launch sequences, keyed by the arguments they bake in
+    struct GraphEntry {
+        int64_t key[6];
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
     double work[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 

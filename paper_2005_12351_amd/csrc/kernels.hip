@@ -692,50 +692,56 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
         float ps = 0.f, pc = 0.f, xs_ = 0.f, xc = 0.f, ys = 0.f, yc = 0.f, zs = 0.f, zc = 0.f;
         // units of work of this wave: (source leaf e, 64-particle chunk s0)
         int e = e0 + wv, s0 = 0;
-        DevCell ca{};
-        if (e < e1) ca = a.cells[a.src[e]];
-        // prefetch registers for the current unit
-        float4 pre[NV];
-        auto fetch = [&](const DevCell &c, int base) {
-            const int j = c.first + base + lane;
-            if (base + lane < c.count) {
-                pre[0] = xi4[j];
-                if (S >= 1) pre[1] = m4[2 * j];
-                if (S == 2) pre[2] = m4[2 * j + 1];
-                if (S == 0) pre[0].w = m4[2 * j].x;
-            }
+        // source leaf fields: first, count, level, ix, iy, iz
+        int cf = 0, cc = 0, cl = 0, cx = 0, cy = 0, cz = 0;
+        auto load_cell = [&](int ee, int &f, int &n_, int &l, int &x, int &y, int &z) {
+            const DevCell c = a.cells[a.src[ee]];
+            f = c.first; n_ = c.count; l = c.level; x = c.ix; y = c.iy; z = c.iz;
         };
-        if (e < e1) fetch(ca, 0);
+        if (e < e1) load_cell(e, cf, cc, cl, cx, cy, cz);
+        // prefetch registers for the current unit
+        float4 pre0 = make_float4(0.f, 0.f, 0.f, 0.f), pre1 = pre0, pre2 = pre0;
+#define P2P_FETCH(first_, count_, base)                      \
+    do {                                                     \
+        const int j_ = (first_) + (base) + lane;             \
+        if ((base) + lane < (count_)) {                      \
+            pre0 = xi4[j_];                                  \
+            if (S >= 1) pre1 = m4[2 * j_];                   \
+            if (S == 2) pre2 = m4[2 * j_ + 1];               \
+            if (S == 0) pre0.w = m4[2 * j_].x;               \
+        }                                                    \
+    } while (0)
+        if (e < e1) P2P_FETCH(cf, cc, 0);
         while (e < e1) {
             const int A = a.src[e];
-            const int ns = min(64, ca.count - s0);
-            const double rho = ldexp(1.0, cb.level - ca.level);
+            const int ns = min(64, cc - s0);
+            const double rho = ldexp(1.0, cb.level - cl);
             const float frho = (float)rho;
             // stage the prefetched sources (offsets rescaled to target-leaf units)
             wave_sync();
             if (lane < ns) {
-                float4 q = pre[0];
+                float4 q = pre0;
                 q.x *= frho;
                 q.y *= frho;
                 q.z *= frho;
                 st[wv][0][lane] = q;
-                if (S >= 1) st[wv][1][lane] = pre[1];
-                if (S == 2) st[wv][2][lane] = pre[2];
+                if (S >= 1) st[wv][1][lane] = pre1;
+                if (S == 2) st[wv][2][lane] = pre2;
             }
             wave_sync();
+            const float dx = (float)((double)(2 * cb.ix + 1) - (double)(2 * cx + 1) * rho);
+            const float dy = (float)((double)(2 * cb.iy + 1) - (double)(2 * cy + 1) * rho);
+            const float dz = (float)((double)(2 * cb.iz + 1) - (double)(2 * cz + 1) * rho);
+            const int s_cur = s0;
             // advance to the next unit and prefetch it while this one is summed
             int en = e, sn = s0 + 64;
-            DevCell cn = ca;
-            if (sn >= ca.count) {
+            if (sn >= cc) {
                 en = e + kP2PWaves;
                 sn = 0;
-                if (en < e1) cn = a.cells[a.src[en]];
+                if (en < e1) load_cell(en, cf, cc, cl, cx, cy, cz);
             }
-            if (en < e1) fetch(cn, sn);
+            if (en < e1) P2P_FETCH(cf, cc, sn);
             if (active) {
-                const float dx = (float)((double)(2 * cb.ix + 1) - (double)(2 * ca.ix + 1) * rho);
-                const float dy = (float)((double)(2 * cb.iy + 1) - (double)(2 * ca.iy + 1) * rho);
-                const float dz = (float)((double)(2 * cb.iz + 1) - (double)(2 * ca.iz + 1) * rho);
                 const float tx = eta.x + dx, ty = eta.y + dy, tz = eta.z + dz;
                 float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
                 const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -744,7 +750,7 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
                         const float4 q = st[wv][0][jj];
                         const float rx = tx - q.x, ry = ty - q.y, rz = tz - q.z;
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
-                        const float inv = (s0 + jj == t0 + ti) ? 0.f : __builtin_amdgcn_rsqf(r2);
+                        const float inv = (s_cur + jj == t0 + ti) ? 0.f : __builtin_amdgcn_rsqf(r2);
                         const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : st[wv][S >= 1 ? 1 : 0][jj];
                         const float4 m1 = S == 2 ? st[wv][2][jj] : zero4;
                         p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
@@ -767,8 +773,8 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
             }
             e = en;
             s0 = sn;
-            ca = cn;
         }
+#undef P2P_FETCH
         __syncthreads();
         red[wv][0][lane] = (double)ps - (double)pc;
         red[wv][1][lane] = (double)xs_ - (double)xc;
@@ -776,15 +782,19 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
         red[wv][3][lane] = (double)zs - (double)zc;
         __syncthreads();
         if (wv == 0 && sl == 0) {
-            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
             for (int w = 0; w < kP2PWaves; ++w)
-                for (int k = 0; k < slices; ++k)
-                    for (int q = 0; q < 4; ++q) v[q] += red[w][q][lane + k * cs];
+                for (int k = 0; k < slices; ++k) {
+                    v0 += red[w][0][lane + k * cs];
+                    v1 += red[w][1][lane + k * cs];
+                    v2 += red[w][2][lane + k * cs];
+                    v3 += red[w][3][lane + k * cs];
+                }
             double *o = a.near + 4 * (size_t)i;
-            o[0] = v[0] * sphi;
-            o[1] = v[1] * sfld;
-            o[2] = v[2] * sfld;
-            o[3] = v[3] * sfld;
+            o[0] = v0 * sphi;
+            o[1] = v1 * sfld;
+            o[2] = v2 * sfld;
+            o[3] = v3 * sfld;
         }
     }
 }
@@ -882,7 +892,9 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
 // ------------------------------------------------------------------ L2P
 // phi = (1/r) sum_{|n|<=q} eta^n/n! L~_n, E_d = -(1/r^2) sum eta^n/n! L~_{n+e_d}
 // (Eq. 9, Eq. 10 with |k| = 1), eta = (x - z)/r, plus the near field, written
-// to the caller's particle order.  Unrolled for each q = p - s.
+// to the caller's particle order.  Compiled per q = p - s: the z powers live
+// in registers and the innermost loop is unrolled; the outer loops run with
+// uniform counters, so the L~ reads are LDS broadcasts.
 template <int Q>
 __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ leaves,
                                                  const DevCell *__restrict__ cells, Geo g, const double *__restrict__ xs,
@@ -902,32 +914,36 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
     const double ir = 1.0 / r;
     for (int k = threadIdx.x; k < cell.count; k += blockDim.x) {
         const int i = cell.first + k;
-        const double e[3] = {(xs[i] - z[0]) * ir, (xs[n + i] - z[1]) * ir, (xs[2 * (size_t)n + i] - z[2]) * ir};
-        double px[Q + 1], py[Q + 1], pz[Q + 1];
-        px[0] = py[0] = pz[0] = 1.0;
+        const double ex = (xs[i] - z[0]) * ir, ey = (xs[n + i] - z[1]) * ir, ez = (xs[2 * (size_t)n + i] - z[2]) * ir;
+        double pz[Q + 1];
+        pz[0] = 1.0;
 #pragma unroll
-        for (int a = 1; a <= Q; ++a) {
-            px[a] = px[a - 1] * e[0] * (1.0 / a);
-            py[a] = py[a - 1] * e[1] * (1.0 / a);
-            pz[a] = pz[a - 1] * e[2] * (1.0 / a);
-        }
+        for (int a = 1; a <= Q; ++a) pz[a] = pz[a - 1] * ez * (1.0 / a);
         double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-#pragma unroll
-        for (int nx = 0; nx <= Q; ++nx)
-#pragma unroll
+        double px = 1.0;
+#pragma unroll 1
+        for (int nx = 0; nx <= Q; ++nx) {
+            if (nx) px *= ex * k_inv.v[nx];
+            double py = 1.0;
+#pragma unroll 1
             for (int ny = 0; ny <= Q - nx; ++ny) {
-                const double pxy = px[nx] * py[ny];
+                if (ny) py *= ey * k_inv.v[ny];
+                const double pxy = px * py;
+                const int lim = Q - nx - ny;
 #pragma unroll
-                for (int nz = 0; nz <= Q - nx - ny; ++nz) {
-                    const double mono = pxy * pz[nz];
-                    ph = fma(mono, ls[mindex(nx, ny, nz)], ph);
-                    if (nx + ny + nz < Q) {
-                        fx = fma(mono, ls[mindex(nx + 1, ny, nz)], fx);
-                        fy = fma(mono, ls[mindex(nx, ny + 1, nz)], fy);
-                        fz = fma(mono, ls[mindex(nx, ny, nz + 1)], fz);
+                for (int nz = 0; nz <= Q; ++nz) {
+                    if (nz <= lim) {
+                        const double mono = pxy * pz[nz];
+                        ph = fma(mono, ls[mindex(nx, ny, nz)], ph);
+                        if (nz < lim) {
+                            fx = fma(mono, ls[mindex(nx + 1, ny, nz)], fx);
+                            fy = fma(mono, ls[mindex(nx, ny + 1, nz)], fy);
+                            fz = fma(mono, ls[mindex(nx, ny, nz + 1)], fz);
+                        }
                     }
                 }
             }
+        }
         const double *nr = near + 4 * (size_t)i;
         const size_t o = (size_t)perm[i];
         if (outputs & FMM_POT) phi[o] = ph * ir + nr[0];
@@ -951,6 +967,7 @@ static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, hip
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
 {
     switch (t->p - t->order) {
+    case 0: l2p_launch<0>(t, outputs, phi, field, s); break;
     case 1: l2p_launch<1>(t, outputs, phi, field, s); break;
     case 2: l2p_launch<2>(t, outputs, phi, field, s); break;
     case 3: l2p_launch<3>(t, outputs, phi, field, s); break;

@@ -58,6 +58,7 @@ fmm_tree_export = _sig("fmm_tree_export", [_vp] + [_vp] * 14)
 fmm_tree_destroy = _sig("fmm_tree_destroy", [_vp])
 fmm_last_error = _sig("fmm_last_error", [], ctypes.c_char_p)
 fmm_ctx_set_overlap = _sig("fmm_ctx_set_overlap", [_vp, ctypes.c_int])
+fmm_ctx_set_graphs = _sig("fmm_ctx_set_graphs", [_vp, ctypes.c_int])
 fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
 fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
 fmm_profile_read = _sig("fmm_profile_read", [_vp, _vp, _vp, _vp, ctypes.c_int])
@@ -70,7 +71,7 @@ fmm_request_times = _sig("fmm_request_times", [_vp, ctypes.c_uint64, _vp, _vp])
 fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_tree_info",
-            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_serve_stop"]
 
@@ -120,6 +121,9 @@ class Context:
 
     def set_overlap(self, on: bool = True):
         _check(fmm_ctx_set_overlap(self.h, int(on)), "fmm_ctx_set_overlap")
+
+    def set_graphs(self, on: bool = True):
+        _check(fmm_ctx_set_graphs(self.h, int(on)), "fmm_ctx_set_graphs")
 
     # profiling -------------------------------------------------------
     def profile(self, on: bool = True):

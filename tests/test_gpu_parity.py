@@ -111,6 +111,41 @@ def test_outputs_mask_and_determinism(orc, ctx):
         assert np.array_equal(p2, ph) and np.array_equal(E2, E)
 
 
+@pytest.mark.parametrize("overlap", [True, False])
+def test_graph_replay_matches_eager(ctx, overlap):
+    """Captured graphs replayed several times, with eager work and
+    synchronisations in between, give exactly the eager result each time."""
+    w = W.small_random(777, 6000, 2, "plummer", p=7, theta=0.5, ncrit=32)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.moments).cuda()
+    ctx.set_overlap(overlap)
+    try:
+        for prec in (fmm.FMM_PREC_MIXED, fmm.FMM_PREC_FP64):
+            t = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+            ctx.set_graphs(False)
+            t.upward(w.order, mom, w.p, prec)
+            e_phi, e_E = t.evaluate()
+            torch.cuda.synchronize()
+            e_phi, e_E = e_phi.cpu().numpy(), e_E.cpu().numpy()
+            ctx.set_graphs(True)
+            phi = torch.empty(w.n, dtype=torch.float64, device="cuda")
+            E = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+            for rep in range(4):
+                phi.fill_(float("nan"))
+                E.fill_(float("nan"))
+                t.upward(w.order, mom, w.p, prec)
+                t.evaluate(fmm.FMM_POT | fmm.FMM_FIELD, phi, E)
+                torch.cuda.synchronize()
+                junk = (pos * 2.0).sum().item()          # eager work between replays
+                assert np.isfinite(junk)
+                assert np.array_equal(phi.cpu().numpy(), e_phi), rep
+                assert np.array_equal(E.cpu().numpy(), e_E), rep
+            t.close()
+    finally:
+        ctx.set_overlap(True)
+        ctx.set_graphs(True)
+
+
 def test_error_codes(ctx):
     pos = torch.rand(100, 3, dtype=torch.float64, device="cuda")
     with pytest.raises(fmm.FMMError) as e:

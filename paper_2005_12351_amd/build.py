@@ -27,8 +27,10 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", CSRC,
 
 def _sources(gen_dir, gen_opt):
     sys.path.insert(0, CSRC)
+    import gen_bh  # noqa: E402
     import gen_m2l  # noqa: E402
     gen = gen_m2l.main(gen_dir, gen_opt)
+    gen_bh.main(gen_dir)
     sys.path.pop(0)
     srcs = [(os.path.join(CSRC, "kernels.hip"), []),
             (os.path.join(CSRC, "fmm_capi.cpp"), ["-ffp-contract=off"]),
@@ -45,7 +47,7 @@ def _sources(gen_dir, gen_opt):
 
 def _compile(src, extra, verbose, build_dir):
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [HIPCC, "-x", "hip", "-c", src, "-o", obj] + COMMON + extra
+    cmd = [HIPCC, "-x", "hip", "-c", src, "-o", obj] + COMMON + ["-I", os.path.join(build_dir, "gen")] + extra
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -23,7 +23,7 @@ TOL_FP64 = 1e-10
 # Mixed path vs oracle: FP32 M2L/P2P (unit roundoff 6e-8) summed over a few
 # hundred list entries per target; see the tolerance derivation in the design
 # notes.  Stated per precision and checked here.
-TOL_MIXED = 2e-5
+TOL_MIXED = 1e-5
 
 
 @pytest.fixture(scope="module")

@@ -55,6 +55,69 @@ def _traffic(kernel_key: str):
     return None
 
 
+def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
+    """Serving workload: requests with N log-uniform in [1e3, 2e5], source
+    order in {0,1,2}, p in {4,6,8}, uniform or Plummer positions, theta 0.5,
+    ncrit 64, mixed precision.  A closed-loop pass (all submitted at once)
+    measures the saturated request rate; the timed open-loop pass replays the
+    Poisson arrivals at 0.7 times that rate.  Latency = done - arrival."""
+    import threading
+    reqs = W.serving_stream(n_requests, rate=1.0)
+    dev = []
+    for r in reqs:
+        w = r.workload
+        dev.append((w, torch.from_numpy(w.pos).cuda(), torch.from_numpy(w.moments).cuda(),
+                    torch.empty(w.n, dtype=torch.float64, device="cuda"),
+                    torch.empty((w.n, 3), dtype=torch.float64, device="cuda")))
+    torch.cuda.synchronize()
+
+    def submit(ctx, d):
+        w = d[0]
+        return ctx.submit(n=w.n, order=w.order, p=w.p, theta=w.theta, ncrit=w.ncrit, pos=d[1], moments=d[2],
+                          phi=d[3], field=d[4], precision=fmm.FMM_PREC_MIXED)
+
+    # closed loop: saturated rate
+    ctx = fmm.Context(0, budget_bytes=budget)
+    ctx.serve_start(slots)
+    t0 = time.perf_counter()
+    tk = [submit(ctx, d) for d in dev]
+    for t in tk:
+        ctx.wait(t)
+    sat_rate = n_requests / (time.perf_counter() - t0)
+    ctx.close()
+    # open loop at 0.7 x saturated rate
+    lam = 0.7 * sat_rate
+    ctx = fmm.Context(0, budget_bytes=budget)
+    ctx.serve_start(slots)
+    tickets = [None] * n_requests
+    start = time.perf_counter()
+
+    def feeder():
+        for k, (r, d) in enumerate(zip(reqs, dev)):
+            delay = start + r.arrival / lam - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[k] = submit(ctx, d)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    for t in tickets:
+        ctx.wait(t)
+    times = [ctx.request_times(t) for t in tickets]
+    stats = ctx.serve_stats()
+    ctx.close()
+    lat = np.array([x["done"] - x["submit"] for x in times])
+    span = max(x["done"] for x in times) - min(x["submit"] for x in times)
+    nsum = sum(d[0].n for d in dev)
+    return {"requests": n_requests, "slots": slots, "budget_bytes": budget, "lambda_req_per_s": lam,
+            "saturated_req_per_s": sat_rate, "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3), "mean_latency_ms": float(lat.mean() * 1e3),
+            "throughput_evals_per_s": nsum / span, "peak_running": stats["peak_running"],
+            "peak_admitted_bytes": stats["peak_in_use"], "total_particles": nsum,
+            "note": "latency includes the host-side tree build of each request"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +126,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error checks")
     ap.add_argument("--n", type=int, default=0, help="shrink the workload (testing only)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream measurement")
+    ap.add_argument("--serve-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -197,6 +262,8 @@ def main():
             errs[name] = e
         errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64" % len(sample)
         line["rel_l2_error"] = errs
+    if not args.no_serve:
+        line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests)
     print(json.dumps(line), flush=True)
     tree.close()
     ctx.close()

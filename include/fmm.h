@@ -166,14 +166,34 @@ typedef struct {
 
 enum { FMM_REQ_QUEUED = 0, FMM_REQ_RUNNING = 1, FMM_REQ_DONE = 2, FMM_REQ_FAILED = 3 };
 
+/* Start the server with `max_concurrent` (1..64) worker slots, each with its
+ * own streams.  Admission is in arrival order: the oldest queued request
+ * starts when a slot is free and its estimated footprint fits in the budget
+ * minus the footprints of the running requests. */
 int fmm_serve_start(fmm_ctx *ctx, int max_concurrent);
+/* Queue a request (copied); FMM_ENOMEM if its footprint exceeds the whole
+ * budget, FMM_EINVAL for bad parameters (nothing is queued then). */
 int fmm_submit(fmm_ctx *ctx, const fmm_request *req, uint64_t *ticket);
 int fmm_poll(fmm_ctx *ctx, uint64_t ticket, int *state);
+/* Block until the request is done (timeout_s < 0: no limit); FMM_ETIMEOUT
+ * if it is not done in time, the request's own error code if it failed. */
 int fmm_wait(fmm_ctx *ctx, uint64_t ticket, double timeout_s);
-/* times in seconds since fmm_serve_start: t[0] submit, t[1] admitted,
- * t[2] done; bytes[0] = admitted footprint */
+/* t[0] submit, t[1] admitted, t[2] done, in seconds since fmm_serve_start;
+ * bytes[0] estimated footprint used for admission, bytes[1] device bytes the
+ * request actually held. */
 int fmm_request_times(fmm_ctx *ctx, uint64_t ticket, double *t, int64_t *bytes);
+/* stats[0..6] = budget, bytes admitted now, peak bytes admitted, running
+ * requests, peak running, queued requests, slots. */
+int fmm_serve_stats(fmm_ctx *ctx, int64_t *stats);
+/* Stop accepting requests, finish the queued and running ones, join the
+ * workers (also done by fmm_ctx_destroy). */
 int fmm_serve_stop(fmm_ctx *ctx);
+
+/* A context without a device whose server runs the scheduling and admission
+ * logic with a simulated executor (each request waits ns_per_particle * n
+ * nanoseconds and touches no memory).  Only the serving entry points accept
+ * it; it exists to test the scheduler on machines without a GPU. */
+int fmm_ctx_create_fake(size_t budget_bytes, double ns_per_particle, fmm_ctx **out);
 
 #ifdef __cplusplus
 }

@@ -128,6 +128,7 @@ extern "C" int fmm_profile_enable(fmm_ctx *ctx, int on)
 extern "C" int fmm_profile_reset(fmm_ctx *ctx)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
+    if (ctx->fake) FAIL(FMM_EINVAL, "context has no device");
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     for (auto &e : ctx->prof) {
@@ -141,6 +142,7 @@ extern "C" int fmm_profile_reset(fmm_ctx *ctx)
 extern "C" int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, int64_t *launches, int cap)
 {
     if (!ctx || cap < 0) FAIL(FMM_EINVAL, "bad arguments");
+    if (ctx->fake) FAIL(FMM_EINVAL, "context has no device");
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     std::vector<const char *> nm;
@@ -205,7 +207,9 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
 static void tree_release_device(fmm_tree *t)
 {
     drop_graphs(t);
-    for (void *p : t->allocs) hipFree(p);
+    // the near field may still run on the auxiliary stream
+    (void)hipStreamSynchronize(t->ctx->aux);
+    for (void *p : t->allocs) (void)hipFreeAsync(p, t->ctx->stream);
     t->allocs.clear();
     t->dev_bytes = 0;
 }
@@ -213,8 +217,12 @@ static void tree_release_device(fmm_tree *t)
 extern "C" int fmm_ctx_destroy(fmm_ctx *c)
 {
     if (!c) return FMM_OK;
-    hipSetDevice(c->device);
     serve_destroy(c);
+    if (c->fake) {
+        delete c;
+        return FMM_OK;
+    }
+    (void)hipSetDevice(c->device);
     hipDeviceSynchronize();
     // trees still alive lose their device memory and become orphans that
     // only fmm_tree_destroy accepts
@@ -223,6 +231,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
         t->ctx = nullptr;
     }
     c->trees.clear();
+    (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->prof) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -238,13 +247,16 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
 }
 
 // ------------------------------------------------------------------ tree
+// Device memory comes from the stream-ordered allocator on the context's
+// stream: allocation and release never synchronise the device, so requests
+// served on other streams keep running while a tree is built or freed.
 int tree_alloc(fmm_tree *t, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
-    if (hipMalloc(p, bytes) != hipSuccess) {
+    if (hipMallocAsync(p, bytes, t->ctx->stream) != hipSuccess) {
         *p = nullptr;
-        FAIL(FMM_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+        FAIL(FMM_ENOMEM, "device allocation of %zu bytes failed", bytes);
     }
     t->allocs.push_back(*p);
     t->dev_bytes += bytes;
@@ -256,7 +268,7 @@ static void tree_free_block(fmm_tree *t, void *p)
     if (!p) return;
     auto it = std::find(t->allocs.begin(), t->allocs.end(), p);
     if (it != t->allocs.end()) t->allocs.erase(it);
-    hipFree(p);
+    (void)hipFreeAsync(p, t->ctx->stream);
 }
 
 template <typename T>
@@ -272,9 +284,7 @@ extern "C" int fmm_tree_destroy(fmm_tree *t)
 {
     if (!t) return FMM_OK;
     if (fmm_ctx *c = t->ctx) {
-        hipSetDevice(c->device);
-        hipStreamSynchronize(c->stream);
-        hipStreamSynchronize(c->aux);
+        (void)hipSetDevice(c->device);
         tree_release_device(t);
         c->trees.erase(std::remove(c->trees.begin(), c->trees.end(), t), c->trees.end());
     }
@@ -288,6 +298,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
                               fmm_tree **out)
 {
     if (!ctx || !out) FAIL(FMM_EINVAL, "null context or output");
+    if (ctx->fake) FAIL(FMM_EINVAL, "context has no device");
     *out = nullptr;
     if (!pos) FAIL(FMM_EINVAL, "positions are NULL");
     if (n < 1 || n > (int64_t)INT32_MAX / 4) FAIL(FMM_EINVAL, "n = %lld out of range", (long long)n);

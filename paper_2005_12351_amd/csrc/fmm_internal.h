@@ -115,6 +115,8 @@ struct fmm_ctx {
     bool profile = false;
     bool overlap = true;                  // P2P on the auxiliary stream
     bool graphs = true;                   // replay captured HIP graphs
+    bool fake = false;                    // no device: serving-logic tests only
+    double fake_ns = 0.0;                 // simulated cost per particle (fake)
     hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;

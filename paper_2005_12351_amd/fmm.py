@@ -69,11 +69,13 @@ fmm_poll = _sig("fmm_poll", [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
 fmm_wait = _sig("fmm_wait", [_vp, ctypes.c_uint64, ctypes.c_double])
 fmm_request_times = _sig("fmm_request_times", [_vp, ctypes.c_uint64, _vp, _vp])
 fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
+fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
+fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_tree_info",
             "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
-            "fmm_request_times", "fmm_serve_stop"]
+            "fmm_request_times", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
 
 class FMMError(RuntimeError):
@@ -100,13 +102,62 @@ def _dev_f64(t: torch.Tensor, cols: Optional[int], name: str) -> torch.Tensor:
 class Context:
     """A libfmm context bound to one device and one HIP stream."""
 
-    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0):
+    def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0,
+                 _handle=None):
         self.device = device
         self.stream = stream
+        if _handle is not None:
+            self.h = _handle
+            return
         h = _vp()
         s = stream.cuda_stream if stream is not None else None
         _check(fmm_ctx_create(device, s, budget_bytes, ctypes.byref(h)), "fmm_ctx_create")
         self.h = h
+
+    @classmethod
+    def fake(cls, budget_bytes: int, ns_per_particle: float = 0.0):
+        """device-less context whose server simulates execution (scheduler tests)"""
+        h = _vp()
+        _check(fmm_ctx_create_fake(int(budget_bytes), float(ns_per_particle), ctypes.byref(h)), "fmm_ctx_create_fake")
+        return cls(-1, None, 0, _handle=h)
+
+    # serving ---------------------------------------------------------
+    def serve_start(self, max_concurrent: int):
+        _check(fmm_serve_start(self.h, int(max_concurrent)), "fmm_serve_start")
+
+    def serve_stop(self):
+        _check(fmm_serve_stop(self.h), "fmm_serve_stop")
+
+    def submit(self, n: int, order: int, p: int, theta: float, ncrit: int, pos=None, moments=None, phi=None,
+               field=None, method: int = FMM_METHOD_FMM, precision: int = FMM_PREC_MIXED,
+               outputs: int = FMM_POT | FMM_FIELD) -> int:
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+        r = fmm_request(ptr(pos), ptr(moments), ptr(phi), ptr(field), int(n), int(order), int(p), int(ncrit),
+                        int(method), int(precision), int(outputs), float(theta))
+        tk = ctypes.c_uint64()
+        _check(fmm_submit(self.h, ctypes.byref(r), ctypes.byref(tk)), "fmm_submit")
+        return tk.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int()
+        _check(fmm_poll(self.h, ticket, ctypes.byref(st)), "fmm_poll")
+        return st.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        _check(fmm_wait(self.h, ticket, float(timeout_s)), "fmm_wait")
+
+    def request_times(self, ticket: int):
+        t = (ctypes.c_double * 3)()
+        b = (ctypes.c_int64 * 2)()
+        _check(fmm_request_times(self.h, ticket, ctypes.cast(t, _vp), ctypes.cast(b, _vp)), "fmm_request_times")
+        return dict(submit=t[0], admit=t[1], done=t[2], footprint=int(b[0]), bytes_used=int(b[1]))
+
+    def serve_stats(self) -> dict:
+        a = (ctypes.c_int64 * 7)()
+        _check(fmm_serve_stats(self.h, ctypes.cast(a, _vp)), "fmm_serve_stats")
+        return dict(zip(["budget", "in_use", "peak_in_use", "running", "peak_running", "queued", "slots"],
+                        [int(v) for v in a]))
 
     def close(self):
         if self.h:

@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error checks")
     ap.add_argument("--n", type=int, default=0, help="shrink the workload (testing only)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream measurement")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -142,6 +144,13 @@ def main():
     mom = torch.from_numpy(w.moments).to(dev)
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     ctx = fmm.Context(0)
+    if args.calibrate_copy:
+        a_ = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
+        b_ = torch.empty_like(a_)
+        torch.cuda.synchronize()
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+        del a_, b_
 
     t0 = time.perf_counter()
     tree = fmm.Tree(ctx, pos, w.ncrit, w.theta)

@@ -33,7 +33,8 @@ PEAK_HBM = 8.0e12
 
 def _src_hash():
     h = hashlib.sha256()
-    for f in ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/kernels.hip"):
+    for f in ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/m2l.hip",
+              "paper_2005_12351_amd/csrc/tree_host.cpp"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

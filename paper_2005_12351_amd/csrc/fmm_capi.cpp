@@ -358,6 +358,19 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
             if (h.nchild[c]) t->level_nonleaf.push_back((int32_t)c);
         t->level_nonleaf_ptr[l + 1] = (int32_t)t->level_nonleaf.size();
     }
+    // M2M is needed only into parents at or below the shallowest M2L source
+    // level, L2L only below the shallowest M2L target level: above them the
+    // multipoles are never read and the locals are zero.  Barnes-Hut may
+    // accept a cell at any level.
+    int src_top = nlev, tgt_top = nlev;
+    if ((int64_t)h.m2l_ptr.size() == nc + 1)
+        for (int64_t c = 0; c < nc; ++c)
+            if (h.m2l_ptr[c + 1] > h.m2l_ptr[c]) {
+                tgt_top = std::min(tgt_top, h.level[c]);
+                for (int64_t e = h.m2l_ptr[c]; e < h.m2l_ptr[c + 1]; ++e) src_top = std::min(src_top, h.level[h.m2l_src[e]]);
+            }
+    t->m2m_top = method == FMM_METHOD_BH ? 0 : src_top;
+    t->l2l_from = tgt_top + 1;
     std::vector<int32_t> pptr(t->nleaves + 1, 0), psrc;
     double p2p_pairs = 0.0;
     for (int64_t k = 0; k < t->nleaves; ++k) {
@@ -507,17 +520,32 @@ extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *mo
     if (rc) return rc;
     hipStream_t s = ctx->stream;
     t->mom_user = moments;
+    const bool fmm = t->method == FMM_METHOD_FMM;
+    hipStream_t a = ctx->overlap && fmm ? ctx->aux : s;
     auto body = [&]() -> int {
         {
             ProfScope ps(ctx, s, "prep_moments");
             KCHK(launch_prep_moments(t, s));
+        }
+        // the near field needs only the sorted moments: it runs on the
+        // auxiliary stream beside the latency-bound upward chain
+        if (fmm) {
+            if (a != s) {
+                KCHK(hipEventRecord(ctx->ev_fork, s));
+                KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
+            }
+            {
+                ProfScope ps(ctx, a, "p2p");
+                KCHK(launch_p2p(t, a));
+            }
+            if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
         }
         {
             ProfScope ps(ctx, s, "p2m");
             KCHK(launch_p2m(t, s));
         }
         const int nlev = (int)t->ht.level_ptr.size() - 1;
-        for (int l = nlev - 2; l >= 0; --l) {
+        for (int l = nlev - 2; l >= t->m2m_top; --l) {
             ProfScope ps(ctx, s, "m2m");
             KCHK(launch_m2m_level(t, l, s));
         }
@@ -525,9 +553,10 @@ extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *mo
             ProfScope ps(ctx, s, "m2_fp32");
             KCHK(launch_to_fp32(t, s));
         }
+        if (a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
         return FMM_OK;
     };
-    const int64_t key[6] = {1, order, p, precision, (int64_t)(uintptr_t)moments, 0};
+    const int64_t key[6] = {1, order, p, precision, (int64_t)(uintptr_t)moments, ctx->overlap};
     rc = run_cached(ctx, t, key, s, body);
     if (rc) return rc;
     t->have_up = 1;
@@ -546,7 +575,7 @@ extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi,
     if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
     if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream, a = ctx->overlap ? ctx->aux : ctx->stream;
+    hipStream_t s = ctx->stream;
     const int s_ = t->order, p = t->p;
     if (t->method == FMM_METHOD_BH) {
         ProfScope ps(ctx, s, "bh");
@@ -555,17 +584,8 @@ extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi,
     }
     const int64_t nc = t->ht.ncells();
     const int nl = nterms(p - s_);
+    // the near field was summed by fmm_upward
     auto body = [&]() -> int {
-        // near field on the auxiliary stream, overlapping the far field
-        if (a != s) {
-            KCHK(hipEventRecord(ctx->ev_fork, s));
-            KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
-        }
-        {
-            ProfScope ps(ctx, a, "p2p");
-            KCHK(launch_p2p(t, a));
-        }
-        if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
         KCHK(launch_fill(t->d_L64, (size_t)nc * nl, s));
         {
             ProfScope ps(ctx, s, "m2l");
@@ -576,18 +596,17 @@ extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi,
             KCHK(launch_m2l_combine(t, s));
         }
         const int nlev = (int)t->ht.level_ptr.size() - 1;
-        for (int l = 1; l < nlev; ++l) {
+        for (int l = std::max(1, t->l2l_from); l < nlev; ++l) {
             ProfScope ps(ctx, s, "l2l");
             KCHK(launch_l2l_level(t, l, s));
         }
-        if (a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
         {
             ProfScope ps(ctx, s, "l2p");
             KCHK(launch_l2p_final(t, outputs, phi, field, s));
         }
         return FMM_OK;
     };
-    const int64_t key[6] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, ctx->overlap, 0};
+    const int64_t key[6] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, 0, 0};
     int rc = run_cached(ctx, t, key, s, body);
     if (rc) return rc;
     // algorithmic work of this evaluation

@@ -24,6 +24,21 @@ constexpr int kPTable = 12;          // multi-index tables cover orders <= 12
 
 struct MultiIndex { int8_t x, y, z, k; };
 
+// multi-indices in storage order (total order ascending; within an order
+// n_x descending, then n_y descending), up to order kPTable
+struct MITable {
+    MultiIndex v[nterms(kPTable)];
+};
+constexpr MITable make_mi()
+{
+    MITable t{};
+    int i = 0;
+    for (int k = 0; k <= kPTable; ++k)
+        for (int nx = k; nx >= 0; --nx)
+            for (int ny = k - nx; ny >= 0; --ny) t.v[i++] = MultiIndex{(int8_t)nx, (int8_t)ny, (int8_t)(k - nx - ny), (int8_t)k};
+    return t;
+}
+
 // ------------------------------------------------------------------ errors
 void set_error(const char *fmt, ...);
 #define FMM_HIP(call)                                                              \
@@ -133,6 +148,8 @@ struct fmm_tree {
     int64_t nleaves = 0;
     std::vector<int32_t> leaves;           // cell index of every leaf
     std::vector<int32_t> level_nonleaf_ptr, level_nonleaf;  // M2M work per level
+    int m2m_top = 0;                       // shallowest parent level M2M runs into
+    int l2l_from = 1;                      // shallowest child level L2L runs into
     M2LTiling tiling;
     // device copies
     DevCell *d_cells = nullptr;

@@ -33,7 +33,7 @@ TILE = 64
 
 # code-shape options (register blocking and scalar-load pipelining); the
 # defaults are the measured best on gfx950, see DEFAULTS
-DEFAULTS = {"acc32": 128, "m32": 128, "acc64": 64, "m64": 48, "dgroup32": 24, "dgroup64": 10, "pipeline": 1,
+DEFAULTS = {"acc32": 128, "m32": 48, "acc64": 64, "m64": 24, "dgroup32": 24, "dgroup64": 10, "pipeline": 1,
             "depth": 1, "scale_branch": 0}
 
 

@@ -1,6 +1,5 @@
-// GPU kernels of libfmm.so other than the generated M2L contraction:
-// particle/moment preparation, P2M, M2M, the derivative tensor table,
-// M2L partial combination, L2L, P2P and L2P (Pepper & Fangohr, arXiv
+// GPU kernels of libfmm.so other than M2L and Barnes-Hut: particle and
+// moment preparation, P2M, M2M, L2L, P2P and L2P (Pepper & Fangohr, arXiv
 // 2005.12351, Section 2 and Section 3.2).
 //
 // All expansions on the GPU are kept in a dimensionless form:
@@ -15,18 +14,6 @@
 #include "pair_kernels.h"
 
 // ------------------------------------------------------------------ tables
-struct MITable {
-    MultiIndex v[nterms(kPTable)];
-};
-constexpr MITable make_mi()
-{
-    MITable t{};
-    int i = 0;
-    for (int k = 0; k <= kPTable; ++k)
-        for (int nx = k; nx >= 0; --nx)
-            for (int ny = k - nx; ny >= 0; --ny) t.v[i++] = MultiIndex{(int8_t)nx, (int8_t)ny, (int8_t)(k - nx - ny), (int8_t)k};
-    return t;
-}
 struct HalfTable {
     double v[kPTable + 2];
 };
@@ -40,7 +27,7 @@ constexpr HalfTable make_half()
     }
     return t;
 }
-__constant__ MITable k_mi = make_mi();
+static __constant__ MITable k_mi = make_mi();
 __constant__ HalfTable k_half = make_half();   // (1/2)^a / a!
 
 __device__ __forceinline__ double cell_radius(int level, double h) { return ldexp(1.0, kMaxLevel - level) * h; }
@@ -281,13 +268,41 @@ hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ M2M
+// ------------------------------------------------------------------ M2M / L2L
+// Both shifts act per child octant sigma (child centre = parent centre +
+// sigma r_child) and factorise over the axes, so each is applied as three 1-D
+// passes over a coefficient row held in LDS.  One workgroup per parent cell:
+// threadIdx.y = child slot (up to 8), threadIdx.x = coefficient slot; every
+// thread keeps the multi-indices of its coefficients and its child's octant
+// signs in registers, so the passes touch LDS only.
+constexpr int kShiftX = 128;                     // coefficient slots per child
+constexpr int kShiftItems = (nterms(kPTable) + kShiftX - 1) / kShiftX;
+
+struct ShiftItems {
+    int n;                                       // items owned by this thread
+    int m[kShiftItems][3];
+    int k[kShiftItems];
+};
+
+__device__ __forceinline__ void shift_items(int nt, ShiftItems &it)
+{
+    it.n = 0;
+#pragma unroll
+    for (int j = 0; j < kShiftItems; ++j) {
+        const int i = threadIdx.x + j * kShiftX;
+        const MultiIndex nn = k_mi.v[i < nt ? i : 0];
+        it.m[j][0] = nn.x;
+        it.m[j][1] = nn.y;
+        it.m[j][2] = nn.z;
+        it.k[j] = nn.k;
+        if (i < nt) it.n = j + 1;
+    }
+}
+
 // M~_n(P) = sum_children 2^-|n| sum_{k <= n} prod_d (-sigma_d)^k_d / k_d! M~_{n-k}(C)
-// (Eq. 4 with new-minus-old centre; the child centre is the parent's plus
-// sigma r_child, and the radii halve).  The triple sum factorises over the
-// axes, so it is applied as three 1-D passes in LDS, all children at once.
-constexpr int kM2MThreads = 256;
-__global__ __launch_bounds__(kM2MThreads) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
+// (Eq. 4 read with new-minus-old centre; radii halve from child to parent).
+// Children are summed in octant order in FP64.
+__global__ __launch_bounds__(kShiftX * 8) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
                                                           const DevCell *__restrict__ cells, double *__restrict__ M)
 {
     extern __shared__ double sm[];   // X[8][nt], Y[8][nt]
@@ -295,45 +310,64 @@ __global__ __launch_bounds__(kM2MThreads) void m2m_kernel(int p, int s, int nmp,
     double *X = sm, *Y = sm + 8 * nt;
     __shared__ double inv_fact[kPTable + 2];
     const int P = parents[blockIdx.x];
-    const DevCell pc = cells[P];
-    const int nch = pc.nchild, kid0 = pc.child0;
-    if (threadIdx.x <= kPTable + 1) {
+    const int nch = cells[P].nchild, kid0 = cells[P].child0;
+    const int k = threadIdx.y;
+    const int tid = threadIdx.y * kShiftX + threadIdx.x;
+    if (tid <= kPTable + 1) {
         double f = 1.0;
-        for (int a = 1; a <= (int)threadIdx.x; ++a) f *= k_inv.v[a];
-        inv_fact[threadIdx.x] = f;
+        for (int a = 1; a <= tid; ++a) f *= k_inv.v[a];
+        inv_fact[tid] = f;
     }
-    for (int it = threadIdx.x; it < nch * nt; it += blockDim.x) {
-        const int k = it / nt, i = it % nt;
-        X[k * nt + i] = i < n0 ? 0.0 : M[(size_t)(kid0 + k) * nmp + (i - n0)];
+    ShiftItems it;
+    shift_items(nt, it);
+    double sg[3] = {1.0, 1.0, 1.0};   // -sigma_d
+    if (k < nch) {
+        const DevCell cc = cells[kid0 + k];
+        sg[0] = (cc.ix & 1) ? -1.0 : 1.0;
+        sg[1] = (cc.iy & 1) ? -1.0 : 1.0;
+        sg[2] = (cc.iz & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int j = 0; j < kShiftItems; ++j) {
+            if (j >= it.n) break;
+            const int i = threadIdx.x + j * kShiftX;
+            X[k * nt + i] = i < n0 ? 0.0 : M[(size_t)(kid0 + k) * nmp + (i - n0)];
+        }
     }
     __syncthreads();
     // pass d: dst_n = sum_{a <= n_d} (-sigma_d)^a / a! src_{n - a e_d}
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double *src = d == 1 ? Y : X;
-        double *dst = d == 1 ? X : Y;
-        for (int it = threadIdx.x; it < nch * nt; it += blockDim.x) {
-            const int k = it / nt, i = it % nt;
-            const DevCell cc = cells[kid0 + k];
-            const int bit = d == 0 ? (cc.ix & 1) : (d == 1 ? (cc.iy & 1) : (cc.iz & 1));
-            const double sg = bit ? -1.0 : 1.0;   // -sigma_d
-            const MultiIndex nn = k_mi.v[i];
-            int m[3] = {nn.x, nn.y, nn.z};
-            const int nd = m[d];
-            double acc = 0.0, sp = 1.0;
-            for (int a = 0; a <= nd; ++a) {
-                acc = fma(sp * inv_fact[a], src[k * nt + mindex(m[0], m[1], m[2])], acc);
-                m[d] -= 1;
-                sp *= sg;
+        const double *src = (d == 1 ? Y : X) + k * nt;
+        double *dst = (d == 1 ? X : Y) + k * nt;
+        if (k < nch) {
+#pragma unroll
+            for (int j = 0; j < kShiftItems; ++j) {
+                if (j >= it.n) break;
+                int mx = it.m[j][0], my = it.m[j][1], mz = it.m[j][2];
+                const int nd = d == 0 ? mx : (d == 1 ? my : mz);
+                double acc = 0.0, sp = 1.0;
+                for (int a = 0; a <= nd; ++a) {
+                    acc = fma(sp * inv_fact[a], src[mindex(mx, my, mz)], acc);
+                    mx -= d == 0;
+                    my -= d == 1;
+                    mz -= d == 2;
+                    sp *= sg[d];
+                }
+                dst[threadIdx.x + j * kShiftX] = acc;
             }
-            dst[k * nt + i] = acc;
         }
         __syncthreads();
     }
-    for (int i = n0 + threadIdx.x; i < nt; i += blockDim.x) {
-        double acc = 0.0;
-        for (int k = 0; k < nch; ++k) acc += Y[k * nt + i];
-        M[(size_t)P * nmp + (i - n0)] = ldexp(acc, -(int)k_mi.v[i].k);
-    }
+    if (k == 0)
+#pragma unroll
+        for (int j = 0; j < kShiftItems; ++j) {
+            if (j >= it.n) break;
+            const int i = threadIdx.x + j * kShiftX;
+            if (i < n0) continue;
+            double acc = 0.0;
+            for (int c = 0; c < nch; ++c) acc += Y[c * nt + i];
+            M[(size_t)P * nmp + (i - n0)] = ldexp(acc, -it.k[j]);
+        }
 }
 
 hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
@@ -342,8 +376,87 @@ hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
     if (b <= a) return hipSuccess;
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     const size_t lds = (size_t)16 * nterms(t->p) * sizeof(double);
-    hipLaunchKernelGGL(m2m_kernel, dim3(b - a), dim3(kM2MThreads), lds, s, t->p, t->order, nmp, t->d_nonleaf + a,
+    hipLaunchKernelGGL(m2m_kernel, dim3(b - a), dim3(kShiftX, 8), lds, s, t->p, t->order, nmp, t->d_nonleaf + a,
                        t->d_cells, t->d_M64);
+    return hipGetLastError();
+}
+
+// L~_n(C) += sum_{a: |n+a| <= q} prod_d sigma_d^a_d / a_d! * 2^-(|n+a|+1) L~_{n+a}(P)
+// (Taylor shift of the local expansion to the child centre, in the
+// normalised form).  The parent row is scaled once and shared by the
+// children of the workgroup.
+__global__ __launch_bounds__(kShiftX * 8) void l2l_kernel(int q, const int32_t *__restrict__ parents,
+                                                          const DevCell *__restrict__ cells, double *__restrict__ L)
+{
+    extern __shared__ double sm[];   // Pr[nl], X[8][nl], Y[8][nl]
+    const int nl = nterms(q);
+    double *Pr = sm, *X = sm + nl, *Y = sm + 9 * nl;
+    __shared__ double inv_fact[kPTable + 2];
+    const int P = parents[blockIdx.x];
+    const int nch = cells[P].nchild, kid0 = cells[P].child0;
+    const int k = threadIdx.y;
+    const int tid = threadIdx.y * kShiftX + threadIdx.x;
+    if (tid <= kPTable + 1) {
+        double f = 1.0;
+        for (int a = 1; a <= tid; ++a) f *= k_inv.v[a];
+        inv_fact[tid] = f;
+    }
+    ShiftItems it;
+    shift_items(nl, it);
+    if (k == 0)
+#pragma unroll
+        for (int j = 0; j < kShiftItems; ++j) {
+            if (j >= it.n) break;
+            const int i = threadIdx.x + j * kShiftX;
+            Pr[i] = ldexp(L[(size_t)P * nl + i], -(it.k[j] + 1));
+        }
+    double sg[3] = {1.0, 1.0, 1.0};   // sigma_d
+    if (k < nch) {
+        const DevCell cc = cells[kid0 + k];
+        sg[0] = (cc.ix & 1) ? 1.0 : -1.0;
+        sg[1] = (cc.iy & 1) ? 1.0 : -1.0;
+        sg[2] = (cc.iz & 1) ? 1.0 : -1.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double *src = d == 0 ? Pr : (d == 1 ? Y : X) + k * nl;
+        double *dst = (d == 1 ? X : Y) + k * nl;
+        if (k < nch) {
+#pragma unroll
+            for (int j = 0; j < kShiftItems; ++j) {
+                if (j >= it.n) break;
+                int mx = it.m[j][0], my = it.m[j][1], mz = it.m[j][2];
+                double acc = 0.0, sp = 1.0;
+                for (int a = 0; a <= q - it.k[j]; ++a) {
+                    acc = fma(sp * inv_fact[a], src[mindex(mx, my, mz)], acc);
+                    mx += d == 0;
+                    my += d == 1;
+                    mz += d == 2;
+                    sp *= sg[d];
+                }
+                dst[threadIdx.x + j * kShiftX] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    if (k < nch)
+#pragma unroll
+        for (int j = 0; j < kShiftItems; ++j) {
+            if (j >= it.n) break;
+            const int i = threadIdx.x + j * kShiftX;
+            L[(size_t)(kid0 + k) * nl + i] += Y[k * nl + i];
+        }
+}
+
+// children at `level` receive from their parents at level - 1
+hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s)
+{
+    const int a = t->level_nonleaf_ptr[level - 1], b = t->level_nonleaf_ptr[level];
+    if (b <= a) return hipSuccess;
+    const int q = t->p - t->order;
+    const size_t lds = (size_t)17 * nterms(q) * sizeof(double);
+    hipLaunchKernelGGL(l2l_kernel, dim3(b - a), dim3(kShiftX, 8), lds, s, q, t->d_nonleaf + a, t->d_cells, t->d_L64);
     return hipGetLastError();
 }
 
@@ -359,198 +472,6 @@ hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s)
     const size_t n = (size_t)(t->ht.ncells() + 1) * nmp;
     const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(to_fp32_kernel, dim3(g), dim3(256), 0, s, n, t->d_M64, t->d_M32);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ D table
-// Derivatives D_k = d^k (1/r) at every M2L class geometry, |k| <= p, by the
-// Hermite-type recursion on R^(j)_n = d^n f^(j)(u), f(u) = (2u)^-1/2,
-// u = r^2/2:  R^(j)_0 = (-1)^j (2j-1)!! r^-(2j+1),
-//             R^(j)_{m+e_d} = x_d R^(j+1)_m + m_d R^(j+1)_{m-e_d},
-// and D_k = R^(0)_k.  FP64; an FP32 copy feeds the mixed-precision M2L.
-// Also writes the scale row rho^k, k = 0..p.
-__global__ __launch_bounds__(64) void dtable_kernel(int p, int nd, int scw, const double *__restrict__ geom,
-                                                    double *__restrict__ D64, float *__restrict__ D32,
-                                                    double *__restrict__ S64, float *__restrict__ S32)
-{
-    __shared__ double Rall[1820];   // all R^(j) blocks: sum_j nterms(p - j) = C(p+4,4) <= 1820 for p <= 12
-    const int c = blockIdx.x;
-    const double x[3] = {geom[4 * c], geom[4 * c + 1], geom[4 * c + 2]};
-    const double rho = geom[4 * c + 3];
-    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-    // offsets of the R^(j) blocks
-    auto off = [&](int j) {
-        int o = 0;
-        for (int q = 0; q < j; ++q) o += nterms(p - q);
-        return o;
-    };
-    if ((int)threadIdx.x <= p) {
-        const int j = threadIdx.x;
-        double v = 1.0 / sqrt(r2);
-        const double ir2 = 1.0 / r2;
-        for (int q = 1; q <= j; ++q) v *= -(2.0 * q - 1.0) * ir2;
-        Rall[off(j)] = v;
-    }
-    __syncthreads();
-    for (int t = 1; t <= p; ++t) {
-        const int per = (t + 1) * (t + 2) / 2;
-        const int items = per * (p - t + 1);
-        for (int it = threadIdx.x; it < items; it += blockDim.x) {
-            const int j = it / per;
-            const MultiIndex nn = k_mi.v[nterms(t - 1) + it % per];
-            int m[3] = {nn.x, nn.y, nn.z};
-            const int d = nn.x > 0 ? 0 : (nn.y > 0 ? 1 : 2);
-            m[d] -= 1;
-            const double *Rn = Rall + off(j + 1);
-            double v = x[d] * Rn[mindex(m[0], m[1], m[2])];
-            if (m[d] > 0) {
-                int q[3] = {m[0], m[1], m[2]};
-                q[d] -= 1;
-                v = fma((double)m[d], Rn[mindex(q[0], q[1], q[2])], v);
-            }
-            Rall[off(j) + mindex(nn.x, nn.y, nn.z)] = v;
-        }
-        __syncthreads();
-    }
-    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
-        const double v = k < nterms(p) ? Rall[k] : 0.0;
-        D64[(size_t)c * nd + k] = v;
-        D32[(size_t)c * nd + k] = (float)v;
-    }
-    for (int k = threadIdx.x; k < scw; k += blockDim.x) {
-        const double v = k <= p ? ldexp(1.0, ilogb(rho) * k) : 0.0;   // rho is a power of two
-        S64[(size_t)c * scw + k] = v;
-        S32[(size_t)c * scw + k] = (float)v;
-    }
-}
-
-hipError_t launch_dtable(fmm_tree *t, hipStream_t s)
-{
-    if (t->tiling.nclasses == 0) return hipSuccess;
-    M2LVariant v;
-    m2l_lookup(t->p, t->order, true, &v);
-    const int scw = (t->p + 1 + 3) / 4 * 4;
-    hipLaunchKernelGGL(dtable_kernel, dim3(t->tiling.nclasses), dim3(64), 0, s, t->p, v.nd, scw, t->d_cls_geom,
-                       t->d_D64, t->d_D32, t->d_sc64, t->d_sc32);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ M2L
-hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
-{
-    const M2LWork &wk = t->m2lwork;
-    if (wk.work.empty()) return hipSuccess;
-    const bool f32 = t->prec == FMM_PREC_MIXED;
-    M2LVariant v;
-    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
-    M2LArgs a;
-    a.work = t->d_work;
-    a.ucls = t->d_ucls;
-    a.usrc = t->d_usrc;
-    a.D = f32 ? (const void *)t->d_D32 : (const void *)t->d_D64;
-    a.sc = f32 ? (const void *)t->d_sc32 : (const void *)t->d_sc64;
-    a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
-    a.part = t->d_part;
-    a.wave_ptr = t->d_wave_ptr;
-    return v.launch(a, wk.nwaves, s);
-}
-
-// sum of the chunk partials of every target slot into L~ (FP64); each output
-// block of a tile has its own chunks
-struct BlockBounds {
-    int lo[17];
-    int nb;
-};
-
-template <typename T>
-__global__ void m2l_combine_kernel(int nslots, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ tile_cell,
-                                   const int32_t *__restrict__ chunk0, const int32_t *__restrict__ nchunk,
-                                   const T *__restrict__ part, double *__restrict__ L)
-{
-    const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (id >= (size_t)nslots * nl) return;
-    const int slot = (int)(id / nl), n = (int)(id % nl);
-    const int cell = tile_cell[slot];
-    if (cell < 0) return;
-    const int tile = slot / kTileW, lane = slot % kTileW;
-    int b = 0;
-    while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
-    double acc = 0.0;
-    const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
-    for (int k = 0; k < nc; ++k) acc += (double)part[((size_t)(c0 + k) * kTileW + lane) * nlp + n];
-    L[(size_t)cell * nl + n] = acc;
-}
-
-hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
-{
-    const M2LTiling &tl = t->tiling;
-    if (tl.ntiles == 0) return hipSuccess;
-    const bool f32 = t->prec == FMM_PREC_MIXED;
-    M2LVariant v;
-    m2l_lookup(t->p, t->order, f32, &v);
-    BlockBounds bb;
-    for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
-    bb.nb = v.nblocks;
-    const int nl = nterms(t->p - t->order);
-    const int nslots = tl.ntiles * kTileW;
-    const size_t tot = (size_t)nslots * nl;
-    const unsigned g = (unsigned)((tot + 255) / 256);
-    if (f32)
-        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
-                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
-    else
-        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
-                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ L2L
-// L~_n(C) += sum_{a: |n+a| <= q} prod_d sigma_d^a_d / a_d! * 2^-(|n+a|+1) L~_{n+a}(P)
-// (Taylor shift of the local expansion by +sigma r_child, in the normalised
-// form).  Applied as three 1-D passes after scaling the parent row.
-__global__ __launch_bounds__(128) void l2l_kernel(int q, const int32_t *__restrict__ cellsl, const DevCell *__restrict__ cells,
-                                                  double *__restrict__ L)
-{
-    __shared__ double X[nterms(kPTable)], Y[nterms(kPTable)];
-    __shared__ double inv_fact[kPTable + 2];
-    const int C = cellsl[blockIdx.x];
-    const DevCell cc = cells[C];
-    const int nl = nterms(q);
-    if (threadIdx.x <= kPTable + 1) {
-        double f = 1.0;
-        for (int a = 1; a <= (int)threadIdx.x; ++a) f *= k_inv.v[a];
-        inv_fact[threadIdx.x] = f;
-    }
-    for (int i = threadIdx.x; i < nl; i += blockDim.x)
-        X[i] = ldexp(L[(size_t)cc.parent * nl + i], -((int)k_mi.v[i].k + 1));
-    __syncthreads();
-    const int bits[3] = {cc.ix & 1, cc.iy & 1, cc.iz & 1};
-    for (int d = 0; d < 3; ++d) {
-        const double *src = d == 1 ? Y : X;
-        double *dst = d == 1 ? X : Y;
-        const double sg = bits[d] ? 1.0 : -1.0;   // sigma_d
-        for (int i = threadIdx.x; i < nl; i += blockDim.x) {
-            const MultiIndex nn = k_mi.v[i];
-            int m[3] = {nn.x, nn.y, nn.z};
-            double acc = 0.0, sp = 1.0;
-            for (int a = 0; a <= q - nn.k; ++a) {
-                acc = fma(sp * inv_fact[a], src[mindex(m[0], m[1], m[2])], acc);
-                m[d] += 1;
-                sp *= sg;
-            }
-            dst[i] = acc;
-        }
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < nl; i += blockDim.x) L[(size_t)C * nl + i] += Y[i];
-}
-
-hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s)
-{
-    const int a = (int)t->ht.level_ptr[level], b = (int)t->ht.level_ptr[level + 1];
-    if (b <= a) return hipSuccess;
-    hipLaunchKernelGGL(l2l_kernel, dim3(b - a), dim3(128), 0, s, t->p - t->order, t->d_level_cells + a, t->d_cells,
-                       t->d_L64);
     return hipGetLastError();
 }
 
@@ -823,9 +744,11 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
 // ------------------------------------------------------------------ L2P
 // phi = (1/r) sum_{|n|<=q} eta^n/n! L~_n, E_d = -(1/r^2) sum eta^n/n! L~_{n+e_d}
 // (Eq. 9, Eq. 10 with |k| = 1), eta = (x - z)/r, plus the near field, written
-// to the caller's particle order.  Compiled per q = p - s: the z powers live
-// in registers and the innermost loop is unrolled; the outer loops run with
-// uniform counters, so the L~ reads are LDS broadcasts.
+// to the caller's particle order.  The leaf's L~ is unpacked into a dense
+// zero-padded cube in LDS, so that for fixed (n_x, n_y) the four sums over
+// n_z are unit-stride and their addresses are compile-time offsets from one
+// base; the outer loops run with uniform counters (LDS broadcasts, scalar
+// branches).  Compiled per q = p - s.
 template <int Q>
 __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ leaves,
                                                  const DevCell *__restrict__ cells, Geo g, const double *__restrict__ xs,
@@ -834,10 +757,17 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
                                                  double *__restrict__ field)
 {
     constexpr int NL = nterms(Q);
-    __shared__ double ls[NL];
+    constexpr int E = Q + 2;                     // edge: room for n + e_d
+    constexpr int NC = E * E * E;
+    __shared__ double cube[NC];
     const int c = leaves[blockIdx.x];
     const DevCell cell = cells[c];
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) ls[i] = L[(size_t)c * NL + i];
+    for (int i = threadIdx.x; i < NC; i += blockDim.x) cube[i] = 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+        const MultiIndex nn = k_mi.v[i];
+        cube[(nn.x * E + nn.y) * E + nn.z] = L[(size_t)c * NL + i];
+    }
     __syncthreads();
     double z[3];
     cell_center(cell, g.lo, g.h, z);
@@ -855,24 +785,27 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
 #pragma unroll 1
         for (int nx = 0; nx <= Q; ++nx) {
             if (nx) px *= ex * k_inv.v[nx];
-            double py = 1.0;
+            double py = px;
 #pragma unroll 1
             for (int ny = 0; ny <= Q - nx; ++ny) {
                 if (ny) py *= ey * k_inv.v[ny];
-                const double pxy = px * py;
+                const double *b = cube + (nx * E + ny) * E;
                 const int lim = Q - nx - ny;
+                // entries beyond the simplex are zero, so the field sums may
+                // run to the same bound as the potential sum
+                double tp = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
 #pragma unroll
                 for (int nz = 0; nz <= Q; ++nz) {
-                    if (nz <= lim) {
-                        const double mono = pxy * pz[nz];
-                        ph = fma(mono, ls[mindex(nx, ny, nz)], ph);
-                        if (nz < lim) {
-                            fx = fma(mono, ls[mindex(nx + 1, ny, nz)], fx);
-                            fy = fma(mono, ls[mindex(nx, ny + 1, nz)], fy);
-                            fz = fma(mono, ls[mindex(nx, ny, nz + 1)], fz);
-                        }
-                    }
+                    if (nz > lim) break;
+                    tp = fma(pz[nz], b[nz], tp);
+                    tx = fma(pz[nz], b[E * E + nz], tx);
+                    ty = fma(pz[nz], b[E + nz], ty);
+                    tz = fma(pz[nz], b[nz + 1], tz);
                 }
+                ph = fma(py, tp, ph);
+                fx = fma(py, tx, fx);
+                fy = fma(py, ty, fy);
+                fz = fma(py, tz, fz);
             }
         }
         const double *nr = near + 4 * (size_t)i;

@@ -1,0 +1,152 @@
+// M2L support kernels of libfmm.so (Pepper & Fangohr, arXiv 2005.12351,
+// Eq. 7-8): the derivative tensor of every translation class, the launch of
+// the generated contraction kernels, and the FP64 combination of their
+// partial rows into the local expansions.
+#include <cmath>
+
+#include "fmm_internal.h"
+
+static __constant__ MITable k_mi = make_mi();
+
+// ------------------------------------------------------------------ D table
+// Derivatives D_k = d^k (1/r) at every M2L class geometry, |k| <= p, by the
+// Hermite-type recursion on R^(j)_n = d^n f^(j)(u), f(u) = (2u)^-1/2,
+// u = r^2/2:  R^(j)_0 = (-1)^j (2j-1)!! r^-(2j+1),
+//             R^(j)_{m+e_d} = x_d R^(j+1)_m + m_d R^(j+1)_{m-e_d},
+// and D_k = R^(0)_k.  FP64; an FP32 copy feeds the mixed-precision M2L.
+// Also writes the scale row rho^k, k = 0..p.
+__global__ __launch_bounds__(64) void dtable_kernel(int p, int nd, int scw, const double *__restrict__ geom,
+                                                    double *__restrict__ D64, float *__restrict__ D32,
+                                                    double *__restrict__ S64, float *__restrict__ S32)
+{
+    __shared__ double Rall[1820];   // all R^(j) blocks: sum_j nterms(p - j) = C(p+4,4) <= 1820 for p <= 12
+    const int c = blockIdx.x;
+    const double x[3] = {geom[4 * c], geom[4 * c + 1], geom[4 * c + 2]};
+    const double rho = geom[4 * c + 3];
+    const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    // offsets of the R^(j) blocks
+    auto off = [&](int j) {
+        int o = 0;
+        for (int q = 0; q < j; ++q) o += nterms(p - q);
+        return o;
+    };
+    if ((int)threadIdx.x <= p) {
+        const int j = threadIdx.x;
+        double v = 1.0 / sqrt(r2);
+        const double ir2 = 1.0 / r2;
+        for (int q = 1; q <= j; ++q) v *= -(2.0 * q - 1.0) * ir2;
+        Rall[off(j)] = v;
+    }
+    __syncthreads();
+    for (int t = 1; t <= p; ++t) {
+        const int per = (t + 1) * (t + 2) / 2;
+        const int items = per * (p - t + 1);
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int j = it / per;
+            const MultiIndex nn = k_mi.v[nterms(t - 1) + it % per];
+            int m[3] = {nn.x, nn.y, nn.z};
+            const int d = nn.x > 0 ? 0 : (nn.y > 0 ? 1 : 2);
+            m[d] -= 1;
+            const double *Rn = Rall + off(j + 1);
+            double v = x[d] * Rn[mindex(m[0], m[1], m[2])];
+            if (m[d] > 0) {
+                int q[3] = {m[0], m[1], m[2]};
+                q[d] -= 1;
+                v = fma((double)m[d], Rn[mindex(q[0], q[1], q[2])], v);
+            }
+            Rall[off(j) + mindex(nn.x, nn.y, nn.z)] = v;
+        }
+        __syncthreads();
+    }
+    for (int k = threadIdx.x; k < nd; k += blockDim.x) {
+        const double v = k < nterms(p) ? Rall[k] : 0.0;
+        D64[(size_t)c * nd + k] = v;
+        D32[(size_t)c * nd + k] = (float)v;
+    }
+    for (int k = threadIdx.x; k < scw; k += blockDim.x) {
+        const double v = k <= p ? ldexp(1.0, ilogb(rho) * k) : 0.0;   // rho is a power of two
+        S64[(size_t)c * scw + k] = v;
+        S32[(size_t)c * scw + k] = (float)v;
+    }
+}
+
+hipError_t launch_dtable(fmm_tree *t, hipStream_t s)
+{
+    if (t->tiling.nclasses == 0) return hipSuccess;
+    M2LVariant v;
+    m2l_lookup(t->p, t->order, true, &v);
+    const int scw = (t->p + 1 + 3) / 4 * 4;
+    hipLaunchKernelGGL(dtable_kernel, dim3(t->tiling.nclasses), dim3(64), 0, s, t->p, v.nd, scw, t->d_cls_geom,
+                       t->d_D64, t->d_D32, t->d_sc64, t->d_sc32);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ M2L
+hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
+{
+    const M2LWork &wk = t->m2lwork;
+    if (wk.work.empty()) return hipSuccess;
+    const bool f32 = t->prec == FMM_PREC_MIXED;
+    M2LVariant v;
+    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
+    M2LArgs a;
+    a.work = t->d_work;
+    a.ucls = t->d_ucls;
+    a.usrc = t->d_usrc;
+    a.D = f32 ? (const void *)t->d_D32 : (const void *)t->d_D64;
+    a.sc = f32 ? (const void *)t->d_sc32 : (const void *)t->d_sc64;
+    a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
+    a.part = t->d_part;
+    a.wave_ptr = t->d_wave_ptr;
+    return v.launch(a, wk.nwaves, s);
+}
+
+// sum of the chunk partials of every target slot into L~ (FP64); each output
+// block of a tile has its own chunks
+struct BlockBounds {
+    int lo[17];
+    int nb;
+};
+
+template <typename T>
+__global__ void m2l_combine_kernel(int nslots, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ tile_cell,
+                                   const int32_t *__restrict__ chunk0, const int32_t *__restrict__ nchunk,
+                                   const T *__restrict__ part, double *__restrict__ L)
+{
+    const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (id >= (size_t)nslots * nl) return;
+    const int slot = (int)(id / nl), n = (int)(id % nl);
+    const int cell = tile_cell[slot];
+    if (cell < 0) return;
+    const int tile = slot / kTileW, lane = slot % kTileW;
+    int b = 0;
+    while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
+    double acc = 0.0;
+    const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
+    for (int k = 0; k < nc; ++k) acc += (double)part[((size_t)(c0 + k) * kTileW + lane) * nlp + n];
+    L[(size_t)cell * nl + n] = acc;
+}
+
+hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
+{
+    const M2LTiling &tl = t->tiling;
+    if (tl.ntiles == 0) return hipSuccess;
+    const bool f32 = t->prec == FMM_PREC_MIXED;
+    M2LVariant v;
+    m2l_lookup(t->p, t->order, f32, &v);
+    BlockBounds bb;
+    for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
+    bb.nb = v.nblocks;
+    const int nl = nterms(t->p - t->order);
+    const int nslots = tl.ntiles * kTileW;
+    const size_t tot = (size_t)nslots * nl;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+    if (f32)
+        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
+                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
+    else
+        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
+                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
+    return hipGetLastError();
+}
+

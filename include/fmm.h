@@ -86,15 +86,19 @@ int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double
                    int method, fmm_tree **out);
 
 /* Upward pass: P2M at the leaves (Eq. 5 with the source tensor
- * S_n = (-1)^|n| T_n / n! of the physical moment T) and M2M to the root
- * (Eq. 4), expansion order p.  order in {0,1,2}; order+1 <= p <= FMM_P_MAX
- * for FMM, order <= p <= FMM_P_MAX for BH.  `moments` must stay valid until
- * fmm_evaluate has been queued (the near field reads it). */
+ * S_n = (-1)^|n| T_n / n! of the physical moment T) and M2M towards the root
+ * (Eq. 4), expansion order p; for FMM trees also the near field (direct
+ * sums over the P2P lists, Section 3.2) into library-owned storage, since it
+ * depends only on the moments.  order in {0,1,2}; order+1 <= p <= FMM_P_MAX
+ * for FMM, order <= p <= FMM_P_MAX for BH.  `moments`: device, n x w FP64
+ * row-major (w = 1, 3, 6), caller-owned, read only by the work this call
+ * queues on the context stream (a sorted copy is kept). */
 int fmm_upward(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int p,
                int precision);
 
-/* Far field (M2L, L2L, L2P or, for BH, M2P) plus near field (P2P) at every
- * particle.  `outputs` is a mask of FMM_POT / FMM_FIELD; phi (n) and field
+/* Far field (M2L, L2L, L2P or, for BH, the whole per-particle traversal
+ * with M2P and direct sums) plus the near field summed by fmm_upward, at
+ * every particle, written in the caller's particle order.  `outputs` is a mask of FMM_POT / FMM_FIELD; phi (n) and field
  * (n x 3) must be non-NULL for the requested outputs.  FMM_ESTATE if
  * fmm_upward has not run on this tree. */
 int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field);
@@ -121,7 +125,7 @@ int fmm_tree_destroy(fmm_tree *tree);
 /* Text of the last error on the calling thread ("" if none). */
 const char *fmm_last_error(void);
 
-/* Near field (P2P) on a second stream overlapping the far field (default on).
+/* Near field (P2P) on a second stream overlapping P2P/M2M (default on).
  * Off: every kernel runs on the context stream, one after the other, so the
  * per-kernel timings below measure each kernel alone. */
 int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);

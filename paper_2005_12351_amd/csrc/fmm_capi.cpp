@@ -308,22 +308,23 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
 
-    std::vector<double> hpos((size_t)n * 3);
-    HIPCHK(hipMemcpyAsync(hpos.data(), pos, hpos.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    for (double v : hpos)
-        if (!std::isfinite(v)) FAIL(FMM_EINVAL, "non-finite position");
-
     fmm_tree *t = new fmm_tree();
     t->ctx = ctx;
     t->method = method;
     t->ncrit = ncrit;
     t->theta = theta;
-    host_build_tree(hpos.data(), n, ncrit, t->ht);
+    {
+        const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht);
+        if (e != hipSuccess) {
+            delete t;
+            if (e == hipErrorInvalidValue) FAIL(FMM_EINVAL, "non-finite position");
+            if (e == hipErrorOutOfMemory) FAIL(FMM_ENOMEM, "tree construction: out of device memory");
+            FAIL(FMM_EDEVICE, "tree construction: %s", hipGetErrorString(e));
+        }
+    }
     HostTree &h = t->ht;
     const int64_t nc = h.ncells();
     if (method == FMM_METHOD_FMM) {
-        host_dual_traversal(h, theta);
         build_m2l_tiling(h, t->tiling);
     } else {
         h.m2l_ptr.assign(nc + 1, 0);

@@ -57,7 +57,7 @@ struct DevCell {       // 48 bytes, canonical order
     int32_t nchild, pad0, pad1, pad2;
 };
 
-struct HostTree {      // canonical tree built on the host
+struct HostTree {      // canonical tree, host copy
     int64_t n = 0;
     double lo[3] = {0, 0, 0}, W = 1.0, h = 0.0;
     std::vector<uint64_t> key;
@@ -70,9 +70,13 @@ struct HostTree {      // canonical tree built on the host
     int64_t ncells() const { return (int64_t)level.size(); }
 };
 
-// host tree construction (tree_host.cpp)
-int host_build_tree(const double *pos_host, int64_t n, int ncrit, HostTree &t);
-void host_dual_traversal(HostTree &t, double theta);
+// canonical tree and (if lists) the dual-tree interaction lists of n device
+// positions, built on the GPU on stream s and returned in host form
+// (tree_gpu.hip).  hipErrorInvalidValue: a position is not finite;
+// hipErrorOutOfMemory: a list or frontier exceeds 2^31 entries or the device
+// is out of memory.
+hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
+                          HostTree &t);
 
 // M2L tiling (tree_host.cpp)
 struct M2LTiling {

@@ -1,0 +1,747 @@
+// Octree construction and dual-tree interaction lists on the GPU (Pepper &
+// Fangohr, arXiv 2005.12351, Section 3.2): root box, 21-bit quantisation,
+// Morton keys, stable sort, adaptive octree (split while a cell holds more
+// than ncrit particles, depth cap 21), and the dual traversal with the FMM
+// acceptance criterion (Eq. 13), which yields the M2L and P2P lists.
+//
+// Canonical definitions (the same as the test oracle's, shared by
+// specification only): root cube of side W = largest extent at the
+// componentwise minimum; q = floor((x - lo) * 2^21 / W) clamped to 2^21 - 1;
+// key = bit interleave with x most significant in every octal digit; stable
+// sort by key; cells level-major in ascending key order, children in octant
+// order, empty children not created; geometry in units of h = W 2^-22 with
+// centre (2i+1) 2^(21-l) and radius (half side) 2^(21-l); acceptance
+// (rA + rB)^2 < theta^2 d^2 evaluated in FP64 on exact integers; when a pair
+// is neither accepted nor a leaf pair the larger cell is split (both on a
+// tie; a leaf is never split).  Each target's lists are sorted by source.
+//
+// Layout of the work: LSD radix sort with 4-bit digits (stable by
+// construction), one thread per cell and level for the tree, and a
+// breadth-first traversal over a frontier of cell pairs with prefix sums for
+// the output positions, so that every pass is deterministic.  The host only
+// reads back totals (sizes of the next level or frontier).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace {
+
+constexpr int kScanT = 256;           // threads per scan block
+constexpr int kScanI = 4;             // items per thread
+constexpr int kScanTile = kScanT * kScanI;
+constexpr int kRadixBits = 4;
+constexpr int kRadixBins = 1 << kRadixBits;
+
+// ---------------------------------------------------------------- scans
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// exclusive prefix over the threads of a block of NT threads; returns the
+// block total through *tot
+template <int NT>
+__device__ int block_excl_scan(int v, int *sh, int *tot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    int base = 0, all = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+        if (k < w) base += sh[k];
+        all += sh[k];
+    }
+    __syncthreads();
+    *tot = all;
+    return base + inc - v;
+}
+
+// one block of 1024 threads: exclusive scan of up to kSmallScan values,
+// 64-bit total to *total
+constexpr int kSmallT = 1024;
+constexpr int kSmallScan = 1 << 16;
+__global__ __launch_bounds__(kSmallT) void scan_small_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                             int n, int64_t *__restrict__ total)
+{
+    __shared__ int sh[kSmallT / 64];
+    __shared__ long long t64[kSmallT / 64];
+    const int per = (n + kSmallT - 1) / kSmallT;
+    const int b0 = threadIdx.x * per, b1 = min(n, b0 + per);
+    int s = 0;
+    for (int b = b0; b < b1; ++b) s += in[b];
+    int tot;
+    int run = block_excl_scan<kSmallT>(s, sh, &tot);
+    for (int b = b0; b < b1; ++b) {
+        const int v = in[b];
+        out[b] = run;
+        run += v;
+    }
+    // 64-bit total: per-wave sums of the per-thread sums
+    long long w64 = s;
+    for (int o = 32; o > 0; o >>= 1) w64 += __shfl_down(w64, o, 64);
+    if ((threadIdx.x & 63) == 0) t64[threadIdx.x >> 6] = w64;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0;
+        for (int k = 0; k < kSmallT / 64; ++k) a += t64[k];
+        *total = a;
+    }
+}
+
+// per block: exclusive scan of its tile, block total to sums[b]
+__global__ __launch_bounds__(kScanT) void scan_tile_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                           int n, int32_t *__restrict__ sums)
+{
+    __shared__ int sh[kScanT / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+    int v[kScanI], s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j) {
+        v[j] = base + j < n ? in[base + j] : 0;
+        s += v[j];
+    }
+    int tot;
+    int run = block_excl_scan<kScanT>(s, sh, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the block sums in place; grand total (64-bit)
+// to *total
+__global__ __launch_bounds__(kScanT) void scan_sums_kernel(int32_t *__restrict__ sums, int nb, int64_t *__restrict__ total)
+{
+    __shared__ int sh[kScanT / 64];
+    const int per = (nb + kScanT - 1) / kScanT;
+    const int b0 = threadIdx.x * per, b1 = min(nb, b0 + per);
+    int s = 0;
+    long long s64 = 0;
+    for (int b = b0; b < b1; ++b) {
+        s += sums[b];
+        s64 += sums[b];
+    }
+    int tot;
+    int run = block_excl_scan<kScanT>(s, sh, &tot);
+    for (int b = b0; b < b1; ++b) {
+        const int v = sums[b];
+        sums[b] = run;
+        run += v;
+    }
+    // 64-bit total, in case the 32-bit prefix overflowed (checked by the host)
+    __shared__ long long t64[kScanT];
+    t64[threadIdx.x] = s64;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long a = 0;
+        for (int k = 0; k < kScanT; ++k) a += t64[k];
+        *total = a;
+    }
+}
+
+__global__ __launch_bounds__(kScanT) void scan_add_kernel(int32_t *__restrict__ out, int n, const int32_t *__restrict__ sums)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+    const int add = sums[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j)
+        if (base + j < n) out[base + j] += add;
+}
+
+// ---------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kScanT) void radix_count_kernel(const uint64_t *__restrict__ keys, int n, int shift,
+                                                             int nb, int32_t *__restrict__ counts)
+{
+    __shared__ int hist[kRadixBins];
+    if (threadIdx.x < kRadixBins) hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j)
+        if (base + j < n) atomicAdd(&hist[(int)((keys[base + j] >> shift) & (kRadixBins - 1))], 1);
+    __syncthreads();
+    if (threadIdx.x < kRadixBins) counts[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
+}
+
+// stable scatter: an item's place is the digit's global offset for this
+// block, plus the items of that digit in earlier threads of the block, plus
+// the earlier items of that digit in its own thread
+__global__ __launch_bounds__(kScanT) void radix_scatter_kernel(const uint64_t *__restrict__ kin,
+                                                               const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+                                                               int32_t *__restrict__ vout, int n, int shift, int nb,
+                                                               const int32_t *__restrict__ offsets)
+{
+    __shared__ int cnt[kRadixBins][kScanT + 1];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanI;
+    uint64_t k[kScanI];
+    int32_t v[kScanI];
+    int dg[kScanI], rk[kScanI];
+    unsigned long long packed = 0;   // 3-bit count per digit (at most 4 items)
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j) {
+        const bool ok = base + j < n;
+        k[j] = ok ? kin[base + j] : 0;
+        v[j] = ok ? vin[base + j] : 0;
+        dg[j] = ok ? (int)((k[j] >> shift) & (kRadixBins - 1)) : -1;
+        if (ok) {
+            rk[j] = (int)((packed >> (3 * dg[j])) & 7);
+            packed += 1ull << (3 * dg[j]);
+        }
+    }
+    for (int d = 0; d < kRadixBins; ++d) cnt[d][t] = (int)((packed >> (3 * d)) & 7);
+    __syncthreads();
+    // exclusive scan of every digit row over the threads: wave w scans rows
+    // w, w + 4, ...; lane l covers threads 4l .. 4l + 3
+    const int lane = t & 63, w = t >> 6;
+    for (int d = w; d < kRadixBins; d += kScanT / 64) {
+        int a[4], s = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = cnt[d][4 * lane + q];
+            s += a[q];
+        }
+        int run = wave_incl_scan(s) - s;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cnt[d][4 * lane + q] = run;
+            run += a[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanI; ++j) {
+        if (dg[j] < 0) continue;
+        const int64_t pos = (int64_t)offsets[dg[j] * nb + blockIdx.x] + cnt[dg[j]][t] + rk[j];
+        kout[pos] = k[j];
+        vout[pos] = v[j];
+    }
+}
+
+// ---------------------------------------------------------------- keys
+// per block: componentwise min and max, and 1 if any coordinate is not finite
+__global__ void bbox_partial_kernel(const double *__restrict__ pos, int64_t n, double *__restrict__ part)
+{
+    __shared__ double sh[7][256];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double bad = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        for (int d = 0; d < 3; ++d) {
+            const double x = pos[3 * i + d];
+            if (!isfinite(x)) bad = 1.0;
+            lo[d] = fmin(lo[d], x);
+            hi[d] = fmax(hi[d], x);
+        }
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    sh[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + s]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + s]);
+            }
+            sh[6][threadIdx.x] = fmax(sh[6][threadIdx.x], sh[6][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[7 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void bbox_final_kernel(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    if (threadIdx.x >= 7) return;
+    const bool mx = threadIdx.x >= 3;
+    double v = part[threadIdx.x];
+    for (int b = 1; b < nb; ++b) v = mx ? fmax(v, part[7 * b + threadIdx.x]) : fmin(v, part[7 * b + threadIdx.x]);
+    out[threadIdx.x] = v;
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffULL;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+struct KeyGeo {
+    double lo[3];
+    double scale;
+};
+
+__global__ void keys_kernel(const double *__restrict__ pos, int n, KeyGeo g, uint64_t *__restrict__ key,
+                            int32_t *__restrict__ idx)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t qmax = (int64_t(1) << kMaxLevel) - 1;
+    uint64_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        const double v = __dmul_rn(__dsub_rn(pos[3 * (size_t)i + d], g.lo[d]), g.scale);
+        const int64_t qi = (int64_t)floor(v);
+        q[d] = (uint64_t)min(max(qi, (int64_t)0), qmax);
+    }
+    key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    idx[i] = i;
+}
+
+// ---------------------------------------------------------------- tree
+// one thread per cell of the level: the particle runs of the 8 octants by
+// binary search on the sorted keys
+__global__ void tree_split_kernel(const DevCell *__restrict__ cells, int lb, int le, const uint64_t *__restrict__ key,
+                                  int ncrit, int level, int32_t *__restrict__ nch, int2 *__restrict__ runs)
+{
+    const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= le) return;
+    const DevCell cell = cells[c];
+    int cntc = 0;
+    if (cell.count > ncrit && level < kMaxLevel) {
+        const int shift = 3 * (kMaxLevel - level - 1);
+        int a = cell.first;
+        const int e = cell.first + cell.count;
+        for (int dig = 0; dig < 8; ++dig) {
+            // first index in [a, e) whose digit exceeds dig
+            int lo = a, hi = e;
+            while (lo < hi) {
+                const int m = (lo + hi) >> 1;
+                if ((int)((key[m] >> shift) & 7) <= dig) lo = m + 1;
+                else hi = m;
+            }
+            runs[(size_t)(c - lb) * 8 + dig] = make_int2(a, lo - a);
+            cntc += lo > a;
+            a = lo;
+        }
+    }
+    nch[c - lb] = cntc;
+}
+
+__global__ void tree_emit_kernel(DevCell *__restrict__ cells, int lb, int le, const int32_t *__restrict__ nch,
+                                 const int32_t *__restrict__ off, const int2 *__restrict__ runs)
+{
+    const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= le) return;
+    const int k = nch[c - lb];
+    DevCell cell = cells[c];
+    cell.child0 = k ? le + off[c - lb] : -1;
+    cell.nchild = k;
+    cells[c] = cell;
+    int o = cell.child0;
+    for (int dig = 0; dig < 8 && k; ++dig) {
+        const int2 r = runs[(size_t)(c - lb) * 8 + dig];
+        if (r.y == 0) continue;
+        DevCell ch{};
+        ch.level = cell.level + 1;
+        ch.ix = 2 * cell.ix + (dig >> 2);
+        ch.iy = 2 * cell.iy + ((dig >> 1) & 1);
+        ch.iz = 2 * cell.iz + (dig & 1);
+        ch.first = r.x;
+        ch.count = r.y;
+        ch.parent = c;
+        ch.child0 = -1;
+        ch.nchild = 0;
+        cells[o++] = ch;
+    }
+}
+
+// ---------------------------------------------------------------- traversal
+struct PairAct {
+    int m2l, p2p, nkids, mode;   // mode: 0 none, 1 children of A, 2 of B, 3 both
+};
+
+__device__ __forceinline__ PairAct pair_action(const DevCell &a, const DevCell &b, double th2)
+{
+    const int64_t ra = int64_t(1) << (kMaxLevel - a.level), rb = int64_t(1) << (kMaxLevel - b.level);
+    const int64_t dx = (2 * (int64_t)b.ix + 1) * rb - (2 * (int64_t)a.ix + 1) * ra;
+    const int64_t dy = (2 * (int64_t)b.iy + 1) * rb - (2 * (int64_t)a.iy + 1) * ra;
+    const int64_t dz = (2 * (int64_t)b.iz + 1) * rb - (2 * (int64_t)a.iz + 1) * ra;
+    const int64_t d2 = dx * dx + dy * dy + dz * dz;
+    const double s = (double)(ra + rb);
+    const bool leafA = a.nchild == 0, leafB = b.nchild == 0;
+    PairAct r{0, 0, 0, 0};
+    if (__dmul_rn(s, s) < __dmul_rn(th2, (double)d2)) {
+        r.m2l = 1;
+    } else if (leafA && leafB) {
+        r.p2p = 1;
+    } else if (leafB || (!leafA && ra > rb)) {
+        r.mode = 1;
+        r.nkids = a.nchild;
+    } else if (leafA || rb > ra) {
+        r.mode = 2;
+        r.nkids = b.nchild;
+    } else {
+        r.mode = 3;
+        r.nkids = a.nchild * b.nchild;
+    }
+    return r;
+}
+
+__global__ void trav_count_kernel(const int2 *__restrict__ fr, int nf, const DevCell *__restrict__ cells, double th2,
+                                  int32_t *__restrict__ nk, int32_t *__restrict__ m2l, int32_t *__restrict__ p2p)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int2 ab = fr[i];
+    const PairAct r = pair_action(cells[ab.x], cells[ab.y], th2);
+    nk[i] = r.nkids;
+    m2l[i] = r.m2l;
+    p2p[i] = r.p2p;
+}
+
+__global__ void trav_emit_kernel(const int2 *__restrict__ fr, int nf, const DevCell *__restrict__ cells, double th2,
+                                 const int32_t *__restrict__ ok, const int32_t *__restrict__ om,
+                                 const int32_t *__restrict__ op, int kb, int2 *__restrict__ next,
+                                 uint64_t *__restrict__ m2l_key, int64_t m2l_base, uint64_t *__restrict__ p2p_key,
+                                 int64_t p2p_base)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int2 ab = fr[i];
+    const DevCell a = cells[ab.x], b = cells[ab.y];
+    const PairAct r = pair_action(a, b, th2);
+    // list entries keyed (target, source) so that one sort gives the CSR
+    if (r.m2l) m2l_key[m2l_base + om[i]] = ((uint64_t)ab.y << kb) | (uint64_t)ab.x;
+    if (r.p2p) p2p_key[p2p_base + op[i]] = ((uint64_t)ab.y << kb) | (uint64_t)ab.x;
+    int o = ok[i];
+    if (r.mode == 1) {
+        for (int k = 0; k < a.nchild; ++k) next[o++] = make_int2(a.child0 + k, ab.y);
+    } else if (r.mode == 2) {
+        for (int k = 0; k < b.nchild; ++k) next[o++] = make_int2(ab.x, b.child0 + k);
+    } else if (r.mode == 3) {
+        for (int ka = 0; ka < a.nchild; ++ka)
+            for (int kb2 = 0; kb2 < b.nchild; ++kb2) next[o++] = make_int2(a.child0 + ka, b.child0 + kb2);
+    }
+}
+
+__global__ void list_count_kernel(const uint64_t *__restrict__ key, int64_t m, int kb, int32_t *__restrict__ cnt)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    atomicAdd(&cnt[(int)(key[i] >> kb)], 1);
+}
+
+__global__ void list_src_kernel(const uint64_t *__restrict__ key, int64_t m, int kb, int32_t *__restrict__ src)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    src[i] = (int32_t)(key[i] & ((1ull << kb) - 1));
+}
+
+__global__ void zero_i32_kernel(int32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------- host side
+struct Dev {
+    hipStream_t s;
+    std::vector<void *> blocks;
+    hipError_t err = hipSuccess;
+    template <typename T>
+    T *alloc(size_t count)
+    {
+        void *p = nullptr;
+        if (err != hipSuccess) return nullptr;
+        err = hipMallocAsync(&p, std::max<size_t>(count, 1) * sizeof(T), s);
+        if (err != hipSuccess) return nullptr;
+        blocks.push_back(p);
+        return (T *)p;
+    }
+    void release(void *p)
+    {
+        auto it = std::find(blocks.begin(), blocks.end(), p);
+        if (it != blocks.end()) {
+            hipFreeAsync(p, s);
+            blocks.erase(it);
+        }
+    }
+    ~Dev()
+    {
+        for (void *p : blocks) hipFreeAsync(p, s);
+    }
+};
+
+#define GCHK(expr)                              \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return e_;        \
+    } while (0)
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+// exclusive scan of n int32 values into out (in place allowed); the 64-bit
+// total goes to the device word *total.  No host synchronisation.
+hipError_t scan_i32(Dev &dv, const int32_t *in, int32_t *out, int n, int64_t *total)
+{
+    if (n <= kSmallScan) {
+        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kSmallT), 0, dv.s, in, out, n, total);
+        return hipGetLastError();
+    }
+    const int nb = (int)nblk(n, kScanTile);
+    int32_t *sums = dv.alloc<int32_t>(nb);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(scan_tile_kernel, dim3(nb), dim3(kScanT), 0, dv.s, in, out, n, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kScanT), 0, dv.s, sums, nb, total);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(nb), dim3(kScanT), 0, dv.s, out, n, sums);
+    GCHK(hipGetLastError());
+    dv.release(sums);
+    return hipSuccess;
+}
+
+// the first k device totals, read on the host (synchronises the stream)
+hipError_t read_totals(Dev &dv, const int64_t *dev, int k, int64_t *host)
+{
+    GCHK(hipMemcpyAsync(host, dev, sizeof(int64_t) * k, hipMemcpyDeviceToHost, dv.s));
+    return hipStreamSynchronize(dv.s);
+}
+
+// stable LSD sort of (key, val) on the low `bits` bits of the key; the result
+// ends in k/v (the buffers are swapped internally as needed)
+hipError_t radix_sort(Dev &dv, uint64_t *&k, int32_t *&v, int n, int bits)
+{
+    if (n <= 1) return hipSuccess;
+    const int nb = (int)nblk(n, kScanTile);
+    uint64_t *k2 = dv.alloc<uint64_t>(n);
+    int32_t *v2 = dv.alloc<int32_t>(n);
+    int32_t *cnt = dv.alloc<int32_t>((size_t)kRadixBins * nb);
+    int64_t *tot = dv.alloc<int64_t>(1);
+    GCHK(dv.err);
+    for (int shift = 0; shift < bits; shift += kRadixBits) {
+        hipLaunchKernelGGL(radix_count_kernel, dim3(nb), dim3(kScanT), 0, dv.s, k, n, shift, nb, cnt);
+        GCHK(hipGetLastError());
+        GCHK(scan_i32(dv, cnt, cnt, kRadixBins * nb, tot));
+        hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kScanT), 0, dv.s, k, v, k2, v2, n, shift, nb, cnt);
+        GCHK(hipGetLastError());
+        std::swap(k, k2);
+        std::swap(v, v2);
+    }
+    // k2/v2 now hold the stale buffers; they are released with the rest
+    return hipSuccess;
+}
+
+int bits_for(int64_t m)
+{
+    int b = 1;
+    while ((int64_t(1) << b) <= m) ++b;
+    return b;
+}
+
+// CSR (ptr over ncells + 1, src) of the (target << kb | source) keys
+hipError_t keys_to_csr(Dev &dv, uint64_t *key, int64_t m, int kb, int nc, std::vector<int64_t> &ptr,
+                       std::vector<int64_t> &src)
+{
+    ptr.assign(nc + 1, 0);
+    src.assign(m, 0);
+    if (m == 0) return hipSuccess;
+    int32_t *val = dv.alloc<int32_t>(m);
+    int32_t *cnt = dv.alloc<int32_t>(nc);
+    int32_t *s32 = dv.alloc<int32_t>(m);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, val, m);
+    GCHK(radix_sort(dv, key, val, (int)m, 2 * kb));
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(nc, 256)), dim3(256), 0, dv.s, cnt, (int64_t)nc);
+    hipLaunchKernelGGL(list_count_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, cnt);
+    hipLaunchKernelGGL(list_src_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, s32);
+    GCHK(hipGetLastError());
+    std::vector<int32_t> c(nc), s(m);
+    GCHK(hipMemcpyAsync(c.data(), cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, dv.s));
+    GCHK(hipMemcpyAsync(s.data(), s32, sizeof(int32_t) * m, hipMemcpyDeviceToHost, dv.s));
+    GCHK(hipStreamSynchronize(dv.s));
+    for (int i = 0; i < nc; ++i) ptr[i + 1] = ptr[i] + c[i];
+    for (int64_t i = 0; i < m; ++i) src[i] = s[i];
+    return hipSuccess;
+}
+
+}  // namespace
+
+// Builds the canonical tree (and, when theta > 0, the interaction lists) of
+// the n device positions on stream s, and returns it in host form.
+hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
+                          HostTree &t)
+{
+    t = HostTree();
+    t.n = n;
+    Dev dv{s};
+    // root box
+    const int nbb = (int)std::min<int64_t>(1024, nblk(n, 256));
+    double *part = dv.alloc<double>(7 * (size_t)nbb), *bb = dv.alloc<double>(7);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(256), 0, s, pos, n, part);
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, part, nbb, bb);
+    GCHK(hipGetLastError());
+    double box[7];
+    GCHK(hipMemcpyAsync(box, bb, sizeof(box), hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    if (box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
+    double W = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
+    if (W == 0.0) W = 1.0;
+    for (int d = 0; d < 3; ++d) t.lo[d] = box[d];
+    t.W = W;
+    t.h = std::ldexp(W, -22);
+    KeyGeo g{{box[0], box[1], box[2]}, std::ldexp(1.0, kMaxLevel) / W};
+
+    // keys and stable sort
+    uint64_t *key = dv.alloc<uint64_t>(n);
+    int32_t *idx = dv.alloc<int32_t>(n);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(keys_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, pos, (int)n, g, key, idx);
+    GCHK(hipGetLastError());
+    GCHK(radix_sort(dv, key, idx, (int)n, 3 * kMaxLevel));
+
+    int64_t *dtot = dv.alloc<int64_t>(4);
+    GCHK(dv.err);
+    // cells level by level
+    size_t cap = std::max<size_t>(64, (size_t)(4 * n / std::max(1, ncrit) + 64));
+    DevCell *cells = dv.alloc<DevCell>(cap);
+    GCHK(dv.err);
+    DevCell root{};
+    root.level = 0;
+    root.first = 0;
+    root.count = (int32_t)n;
+    root.parent = -1;
+    root.child0 = -1;
+    GCHK(hipMemcpyAsync(cells, &root, sizeof(DevCell), hipMemcpyHostToDevice, s));
+    t.level_ptr.push_back(0);
+    int lb = 0, le = 1;
+    for (int l = 0;; ++l) {
+        t.level_ptr.push_back(le);
+        const int m = le - lb;
+        int32_t *nch = dv.alloc<int32_t>(m), *off = dv.alloc<int32_t>(m);
+        int2 *runs = dv.alloc<int2>((size_t)m * 8);
+        GCHK(dv.err);
+        hipLaunchKernelGGL(tree_split_kernel, dim3(nblk(m, 256)), dim3(256), 0, s, cells, lb, le, key, ncrit, l, nch, runs);
+        GCHK(hipGetLastError());
+        int64_t tot;
+        GCHK(scan_i32(dv, nch, off, m, dtot));
+        GCHK(read_totals(dv, dtot, 1, &tot));
+        if ((size_t)le + (size_t)tot > cap) {
+            const size_t ncap = std::max(2 * cap, (size_t)le + (size_t)tot);
+            DevCell *c2 = dv.alloc<DevCell>(ncap);
+            GCHK(dv.err);
+            GCHK(hipMemcpyAsync(c2, cells, sizeof(DevCell) * le, hipMemcpyDeviceToDevice, s));
+            dv.release(cells);
+            cells = c2;
+            cap = ncap;
+        }
+        hipLaunchKernelGGL(tree_emit_kernel, dim3(nblk(m, 256)), dim3(256), 0, s, cells, lb, le, nch, off, runs);
+        GCHK(hipGetLastError());
+        dv.release(nch);
+        dv.release(off);
+        dv.release(runs);
+        if (tot == 0) break;
+        lb = le;
+        le = le + (int)tot;
+    }
+    const int nc = le;
+
+    // interaction lists: breadth-first over cell pairs
+    if (lists) {
+        const double th2 = theta * theta;
+        const int kb = bits_for(nc);
+        std::vector<uint64_t *> m2l_parts, p2p_parts;
+        std::vector<int64_t> m2l_sz, p2p_sz;
+        int2 *fr = dv.alloc<int2>(1);
+        GCHK(dv.err);
+        const int2 rr = make_int2(0, 0);
+        GCHK(hipMemcpyAsync(fr, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
+        int64_t nf = 1;
+        while (nf > 0) {
+            if (nf > INT32_MAX) return hipErrorOutOfMemory;
+            int32_t *nk = dv.alloc<int32_t>(nf), *fm = dv.alloc<int32_t>(nf), *fp = dv.alloc<int32_t>(nf);
+            GCHK(dv.err);
+            hipLaunchKernelGGL(trav_count_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, fr, (int)nf, cells, th2, nk, fm, fp);
+            GCHK(hipGetLastError());
+            GCHK(scan_i32(dv, nk, nk, (int)nf, dtot));
+            GCHK(scan_i32(dv, fm, fm, (int)nf, dtot + 1));
+            GCHK(scan_i32(dv, fp, fp, (int)nf, dtot + 2));
+            int64_t tt[3];
+            GCHK(read_totals(dv, dtot, 3, tt));
+            const int64_t tk = tt[0], tm = tt[1], tp = tt[2];
+            if (tk > INT32_MAX) return hipErrorOutOfMemory;
+            int2 *next = dv.alloc<int2>(tk);
+            uint64_t *mk = dv.alloc<uint64_t>(tm), *pk = dv.alloc<uint64_t>(tp);
+            GCHK(dv.err);
+            hipLaunchKernelGGL(trav_emit_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, fr, (int)nf, cells, th2, nk, fm, fp,
+                               kb, next, mk, (int64_t)0, pk, (int64_t)0);
+            GCHK(hipGetLastError());
+            dv.release(nk);
+            dv.release(fm);
+            dv.release(fp);
+            dv.release(fr);
+            fr = next;
+            nf = tk;
+            m2l_parts.push_back(mk);
+            m2l_sz.push_back(tm);
+            p2p_parts.push_back(pk);
+            p2p_sz.push_back(tp);
+        }
+        // gather the per-step outputs, then sort by (target, source)
+        auto gather = [&](std::vector<uint64_t *> &parts, std::vector<int64_t> &sz, uint64_t *&all, int64_t &m) -> hipError_t {
+            m = 0;
+            for (int64_t z : sz) m += z;
+            all = dv.alloc<uint64_t>(m);
+            GCHK(dv.err);
+            int64_t o = 0;
+            for (size_t i = 0; i < parts.size(); ++i) {
+                if (sz[i]) GCHK(hipMemcpyAsync(all + o, parts[i], sizeof(uint64_t) * sz[i], hipMemcpyDeviceToDevice, s));
+                o += sz[i];
+                dv.release(parts[i]);
+            }
+            return hipSuccess;
+        };
+        uint64_t *mall, *pall;
+        int64_t mm, pm;
+        GCHK(gather(m2l_parts, m2l_sz, mall, mm));
+        GCHK(gather(p2p_parts, p2p_sz, pall, pm));
+        if (mm > INT32_MAX || pm > INT32_MAX) return hipErrorOutOfMemory;
+        GCHK(keys_to_csr(dv, mall, mm, kb, nc, t.m2l_ptr, t.m2l_src));
+        GCHK(keys_to_csr(dv, pall, pm, kb, nc, t.p2p_ptr, t.p2p_src));
+    }
+
+    // host copies of the order, the keys and the cells
+    std::vector<DevCell> hc(nc);
+    std::vector<int32_t> perm(n);
+    t.key.resize(n);
+    GCHK(hipMemcpyAsync(hc.data(), cells, sizeof(DevCell) * nc, hipMemcpyDeviceToHost, s));
+    GCHK(hipMemcpyAsync(perm.data(), idx, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    GCHK(hipMemcpyAsync(t.key.data(), key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    t.perm.assign(perm.begin(), perm.end());
+    t.level.resize(nc);
+    t.ix.resize(3 * (size_t)nc);
+    t.first.resize(nc);
+    t.count.resize(nc);
+    t.parent.resize(nc);
+    t.child0.resize(nc);
+    t.nchild.resize(nc);
+    for (int c = 0; c < nc; ++c) {
+        const DevCell &d = hc[c];
+        t.level[c] = d.level;
+        t.ix[3 * c] = d.ix;
+        t.ix[3 * c + 1] = d.iy;
+        t.ix[3 * c + 2] = d.iz;
+        t.first[c] = d.first;
+        t.count[c] = d.count;
+        t.parent[c] = d.parent;
+        t.child0[c] = d.child0;
+        t.nchild[c] = d.nchild;
+    }
+    return hipSuccess;
+}

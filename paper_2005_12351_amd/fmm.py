@@ -227,7 +227,7 @@ class Tree:
 
     def upward(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED):
         _dev_f64(moments, None, "moments")
-        self._moments = moments       # the near field reads it during evaluate
+        self._moments = moments       # read by the queued upward work (and baked into its graph)
         _check(fmm_upward(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision)), "fmm_upward")
 
     def evaluate(self, outputs: int = FMM_POT | FMM_FIELD, phi: Optional[torch.Tensor] = None,

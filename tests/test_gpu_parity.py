@@ -58,6 +58,39 @@ def test_tree_bit_exact(orc, ctx, kind, n, ncrit, theta):
         assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
 
 
+def _tree_equal(gt, o):
+    g = gt.export()
+    assert np.array_equal(g["geom"][:3], o.lo) and g["geom"][3] == o.W
+    for k in ("key", "perm", "level", "ix", "first", "count", "parent", "child0", "nchild", "m2l_ptr", "m2l_src",
+              "p2p_ptr", "p2p_src"):
+        a, b = g[k], getattr(o, k)
+        assert a.shape == b.shape, k
+        assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), k
+
+
+@pytest.mark.parametrize("index", [2, 3, 4])
+def test_tree_bit_exact_full_size(orc, ctx, index):
+    """keys, permutation, cells and lists at the full benchmark sizes
+    (100k uniform, 1M Plummer, 2M lattice)"""
+    w = W.config(index)
+    _say(f"[tree full] {w.name} n={w.n} ncrit={w.ncrit} theta={w.theta}")
+    gt = fmm.Tree(ctx, torch.from_numpy(w.pos).cuda(), w.ncrit, w.theta)
+    _tree_equal(gt, orc.Tree(w.pos, w.ncrit, w.theta).dump())
+    gt.close()
+
+
+def test_tree_depth_cap(orc, ctx):
+    """a cluster finer than the 21-bit grid: the cell at level 21 keeps more
+    than ncrit particles"""
+    rng = np.random.default_rng(7)
+    pos = np.concatenate([rng.random((300, 3)), 0.25 + 1e-9 * rng.random((40, 3))])
+    _say("[tree depth cap] n=340 ncrit=4")
+    gt = fmm.Tree(ctx, torch.from_numpy(pos).cuda(), 4, 0.5)
+    assert gt.info()["nlevels"] == 22
+    _tree_equal(gt, orc.Tree(pos, 4, 0.5).dump())
+    gt.close()
+
+
 PARITY = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2, 10, "lattice", 3375, 64, 0.5),
           (1, 6, "plummer", 4000, 32, 0.6), (0, 1, "uniform", 1500, 16, 0.5), (2, 3, "plummer", 2500, 8, 0.4),
           (1, 2, "uniform", 700, 4, 0.3), (0, 10, "plummer", 1200, 8, 0.5)]

@@ -106,6 +106,7 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
     for t in tickets:
         ctx.wait(t)
     times = [ctx.request_times(t) for t in tickets]
+    phases = [ctx.request_phases(t) for t in tickets]
     stats = ctx.serve_stats()
     ctx.close()
     lat = np.array([x["done"] - x["submit"] for x in times])
@@ -116,7 +117,11 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3), "mean_latency_ms": float(lat.mean() * 1e3),
             "throughput_evals_per_s": nsum / span, "peak_running": stats["peak_running"],
             "peak_admitted_bytes": stats["peak_in_use"], "total_particles": nsum,
-            "note": "latency includes the host-side tree build of each request"}
+            "mean_phase_ms": {"queued": float(np.mean([x["admit"] - x["submit"] for x in times]) * 1e3),
+                              "tree_build": float(np.mean([p["built"] - x["admit"] for x, p in zip(times, phases)]) * 1e3),
+                              "upward_evaluate": float(np.mean([p["computed"] - p["built"] for p in phases]) * 1e3),
+                              "release": float(np.mean([x["done"] - p["computed"] for x, p in zip(times, phases)]) * 1e3)},
+            "note": "latency = done - arrival; it includes the tree build of each request"}
 
 
 def main():

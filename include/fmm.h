@@ -186,6 +186,11 @@ int fmm_wait(fmm_ctx *ctx, uint64_t ticket, double timeout_s);
  * bytes[0] estimated footprint used for admission, bytes[1] device bytes the
  * request actually held. */
 int fmm_request_times(fmm_ctx *ctx, uint64_t ticket, double *t, int64_t *bytes);
+/* Worker-side phases of a finished request, seconds since fmm_serve_start:
+ * t[0] tree and lists built, t[1] results on the device (after the stream
+ * synchronisation); the device memory is released between t[1] and done.
+ * Zero for a fake context or a request that has not run. */
+int fmm_request_phases(fmm_ctx *ctx, uint64_t ticket, double *t);
 /* stats[0..6] = budget, bytes admitted now, peak bytes admitted, running
  * requests, peak running, queued requests, slots. */
 int fmm_serve_stats(fmm_ctx *ctx, int64_t *stats);

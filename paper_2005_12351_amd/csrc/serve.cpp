@@ -33,6 +33,7 @@ struct Req {
     int state = FMM_REQ_QUEUED;
     int status = FMM_OK;
     double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_built = 0, t_computed = 0;   // tree and lists ready; results ready
     int64_t bytes_used = 0;
 };
 
@@ -76,14 +77,15 @@ static int run_real(Server *S, fmm_ctx *c, Req &q)
     const fmm_request &r = q.r;
     fmm_tree *t = nullptr;
     int rc = fmm_build_tree(c, r.pos, r.n, r.ncrit, r.theta, r.method, &t);
+    q.t_built = S->now();
     if (rc == FMM_OK) rc = fmm_upward(c, t, r.order, r.moments, r.p, r.precision);
     if (rc == FMM_OK) rc = fmm_evaluate(c, t, r.outputs, r.phi, r.field);
     if (rc == FMM_OK && hipStreamSynchronize(c->stream) != hipSuccess) rc = FMM_EDEVICE;
+    q.t_computed = S->now();
     if (t) {
         q.bytes_used = (int64_t)t->dev_bytes;
         fmm_tree_destroy(t);
     }
-    (void)S;
     return rc;
 }
 
@@ -325,6 +327,28 @@ extern "C" int fmm_request_times(fmm_ctx *ctx, uint64_t ticket, double *t, int64
         bytes[0] = (int64_t)it->second.footprint;
         bytes[1] = it->second.bytes_used;
     }
+    return FMM_OK;
+}
+
+extern "C" int fmm_request_phases(fmm_ctx *ctx, uint64_t ticket, double *t)
+{
+    if (!ctx || !ctx->server) {
+        set_error("server not started");
+        return FMM_ESTATE;
+    }
+    if (!t) {
+        set_error("null output");
+        return FMM_EINVAL;
+    }
+    Server *S = ctx->server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("unknown ticket");
+        return FMM_EINVAL;
+    }
+    t[0] = it->second.t_built;
+    t[1] = it->second.t_computed;
     return FMM_OK;
 }
 

@@ -68,6 +68,7 @@ fmm_submit = _sig("fmm_submit", [_vp, ctypes.POINTER(fmm_request), ctypes.POINTE
 fmm_poll = _sig("fmm_poll", [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)])
 fmm_wait = _sig("fmm_wait", [_vp, ctypes.c_uint64, ctypes.c_double])
 fmm_request_times = _sig("fmm_request_times", [_vp, ctypes.c_uint64, _vp, _vp])
+fmm_request_phases = _sig("fmm_request_phases", [_vp, ctypes.c_uint64, _vp])
 fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
 fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
@@ -75,7 +76,7 @@ fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_dou
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_tree_info",
             "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
-            "fmm_request_times", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
+            "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
 
 class FMMError(RuntimeError):
@@ -152,6 +153,11 @@ class Context:
         b = (ctypes.c_int64 * 2)()
         _check(fmm_request_times(self.h, ticket, ctypes.cast(t, _vp), ctypes.cast(b, _vp)), "fmm_request_times")
         return dict(submit=t[0], admit=t[1], done=t[2], footprint=int(b[0]), bytes_used=int(b[1]))
+
+    def request_phases(self, ticket: int):
+        t = (ctypes.c_double * 2)()
+        _check(fmm_request_phases(self.h, ticket, ctypes.cast(t, _vp)), "fmm_request_phases")
+        return dict(built=t[0], computed=t[1])
 
     def serve_stats(self) -> dict:
         a = (ctypes.c_int64 * 7)()

@@ -164,20 +164,19 @@ def main():
     info = tree.info()
 
     def run(prec, steps, warmup):
-        """the timed region: captured graphs replayed, near and far field
-        overlapped on two streams, no per-kernel events"""
+        """the timed region: each step is fmm_run (upward + evaluate as one
+        captured graph, replayed), near field overlapped with the far field on
+        a second stream, no per-kernel events"""
         phi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
         fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
         ctx.profile(False)
         ctx.set_overlap(True)
         for _ in range(warmup):
-            tree.upward(w.order, mom, w.p, prec)
-            tree.evaluate(outputs, phi, fld)
+            tree.run(w.order, mom, w.p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            tree.upward(w.order, mom, w.p, prec)
-            tree.evaluate(outputs, phi, fld)
+            tree.run(w.order, mom, w.p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return dt / steps, (phi, fld)

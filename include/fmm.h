@@ -108,6 +108,14 @@ int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double 
  * device bytes held. */
 int fmm_tree_info(const fmm_tree *tree, int64_t *info);
 
+/* fmm_upward followed by fmm_evaluate, with the same arguments, results and
+ * errors, queued as one launch sequence (one captured graph when graphs are
+ * on): the near field then overlaps the whole far field and is joined only
+ * before the final L2P.  The tree keeps the upward state afterwards, so
+ * fmm_evaluate may follow. */
+int fmm_run(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int p, int precision,
+            int outputs, double *phi, double *field);
+
 /* Copy the canonical tree to HOST arrays (any pointer may be NULL), sized by
  * fmm_tree_info: geom[4] = lo_x, lo_y, lo_z, W; key[n] Morton keys of the
  * sorted particles; perm[n] input index of sorted particle i; per cell

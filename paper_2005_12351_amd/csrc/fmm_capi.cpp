@@ -507,7 +507,7 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
         if (e_ != hipSuccess) FAIL(FMM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
     } while (0)
 
-extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
+static int check_upward_args(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
 {
     if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
     if (order < 0 || order > 2) FAIL(FMM_EINVAL, "source order %d not in {0,1,2}", order);
@@ -515,52 +515,90 @@ extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *mo
     if (precision != FMM_PREC_FP64 && precision != FMM_PREC_MIXED) FAIL(FMM_EINVAL, "unknown precision %d", precision);
     const int pmin = t->method == FMM_METHOD_FMM ? order + 1 : std::max(order, 1);
     if (p < pmin || p > FMM_P_MAX) FAIL(FMM_EINVAL, "p = %d must lie in [%d, %d]", p, pmin, FMM_P_MAX);
-    HIPCHK(hipSetDevice(ctx->device));
-    t->have_up = 0;
-    int rc = ensure_expansions(t, order, p, precision);
-    if (rc) return rc;
+    return FMM_OK;
+}
+
+static int check_eval_args(fmm_ctx *ctx, fmm_tree *t, int outputs, const double *phi, const double *field)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (outputs <= 0 || (outputs & ~(FMM_POT | FMM_FIELD))) FAIL(FMM_EINVAL, "bad output mask %d", outputs);
+    if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
+    if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
+    return FMM_OK;
+}
+
+// Queues the upward pass on the context stream: sorted moments, P2M, M2M by
+// level, FP32 copy of the multipoles.  For FMM trees the near field (which
+// needs only the sorted moments) is forked onto the auxiliary stream; with
+// join it is joined back at the end, otherwise the caller joins it (ev_near).
+static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
+{
     hipStream_t s = ctx->stream;
-    t->mom_user = moments;
     const bool fmm = t->method == FMM_METHOD_FMM;
     hipStream_t a = ctx->overlap && fmm ? ctx->aux : s;
-    auto body = [&]() -> int {
-        {
-            ProfScope ps(ctx, s, "prep_moments");
-            KCHK(launch_prep_moments(t, s));
-        }
-        // the near field needs only the sorted moments: it runs on the
-        // auxiliary stream beside the latency-bound upward chain
-        if (fmm) {
-            if (a != s) {
-                KCHK(hipEventRecord(ctx->ev_fork, s));
-                KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
-            }
-            {
-                ProfScope ps(ctx, a, "p2p");
-                KCHK(launch_p2p(t, a));
-            }
-            if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
+    {
+        ProfScope ps(ctx, s, "prep_moments");
+        KCHK(launch_prep_moments(t, s));
+    }
+    if (fmm) {
+        if (a != s) {
+            KCHK(hipEventRecord(ctx->ev_fork, s));
+            KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
         }
         {
-            ProfScope ps(ctx, s, "p2m");
-            KCHK(launch_p2m(t, s));
+            ProfScope ps(ctx, a, "p2p");
+            KCHK(launch_p2p(t, a));
         }
-        const int nlev = (int)t->ht.level_ptr.size() - 1;
-        for (int l = nlev - 2; l >= t->m2m_top; --l) {
-            ProfScope ps(ctx, s, "m2m");
-            KCHK(launch_m2m_level(t, l, s));
-        }
-        if (precision == FMM_PREC_MIXED) {
-            ProfScope ps(ctx, s, "m2_fp32");
-            KCHK(launch_to_fp32(t, s));
-        }
-        if (a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+        if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
+    }
+    {
+        ProfScope ps(ctx, s, "p2m");
+        KCHK(launch_p2m(t, s));
+    }
+    const int nlev = (int)t->ht.level_ptr.size() - 1;
+    for (int l = nlev - 2; l >= t->m2m_top; --l) {
+        ProfScope ps(ctx, s, "m2m");
+        KCHK(launch_m2m_level(t, l, s));
+    }
+    if (t->prec == FMM_PREC_MIXED) {
+        ProfScope ps(ctx, s, "m2_fp32");
+        KCHK(launch_to_fp32(t, s));
+    }
+    if (join && a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+    return FMM_OK;
+}
+
+// Queues the far field and the final combination (FMM) or the Barnes-Hut
+// traversal; wait_near: join the near field forked by queue_upward right
+// before the final L2P.
+static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, bool wait_near)
+{
+    hipStream_t s = ctx->stream;
+    if (t->method == FMM_METHOD_BH) {
+        ProfScope ps(ctx, s, "bh");
+        KCHK(launch_bh(t, outputs, phi, field, s));
         return FMM_OK;
-    };
-    const int64_t key[6] = {1, order, p, precision, (int64_t)(uintptr_t)moments, ctx->overlap};
-    rc = run_cached(ctx, t, key, s, body);
-    if (rc) return rc;
-    t->have_up = 1;
+    }
+    const int64_t nc = t->ht.ncells();
+    KCHK(launch_fill(t->d_L64, (size_t)nc * nterms(t->p - t->order), s));
+    {
+        ProfScope ps(ctx, s, "m2l");
+        KCHK(launch_m2l(t, s));
+    }
+    {
+        ProfScope ps(ctx, s, "m2l_combine");
+        KCHK(launch_m2l_combine(t, s));
+    }
+    const int nlev = (int)t->ht.level_ptr.size() - 1;
+    for (int l = std::max(1, t->l2l_from); l < nlev; ++l) {
+        ProfScope ps(ctx, s, "l2l");
+        KCHK(launch_l2l_level(t, l, s));
+    }
+    if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+    {
+        ProfScope ps(ctx, s, "l2p");
+        KCHK(launch_l2p_final(t, outputs, phi, field, s));
+    }
     return FMM_OK;
 }
 
@@ -568,59 +606,71 @@ extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *mo
 // reciprocal square root = 1), potential and field
 static double p2p_flops(int order) { return order == 0 ? 20.0 : (order == 1 ? 32.0 : 58.0); }
 
-extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field)
+// algorithmic work of an evaluation (see fmm_work_counts)
+static void set_work_counts(fmm_tree *t)
 {
-    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
-    if (outputs <= 0 || (outputs & ~(FMM_POT | FMM_FIELD))) FAIL(FMM_EINVAL, "bad output mask %d", outputs);
-    if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
-    if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
-    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
-    HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = ctx->stream;
+    if (t->method != FMM_METHOD_FMM) return;
     const int s_ = t->order, p = t->p;
-    if (t->method == FMM_METHOD_BH) {
-        ProfScope ps(ctx, s, "bh");
-        KCHK(launch_bh(t, outputs, phi, field, s));
-        return FMM_OK;
-    }
     const int64_t nc = t->ht.ncells();
     const int nl = nterms(p - s_);
-    // the near field was summed by fmm_upward
-    auto body = [&]() -> int {
-        KCHK(launch_fill(t->d_L64, (size_t)nc * nl, s));
-        {
-            ProfScope ps(ctx, s, "m2l");
-            KCHK(launch_m2l(t, s));
-        }
-        {
-            ProfScope ps(ctx, s, "m2l_combine");
-            KCHK(launch_m2l_combine(t, s));
-        }
-        const int nlev = (int)t->ht.level_ptr.size() - 1;
-        for (int l = std::max(1, t->l2l_from); l < nlev; ++l) {
-            ProfScope ps(ctx, s, "l2l");
-            KCHK(launch_l2l_level(t, l, s));
-        }
-        {
-            ProfScope ps(ctx, s, "l2p");
-            KCHK(launch_l2p_final(t, outputs, phi, field, s));
-        }
-        return FMM_OK;
-    };
-    const int64_t key[6] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, 0, 0};
-    int rc = run_cached(ctx, t, key, s, body);
-    if (rc) return rc;
-    // algorithmic work of this evaluation
-    const double fc = [&] {
-        double f = 0;
-        for (int k = 0; k <= p - s_; ++k) f += (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
-        return f;
-    }();
+    double fc = 0;
+    for (int k = 0; k <= p - s_; ++k) fc += (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
     const size_t es = t->prec == FMM_PREC_MIXED ? 4 : 8;
     t->work[1] = 2.0 * fc * t->work[0];
     t->work[3] = p2p_flops(s_) * t->work[2];
     t->work[6] = (double)nc * (double)(nterms(p) - nterms(s_ - 1) + nl) * es;
     t->work[7] = (double)t->ht.n * (es * (4 + 8) + 32);
+}
+
+extern "C" int fmm_upward(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
+{
+    int rc = check_upward_args(ctx, t, order, moments, p, precision);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    t->have_up = 0;
+    if ((rc = ensure_expansions(t, order, p, precision))) return rc;
+    t->mom_user = moments;
+    const int64_t key[kGraphKey] = {1, order, p, precision, (int64_t)(uintptr_t)moments, ctx->overlap, 0, 0, 0, 0};
+    rc = run_cached(ctx, t, key, ctx->stream, [&]() { return queue_upward(ctx, t, true); });
+    if (rc) return rc;
+    t->have_up = 1;
+    return FMM_OK;
+}
+
+extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field)
+{
+    int rc = check_eval_args(ctx, t, outputs, phi, field);
+    if (rc) return rc;
+    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (t->method == FMM_METHOD_BH) return queue_evaluate(ctx, t, outputs, phi, field, false);
+    const int64_t key[kGraphKey] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, 0, 0, 0, 0, 0, 0};
+    rc = run_cached(ctx, t, key, ctx->stream, [&]() { return queue_evaluate(ctx, t, outputs, phi, field, false); });
+    if (rc) return rc;
+    set_work_counts(t);
+    return FMM_OK;
+}
+
+extern "C" int fmm_run(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision, int outputs,
+                       double *phi, double *field)
+{
+    int rc = check_upward_args(ctx, t, order, moments, p, precision);
+    if (rc || (rc = check_eval_args(ctx, t, outputs, phi, field))) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    t->have_up = 0;
+    if ((rc = ensure_expansions(t, order, p, precision))) return rc;
+    t->mom_user = moments;
+    // one launch sequence: the near field overlaps the whole far field and is
+    // joined before the final L2P
+    const int64_t key[kGraphKey] = {3, order, p, precision, (int64_t)(uintptr_t)moments, ctx->overlap,
+                                    outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, 0};
+    rc = run_cached(ctx, t, key, ctx->stream, [&]() {
+        const int r = queue_upward(ctx, t, false);
+        return r ? r : queue_evaluate(ctx, t, outputs, phi, field, true);
+    });
+    if (rc) return rc;
+    t->have_up = 1;
+    set_work_counts(t);
     return FMM_OK;
 }
 

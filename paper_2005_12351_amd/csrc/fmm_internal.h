@@ -20,7 +20,8 @@ __host__ __device__ constexpr int mindex(int nx, int ny, int nz)
 
 constexpr int kMaxLevel = 21;        // 21 bits per axis, 63-bit keys
 constexpr int kTileW = 64;           // targets per M2L tile = wavefront width
-constexpr int kPTable = 12;          // multi-index tables cover orders <= 12
+constexpr int kPTable = 12;
+constexpr int kGraphKey = 10;        // arguments a captured launch sequence is keyed by          // multi-index tables cover orders <= 12
 
 struct MultiIndex { int8_t x, y, z, k; };
 
@@ -186,7 +187,7 @@ struct fmm_tree {
     std::vector<void *> allocs;
     // captured launch sequences, keyed by the arguments they bake in
     struct GraphEntry {
-        int64_t key[6];
+        int64_t key[kGraphKey];
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;

@@ -34,7 +34,7 @@ TILE = 64
 # code-shape options (register blocking and scalar-load pipelining); the
 # defaults are the measured best on gfx950, see DEFAULTS
 DEFAULTS = {"acc32": 128, "m32": 48, "acc64": 64, "m64": 24, "dgroup32": 24, "dgroup64": 10, "pipeline": 1,
-            "depth": 1, "scale_branch": 0}
+            "mpre": 0, "scale_branch": 0}
 
 
 def orders(p):
@@ -130,28 +130,34 @@ def gen_kernel(p, s, fp32, opt=None):
             chunks.append(cur)
         L.append("        for (int u = w.y; u < w.z; ++u) {")
         L.append("            const int cls = a.ucls[u];")
-        L.append(f"            const {T} *__restrict__ D = Db + (size_t)cls * {nd};")
-        L.append(f"            const {T} *__restrict__ sc = Sb + (size_t)cls * {scw};")
+        # the class tables are read-only for the whole kernel: reading them
+        # through the constant address space lets the uniform loads go
+        # through the scalar unit into SGPRs (an operand of every FMA)
+        L.append(f"            const {T} __attribute__((address_space(4))) *D = "
+                 f"(const {T} __attribute__((address_space(4))) *)(Db + (size_t)cls * {nd});")
+        L.append(f"            const {T} __attribute__((address_space(4))) *sc = "
+                 f"(const {T} __attribute__((address_space(4))) *)(Sb + (size_t)cls * {scw});")
         L.append(f"            const {T} *__restrict__ Mr = Mb + (size_t)a.usrc[(size_t)u * {TILE} + lane] * {nmp};")
         comps = "xyzw"
-        for ch in chunks:
-            L.append("            {")
-            groups = sorted(set(j // VW for j in ch))
-            for g in groups:
-                L.append(f"                const {V} v{g} = *(const {V} *)(Mr + {g * VW});")
+        SB = '            __builtin_amdgcn_sched_barrier(0);'
+
+        def mload(ch):
+            return [f"            const {V} v{g} = *(const {V} *)(Mr + {g * VW});" for g in sorted(set(j // VW for j in ch))]
+
+        def mscale(ch):
             if opt["scale_branch"]:
                 # rho = r_A / r_B is 1 for pairs of one level: skip the scaling then
-                for j in ch:
-                    L.append(f"                {T} m{j} = v{j // VW}.{comps[j % VW]};")
-                L.append("                if (sc[1] != 1) {")
-                for j in ch:
-                    L.append(f"                    m{j} *= sc[{sum(ms[j])}];")
-                L.append("                }")
-            else:
-                for j in ch:
-                    L.append(f"                const {T} m{j} = v{j // VW}.{comps[j % VW]} * sc[{sum(ms[j])}];")
+                out = [f"            {T} m{j} = v{j // VW}.{comps[j % VW]};" for j in ch]
+                out.append("            if (sc[1] != 1) {")
+                out += [f"                m{j} *= sc[{sum(ms[j])}];" for j in ch]
+                out.append("            }")
+                return out
+            return [f"            const {T} m{j} = v{j // VW}.{comps[j % VW]} * sc[{sum(ms[j])}];" for j in ch]
+
+        def chunk_groups(ch):
             # multiply-adds of this chunk, ordered by derivative index k = n + m
-            # (bands of equal |k| are contiguous in the coefficient order)
+            # (bands of equal |k| are contiguous in the coefficient order),
+            # in groups of at most dgroup distinct k, never spanning two bands
             terms = []
             for i in range(n0, n1):
                 n = ns[i]
@@ -159,10 +165,8 @@ def gen_kernel(p, s, fp32, opt=None):
                     m = ms[j]
                     if sum(n) + sum(m) > p:
                         continue
-                    k = idx((n[0] + m[0], n[1] + m[1], n[2] + m[2]))
-                    terms.append((k, i, j))
+                    terms.append((idx((n[0] + m[0], n[1] + m[1], n[2] + m[2])), i, j))
             terms.sort()
-            # groups of at most dgroup distinct k, never spanning two bands
             groups, cur, curk = [], [], []
             for k, i, j in terms:
                 band = sum(orders(p)[k])
@@ -174,30 +178,64 @@ def gen_kernel(p, s, fp32, opt=None):
                 cur.append((k, i, j))
             if cur:
                 groups.append((curk, cur))
-            D = "d"
-            def loads(gi):
-                ks, _ = groups[gi]
-                return [f"                const {T} {D}{k} = D[{k}];" for k in ks]
-            def fmas(gi):
-                _, ts = groups[gi]
-                return [f"                c{i} = {fma}({D}{k}, m{j}, c{i});" for k, i, j in ts]
-            if opt["pipeline"]:
-                # loads of group g+depth are issued before the multiply-adds of group g
-                dep = opt["depth"]
-                L.append('                __builtin_amdgcn_sched_barrier(0);')
-                for gi in range(min(dep, len(groups))):
-                    L.extend(loads(gi))
-                for gi in range(len(groups)):
-                    L.append('                __builtin_amdgcn_sched_barrier(0);')
-                    if gi + dep < len(groups):
-                        L.extend(loads(gi + dep))
-                    L.extend(fmas(gi))
+            return groups
+
+        def loads(g):
+            return [f"            const {T} d{g[2]}_{k} = D[{k}];" for k in g[0]]
+
+        def fmas(g):
+            return [f"            c{i} = {fma}(d{g[2]}_{k}, m{j}, c{i});" for k, i, j in g[1]]
+
+        mode = opt["pipeline"]
+        mpre = opt["mpre"]
+        if mpre:
+            L.extend(mload(chunks[0]))
+        for ci, ch in enumerate(chunks):
+            if not mpre:
+                L.extend(mload(ch))
+            L.extend(mscale(ch))
+            groups = [(ks, ts, ci) for ks, ts in chunk_groups(ch)]
+            mid = len(groups) // 2
+            nxt = chunks[ci + 1] if ci + 1 < len(chunks) else None
+            if mode == 0:
+                for gi, g in enumerate(groups):
+                    L.append(SB)
+                    L.extend(loads(g))
+                    L.extend(fmas(g))
+                    if mpre and nxt and gi == mid:
+                        L.append(SB)
+                        L.extend(mload(nxt))
+            elif mode == 1:
+                # loads of group g+1 are issued before the multiply-adds of group g
+                L.append(SB)
+                L.extend(loads(groups[0]))
+                for gi, g in enumerate(groups):
+                    L.append(SB)
+                    if gi + 1 < len(groups):
+                        L.extend(loads(groups[gi + 1]))
+                    L.extend(fmas(g))
+                    if mpre and nxt and gi == mid:
+                        L.append(SB)
+                        L.extend(mload(nxt))
             else:
-                for gi in range(len(groups)):
-                    L.append('                __builtin_amdgcn_sched_barrier(0);')
-                    L.extend(loads(gi))
-                    L.extend(fmas(gi))
-            L.append("            }")
+                # loads of group g+1 are issued half way through the
+                # multiply-adds of group g: scalar loads complete out of
+                # order, so the wait before group g+1 covers every scalar
+                # load in flight; this way only group g+1's are
+                L.append(SB)
+                L.extend(loads(groups[0]))
+                for gi, g in enumerate(groups):
+                    f_ = fmas(g)
+                    h = len(f_) // 2
+                    L.append(SB)
+                    L.extend(f_[:h])
+                    L.append(SB)
+                    if gi + 1 < len(groups):
+                        L.extend(loads(groups[gi + 1]))
+                    if mpre and nxt and gi == mid:
+                        L.extend(mload(nxt))
+                    L.append(SB)
+                    L.extend(f_[h:])
         L.append("        }")
         for i in range(n0, n1):
             L.append(f"        out[{i}] = c{i};")

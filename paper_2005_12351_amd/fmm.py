@@ -53,6 +53,7 @@ fmm_build_tree = _sig("fmm_build_tree", [_vp, _vp, _i64, ctypes.c_int, ctypes.c_
                                          ctypes.POINTER(_vp)])
 fmm_upward = _sig("fmm_upward", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int])
 fmm_evaluate = _sig("fmm_evaluate", [_vp, _vp, ctypes.c_int, _vp, _vp])
+fmm_run = _sig("fmm_run", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp])
 fmm_tree_info = _sig("fmm_tree_info", [_vp, _vp])
 fmm_tree_export = _sig("fmm_tree_export", [_vp] + [_vp] * 14)
 fmm_tree_destroy = _sig("fmm_tree_destroy", [_vp])
@@ -73,7 +74,7 @@ fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
 fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
-EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_tree_info",
+EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_run", "fmm_tree_info",
             "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
@@ -245,6 +246,22 @@ class Tree:
             field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
         _check(fmm_evaluate(self.ctx.h, self.h, int(outputs), phi.data_ptr() if phi is not None else None,
                             field.data_ptr() if field is not None else None), "fmm_evaluate")
+        return phi, field
+
+    def run(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED,
+            outputs: int = FMM_POT | FMM_FIELD, phi: Optional[torch.Tensor] = None,
+            field: Optional[torch.Tensor] = None):
+        """upward + evaluate as one launch sequence (fmm_run)"""
+        _dev_f64(moments, None, "moments")
+        self._moments = moments
+        dev = torch.device("cuda", self.ctx.device)
+        if (outputs & FMM_POT) and phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if (outputs & FMM_FIELD) and field is None:
+            field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        _check(fmm_run(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision), int(outputs),
+                       phi.data_ptr() if phi is not None else None, field.data_ptr() if field is not None else None),
+               "fmm_run")
         return phi, field
 
     def work_counts(self):

@@ -179,6 +179,51 @@ def test_graph_replay_matches_eager(ctx, overlap):
         ctx.set_graphs(True)
 
 
+@pytest.mark.parametrize("overlap", [True, False])
+@pytest.mark.parametrize("method", ["fmm", "bh"])
+def test_run_matches_upward_evaluate(ctx, overlap, method):
+    """fmm_run (one launch sequence) gives exactly the result of fmm_upward +
+    fmm_evaluate, eagerly and over several graph replays with eager work and
+    synchronisations in between."""
+    w = W.small_random(4242, 5000, 1, "plummer", p=6, theta=0.5, ncrit=32)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.moments).cuda()
+    m = fmm.FMM_METHOD_FMM if method == "fmm" else fmm.FMM_METHOD_BH
+    ctx.set_overlap(overlap)
+    try:
+        for prec in (fmm.FMM_PREC_MIXED, fmm.FMM_PREC_FP64):
+            _say(f"[run] {method} overlap={overlap} precision={prec}")
+            t = fmm.Tree(ctx, pos, w.ncrit, w.theta, m)
+            ctx.set_graphs(False)
+            t.upward(w.order, mom, w.p, prec)
+            e_phi, e_E = t.evaluate()
+            torch.cuda.synchronize()
+            e_phi, e_E = e_phi.cpu().numpy(), e_E.cpu().numpy()
+            r_phi, r_E = t.run(w.order, mom, w.p, prec)
+            torch.cuda.synchronize()
+            assert np.array_equal(r_phi.cpu().numpy(), e_phi) and np.array_equal(r_E.cpu().numpy(), e_E)
+            ctx.set_graphs(True)
+            phi = torch.empty(w.n, dtype=torch.float64, device="cuda")
+            E = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+            for rep in range(4):
+                phi.fill_(float("nan"))
+                E.fill_(float("nan"))
+                t.run(w.order, mom, w.p, prec, fmm.FMM_POT | fmm.FMM_FIELD, phi, E)
+                torch.cuda.synchronize()
+                junk = (pos * 2.0).sum().item()          # eager work between replays
+                assert np.isfinite(junk)
+                assert np.array_equal(phi.cpu().numpy(), e_phi), rep
+                assert np.array_equal(E.cpu().numpy(), e_E), rep
+            # the upward state stays valid: a plain evaluate reproduces it
+            p2, E2 = t.evaluate()
+            torch.cuda.synchronize()
+            assert np.array_equal(E2.cpu().numpy(), e_E)
+            t.close()
+    finally:
+        ctx.set_overlap(True)
+        ctx.set_graphs(True)
+
+
 def test_error_codes(ctx):
     pos = torch.rand(100, 3, dtype=torch.float64, device="cuda")
     with pytest.raises(fmm.FMMError) as e:

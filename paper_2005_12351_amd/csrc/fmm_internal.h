@@ -111,6 +111,8 @@ struct M2LArgs {
     const void *D, *sc, *M;
     void *part;
     const int32_t *wave_ptr;   // pieces of wave w: work[wave_ptr[w] .. wave_ptr[w+1])
+    int zero;                  // always 0; offsets the table pointer per chunk so
+                               // that the compiler reloads instead of keeping it live
 };
 // generated dispatch (m2l_generated_*.hip)
 typedef hipError_t (*m2l_launch_fn)(const M2LArgs &, int nwaves, hipStream_t);

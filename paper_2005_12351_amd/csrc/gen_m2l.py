@@ -33,8 +33,8 @@ TILE = 64
 
 # code-shape options (register blocking and scalar-load pipelining); the
 # defaults are the measured best on gfx950, see DEFAULTS
-DEFAULTS = {"acc32": 128, "m32": 48, "acc64": 64, "m64": 24, "dgroup32": 24, "dgroup64": 10, "pipeline": 1,
-            "mpre": 0, "scale_branch": 0}
+DEFAULTS = {"acc32": 128, "m32": 64, "acc64": 64, "m64": 32, "dgroup32": 32, "dgroup64": 16, "pipeline": 1,
+            "mpre": 0, "launder": 1, "scale_branch": 0}
 
 
 def orders(p):
@@ -133,7 +133,7 @@ def gen_kernel(p, s, fp32, opt=None):
         # the class tables are read-only for the whole kernel: reading them
         # through the constant address space lets the uniform loads go
         # through the scalar unit into SGPRs (an operand of every FMA)
-        L.append(f"            const {T} __attribute__((address_space(4))) *D = "
+        L.append(f"            const {T} __attribute__((address_space(4))) *const D = "
                  f"(const {T} __attribute__((address_space(4))) *)(Db + (size_t)cls * {nd});")
         L.append(f"            const {T} __attribute__((address_space(4))) *sc = "
                  f"(const {T} __attribute__((address_space(4))) *)(Sb + (size_t)cls * {scw});")
@@ -181,7 +181,8 @@ def gen_kernel(p, s, fp32, opt=None):
             return groups
 
         def loads(g):
-            return [f"            const {T} d{g[2]}_{k} = D[{k}];" for k in g[0]]
+            base = f"D{g[2]}" if opt["launder"] else "D"
+            return [f"            const {T} d{g[2]}_{k} = {base}[{k}];" for k in g[0]]
 
         def fmas(g):
             return [f"            c{i} = {fma}(d{g[2]}_{k}, m{j}, c{i});" for k, i, j in g[1]]
@@ -191,6 +192,12 @@ def gen_kernel(p, s, fp32, opt=None):
         if mpre:
             L.extend(mload(chunks[0]))
         for ci, ch in enumerate(chunks):
+            if opt["launder"]:
+                # a table pointer per chunk that the compiler cannot prove
+                # equal to the previous one: it reloads the derivatives each
+                # chunk needs instead of keeping the whole tensor live in
+                # scalar registers
+                L.append(f"            const {T} __attribute__((address_space(4))) *const D{ci} = D + (size_t)(a.zero * {ci + 1});")
             if not mpre:
                 L.extend(mload(ch))
             L.extend(mscale(ch))

@@ -98,6 +98,7 @@ hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
     a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
     a.part = t->d_part;
     a.wave_ptr = t->d_wave_ptr;
+    a.zero = 0;
     return v.launch(a, wk.nwaves, s);
 }
 

@@ -130,6 +130,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--method", choices=["fmm", "bh"], default="fmm",
+                    help="FMM with dual-tree lists (default) or multipolar Barnes-Hut")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline and error checks")
     ap.add_argument("--n", type=int, default=0, help="shrink the workload (testing only)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream measurement")
@@ -144,6 +146,7 @@ def main():
     import torch
     from paper_2005_12351_amd import fmm, workloads as W
 
+    bh = args.method == "bh"
     w = W.config(args.config, n_override=args.n or None)
     dev = torch.device("cuda", 0)
     pos = torch.from_numpy(w.pos).to(dev)
@@ -159,7 +162,8 @@ def main():
         del a_, b_
 
     t0 = time.perf_counter()
-    tree = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+    tree = fmm.Tree(ctx, pos, w.ncrit, w.theta, fmm.FMM_METHOD_BH if bh else fmm.FMM_METHOD_FMM)
+    torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     info = tree.info()
 
@@ -205,36 +209,55 @@ def main():
         res[name] = dict(step_s=step_s, prof=prof, out=(None if out[0] is None else out[0].cpu().numpy(),
                                                          out[1].cpu().numpy()), work=work)
 
-    m = res["mixed"]
-    prof = m["prof"]
-    kern_ms = {k: v[0] / max(1, v[1]) for k, v in prof.items()}
-    # dominant kernel: M2L (FP32 VALU contraction)
-    m2l_ms = kern_ms.get("m2l", float("nan"))
-    p2p_ms = kern_ms.get("p2p", float("nan"))
-    m2l_flops = m["work"]["m2l_flops"]
-    achieved = m2l_flops / (m2l_ms * 1e-3) if m2l_ms > 0 else None
-    roofline = {"bound": "alu", "kernel": "m2l (FP32)", "achieved": achieved / 1e12 if achieved else None,
-                "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
-                "traffic": _traffic("m2l_c%d_mixed" % args.config),
-                "flops_per_launch": m2l_flops, "avg_launch_ms": m2l_ms,
-                "p2p": {"achieved": m["work"]["p2p_flops"] / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None,
-                        "avg_launch_ms": p2p_ms, "flops_per_launch": m["work"]["p2p_flops"]}}
-    f64 = res["fp64"]
-    f64_m2l = f64["prof"].get("m2l", (float("nan"), 1))
-    f64_m2l_ms = f64_m2l[0] / max(1, f64_m2l[1])
+    def kavg(prof, k):
+        v = prof.get(k)
+        return v[0] / max(1, v[1]) if v else float("nan")
+
+    m, f64 = res["mixed"], res["fp64"]
+    kern_ms = {k: v[0] / max(1, v[1]) for k, v in m["prof"].items()}
+    if bh:
+        # dominant (and only) evaluation kernel: the traversal with M2P and direct sums
+        k_ms = kavg(m["prof"], "bh")
+        flops = m["work"]["m2p_flops"] + m["work"]["p2p_flops"]
+        achieved = flops / (k_ms * 1e-3) if k_ms > 0 else None
+        roofline = {"bound": "alu", "kernel": "bh traversal + M2P + P2P (FP32)",
+                    "achieved": achieved / 1e12 if achieved else None, "peak": PEAK_FP32_VALU / 1e12,
+                    "unit": "TFLOP/s", "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
+                    "traffic": _traffic("bh_c%d_mixed" % args.config), "flops_per_launch": flops,
+                    "avg_launch_ms": k_ms, "m2p_pairs": m["work"]["m2p_pairs"], "p2p_pairs": m["work"]["p2p_pairs"]}
+        f64_ms = kavg(f64["prof"], "bh")
+        f64_flops = f64["work"]["m2p_flops"] + f64["work"]["p2p_flops"]
+        f64_k = {"bh_avg_launch_ms": f64_ms,
+                 "bh_achieved_tflops": f64_flops / (f64_ms * 1e-3) / 1e12 if f64_ms > 0 else None}
+    else:
+        # dominant kernel: M2L (FP32 VALU contraction)
+        m2l_ms, p2p_ms = kavg(m["prof"], "m2l"), kavg(m["prof"], "p2p")
+        m2l_flops = m["work"]["m2l_flops"]
+        achieved = m2l_flops / (m2l_ms * 1e-3) if m2l_ms > 0 else None
+        roofline = {"bound": "alu", "kernel": "m2l (FP32)", "achieved": achieved / 1e12 if achieved else None,
+                    "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                    "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
+                    "traffic": _traffic("m2l_c%d_mixed" % args.config),
+                    "flops_per_launch": m2l_flops, "avg_launch_ms": m2l_ms,
+                    "p2p": {"achieved": m["work"]["p2p_flops"] / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None,
+                            "avg_launch_ms": p2p_ms, "flops_per_launch": m["work"]["p2p_flops"]}}
+        f64_ms = kavg(f64["prof"], "m2l")
+        f64_k = {"m2l_avg_launch_ms": f64_ms,
+                 "m2l_achieved_tflops": f64["work"]["m2l_flops"] / (f64_ms * 1e-3) / 1e12 if f64_ms > 0 else None,
+                 "m2l_frac_fp64_peak": (f64["work"]["m2l_flops"] / (f64_ms * 1e-3) / PEAK_FP64_VALU) if f64_ms > 0 else None}
     value = w.n / m["step_s"]
+    evals = "field" if w.outputs == "field" else "pot+field"
     line = {
-        "metric": "FMM particle evals/sec (pot+field), FP32-bulk (MIXED); FP64 GPU path reported beside it",
+        "metric": "FMM particle evals/sec (%s), FP32-bulk (MIXED); FP64 GPU path reported beside it" % evals
+                  if not bh else "Barnes-Hut particle evals/sec (%s), FP32-bulk (MIXED); FP64 beside it" % evals,
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": m["step_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 (M2L, P2P) + f64 (P2M, M2M, L2L, L2P)", "data": "synthetic",
+        "dtype": "f32 (M2L, P2P) + f64 (P2M, M2M, L2L, L2P)" if not bh else "f32 (M2P, P2P) + f64 (P2M, M2M)",
+        "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
-                   "ncrit": w.ncrit, "outputs": w.outputs, "method": "FMM (dual-tree lists)"},
-        "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3,
-                 "m2l_avg_launch_ms": f64_m2l_ms,
-                 "m2l_achieved_tflops": f64["work"]["m2l_flops"] / (f64_m2l_ms * 1e-3) / 1e12 if f64_m2l_ms > 0 else None,
-                 "m2l_frac_fp64_peak": (f64["work"]["m2l_flops"] / (f64_m2l_ms * 1e-3) / PEAK_FP64_VALU) if f64_m2l_ms > 0 else None},
+                   "ncrit": w.ncrit, "outputs": w.outputs,
+                   "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)"},
+        "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         "kernel_timing": "separate pass of the same steps, kernels serialised, HIP events on the launch stream",
         "kernel_avg_ms_mixed": kern_ms,
         "kernel_avg_ms_fp64": {k: v[0] / max(1, v[1]) for k, v in f64["prof"].items()},
@@ -247,34 +270,38 @@ def main():
         oracle.lib()
         cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         t0 = time.perf_counter()
-        ot = oracle.Tree(w.pos, w.ncrit, w.theta)
+        ot = oracle.Tree(w.pos, w.ncrit, None if bh else w.theta)
         tb = time.perf_counter() - t0
         sample = w.sample if w.sample is not None else np.arange(w.n)
         full = w.n <= 200_000
         t0 = time.perf_counter()
-        if full:
+        if bh:
+            po_s, Eo_s = ot.bh(w.order, w.moments, w.p, w.theta, targets=sample)
+            full = False
+        elif full:
             po, Eo = ot.fmm(w.order, w.moments, w.p)
             po_s, Eo_s = (po[sample] if po is not None else None), Eo[sample]
         else:
             po_s, Eo_s = ot.fmm(w.order, w.moments, w.p, targets=sample)
         tc = time.perf_counter() - t0
         nev = w.n if full else len(sample)
+        kind = "Barnes-Hut" if bh else "FMM"
         line["cpu_baseline"] = {"value": nev / tc, "unit": "evals/s", "cores": cores, "kind": "oracle",
                                 "sample": ("full workload, one upward+evaluate of the plain FP64 C oracle (tree "
                                            "build %.2f s excluded)" % tb) if full else
-                                          ("%d sampled targets of the workload (full upward pass, lists of the "
-                                           "sampled leaves only)" % len(sample)),
+                                          ("%d sampled targets of the workload, plain FP64 C oracle %s (full upward "
+                                           "pass; tree build %.2f s excluded)" % (len(sample), kind, tb)),
                                 "seconds": tc}
         pd, Ed = oracle.direct(w.pos, w.order, w.moments, targets=sample)
         errs = {}
         for name in ("mixed", "fp64"):
             ph, E = res[name]["out"]
-            e = {"E_vs_direct": oracle.rel_l2(E[sample], Ed), "E_vs_oracle_fmm": oracle.rel_l2(E[sample], Eo_s)}
+            e = {"E_vs_direct": oracle.rel_l2(E[sample], Ed), "E_vs_oracle": oracle.rel_l2(E[sample], Eo_s)}
             if ph is not None:
                 e["phi_vs_direct"] = oracle.rel_l2(ph[sample], pd)
-                e["phi_vs_oracle_fmm"] = oracle.rel_l2(ph[sample], po_s)
+                e["phi_vs_oracle"] = oracle.rel_l2(ph[sample], po_s)
             errs[name] = e
-        errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64" % len(sample)
+        errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s" % (len(sample), kind)
         line["rel_l2_error"] = errs
     if not args.no_serve:
         line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests)

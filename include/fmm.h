@@ -157,7 +157,9 @@ int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, int64_t *laun
  * accounting): w[0] = M2L list entries, w[1] = M2L FLOPs (2 per
  * multiply-add of the contraction), w[2] = P2P pairs, w[3] = P2P FLOPs,
  * w[4] = M2P (cell, particle) pairs, w[5] = M2P FLOPs, w[6] = M2L input
- * and output bytes, w[7] = P2P input and output bytes. */
+ * and output bytes, w[7] = P2P input and output bytes.  For Barnes-Hut trees
+ * the traversal kernel counts its accepted cells and direct pairs itself;
+ * reading them synchronises the context stream. */
 int fmm_work_counts(const fmm_tree *tree, double *w);
 
 /* ---------------------------------------------------------------- serving

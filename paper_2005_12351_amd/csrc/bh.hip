@@ -35,6 +35,7 @@ struct BHArgs {
     int n, nmp, outputs;
     double theta2;
     BHGeo g;
+    unsigned long long *counts;   // [0] accepted (particle, cell) pairs, [1] direct pairs
 };
 
 constexpr int kStack = 8 * (kMaxLevel + 3);
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
     sp = 1;
     wave_sync_bh();
     const T *Mb = (const T *)a.M;
+    unsigned int n_m2p = 0, n_p2p = 0;
     while (sp > 0) {
         --sp;
         const int c = stk_c[sp];
@@ -88,6 +90,7 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
         const unsigned long long acc_m = __ballot(accept);
         const unsigned long long rest = mask & ~acc_m;
         if (accept) {
+            ++n_m2p;
             // M2P in the normalised form: u = (x - z)/r, phi = (1/r) sum M~ D(u),
             // E = -(1/r^2) sum M~ D_{+e}(u)
             const double ir = 1.0 / r;
@@ -102,6 +105,7 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
         if (rest) {
             if (cell.nchild == 0) {
                 if ((rest >> lane) & 1ull) {
+                    n_p2p += (unsigned)cell.count - (inside ? 1u : 0u);
                     if (F32) {
                         // sources in units of the leaf radius, FP32 block sum
                         const double ir = 1.0 / r;
@@ -139,6 +143,16 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
             }
         }
     }
+    // interaction counts of the wave, one atomic per wave
+    unsigned long long c0 = n_m2p, c1 = n_p2p;
+    for (int o = 32; o > 0; o >>= 1) {
+        c0 += __shfl_down(c0, o, 64);
+        c1 += __shfl_down(c1, o, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&a.counts[0], c0);
+        atomicAdd(&a.counts[1], c1);
+    }
     if (valid) {
         const size_t o = (size_t)a.perm[i];
         if (a.outputs & FMM_POT) a.phi[o] = ph;
@@ -148,6 +162,13 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
             a.field[3 * o + 2] = ez;
         }
     }
+}
+
+// counters are cleared by a kernel, not a memset, so that the launch
+// sequence can be captured into a graph
+__global__ void zero_u64_kernel(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 typedef void (*bh_fn)(BHArgs);
@@ -191,6 +212,8 @@ hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipSt
     a.theta2 = t->theta * t->theta;
     for (int d = 0; d < 3; ++d) a.g.lo[d] = t->ht.lo[d];
     a.g.h = t->ht.h;
+    a.counts = t->d_bhcount;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, t->d_bhcount, 2);
     hipLaunchKernelGGL(k, dim3((unsigned)((t->ht.n + 63) / 64)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

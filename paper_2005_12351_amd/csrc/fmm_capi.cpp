@@ -458,6 +458,9 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
         (rc = tree_alloc(t, (void **)&t->d_near, sizeof(double) * 4 * n)))
         return rc;
     if (prec == FMM_PREC_MIXED && (rc = tree_alloc(t, (void **)&t->d_M32, sizeof(float) * (nc + 1) * nmp))) return rc;
+    if (t->method == FMM_METHOD_BH && !t->d_bhcount &&
+        (rc = tree_alloc(t, (void **)&t->d_bhcount, 2 * sizeof(unsigned long long))))
+        return rc;
     if (t->method == FMM_METHOD_FMM) {
         M2LVariant v;
         if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, &v)) FAIL(FMM_EINVAL, "no M2L kernel for p=%d s=%d", p, order);
@@ -678,6 +681,20 @@ extern "C" int fmm_work_counts(const fmm_tree *t, double *w)
 {
     if (!t || !w) FAIL(FMM_EINVAL, "null argument");
     for (int k = 0; k < 8; ++k) w[k] = t->work[k];
+    if (t->method == FMM_METHOD_BH && t->d_bhcount && t->have_up) {
+        // counted by the traversal kernel itself (synchronises the stream)
+        unsigned long long c[2] = {0, 0};
+        HIPCHK(hipSetDevice(t->ctx->device));
+        HIPCHK(hipMemcpyAsync(c, t->d_bhcount, sizeof(c), hipMemcpyDeviceToHost, t->ctx->stream));
+        HIPCHK(hipStreamSynchronize(t->ctx->stream));
+        const int p = t->p, s_ = t->order;
+        const double nm = (double)(nterms(p) - nterms(s_ - 1));
+        const double np4 = (double)(p + 4) * (p + 3) * (p + 2) / 6.0;   // C(p+4, 3) derivative terms
+        w[2] = (double)c[1];
+        w[3] = p2p_flops(s_) * w[2];
+        w[4] = (double)c[0];
+        w[5] = (8.0 * nm + 12.0 * np4) * w[4];
+    }
     return FMM_OK;
 }
 

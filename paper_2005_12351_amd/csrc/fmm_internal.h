@@ -172,7 +172,7 @@ struct fmm_tree {
     int32_t *d_wave_ptr = nullptr;
     M2LWork m2lwork;
     double *d_cls_geom = nullptr;
-    int32_t *d_bh_leafgroup = nullptr;
+    unsigned long long *d_bhcount = nullptr;   // Barnes-Hut interaction counters (2)
     // per expansion state
     int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;
     const double *mom_user = nullptr;

@@ -142,11 +142,6 @@ def gen_kernel(p, s, fp32, opt=None):
         SB = '            __builtin_amdgcn_sched_barrier(0);'
 
         def mload(ch):
-            if opt.get("nomload"):
-                # timing probe only: multipoles from registers instead of memory
-                comps_ = [f"({T})(lane + {{g}})", f"({T})(u + {{g}})", f"({T}){{g}}", f"({T})lane"][:VW]
-                return [f"            const {V} v{g} = {V}{{" + ", ".join(c.format(g=g) for c in comps_) + "};"
-                        for g in sorted(set(j // VW for j in ch))]
             return [f"            const {V} v{g} = *(const {V} *)(Mr + {g * VW});" for g in sorted(set(j // VW for j in ch))]
 
         def mscale(ch):

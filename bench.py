@@ -169,12 +169,11 @@ def main():
 
     def run(prec, steps, warmup):
         """the timed region: each step is fmm_run (upward + evaluate as one
-        captured graph, replayed), near field overlapped with the far field on
-        a second stream, no per-kernel events"""
+        captured graph, replayed, on one stream), no per-kernel events"""
         phi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
         fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
         ctx.profile(False)
-        ctx.set_overlap(True)
+        ctx.set_overlap(False)
         for _ in range(warmup):
             tree.run(w.order, mom, w.p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
@@ -199,7 +198,6 @@ def main():
             tree.evaluate(outputs, phi, fld)
         torch.cuda.synchronize()
         ctx.profile(False)
-        ctx.set_overlap(True)
         return ctx.profile_read(), tree.work_counts()
 
     res = {}

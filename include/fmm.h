@@ -133,9 +133,10 @@ int fmm_tree_destroy(fmm_tree *tree);
 /* Text of the last error on the calling thread ("" if none). */
 const char *fmm_last_error(void);
 
-/* Near field (P2P) on a second stream overlapping P2P/M2M (default on).
- * Off: every kernel runs on the context stream, one after the other, so the
- * per-kernel timings below measure each kernel alone. */
+/* Near field (P2P) on a second stream beside the far field (default off: on
+ * MI355X the near field fills the GPU by itself and the overlap measured no
+ * gain).  Off: every kernel runs on the context stream, one after the other,
+ * so the per-kernel timings below measure each kernel alone. */
 int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
 
 /* Replay HIP graphs (default on): the kernel sequence of fmm_upward and of

@@ -387,8 +387,9 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     std::vector<double> leaf_cost(t->nleaves, 0.0);
     for (int64_t k = 0; k < t->nleaves; ++k) {
         const int64_t b = t->leaves[k];
+        // a workgroup's time grows with its pairs
         for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) leaf_cost[k] += (double)h.count[h.p2p_src[e]];
-        leaf_cost[k] *= (double)std::max<int64_t>(1, (h.count[b] + 63) / 64) * 64.0;
+        leaf_cost[k] *= (double)h.count[b];
     }
     std::vector<int32_t> p2p_order(t->nleaves);
     for (int64_t k = 0; k < t->nleaves; ++k) p2p_order[k] = (int32_t)k;

@@ -135,7 +135,7 @@ struct fmm_ctx {
     bool own_stream = false;
     size_t budget = 0;
     bool profile = false;
-    bool overlap = true;                  // P2P on the auxiliary stream
+    bool overlap = false;                 // P2P on the auxiliary stream
     bool graphs = true;                   // replay captured HIP graphs
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)

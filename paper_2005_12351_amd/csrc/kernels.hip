@@ -476,12 +476,16 @@ hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ P2P
-// Direct interaction over the near-field lists (Section 3.2): one workgroup
-// per target leaf, lanes = (target, source slice).  MIXED: offsets from the
-// leaf centres in units of the target leaf radius, FP32 arithmetic, FP32
-// sums per source block added into Kahan-compensated accumulators; the result
-// is scaled back to physical units in FP64.  FP64: physical positions, IEEE
-// division and square root.
+// Direct interaction over the near-field lists (Section 3.2).  One workgroup
+// of 256 threads per target leaf (heaviest leaves first).  The sources of the
+// leaf's list are staged in LDS in chunks, in list order; the threads form a
+// (target, slice) grid with floor(256 / targets) slices, each slice taking a
+// contiguous share of every chunk, so nearly all lanes work for any leaf size.
+// The slices' sums are added per target in a fixed order (deterministic).
+// MIXED: positions relative to the target leaf centre in units of its radius
+// (FP32 stays well scaled for any box), FP32 pair terms summed per chunk and
+// added into Kahan-compensated accumulators, scaled back in FP64.  FP64:
+// physical positions, reciprocal square root refined to full precision.
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 {
     const float y = v - c;
@@ -502,31 +506,87 @@ struct P2PArgs {
     double h;
 };
 
-// Lanes of one wave sharing LDS data written by other lanes of the same wave:
-// a wavefront-scope fence around a wave barrier (no workgroup barrier, so the
-// four waves of a workgroup may run different numbers of source leaves).
-__device__ __forceinline__ void wave_sync()
+constexpr int kPT = 256;        // threads per target leaf
+constexpr int kPList = 256;     // list entries per window
+constexpr int kPChunk32 = 512;  // staged sources per chunk (FP32)
+constexpr int kPChunk64 = 256;  // staged sources per chunk (FP64)
+
+// exclusive prefix over the 256 threads of the block; block total to *tot
+__device__ __forceinline__ int p2p_block_scan(int v, int *sh, int *tot)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    int base = 0, all = 0;
+    for (int k = 0; k < kPT / 64; ++k) {
+        if (k < w) base += sh[k];
+        all += sh[k];
+    }
+    __syncthreads();
+    *tot = all;
+    return base + inc - v;
 }
 
-constexpr int kP2PWaves = 4;
+// Window of up to kPList list entries: start offset of each entry's particles
+// within the window, first particle, source geometry relative to the target
+// leaf (centre difference in units of r_b, and r_A / r_b), and the window
+// offset of the target leaf's own entry (-1 if absent).  Returns the number
+// of staged sources of the window.
+__device__ int p2p_window(const P2PArgs &a, const DevCell &cb, int b, int w0, int nw, int *wstart, int *wfirst,
+                          float4 *wgeo, int *wself, int *sh)
+{
+    const int q = threadIdx.x;
+    int cnt = 0;
+    if (q < nw) {
+        const int A = a.src[w0 + q];
+        const DevCell c = a.cells[A];
+        cnt = c.count;
+        wfirst[q] = c.first;
+        const double rho = ldexp(1.0, cb.level - c.level);
+        wgeo[q] = make_float4((float)((double)(2 * c.ix + 1) * rho - (double)(2 * cb.ix + 1)),
+                              (float)((double)(2 * c.iy + 1) * rho - (double)(2 * cb.iy + 1)),
+                              (float)((double)(2 * c.iz + 1) * rho - (double)(2 * cb.iz + 1)), (float)rho);
+        if (A == b) *wself = -2 - q;   // marks the entry; replaced by its start below
+    }
+    int tot;
+    const int st = p2p_block_scan(cnt, sh, &tot);
+    if (q < nw) wstart[q] = st;
+    __syncthreads();
+    if (q < nw && *wself == -2 - q) *wself = st;
+    __syncthreads();
+    return tot;
+}
 
-// One workgroup per target leaf, kP2PWaves waves; wave w takes the source
-// leaves w, w + kP2PWaves, ... of the list, stages them in its own LDS slots
-// (the next leaf is prefetched into registers while the current one is
-// summed), and the waves' compensated partial sums are added in a fixed order
-// at the end.
+// entry of window source j: the last q with wstart[q] <= j
+__device__ __forceinline__ int p2p_entry(const int *wstart, int nw, int j)
+{
+    int lo = 0, hi = nw - 1;
+    while (lo < hi) {
+        const int m = (lo + hi + 1) >> 1;
+        if (wstart[m] <= j) lo = m;
+        else hi = m - 1;
+    }
+    return lo;
+}
+
 template <int S>
-__global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
+__global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
 {
     constexpr int NV = S == 0 ? 1 : (S == 1 ? 2 : 3);   // float4 per staged source
-    __shared__ float4 st[kP2PWaves][NV][64];
-    __shared__ double red[kP2PWaves][4][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int lk = a.order[blockIdx.x];   // workgroups are dispatched in order: heavy leaves first
+    __shared__ float4 sp[NV][kPChunk32];
+    __shared__ int wstart[kPList], wfirst[kPList];
+    __shared__ float4 wgeo[kPList];
+    __shared__ double red[4][kPT];
+    __shared__ int sh[kPT / 64];
+    __shared__ int wself;
+    const int tid = threadIdx.x;
+    const int lk = a.order[blockIdx.x];
     const int b = a.leaves[lk];
     const DevCell cb = a.cells[b];
     const double rb = ldexp(1.0, kMaxLevel - cb.level) * a.h;
@@ -534,114 +594,72 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
     const int e0 = a.ptr[lk], e1 = a.ptr[lk + 1];
     const float4 *xi4 = reinterpret_cast<const float4 *>(a.xi);
     const float4 *m4 = reinterpret_cast<const float4 *>(a.m32);
-    for (int t0 = 0; t0 < cb.count; t0 += 64) {
-        const int cs = min(64, cb.count - t0);
-        const int slices = 64 / cs;
-        const int ti = lane % cs, sl = lane / cs;
-        const bool active = sl < slices;
-        const int i = cb.first + t0 + ti;
+    for (int tg0 = 0; tg0 < cb.count; tg0 += kPT) {
+        const int cs = min(kPT, cb.count - tg0);
+        const int ns = kPT / cs;                 // slices
+        const int t = tid % cs, sl = tid / cs;
+        const bool act = sl < ns;
+        const int i = cb.first + tg0 + t;
         const float4 eta = xi4[i];
         float ps = 0.f, pc = 0.f, xs_ = 0.f, xc = 0.f, ys = 0.f, yc = 0.f, zs = 0.f, zc = 0.f;
-        // units of work of this wave: (source leaf e, 64-particle chunk s0)
-        int e = e0 + wv, s0 = 0;
-        // source leaf fields: first, count, level, ix, iy, iz
-        int cf = 0, cc = 0, cl = 0, cx = 0, cy = 0, cz = 0;
-        auto load_cell = [&](int ee, int &f, int &n_, int &l, int &x, int &y, int &z) {
-            const DevCell c = a.cells[a.src[ee]];
-            f = c.first; n_ = c.count; l = c.level; x = c.ix; y = c.iy; z = c.iz;
-        };
-        if (e < e1) load_cell(e, cf, cc, cl, cx, cy, cz);
-        // prefetch registers for the current unit
-        float4 pre0 = make_float4(0.f, 0.f, 0.f, 0.f), pre1 = pre0, pre2 = pre0;
-#define P2P_FETCH(first_, count_, base)                      \
-    do {                                                     \
-        const int j_ = (first_) + (base) + lane;             \
-        if ((base) + lane < (count_)) {                      \
-            pre0 = xi4[j_];                                  \
-            if (S >= 1) pre1 = m4[2 * j_];                   \
-            if (S == 2) pre2 = m4[2 * j_ + 1];               \
-            if (S == 0) pre0.w = m4[2 * j_].x;               \
-        }                                                    \
-    } while (0)
-        if (e < e1) P2P_FETCH(cf, cc, 0);
-        while (e < e1) {
-            const int A = a.src[e];
-            const int ns = min(64, cc - s0);
-            const double rho = ldexp(1.0, cb.level - cl);
-            const float frho = (float)rho;
-            // stage the prefetched sources (offsets rescaled to target-leaf units)
-            wave_sync();
-            if (lane < ns) {
-                float4 q = pre0;
-                q.x *= frho;
-                q.y *= frho;
-                q.z *= frho;
-                st[wv][0][lane] = q;
-                if (S >= 1) st[wv][1][lane] = pre1;
-                if (S == 2) st[wv][2][lane] = pre2;
-            }
-            wave_sync();
-            const float dx = (float)((double)(2 * cb.ix + 1) - (double)(2 * cx + 1) * rho);
-            const float dy = (float)((double)(2 * cb.iy + 1) - (double)(2 * cy + 1) * rho);
-            const float dz = (float)((double)(2 * cb.iz + 1) - (double)(2 * cz + 1) * rho);
-            const int s_cur = s0;
-            // advance to the next unit and prefetch it while this one is summed
-            int en = e, sn = s0 + 64;
-            if (sn >= cc) {
-                en = e + kP2PWaves;
-                sn = 0;
-                if (en < e1) load_cell(en, cf, cc, cl, cx, cy, cz);
-            }
-            if (en < e1) P2P_FETCH(cf, cc, sn);
-            if (active) {
-                const float tx = eta.x + dx, ty = eta.y + dy, tz = eta.z + dz;
-                float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-                const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (A == b) {
-                    for (int jj = sl; jj < ns; jj += slices) {
-                        const float4 q = st[wv][0][jj];
-                        const float rx = tx - q.x, ry = ty - q.y, rz = tz - q.z;
-                        const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
-                        const float inv = (s_cur + jj == t0 + ti) ? 0.f : __builtin_amdgcn_rsqf(r2);
-                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : st[wv][S >= 1 ? 1 : 0][jj];
-                        const float4 m1 = S == 2 ? st[wv][2][jj] : zero4;
-                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
-                    }
-                } else {
-                    for (int jj = sl; jj < ns; jj += slices) {
-                        const float4 q = st[wv][0][jj];
-                        const float rx = tx - q.x, ry = ty - q.y, rz = tz - q.z;
-                        const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
-                        const float inv = __builtin_amdgcn_rsqf(r2);
-                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : st[wv][S >= 1 ? 1 : 0][jj];
-                        const float4 m1 = S == 2 ? st[wv][2][jj] : zero4;
-                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
-                    }
+        for (int w0 = e0; w0 < e1; w0 += kPList) {
+            const int nw = min(kPList, e1 - w0);
+            __syncthreads();
+            if (tid == 0) wself = -1;
+            __syncthreads();
+            const int nsw = p2p_window(a, cb, b, w0, nw, wstart, wfirst, wgeo, &wself, sh);
+            for (int c0 = 0; c0 < nsw; c0 += kPChunk32) {
+                const int nc = min(kPChunk32, nsw - c0);
+                __syncthreads();
+                for (int j = tid; j < nc; j += kPT) {
+                    const int q = p2p_entry(wstart, nw, c0 + j);
+                    const int pj = wfirst[q] + (c0 + j - wstart[q]);
+                    const float4 x = xi4[pj];
+                    const float4 g = wgeo[q];
+                    float4 sv = make_float4(__builtin_fmaf(x.x, g.w, g.x), __builtin_fmaf(x.y, g.w, g.y),
+                                            __builtin_fmaf(x.z, g.w, g.z), 0.f);
+                    if (S == 0) sv.w = m4[2 * (size_t)pj].x;
+                    sp[0][j] = sv;
+                    if (S >= 1) sp[S >= 1 ? 1 : 0][j] = m4[2 * (size_t)pj];
+                    if (S == 2) sp[S == 2 ? 2 : 0][j] = m4[2 * (size_t)pj + 1];
                 }
-                kahan_add(ps, pc, bp);
-                kahan_add(xs_, xc, bx);
-                kahan_add(ys, yc, by);
-                kahan_add(zs, zc, bz);
+                __syncthreads();
+                if (act) {
+                    const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
+                    // the target itself, if it is staged in this chunk
+                    const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
+                    float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+                    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int j = ja; j < jb; ++j) {
+                        const float4 q = sp[0][j];
+                        const float rx = eta.x - q.x, ry = eta.y - q.y, rz = eta.z - q.z;
+                        const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
+                        const float inv = j == jself ? 0.f : __builtin_amdgcn_rsqf(r2);
+                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : sp[S >= 1 ? 1 : 0][j];
+                        const float4 m1 = S == 2 ? sp[S == 2 ? 2 : 0][j] : zero4;
+                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
+                    }
+                    kahan_add(ps, pc, bp);
+                    kahan_add(xs_, xc, bx);
+                    kahan_add(ys, yc, by);
+                    kahan_add(zs, zc, bz);
+                }
             }
-            e = en;
-            s0 = sn;
         }
-#undef P2P_FETCH
         __syncthreads();
-        red[wv][0][lane] = (double)ps - (double)pc;
-        red[wv][1][lane] = (double)xs_ - (double)xc;
-        red[wv][2][lane] = (double)ys - (double)yc;
-        red[wv][3][lane] = (double)zs - (double)zc;
+        red[0][tid] = act ? (double)ps - (double)pc : 0.0;
+        red[1][tid] = act ? (double)xs_ - (double)xc : 0.0;
+        red[2][tid] = act ? (double)ys - (double)yc : 0.0;
+        red[3][tid] = act ? (double)zs - (double)zc : 0.0;
         __syncthreads();
-        if (wv == 0 && sl == 0) {
+        if (tid < cs) {
             double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-            for (int w = 0; w < kP2PWaves; ++w)
-                for (int k = 0; k < slices; ++k) {
-                    v0 += red[w][0][lane + k * cs];
-                    v1 += red[w][1][lane + k * cs];
-                    v2 += red[w][2][lane + k * cs];
-                    v3 += red[w][3][lane + k * cs];
-                }
+            for (int k = 0; k < ns; ++k) {
+                v0 += red[0][tid + k * cs];
+                v1 += red[1][tid + k * cs];
+                v2 += red[2][tid + k * cs];
+                v3 += red[3][tid + k * cs];
+            }
             double *o = a.near + 4 * (size_t)i;
             o[0] = v0 * sphi;
             o[1] = v1 * sfld;
@@ -652,64 +670,78 @@ __global__ __launch_bounds__(64 * kP2PWaves) void p2p_f32_kernel(P2PArgs a)
 }
 
 template <int S>
-__global__ __launch_bounds__(64) void p2p_f64_kernel(P2PArgs a)
+__global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
 {
     constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
-    __shared__ double sx[64], sy[64], sz[64], sm[64][W];
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x;
-    {
-    // workgroups are dispatched in order: leaves with the most work first
+    __shared__ double sx[kPChunk64], sy[kPChunk64], sz[kPChunk64], sm[W][kPChunk64];
+    __shared__ int wstart[kPList], wfirst[kPList];
+    __shared__ float4 wgeo[kPList];
+    __shared__ double red[4][kPT];
+    __shared__ int sh[kPT / 64];
+    __shared__ int wself;
+    const int tid = threadIdx.x;
     const int lk = a.order[blockIdx.x];
     const int b = a.leaves[lk];
     const DevCell cb = a.cells[b];
     const size_t n = a.n;
-    for (int t0 = 0; t0 < cb.count; t0 += 64) {
-        const int cs = min(64, cb.count - t0);
-        const int slices = 64 / cs;
-        const int ti = lane % cs, sl = lane / cs;
-        const bool active = sl < slices;
-        const int i = cb.first + t0 + ti;
+    const int e0 = a.ptr[lk], e1 = a.ptr[lk + 1];
+    for (int tg0 = 0; tg0 < cb.count; tg0 += kPT) {
+        const int cs = min(kPT, cb.count - tg0);
+        const int ns = kPT / cs;
+        const int t = tid % cs, sl = tid / cs;
+        const bool act = sl < ns;
+        const int i = cb.first + tg0 + t;
         const double xi = a.xs[i], yi = a.xs[n + i], zi = a.xs[2 * n + i];
         double ph = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (int e = a.ptr[lk]; e < a.ptr[lk + 1]; ++e) {
-            const int A = a.src[e];
-            const DevCell ca = a.cells[A];
-            for (int s0 = 0; s0 < ca.count; s0 += 64) {
-                const int ns = min(64, ca.count - s0);
+        for (int w0 = e0; w0 < e1; w0 += kPList) {
+            const int nw = min(kPList, e1 - w0);
+            __syncthreads();
+            if (tid == 0) wself = -1;
+            __syncthreads();
+            const int nsw = p2p_window(a, cb, b, w0, nw, wstart, wfirst, wgeo, &wself, sh);
+            for (int c0 = 0; c0 < nsw; c0 += kPChunk64) {
+                const int nc = min(kPChunk64, nsw - c0);
                 __syncthreads();
-                if (lane < ns) {
-                    const size_t j = ca.first + s0 + lane;
-                    sx[lane] = a.xs[j];
-                    sy[lane] = a.xs[n + j];
-                    sz[lane] = a.xs[2 * n + j];
-                    for (int q = 0; q < W; ++q) sm[lane][q] = a.m64[j * W + q];
+                for (int j = tid; j < nc; j += kPT) {
+                    const int q = p2p_entry(wstart, nw, c0 + j);
+                    const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
+                    sx[j] = a.xs[pj];
+                    sy[j] = a.xs[n + pj];
+                    sz[j] = a.xs[2 * n + pj];
+#pragma unroll
+                    for (int c = 0; c < W; ++c) sm[c][j] = a.m64[pj * W + c];
                 }
                 __syncthreads();
-                if (!active) continue;
-                for (int jj = sl; jj < ns; jj += slices) {
-                    if (A == b && s0 + jj == t0 + ti) continue;
-                    p2p_pair_f64<S>(xi - sx[jj], yi - sy[jj], zi - sz[jj], sm[jj], ph, ex, ey, ez);
+                if (act) {
+                    const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
+                    const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
+                    for (int j = ja; j < jb; ++j) {
+                        if (j == jself) continue;
+                        const double rx = xi - sx[j], ry = yi - sy[j], rz = zi - sz[j];
+                        double m[W];
+#pragma unroll
+                        for (int c = 0; c < W; ++c) m[c] = sm[c][j];
+                        p2p_pair_f64<S>(rx, ry, rz, m, ph, ex, ey, ez);
+                    }
                 }
             }
         }
         __syncthreads();
-        red[0][lane] = ph;
-        red[1][lane] = ex;
-        red[2][lane] = ey;
-        red[3][lane] = ez;
+        red[0][tid] = act ? ph : 0.0;
+        red[1][tid] = act ? ex : 0.0;
+        red[2][tid] = act ? ey : 0.0;
+        red[3][tid] = act ? ez : 0.0;
         __syncthreads();
-        if (sl == 0) {
-            double v[4] = {red[0][lane], red[1][lane], red[2][lane], red[3][lane]};
-            for (int k = 1; k < slices; ++k)
-                for (int q = 0; q < 4; ++q) v[q] += red[q][lane + k * cs];
+        if (tid < cs) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 0; k < ns; ++k)
+                for (int c = 0; c < 4; ++c) v[c] += red[c][tid + k * cs];
             double *o = a.near + 4 * (size_t)i;
             o[0] = v[0];
             o[1] = v[1];
             o[2] = v[2];
             o[3] = v[3];
         }
-    }
     }
 }
 
@@ -728,15 +760,15 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
     a.n = (int)t->ht.n;
     a.h = t->ht.h;
     a.order = t->d_p2p_order;
-    const dim3 g((unsigned)t->nleaves), b(64), bw(64 * kP2PWaves);
+    const dim3 g((unsigned)t->nleaves), bl(kPT);
     if (t->prec == FMM_PREC_MIXED) {
-        if (t->order == 0) hipLaunchKernelGGL(p2p_f32_kernel<0>, g, bw, 0, s, a);
-        else if (t->order == 1) hipLaunchKernelGGL(p2p_f32_kernel<1>, g, bw, 0, s, a);
-        else hipLaunchKernelGGL(p2p_f32_kernel<2>, g, bw, 0, s, a);
+        if (t->order == 0) hipLaunchKernelGGL(p2p_f32_kernel<0>, g, bl, 0, s, a);
+        else if (t->order == 1) hipLaunchKernelGGL(p2p_f32_kernel<1>, g, bl, 0, s, a);
+        else hipLaunchKernelGGL(p2p_f32_kernel<2>, g, bl, 0, s, a);
     } else {
-        if (t->order == 0) hipLaunchKernelGGL(p2p_f64_kernel<0>, g, b, 0, s, a);
-        else if (t->order == 1) hipLaunchKernelGGL(p2p_f64_kernel<1>, g, b, 0, s, a);
-        else hipLaunchKernelGGL(p2p_f64_kernel<2>, g, b, 0, s, a);
+        if (t->order == 0) hipLaunchKernelGGL(p2p_f64_kernel<0>, g, bl, 0, s, a);
+        else if (t->order == 1) hipLaunchKernelGGL(p2p_f64_kernel<1>, g, bl, 0, s, a);
+        else hipLaunchKernelGGL(p2p_f64_kernel<2>, g, bl, 0, s, a);
     }
     return hipGetLastError();
 }

@@ -46,7 +46,11 @@ __device__ __forceinline__ void p2p_pair_f64(double rx, double ry, double rz, co
                                              double &ey, double &ez)
 {
     const double r2 = rx * rx + ry * ry + rz * rz;
-    const double inv = 1.0 / sqrt(r2);
+    // hardware reciprocal square root estimate, two Newton steps
+    double inv = __builtin_amdgcn_rsq(r2);
+    const double hr = 0.5 * r2;
+    inv = inv * __builtin_fma(-hr * inv, inv, 1.5);
+    inv = inv * __builtin_fma(-hr * inv, inv, 1.5);
     const double inv2 = inv * inv;
     const double inv3 = inv * inv2;
     if (S == 0) {

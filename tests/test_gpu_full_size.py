@@ -1,6 +1,5 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
-benchmark times (captured graphs replayed, near field on the second
-stream): 100k uniform dipoles (p 8), 1M Plummer dipoles (p 6, field only,
+benchmark times (fmm_run, one captured graph per step, replayed): 100k uniform dipoles (p 8), 1M Plummer dipoles (p 6, field only,
 FMM and Barnes-Hut) and 2M lattice quadrupoles (p 10).  The oracle cannot
 evaluate every particle at these sizes, so it runs its full upward pass and
 evaluates 4 096 seeded sample targets one by one (Section 3.2 lists of the
@@ -27,7 +26,7 @@ PREC = {"fp64": fmm.FMM_PREC_FP64, "mixed": fmm.FMM_PREC_MIXED}
 def ctx():
     c = fmm.Context(0)
     c.set_graphs(True)
-    c.set_overlap(True)
+    c.set_overlap(False)
     yield c
     c.close()
 
@@ -52,9 +51,8 @@ def _run(ctx, w, prec, method):
     mom = to_dev(w.moments)
     phi = torch.empty(w.n, dtype=torch.float64, device="cuda") if outputs & fmm.FMM_POT else None
     fld = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
-    for _ in range(3):      # first call captures the graphs, the others replay them
-        t.upward(w.order, mom, w.p, PREC[prec])
-        t.evaluate(outputs, phi, fld)
+    for _ in range(3):      # first call captures the graph, the others replay it
+        t.run(w.order, mom, w.p, PREC[prec], outputs, phi, fld)
     torch.cuda.synchronize()
     s = torch.from_numpy(w.sample).cuda()
     out = (None if phi is None else phi[s].cpu().numpy(), fld[s].cpu().numpy())

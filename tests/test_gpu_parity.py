@@ -175,7 +175,7 @@ def test_graph_replay_matches_eager(ctx, overlap):
                 assert np.array_equal(E.cpu().numpy(), e_E), rep
             t.close()
     finally:
-        ctx.set_overlap(True)
+        ctx.set_overlap(False)
         ctx.set_graphs(True)
 
 
@@ -220,7 +220,7 @@ def test_run_matches_upward_evaluate(ctx, overlap, method):
             assert np.array_equal(E2.cpu().numpy(), e_E)
             t.close()
     finally:
-        ctx.set_overlap(True)
+        ctx.set_overlap(False)
         ctx.set_graphs(True)
 
 

@@ -416,7 +416,10 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         const M2LTiling &tl = t->tiling;
         UP(t->d_ucls, tl.ucls);
         UP(t->d_usrc, tl.usrc);
-        UP(t->d_tile_cell, tl.tile_cell);
+        std::vector<int32_t> cell_slot(nc, -1);
+        for (size_t k = 0; k < tl.tile_cell.size(); ++k)
+            if (tl.tile_cell[k] >= 0) cell_slot[tl.tile_cell[k]] = (int32_t)k;
+        UP(t->d_cell_slot, cell_slot);
         UP(t->d_cls_geom, tl.cls_geom);
         t->work[0] = (double)tl.pairs;
     }
@@ -490,6 +493,29 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
             (rc = tree_alloc(t, (void **)&t->d_sc64, sizeof(double) * nc_ * scw)) ||
             (rc = tree_alloc(t, (void **)&t->d_sc32, sizeof(float) * nc_ * scw)))
             return rc;
+    }
+    if (t->method == FMM_METHOD_FMM && t->l2p_pack_q != p - order) {
+        // L2P waves: consecutive leaves while they hold at most 64 particles
+        // together (a larger leaf gets a wave of its own)
+        const int kmax = l2p_pack_limit(p - order);
+        std::vector<int32_t> pack(1, 0);
+        int64_t cnt = 0;
+        for (int64_t k = 0; k < t->nleaves; ++k) {
+            const int64_t c = t->ht.count[t->leaves[k]];
+            const int in_pack = (int)(k - pack.back());
+            if (in_pack > 0 && (cnt + c > 64 || in_pack >= kmax)) {
+                pack.push_back((int32_t)k);
+                cnt = 0;
+            }
+            cnt += c;
+        }
+        pack.push_back((int32_t)t->nleaves);
+        if (t->d_l2p_pack) tree_free_block(t, t->d_l2p_pack);
+        t->d_l2p_pack = nullptr;
+        if ((rc = upload(t, &t->d_l2p_pack, pack, t->ctx->stream))) return rc;
+        HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the host vector dies here
+        t->l2p_npacks = (int)pack.size() - 1;
+        t->l2p_pack_q = p - order;
     }
     hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
     if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
@@ -583,8 +609,6 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         KCHK(launch_bh(t, outputs, phi, field, s));
         return FMM_OK;
     }
-    const int64_t nc = t->ht.ncells();
-    KCHK(launch_fill(t->d_L64, (size_t)nc * nterms(t->p - t->order), s));
     {
         ProfScope ps(ctx, s, "m2l");
         KCHK(launch_m2l(t, s));

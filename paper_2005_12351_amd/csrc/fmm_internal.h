@@ -166,9 +166,11 @@ struct fmm_tree {
     float *d_xi = nullptr;                 // FP32 offsets from own leaf centre / leaf radius, 4 per particle
     int32_t *d_p2p_ptr = nullptr, *d_p2p_src = nullptr;   // per leaf, sources as cell ids
     int4 *d_work = nullptr;                // per expansion configuration
-    int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_tile_cell = nullptr;
+    int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_cell_slot = nullptr;   // cell -> tile slot or -1
     int32_t *d_tile_chunk0 = nullptr, *d_tile_nchunk = nullptr;
     int32_t *d_p2p_order = nullptr;        // leaf ordinals by decreasing near-field cost
+    int32_t *d_l2p_pack = nullptr;         // L2P: leaf-ordinal range of every wave
+    int l2p_npacks = 0, l2p_pack_q = -1;
     int32_t *d_wave_ptr = nullptr;
     M2LWork m2lwork;
     double *d_cls_geom = nullptr;
@@ -222,6 +224,7 @@ hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s);
 hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
 hipError_t launch_p2p(fmm_tree *t, hipStream_t s);
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
+int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
 
 // serving (serve.cpp)

@@ -776,38 +776,67 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
 // ------------------------------------------------------------------ L2P
 // phi = (1/r) sum_{|n|<=q} eta^n/n! L~_n, E_d = -(1/r^2) sum eta^n/n! L~_{n+e_d}
 // (Eq. 9, Eq. 10 with |k| = 1), eta = (x - z)/r, plus the near field, written
-// to the caller's particle order.  The leaf's L~ is unpacked into a dense
-// zero-padded cube in LDS, so that for fixed (n_x, n_y) the four sums over
-// n_z are unit-stride and their addresses are compile-time offsets from one
-// base; the outer loops run with uniform counters (LDS broadcasts, scalar
-// branches).  Compiled per q = p - s.
+// to the caller's particle order.  One wave per pack of consecutive leaves
+// holding at most 64 particles together (the host packs them, so that most
+// lanes work although leaves hold ~ncrit/3 particles on average).  Each
+// leaf's L~ is unpacked into a dense zero-padded cube in LDS, so that for
+// fixed (n_x, n_y) the four sums over n_z are unit-stride from one base; the
+// loop structure is the same for every lane.  Compiled per q = p - s.
+constexpr int kL2PMaxLeaves = 8;
+constexpr int kL2PLds = 16384;   // bytes of cubes per wave
+
+__host__ __device__ constexpr int l2p_cube(int q) { return (q + 2) * (q + 2) * (q + 2); }
+int l2p_pack_limit(int q) { return std::max(1, std::min(kL2PMaxLeaves, kL2PLds / (int)(8 * l2p_cube(q)))); }
+
 template <int Q>
-__global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ leaves,
-                                                 const DevCell *__restrict__ cells, Geo g, const double *__restrict__ xs,
-                                                 int n, const double *__restrict__ L, const double *__restrict__ near,
+__global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ pack,
+                                                 const int32_t *__restrict__ leaves, const DevCell *__restrict__ cells,
+                                                 Geo g, const double *__restrict__ xs, int n,
+                                                 const double *__restrict__ L, const double *__restrict__ near,
                                                  const int32_t *__restrict__ perm, double *__restrict__ phi,
                                                  double *__restrict__ field)
 {
     constexpr int NL = nterms(Q);
     constexpr int E = Q + 2;                     // edge: room for n + e_d
     constexpr int NC = E * E * E;
-    __shared__ double cube[NC];
-    const int c = leaves[blockIdx.x];
-    const DevCell cell = cells[c];
-    for (int i = threadIdx.x; i < NC; i += blockDim.x) cube[i] = 0.0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < NL; i += blockDim.x) {
-        const MultiIndex nn = k_mi.v[i];
-        cube[(nn.x * E + nn.y) * E + nn.z] = L[(size_t)c * NL + i];
+    extern __shared__ double cubes[];            // one cube per leaf of the pack
+    __shared__ int lfirst[kL2PMaxLeaves], lstart[kL2PMaxLeaves + 1];
+    __shared__ double lgeo[kL2PMaxLeaves][4];    // centre, 1 / radius
+    const int p0 = pack[blockIdx.x], nlv = pack[blockIdx.x + 1] - p0;
+    for (int i = threadIdx.x; i < nlv * NC; i += blockDim.x) cubes[i] = 0.0;
+    if ((int)threadIdx.x < nlv) {
+        const DevCell c = cells[leaves[p0 + threadIdx.x]];
+        double z[3];
+        cell_center(c, g.lo, g.h, z);
+        lfirst[threadIdx.x] = c.first;
+        lstart[threadIdx.x + 1] = c.count;
+        lgeo[threadIdx.x][0] = z[0];
+        lgeo[threadIdx.x][1] = z[1];
+        lgeo[threadIdx.x][2] = z[2];
+        lgeo[threadIdx.x][3] = 1.0 / cell_radius(c.level, g.h);
     }
     __syncthreads();
-    double z[3];
-    cell_center(cell, g.lo, g.h, z);
-    const double r = cell_radius(cell.level, g.h);
-    const double ir = 1.0 / r;
-    for (int k = threadIdx.x; k < cell.count; k += blockDim.x) {
-        const int i = cell.first + k;
-        const double ex = (xs[i] - z[0]) * ir, ey = (xs[n + i] - z[1]) * ir, ez = (xs[2 * (size_t)n + i] - z[2]) * ir;
+    if (threadIdx.x == 0) {
+        lstart[0] = 0;
+        for (int q = 0; q < nlv; ++q) lstart[q + 1] += lstart[q];
+    }
+    for (int q = 0; q < nlv; ++q) {
+        const size_t c = (size_t)leaves[p0 + q];
+        for (int i = threadIdx.x; i < NL; i += blockDim.x) {
+            const MultiIndex nn = k_mi.v[i];
+            cubes[q * NC + (nn.x * E + nn.y) * E + nn.z] = L[c * NL + i];
+        }
+    }
+    __syncthreads();
+    const int tot = lstart[nlv];
+    for (int k = threadIdx.x; k < tot; k += blockDim.x) {
+        int q = 0;
+        while (q + 1 < nlv && k >= lstart[q + 1]) ++q;
+        const int i = lfirst[q] + (k - lstart[q]);
+        const double *cube = cubes + q * NC;
+        const double ir = lgeo[q][3];
+        const double ex = (xs[i] - lgeo[q][0]) * ir, ey = (xs[n + i] - lgeo[q][1]) * ir,
+                     ez = (xs[2 * (size_t)n + i] - lgeo[q][2]) * ir;
         double pz[Q + 1];
         pz[0] = 1.0;
 #pragma unroll
@@ -856,8 +885,9 @@ template <int Q>
 static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
-    hipLaunchKernelGGL(l2p_kernel<Q>, dim3((unsigned)t->nleaves), dim3(64), 0, s, outputs, t->d_leaves, t->d_cells, g,
-                       t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm, phi, field);
+    const size_t lds = (size_t)l2p_pack_limit(Q) * l2p_cube(Q) * sizeof(double);
+    hipLaunchKernelGGL(l2p_kernel<Q>, dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs, t->d_l2p_pack,
+                       t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm, phi, field);
 }
 
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)

@@ -102,52 +102,64 @@ hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
     return v.launch(a, wk.nwaves, s);
 }
 
-// sum of the chunk partials of every target slot into L~ (FP64); each output
-// block of a tile has its own chunks
+// L~ of every cell (FP64): the sum, in chunk order, of the partial rows of the
+// cell's tile slot (each output block of a tile has its own chunks), or zero
+// for a cell without M2L sources; so the locals need no separate clearing.
+// The loads of eight chunks are issued before their fixed-order sum.
 struct BlockBounds {
     int lo[17];
     int nb;
 };
 
 template <typename T>
-__global__ void m2l_combine_kernel(int nslots, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ tile_cell,
+__global__ void m2l_combine_kernel(int ncells, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ cell_slot,
                                    const int32_t *__restrict__ chunk0, const int32_t *__restrict__ nchunk,
                                    const T *__restrict__ part, double *__restrict__ L)
 {
     const size_t id = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (id >= (size_t)nslots * nl) return;
-    const int slot = (int)(id / nl), n = (int)(id % nl);
-    const int cell = tile_cell[slot];
-    if (cell < 0) return;
-    const int tile = slot / kTileW, lane = slot % kTileW;
-    int b = 0;
-    while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
+    if (id >= (size_t)ncells * nl) return;
+    const int cell = (int)(id / nl), n = (int)(id % nl);
+    const int slot = cell_slot[cell];
     double acc = 0.0;
-    const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
-    for (int k = 0; k < nc; ++k) acc += (double)part[((size_t)(c0 + k) * kTileW + lane) * nlp + n];
+    if (slot >= 0) {
+        const int tile = slot / kTileW, lane = slot % kTileW;
+        int b = 0;
+        while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
+        const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
+        const T *p = part + ((size_t)c0 * kTileW + lane) * nlp + n;
+        const size_t stride = (size_t)kTileW * nlp;
+        int k = 0;
+        for (; k + 8 <= nc; k += 8) {
+            T v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = p[(size_t)(k + q) * stride];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += (double)v[q];
+        }
+        for (; k < nc; ++k) acc += (double)p[(size_t)k * stride];
+    }
     L[(size_t)cell * nl + n] = acc;
 }
 
 hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
 {
     const M2LTiling &tl = t->tiling;
-    if (tl.ntiles == 0) return hipSuccess;
+    const int nl = nterms(t->p - t->order);
+    const int64_t nc = t->ht.ncells();
+    const size_t tot = (size_t)nc * nl;
+    const unsigned g = (unsigned)((tot + 255) / 256);
     const bool f32 = t->prec == FMM_PREC_MIXED;
     M2LVariant v;
-    m2l_lookup(t->p, t->order, f32, &v);
+    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
     BlockBounds bb;
     for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
     bb.nb = v.nblocks;
-    const int nl = nterms(t->p - t->order);
-    const int nslots = tl.ntiles * kTileW;
-    const size_t tot = (size_t)nslots * nl;
-    const unsigned g = (unsigned)((tot + 255) / 256);
+    (void)tl;
     if (f32)
-        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
-                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
+        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, (int)nc, nl, v.nl_pad, bb,
+                           t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
     else
-        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, nslots, nl, v.nl_pad, bb,
-                           t->d_tile_cell, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
+        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, (int)nc, nl, v.nl_pad, bb,
+                           t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
     return hipGetLastError();
 }
-

@@ -201,7 +201,10 @@ class Tree:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_tree_free(h)
+            try:
+                lib().orc_tree_free(h)
+            except TypeError:       # interpreter shutdown: module globals already cleared
+                pass
             self._h = None
 
     def lists(self, theta: float):

@@ -331,7 +331,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         h.p2p_ptr.assign(nc + 1, 0);
     }
     // leaves, per-particle leaf, non-leaf cells per level, P2P CSR per leaf
-    std::vector<int32_t> leaf_of(n), level_cells(nc);
+    std::vector<int32_t> level_cells(nc);
     std::vector<DevCell> cells(nc);
     for (int64_t c = 0; c < nc; ++c) {
         DevCell d{};
@@ -348,7 +348,6 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         level_cells[c] = (int32_t)c;
         if (h.nchild[c] == 0) {
             t->leaves.push_back((int32_t)c);
-            for (int64_t i = h.first[c]; i < h.first[c] + h.count[c]; ++i) leaf_of[i] = (int32_t)c;
         }
     }
     t->nleaves = (int64_t)t->leaves.size();
@@ -405,7 +404,6 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     }
     UP(t->d_cells, cells);
     UP(t->d_perm, perm32);
-    UP(t->d_leaf_of, leaf_of);
     UP(t->d_leaves, t->leaves);
     UP(t->d_nonleaf, t->level_nonleaf);
     UP(t->d_level_cells, level_cells);
@@ -424,8 +422,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         t->work[0] = (double)tl.pairs;
     }
 #undef UP
-    if ((rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n)) ||
-        (rc = tree_alloc(t, (void **)&t->d_xi, sizeof(float) * 4 * n))) {
+    if ((rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n))) {
         fmm_tree_destroy(t);
         return rc;
     }

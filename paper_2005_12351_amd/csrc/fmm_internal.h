@@ -160,10 +160,9 @@ struct fmm_tree {
     M2LTiling tiling;
     // device copies
     DevCell *d_cells = nullptr;
-    int32_t *d_perm = nullptr, *d_leaf_of = nullptr, *d_leaves = nullptr;
+    int32_t *d_perm = nullptr, *d_leaves = nullptr;
     int32_t *d_nonleaf = nullptr, *d_level_cells = nullptr;
     double *d_x = nullptr;                 // sorted positions, SoA x[n] y[n] z[n]
-    float *d_xi = nullptr;                 // FP32 offsets from own leaf centre / leaf radius, 4 per particle
     int32_t *d_p2p_ptr = nullptr, *d_p2p_src = nullptr;   // per leaf, sources as cell ids
     int4 *d_work = nullptr;                // per expansion configuration
     int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_cell_slot = nullptr;   // cell -> tile slot or -1

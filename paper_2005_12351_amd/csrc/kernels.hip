@@ -66,37 +66,22 @@ hipError_t launch_fill(double *p, size_t count, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ particles
-// sorted SoA positions and per-particle FP32 offsets from the own leaf centre
-// in units of the leaf radius
+// sorted SoA positions
 __global__ void prep_particles_kernel(int n, const double *__restrict__ pos, const int32_t *__restrict__ perm,
-                                      const int32_t *__restrict__ leaf_of, const DevCell *__restrict__ cells, Geo g,
-                                      double *__restrict__ xs, float *__restrict__ xi)
+                                      double *__restrict__ xs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int j = perm[i];
-    const double x = pos[3 * (size_t)j], y = pos[3 * (size_t)j + 1], z = pos[3 * (size_t)j + 2];
-    xs[i] = x;
-    xs[n + i] = y;
-    xs[2 * (size_t)n + i] = z;
-    const DevCell c = cells[leaf_of[i]];
-    double zc[3];
-    cell_center(c, g.lo, g.h, zc);
-    const double ir = 1.0 / cell_radius(c.level, g.h);
-    float4 v;
-    v.x = (float)((x - zc[0]) * ir);
-    v.y = (float)((y - zc[1]) * ir);
-    v.z = (float)((z - zc[2]) * ir);
-    v.w = 0.f;
-    reinterpret_cast<float4 *>(xi)[i] = v;
+    xs[i] = pos[3 * (size_t)j];
+    xs[n + i] = pos[3 * (size_t)j + 1];
+    xs[2 * (size_t)n + i] = pos[3 * (size_t)j + 2];
 }
 
 hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s)
 {
     const int n = (int)t->ht.n;
-    Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
-    hipLaunchKernelGGL(prep_particles_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, t->d_perm,
-                       t->d_leaf_of, t->d_cells, g, t->d_x, t->d_xi);
+    hipLaunchKernelGGL(prep_particles_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, pos, t->d_perm, t->d_x);
     return hipGetLastError();
 }
 
@@ -497,13 +482,12 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v)
 struct P2PArgs {
     const int32_t *leaves, *ptr, *src, *order;
     const DevCell *cells;
-    const float *xi;        // 4 per particle
     const float *m32;       // 8 per particle
     const double *xs;       // SoA
     const double *m64;
     double *near;           // 4 per particle
     int n;
-    double h;
+    double h, lo[3];
 };
 
 constexpr int kPT = 256;        // threads per target leaf
@@ -578,8 +562,9 @@ __device__ __forceinline__ int p2p_entry(const int *wstart, int nw, int j)
 template <int S>
 __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
 {
-    constexpr int NV = S == 0 ? 1 : (S == 1 ? 2 : 3);   // float4 per staged source
-    __shared__ float4 sp[NV][kPChunk32];
+    constexpr int NV = S == 2 ? 2 : 1;   // float4 of moments per staged source
+    __shared__ double spx[kPChunk32], spy[kPChunk32], spz[kPChunk32];
+    __shared__ float4 spm[NV][kPChunk32];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
     __shared__ double red[4][kPT];
@@ -590,9 +575,17 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
     const int b = a.leaves[lk];
     const DevCell cb = a.cells[b];
     const double rb = ldexp(1.0, kMaxLevel - cb.level) * a.h;
+    const double irb = 1.0 / rb;
     const double sphi = 1.0 / pow(rb, (double)(S + 1)), sfld = sphi / rb;
+    double zb[3];
+    {
+        const double r = ldexp(1.0, kMaxLevel - cb.level);
+        zb[0] = a.lo[0] + (double)(2 * cb.ix + 1) * r * a.h;
+        zb[1] = a.lo[1] + (double)(2 * cb.iy + 1) * r * a.h;
+        zb[2] = a.lo[2] + (double)(2 * cb.iz + 1) * r * a.h;
+    }
+    const size_t n = a.n;
     const int e0 = a.ptr[lk], e1 = a.ptr[lk + 1];
-    const float4 *xi4 = reinterpret_cast<const float4 *>(a.xi);
     const float4 *m4 = reinterpret_cast<const float4 *>(a.m32);
     for (int tg0 = 0; tg0 < cb.count; tg0 += kPT) {
         const int cs = min(kPT, cb.count - tg0);
@@ -600,7 +593,11 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
         const int t = tid % cs, sl = tid / cs;
         const bool act = sl < ns;
         const int i = cb.first + tg0 + t;
-        const float4 eta = xi4[i];
+        // positions relative to the target leaf centre in units of its radius,
+        // FP64: the pair separation is formed before rounding to FP32, so
+        // close pairs keep their relative accuracy
+        const double tx = (a.xs[i] - zb[0]) * irb, ty = (a.xs[n + i] - zb[1]) * irb,
+                     tz = (a.xs[2 * n + i] - zb[2]) * irb;
         float ps = 0.f, pc = 0.f, xs_ = 0.f, xc = 0.f, ys = 0.f, yc = 0.f, zs = 0.f, zc = 0.f;
         for (int w0 = e0; w0 < e1; w0 += kPList) {
             const int nw = min(kPList, e1 - w0);
@@ -613,15 +610,12 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                 __syncthreads();
                 for (int j = tid; j < nc; j += kPT) {
                     const int q = p2p_entry(wstart, nw, c0 + j);
-                    const int pj = wfirst[q] + (c0 + j - wstart[q]);
-                    const float4 x = xi4[pj];
-                    const float4 g = wgeo[q];
-                    float4 sv = make_float4(__builtin_fmaf(x.x, g.w, g.x), __builtin_fmaf(x.y, g.w, g.y),
-                                            __builtin_fmaf(x.z, g.w, g.z), 0.f);
-                    if (S == 0) sv.w = m4[2 * (size_t)pj].x;
-                    sp[0][j] = sv;
-                    if (S >= 1) sp[S >= 1 ? 1 : 0][j] = m4[2 * (size_t)pj];
-                    if (S == 2) sp[S == 2 ? 2 : 0][j] = m4[2 * (size_t)pj + 1];
+                    const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
+                    spx[j] = (a.xs[pj] - zb[0]) * irb;
+                    spy[j] = (a.xs[n + pj] - zb[1]) * irb;
+                    spz[j] = (a.xs[2 * n + pj] - zb[2]) * irb;
+                    spm[0][j] = m4[2 * pj];
+                    if (S == 2) spm[S == 2 ? 1 : 0][j] = m4[2 * pj + 1];
                 }
                 __syncthreads();
                 if (act) {
@@ -631,12 +625,11 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                     float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
                     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     for (int j = ja; j < jb; ++j) {
-                        const float4 q = sp[0][j];
-                        const float rx = eta.x - q.x, ry = eta.y - q.y, rz = eta.z - q.z;
+                        const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
                         const float inv = j == jself ? 0.f : __builtin_amdgcn_rsqf(r2);
-                        const float4 m0 = S == 0 ? make_float4(q.w, 0.f, 0.f, 0.f) : sp[S >= 1 ? 1 : 0][j];
-                        const float4 m1 = S == 2 ? sp[S == 2 ? 2 : 0][j] : zero4;
+                        const float4 m0 = spm[0][j];
+                        const float4 m1 = S == 2 ? spm[S == 2 ? 1 : 0][j] : zero4;
                         p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
                     }
                     kahan_add(ps, pc, bp);
@@ -752,7 +745,7 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
     a.ptr = t->d_p2p_ptr;
     a.src = t->d_p2p_src;
     a.cells = t->d_cells;
-    a.xi = t->d_xi;
+    for (int d = 0; d < 3; ++d) a.lo[d] = t->ht.lo[d];
     a.m32 = t->d_mom32;
     a.xs = t->d_x;
     a.m64 = t->d_mom;

@@ -19,7 +19,7 @@ from paper_2005_12351_amd import workloads as W  # noqa: E402
 from tests.gpu_helpers import gpu_fmm, rel_l2  # noqa: E402
 
 TOL_FP64 = 1e-10
-TOL_MIXED = 1e-5
+TOL_MIXED = 1e-6   # FP32 M2P and direct terms, as the FMM mixed bound
 
 
 @pytest.fixture(scope="module")

@@ -4,7 +4,7 @@ FMM and Barnes-Hut) and 2M lattice quadrupoles (p 10).  The oracle cannot
 evaluate every particle at these sizes, so it runs its full upward pass and
 evaluates 4 096 seeded sample targets one by one (Section 3.2 lists of the
 sampled leaves only); the GPU values at those targets are compared with the
-same bounds as the small cases: FP64 1e-10, MIXED 1e-5 (relative L2)."""
+same bounds as the small cases: FP64 1e-10, MIXED 1e-6 (relative L2)."""
 import numpy as np
 import pytest
 
@@ -18,7 +18,7 @@ from paper_2005_12351_amd import fmm  # noqa: E402
 from paper_2005_12351_amd import workloads as W  # noqa: E402
 from tests.gpu_helpers import rel_l2, to_dev  # noqa: E402
 
-TOL = {"fp64": 1e-10, "mixed": 1e-5}
+TOL = {"fp64": 1e-10, "mixed": 1e-6}
 PREC = {"fp64": fmm.FMM_PREC_FP64, "mixed": fmm.FMM_PREC_MIXED}
 
 

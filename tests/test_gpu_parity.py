@@ -20,10 +20,12 @@ from tests.gpu_helpers import gpu_fmm, rel_l2  # noqa: E402
 # FP64 path vs oracle: same tree, lists and truncation; differences come only
 # from the summation order and the normalised (dyadic) form of the operators.
 TOL_FP64 = 1e-10
-# Mixed path vs oracle: FP32 M2L/P2P (unit roundoff 6e-8) summed over a few
-# hundred list entries per target; see the tolerance derivation in the design
-# notes.  Stated per precision and checked here.
-TOL_MIXED = 1e-5
+# Mixed path vs oracle: FP32 M2L and P2P terms (unit roundoff u = 6e-8) with
+# the pair separations formed in FP64, FP32 sums per chunk added in FP64 or
+# Kahan-compensated; the relative error of a coefficient or pair term is a
+# few u, and the cancellation between signed dipole and quadrupole
+# contributions amplifies it up to ~10x in phi and E: observed 0.7-5.6e-7.
+TOL_MIXED = 1e-6
 
 
 @pytest.fixture(scope="module")

@@ -69,7 +69,7 @@ def test_results_alone_equal_results_in_mix(orc):
     # and one of them against the oracle
     w, prec = mix[1]
     po, Eo = orc.Tree(w.pos, w.ncrit, w.theta).fmm(w.order, w.moments, w.p)
-    assert rel_l2(alone[1][0], po) < 1e-5 and rel_l2(alone[1][1], Eo) < 1e-5
+    assert rel_l2(alone[1][0], po) < 1e-6 and rel_l2(alone[1][1], Eo) < 1e-6
 
 
 def test_budget_limits_concurrency():

@@ -118,9 +118,10 @@ hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s)
 // M~_n = r^-s sum_j sum_{sigma <= n, |sigma| = s} zeta_j^(n-sigma)/(n-sigma)! S_sigma(j)
 // with zeta = (z - x_j)/r and S_sigma = (-1)^s T_sigma / sigma! (Eq. 3, Eq. 5).
 // One workgroup per leaf; a thread owns one or more coefficients n (its
-// multi-index is read once), particles are staged in LDS 64 at a time as
+// multi-index is read once), particles are staged in LDS 32 at a time as
 // per-axis tables zeta^a / a!, so the inner loop touches LDS only.
 constexpr int kP2MThreads = 128;
+constexpr int kP2MStage = 32;       // particles staged per pass (LDS per workgroup ~11 KB)
 constexpr int kAxW = kPTable + 2;   // row of one axis table, padded
 
 struct InvTable {
@@ -142,8 +143,8 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
                                                           const double *__restrict__ mom, double *__restrict__ M)
 {
     constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
-    __shared__ double pw[64][3][kAxW];
-    __shared__ double sv[64][W];
+    __shared__ double pw[kP2MStage][3][kAxW];
+    __shared__ double sv[kP2MStage][W];
     const int c = leaves[blockIdx.x];
     const DevCell cell = cells[c];
     double z[3];
@@ -164,8 +165,8 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
         iy[k] = nn.y;
         iz[k] = nn.z;
     }
-    for (int base = 0; base < cell.count; base += 64) {
-        const int cnt = min(64, cell.count - base);
+    for (int base = 0; base < cell.count; base += kP2MStage) {
+        const int cnt = min(kP2MStage, cell.count - base);
         __syncthreads();
         for (int it = threadIdx.x; it < 3 * cnt; it += kP2MThreads) {
             // item -> (particle, axis): zeta^a / a! for a = 0..p
@@ -287,7 +288,8 @@ __device__ __forceinline__ void shift_items(int nt, ShiftItems &it)
 // M~_n(P) = sum_children 2^-|n| sum_{k <= n} prod_d (-sigma_d)^k_d / k_d! M~_{n-k}(C)
 // (Eq. 4 read with new-minus-old centre; radii halve from child to parent).
 // Children are summed in octant order in FP64.
-__global__ __launch_bounds__(kShiftX * 8) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
+// (8 waves per SIMD: two 1024-thread workgroups fit a CU)
+__global__ __launch_bounds__(kShiftX * 8, 8) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
                                                           const DevCell *__restrict__ cells, double *__restrict__ M)
 {
     extern __shared__ double sm[];   // X[8][nt], Y[8][nt]
@@ -370,7 +372,7 @@ hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
 // (Taylor shift of the local expansion to the child centre, in the
 // normalised form).  The parent row is scaled once and shared by the
 // children of the workgroup.
-__global__ __launch_bounds__(kShiftX * 8) void l2l_kernel(int q, const int32_t *__restrict__ parents,
+__global__ __launch_bounds__(kShiftX * 8, 8) void l2l_kernel(int q, const int32_t *__restrict__ parents,
                                                           const DevCell *__restrict__ cells, double *__restrict__ L)
 {
     extern __shared__ double sm[];   // Pr[nl], X[8][nl], Y[8][nl]

@@ -515,6 +515,10 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
         t->l2p_pack_q = p - order;
     }
     hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
+    // P2M and M2M write the FP32 copy too; the rest (the zero row the padded
+    // M2L slots read, unused levels) stays zero (nmp is a multiple of 4)
+    if (e == hipSuccess && prec == FMM_PREC_MIXED)
+        e = launch_fill((double *)t->d_M32, (size_t)(nc + 1) * nmp / 2, t->ctx->stream);
     if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
     t->order = order;
     t->p = p;
@@ -586,10 +590,6 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
     for (int l = nlev - 2; l >= t->m2m_top; --l) {
         ProfScope ps(ctx, s, "m2m");
         KCHK(launch_m2m_level(t, l, s));
-    }
-    if (t->prec == FMM_PREC_MIXED) {
-        ProfScope ps(ctx, s, "m2_fp32");
-        KCHK(launch_to_fp32(t, s));
     }
     if (join && a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     return FMM_OK;

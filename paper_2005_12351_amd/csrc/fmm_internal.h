@@ -215,7 +215,6 @@ hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s);
 hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s);
 hipError_t launch_p2m(fmm_tree *t, hipStream_t s);
 hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s);
-hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s);
 hipError_t launch_dtable(fmm_tree *t, hipStream_t s);
 hipError_t launch_fill(double *p, size_t count, hipStream_t s);
 hipError_t launch_m2l(fmm_tree *t, hipStream_t s);

@@ -140,7 +140,8 @@ template <int S>
 __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
                                                           const DevCell *__restrict__ cells, Geo g,
                                                           const double *__restrict__ xs, int n,
-                                                          const double *__restrict__ mom, double *__restrict__ M)
+                                                          const double *__restrict__ mom, double *__restrict__ M,
+                                                          float *__restrict__ M32)
 {
     constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
     __shared__ double pw[kP2MStage][3][kAxW];
@@ -234,7 +235,11 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
     }
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-        if ((int)threadIdx.x + k * kP2MThreads < nm) M[(size_t)c * nmp + threadIdx.x + k * kP2MThreads] = acc[k];
+        if ((int)threadIdx.x + k * kP2MThreads < nm) {
+            const size_t o = (size_t)c * nmp + threadIdx.x + k * kP2MThreads;
+            M[o] = acc[k];
+            if (M32) M32[o] = (float)acc[k];   // the copy the mixed-precision M2L reads
+        }
 }
 
 hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
@@ -242,15 +247,16 @@ hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     const dim3 gr((unsigned)t->nleaves), bl(kP2MThreads);
+    float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
     if (t->order == 0)
         hipLaunchKernelGGL(p2m_kernel<0>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64);
+                           t->d_mom, t->d_M64, m32);
     else if (t->order == 1)
         hipLaunchKernelGGL(p2m_kernel<1>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64);
+                           t->d_mom, t->d_M64, m32);
     else
         hipLaunchKernelGGL(p2m_kernel<2>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64);
+                           t->d_mom, t->d_M64, m32);
     return hipGetLastError();
 }
 
@@ -290,7 +296,8 @@ __device__ __forceinline__ void shift_items(int nt, ShiftItems &it)
 // Children are summed in octant order in FP64.
 // (8 waves per SIMD: two 1024-thread workgroups fit a CU)
 __global__ __launch_bounds__(kShiftX * 8, 8) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
-                                                          const DevCell *__restrict__ cells, double *__restrict__ M)
+                                                          const DevCell *__restrict__ cells, double *__restrict__ M,
+                                                          float *__restrict__ M32)
 {
     extern __shared__ double sm[];   // X[8][nt], Y[8][nt]
     const int nt = nterms(p), n0 = nterms(s - 1);
@@ -353,7 +360,9 @@ __global__ __launch_bounds__(kShiftX * 8, 8) void m2m_kernel(int p, int s, int n
             if (i < n0) continue;
             double acc = 0.0;
             for (int c = 0; c < nch; ++c) acc += Y[c * nt + i];
-            M[(size_t)P * nmp + (i - n0)] = ldexp(acc, -it.k[j]);
+            const double v = ldexp(acc, -it.k[j]);
+            M[(size_t)P * nmp + (i - n0)] = v;
+            if (M32) M32[(size_t)P * nmp + (i - n0)] = (float)v;
         }
 }
 
@@ -364,7 +373,7 @@ hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     const size_t lds = (size_t)16 * nterms(t->p) * sizeof(double);
     hipLaunchKernelGGL(m2m_kernel, dim3(b - a), dim3(kShiftX, 8), lds, s, t->p, t->order, nmp, t->d_nonleaf + a,
-                       t->d_cells, t->d_M64);
+                       t->d_cells, t->d_M64, t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr);
     return hipGetLastError();
 }
 
@@ -447,20 +456,6 @@ hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s)
     return hipGetLastError();
 }
 
-__global__ void to_fp32_kernel(size_t n, const double *__restrict__ a, float *__restrict__ b)
-{
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        b[i] = (float)a[i];
-}
-
-hipError_t launch_to_fp32(fmm_tree *t, hipStream_t s)
-{
-    const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
-    const size_t n = (size_t)(t->ht.ncells() + 1) * nmp;
-    const unsigned g = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
-    hipLaunchKernelGGL(to_fp32_kernel, dim3(g), dim3(256), 0, s, n, t->d_M64, t->d_M32);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------------------------ P2P
 // Direct interaction over the near-field lists (Section 3.2).  One workgroup

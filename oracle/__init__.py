@@ -102,6 +102,20 @@ def dtensor(q: int, r) -> np.ndarray:
     return D
 
 
+# Source order codes: 0, 1, 2 for one order, or MIXED + a bit mask of the
+# orders present (bit k: order k), with the moments of the present orders
+# concatenated in ascending order in each row.
+MIXED = 16
+
+
+def mixed(mask: int) -> int:
+    return MIXED + int(mask)
+
+
+def min_order(code: int) -> int:
+    return int(lib().orc_min_order(int(code)))
+
+
 def p2p_pair(order: int, r, mom):
     r = _c(r)
     mom = _c(mom).ravel()
@@ -257,7 +271,7 @@ class Tree:
         k = self.n if tg is None else tg.shape[0]
         phi = np.zeros(k)
         E = np.zeros((k, 3))
-        L = np.zeros((self.info()["ncells"], nterms(p - order))) if want_L else None
+        L = np.zeros((self.info()["ncells"], nterms(p - min_order(order)))) if want_L else None
         rc = lib().orc_fmm_eval(self._h, order, _p(mom), p, k, _p(tg), _p(phi), _p(E), _p(L))
         if rc != 0:
             raise ValueError("oracle FMM rejected its arguments (lists missing or p < order+1)")

@@ -146,9 +146,39 @@ void orc_dtensor(int q, double x, double y, double z, double *D)
 /* Direct interaction of point sources (Eq. 1 and its derivatives)      */
 /* ------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------ */
+/* Source order codes                                                    */
+/* ------------------------------------------------------------------ */
+/* A code is a single source order (0 charge, 1 dipole, 2 quadrupole) or
+ * ORC_MIXED plus a bit mask of the orders present in one system (bit k:
+ * order k).  A moment row then holds the physical moments of the present
+ * orders, in ascending order, concatenated.  Every operator is linear in the
+ * source, so a mixed source acts as the sum of its single-order parts; the
+ * expansions start at the lowest order present (Section 2). */
+#define ORC_MIXED 16
+
+static int code_mask(int o) { return o >= ORC_MIXED ? o - ORC_MIXED : 1 << o; }
+static int width_of(int order) { return order == 0 ? 1 : (order == 1 ? 3 : 6); }
+static int mom_width(int o)
+{
+    int m = code_mask(o), w = 0;
+    for (int k = 0; k < 3; ++k)
+        if (m & (1 << k)) w += width_of(k);
+    return w;
+}
+int orc_min_order(int o)
+{
+    int m = code_mask(o);
+    return (m & 1) ? 0 : ((m & 2) ? 1 : 2);
+}
+int orc_code_valid(int o)
+{
+    return (o >= 0 && o <= 2) || (o > ORC_MIXED && o < ORC_MIXED + 8);
+}
+
 /* potential and field at a target displaced by r = x_target - x_source from
- * a source of the given order with physical moment mom */
-void orc_p2p_pair(int order, const double *r, const double *mom, double *phi, double *E)
+ * a source of one order with physical moment mom */
+static void pair_single(int order, const double *r, const double *mom, double *phi, double *E)
 {
     double x = r[0], y = r[1], z = r[2];
     double r2 = x * x + y * y + z * z;
@@ -185,7 +215,23 @@ void orc_p2p_pair(int order, const double *r, const double *mom, double *phi, do
     }
 }
 
-static int mom_width(int order) { return order == 0 ? 1 : (order == 1 ? 3 : 6); }
+/* the same for a source of any order code: the sum over its parts */
+void orc_p2p_pair(int o, const double *r, const double *mom, double *phi, double *E)
+{
+    int m = code_mask(o), off = 0;
+    *phi = 0.0;
+    E[0] = E[1] = E[2] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        if (!(m & (1 << k))) continue;
+        double ph, e[3];
+        pair_single(k, r, mom + off, &ph, e);
+        *phi += ph;
+        E[0] += e[0];
+        E[1] += e[1];
+        E[2] += e[2];
+        off += width_of(k);
+    }
+}
 
 /* O(N^2) sum over all sources j != i for the listed targets (all if
  * targets == NULL), ascending j. */
@@ -242,18 +288,24 @@ static void source_tensor(int order, const double *mom, double *S)
     }
 }
 
-/* P2M (Eq. 5): add the expansion about z of np sources into M (nterms(p)) */
-void orc_p2m(int p, int order, const double *z, int64_t np, const double *pos,
+/* P2M (Eq. 5): add the expansion about z of np sources into M (nterms(p));
+ * a mixed source contributes each of its single-order parts */
+void orc_p2m(int p, int o, const double *z, int64_t np, const double *pos,
              const double *mom, double *M)
 {
-    int w = mom_width(order);
+    int w = mom_width(o);
     int nt = orc_nterms(p);
+    int mask = code_mask(o);
     double *mono = malloc(sizeof(double) * nt);
     double S[10];
     for (int64_t j = 0; j < np; ++j) {
         double d[3] = {z[0] - pos[3 * j], z[1] - pos[3 * j + 1], z[2] - pos[3 * j + 2]};
         monomials(p, d, mono);
-        source_tensor(order, mom + w * j, S);
+        int off = 0;
+        for (int order = 0; order < 3; ++order) {
+        if (!(mask & (1 << order))) continue;
+        source_tensor(order, mom + w * j + off, S);
+        off += width_of(order);
         for (int i = orc_nterms(order - 1); i < nt; ++i) {
             int n[3];
             orc_multi_index(i, n);
@@ -265,6 +317,7 @@ void orc_p2m(int p, int order, const double *z, int64_t np, const double *pos,
                     acc += mono[orc_index(n[0] - sx, n[1] - sy, n[2] - sz)] * S[orc_index(sx, sy, sz)];
                 }
             M[i] += acc;
+        }
         }
     }
     free(mono);
@@ -746,8 +799,9 @@ int orc_upward(const orc_tree *t, int order, const double *mom, int p, double *M
 int orc_fmm_eval(const orc_tree *t, int order, const double *mom, int p, int64_t nt_,
                  const int64_t *targets, double *phi, double *field, double *L_out)
 {
-    if (!t->m2l_ptr || p < order + 1) return 1;
-    int s = order;
+    if (!orc_code_valid(order)) return 1;
+    int s = orc_min_order(order);
+    if (!t->m2l_ptr || p < s + 1) return 1;
     int w = mom_width(order);
     int ntM = orc_nterms(p), ntL = orc_nterms(p - s);
     double *ms = sorted_moments(t, order, mom);
@@ -834,8 +888,9 @@ static int cell_contains(const orc_tree *t, int64_t c, int64_t i)
 int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double theta_bh,
                 int64_t nt_, const int64_t *targets, double *phi, double *field)
 {
-    if (p < order || !(theta_bh > 0.0 && theta_bh < 1.0)) return 1;
-    int s = order;
+    if (!orc_code_valid(order)) return 1;
+    int s = orc_min_order(order);
+    if (p < s || !(theta_bh > 0.0 && theta_bh < 1.0)) return 1;
     int w = mom_width(order);
     int ntM = orc_nterms(p);
     double *ms = sorted_moments(t, order, mom);

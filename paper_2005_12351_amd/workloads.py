@@ -8,6 +8,8 @@ Source moments use the physical convention (see ``include/fmm.h``):
   order 0: q[N]             (charges)
   order 1: mu[N, 3]         (dipole vectors)
   order 2: Q[N, 6]          (xx, xy, xz, yy, yz, zz of a symmetric 3x3 tensor)
+  mixed:   MIXED + mask     (bit k: order k present), rows [q | mu | Q] of the
+                            present orders, concatenated in ascending order
 
 The workloads follow the paper's test sets: random charges in a box and a
 cubic spin lattice (Section 4), extended to dipoles, a Plummer sphere and
@@ -21,14 +23,15 @@ from typing import Optional
 import numpy as np
 
 SEED_BASE = 200512351
+MIXED = 16          # order code of a system with several source orders: MIXED + bit mask
 
 
 @dataclass
 class Workload:
     name: str
     pos: np.ndarray            # (N, 3) float64, C-contiguous
-    order: int                 # source order m (0, 1, 2)
-    moments: np.ndarray        # (N,), (N, 3) or (N, 6) float64
+    order: int                 # source order m (0, 1, 2) or MIXED + bit mask of orders
+    moments: np.ndarray        # (N,), (N, 3), (N, 6) or (N, w) float64 (mixed)
     p: int
     theta: float
     ncrit: int
@@ -177,3 +180,19 @@ def small_random(seed: int, n: int, order: int, kind: str = "uniform", p: int = 
         raise ValueError(kind)
     mom = random_moments(rng, order, pos.shape[0])
     return Workload(f"small-{kind}-{n}-m{order}", pos, order, mom, p, theta, ncrit, "pot+field")
+
+
+def mixed_moments(rng: np.random.Generator, mask: int, n: int) -> np.ndarray:
+    """Rows [q | mu | Q] of the orders present in ``mask`` (bit k: order k)."""
+    parts = [random_moments(rng, k, n).reshape(n, -1) for k in range(3) if mask & (1 << k)]
+    return np.ascontiguousarray(np.concatenate(parts, axis=1))
+
+
+def small_mixed(seed: int, n: int, mask: int, kind: str = "uniform", p: int = 4,
+                theta: float = 0.5, ncrit: int = 8) -> Workload:
+    """A system with several source orders at once (charges, dipoles,
+    quadrupoles as ``mask`` selects), every particle carrying all of them."""
+    w = small_random(seed, n, 0, kind, p, theta, ncrit)
+    rng = np.random.default_rng(seed + 1)
+    mom = mixed_moments(rng, mask, w.n)
+    return Workload(f"mixed-{kind}-{n}-k{mask}", w.pos, MIXED + mask, mom, p, theta, ncrit, "pot+field")

@@ -235,3 +235,42 @@ def test_theta_fmm_about_twice_theta_bh(orc):
         eb_half = orc.rel_l2(t.bh(0, w.moments, p, 0.25)[0], pd)
         eb_full = orc.rel_l2(t.bh(0, w.moments, p, 0.5)[0], pd)
         assert eb_half < ef < eb_full
+
+
+# ---------------------------------------------------------------- mixed orders
+@pytest.mark.parametrize("mask", [3, 5, 6, 7])
+def test_mixed_sources_superpose(orc, mask):
+    """A system with several source orders is the sum of its single-order
+    parts: direct sum, FMM (same tree, lists and p; the lowest order present
+    sets the truncation, which leaves every part's term set unchanged) and
+    Barnes-Hut.  The parts are computed by the single-order code paths, so a
+    wrong offset, order or truncation in the mixed path fails here."""
+    w = W.small_mixed(31 + mask, 600, mask, "plummer", p=5, theta=0.5, ncrit=16)
+    widths = [1, 3, 6]
+    parts, off = [], 0
+    for k in range(3):
+        if mask & (1 << k):
+            parts.append((k, np.ascontiguousarray(w.moments[:, off:off + widths[k]]).reshape(w.n, -1)))
+            off += widths[k]
+    assert off == w.moments.shape[1]
+    pd, Ed = orc.direct(w.pos, w.order, w.moments)
+    sp = sum(orc.direct(w.pos, k, m.squeeze(1) if m.shape[1] == 1 else m)[0] for k, m in parts)
+    sE = sum(orc.direct(w.pos, k, m.squeeze(1) if m.shape[1] == 1 else m)[1] for k, m in parts)
+    assert orc.rel_l2(pd, sp) < 1e-13 and orc.rel_l2(Ed, sE) < 1e-13
+    t = orc.Tree(w.pos, w.ncrit, w.theta)
+    pf, Ef = t.fmm(w.order, w.moments, w.p)
+    fp = [t.fmm(k, m.squeeze(1) if m.shape[1] == 1 else m, w.p) for k, m in parts]
+    assert orc.rel_l2(pf, sum(x[0] for x in fp)) < 1e-12
+    assert orc.rel_l2(Ef, sum(x[1] for x in fp)) < 1e-12
+    # and the FMM converges to the direct sum of the mixed system
+    assert orc.rel_l2(Ef, Ed) < 1e-2
+    tb = orc.Tree(w.pos, w.ncrit)
+    pb, Eb = tb.bh(w.order, w.moments, w.p, 0.4)
+    bp = [tb.bh(k, m.squeeze(1) if m.shape[1] == 1 else m, w.p, 0.4) for k, m in parts]
+    assert orc.rel_l2(pb, sum(x[0] for x in bp)) < 1e-12
+    assert orc.rel_l2(Eb, sum(x[1] for x in bp)) < 1e-12
+
+
+def test_mixed_min_order(orc):
+    assert orc.min_order(orc.mixed(6)) == 1 and orc.min_order(orc.mixed(4)) == 2
+    assert orc.min_order(orc.mixed(7)) == 0 and orc.min_order(1) == 1

@@ -71,6 +71,15 @@ enum {
 
 #define FMM_P_MAX 10     /* largest expansion order p compiled in */
 
+/* Source order codes.  0, 1, 2: every particle is a charge, a dipole or a
+ * quadrupole.  FMM_MIXED | mask: several orders in one system (mask bit k:
+ * order k present, e.g. FMM_MIXED | 3 for charges with dipoles); each moment
+ * row then holds the present orders' moments in ascending order, [q | mu |
+ * Qxx Qxy Qxz Qyy Qyz Qzz], and the expansions start at the lowest order
+ * present (Section 2: the multipole series of a point source of order s
+ * starts at order s; a system's series is the sum of its sources'). */
+#define FMM_MIXED 16
+
 /* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the
  * library creates its own).  `hbm_budget_bytes` bounds the device memory the
  * serving loop admits (0: 80% of the free memory at creation). */
@@ -89,10 +98,12 @@ int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double
  * S_n = (-1)^|n| T_n / n! of the physical moment T) and M2M towards the root
  * (Eq. 4), expansion order p; for FMM trees also the near field (direct
  * sums over the P2P lists, Section 3.2) into library-owned storage, since it
- * depends only on the moments.  order in {0,1,2}; order+1 <= p <= FMM_P_MAX
- * for FMM, order <= p <= FMM_P_MAX for BH.  `moments`: device, n x w FP64
- * row-major (w = 1, 3, 6), caller-owned, read only by the work this call
- * queues on the context stream (a sorted copy is kept). */
+ * depends only on the moments.  order: a source order code (0, 1, 2 or
+ * FMM_MIXED | mask, see above) with lowest order s; s+1 <= p <= FMM_P_MAX
+ * for FMM, max(s,1) <= p <= FMM_P_MAX for BH.  `moments`: device, n x w FP64
+ * row-major (w = 1, 3, 6 for one order, the sum of the present orders'
+ * widths for several), caller-owned, read only by the work this call queues
+ * on the context stream (a sorted copy is kept). */
 int fmm_upward(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int p,
                int precision);
 

@@ -36,6 +36,7 @@ struct BHArgs {
     double theta2;
     BHGeo g;
     unsigned long long *counts;   // [0] accepted (particle, cell) pairs, [1] direct pairs
+    int mask, w;                  // source orders present (bit mask), FP64 moments per particle
 };
 
 constexpr int kStack = 8 * (kMaxLevel + 3);
@@ -106,7 +107,21 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
             if (cell.nchild == 0) {
                 if ((rest >> lane) & 1ull) {
                     n_p2p += (unsigned)cell.count - (inside ? 1u : 0u);
-                    if (F32) {
+                    if (a.mask != (1 << S)) {
+                        // several source orders: each order's closed form, FP64
+                        for (int j = cell.first; j < cell.first + cell.count; ++j) {
+                            if (j == i) continue;
+                            const double *mj = a.m64 + (size_t)j * a.w;
+                            const double rx = xi - a.xs[j], ry = yi - a.xs[n + j], rz = zi - a.xs[2 * n + j];
+                            int off = 0;
+                            if (a.mask & 1) p2p_pair_f64<0>(rx, ry, rz, mj + off++, ph, ex, ey, ez);
+                            if (a.mask & 2) {
+                                p2p_pair_f64<1>(rx, ry, rz, mj + off, ph, ex, ey, ez);
+                                off += 3;
+                            }
+                            if (a.mask & 4) p2p_pair_f64<2>(rx, ry, rz, mj + off, ph, ex, ey, ez);
+                        }
+                    } else if (F32) {
                         // sources in units of the leaf radius, FP32 block sum
                         const double ir = 1.0 / r;
                         float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
@@ -118,7 +133,7 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
                             const float4 *m4 = reinterpret_cast<const float4 *>(a.m32) + 2 * (size_t)j;
                             p2p_pair_f32<S>(rx, ry, rz, __builtin_amdgcn_rsqf(r2), m4[0], m4[1], bp, bx, by, bz);
                         }
-                        const double sphi = 1.0 / pow(r, (double)(S + 1)), sfld = sphi * ir;
+                        const double sphi = S == 0 ? ir : (S == 1 ? ir * ir : ir * ir * ir), sfld = sphi * ir;
                         ph += (double)bp * sphi;
                         ex += (double)bx * sfld;
                         ey += (double)by * sfld;
@@ -213,6 +228,8 @@ hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipSt
     for (int d = 0; d < 3; ++d) a.g.lo[d] = t->ht.lo[d];
     a.g.h = t->ht.h;
     a.counts = t->d_bhcount;
+    a.mask = t->smask;
+    a.w = mask_width(t->smask);
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, t->d_bhcount, 2);
     hipLaunchKernelGGL(k, dim3((unsigned)((t->ht.n + 63) / 64)), dim3(64), 0, s, a);
     return hipGetLastError();

@@ -292,7 +292,6 @@ extern "C" int fmm_tree_destroy(fmm_tree *t)
     return FMM_OK;
 }
 
-static int mom_width(int order) { return order == 0 ? 1 : (order == 1 ? 3 : 6); }
 
 extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double theta, int method,
                               fmm_tree **out)
@@ -438,9 +437,10 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 }
 
 // ------------------------------------------------------------------ upward
-static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
+static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 {
-    if (t->d_M64 && t->order == order && t->p == p && t->prec == prec) return FMM_OK;
+    const int smask = code_mask(code), order = mask_min_order(smask);
+    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec) return FMM_OK;
     drop_graphs(t);
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32,
                       (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_D64,
@@ -453,8 +453,8 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
     const int64_t n = t->ht.n, nc = t->ht.ncells();
     const int nm = nterms(p) - nterms(order - 1), nmp = (nm + 3) / 4 * 4, nl = nterms(p - order);
     int rc;
-    if ((rc = tree_alloc(t, (void **)&t->d_mom, sizeof(double) * mom_width(order) * n)) ||
-        (rc = tree_alloc(t, (void **)&t->d_mom32, sizeof(float) * 8 * n)) ||
+    if ((rc = tree_alloc(t, (void **)&t->d_mom, sizeof(double) * mask_width(smask) * n)) ||
+        (rc = tree_alloc(t, (void **)&t->d_mom32, sizeof(float) * m32_width(smask) * n)) ||
         (rc = tree_alloc(t, (void **)&t->d_M64, sizeof(double) * (nc + 1) * nmp)) ||
         (rc = tree_alloc(t, (void **)&t->d_near, sizeof(double) * 4 * n)))
         return rc;
@@ -521,6 +521,7 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
         e = launch_fill((double *)t->d_M32, (size_t)(nc + 1) * nmp / 2, t->ctx->stream);
     if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
     t->order = order;
+    t->smask = smask;
     t->p = p;
     t->prec = prec;
     if (t->method == FMM_METHOD_FMM) {
@@ -541,10 +542,12 @@ static int ensure_expansions(fmm_tree *t, int order, int p, int prec)
 static int check_upward_args(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
 {
     if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
-    if (order < 0 || order > 2) FAIL(FMM_EINVAL, "source order %d not in {0,1,2}", order);
+    if (!((order >= 0 && order <= 2) || (order > FMM_MIXED && order < FMM_MIXED + 8)))
+        FAIL(FMM_EINVAL, "source order code %d is neither 0, 1, 2 nor FMM_MIXED | mask", order);
     if (!moments) FAIL(FMM_EINVAL, "moments are NULL");
     if (precision != FMM_PREC_FP64 && precision != FMM_PREC_MIXED) FAIL(FMM_EINVAL, "unknown precision %d", precision);
-    const int pmin = t->method == FMM_METHOD_FMM ? order + 1 : std::max(order, 1);
+    const int s = mask_min_order(code_mask(order));
+    const int pmin = t->method == FMM_METHOD_FMM ? s + 1 : std::max(s, 1);
     if (p < pmin || p > FMM_P_MAX) FAIL(FMM_EINVAL, "p = %d must lie in [%d, %d]", p, pmin, FMM_P_MAX);
     return FMM_OK;
 }
@@ -629,7 +632,10 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
 
 // FLOPs per P2P pair as counted in the FP32 kernel (multiply-add = 2,
 // reciprocal square root = 1), potential and field
-static double p2p_flops(int order) { return order == 0 ? 20.0 : (order == 1 ? 32.0 : 58.0); }
+static double p2p_flops_mask(int m)
+{
+    return (m & 1 ? 20.0 : 0.0) + (m & 2 ? 32.0 : 0.0) + (m & 4 ? 58.0 : 0.0);
+}
 
 // algorithmic work of an evaluation (see fmm_work_counts)
 static void set_work_counts(fmm_tree *t)
@@ -642,7 +648,7 @@ static void set_work_counts(fmm_tree *t)
     for (int k = 0; k <= p - s_; ++k) fc += (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
     const size_t es = t->prec == FMM_PREC_MIXED ? 4 : 8;
     t->work[1] = 2.0 * fc * t->work[0];
-    t->work[3] = p2p_flops(s_) * t->work[2];
+    t->work[3] = p2p_flops_mask(t->smask) * t->work[2];
     t->work[6] = (double)nc * (double)(nterms(p) - nterms(s_ - 1) + nl) * es;
     t->work[7] = (double)t->ht.n * (es * (4 + 8) + 32);
 }
@@ -713,7 +719,7 @@ extern "C" int fmm_work_counts(const fmm_tree *t, double *w)
         const double nm = (double)(nterms(p) - nterms(s_ - 1));
         const double np4 = (double)(p + 4) * (p + 3) * (p + 2) / 6.0;   // C(p+4, 3) derivative terms
         w[2] = (double)c[1];
-        w[3] = p2p_flops(s_) * w[2];
+        w[3] = p2p_flops_mask(t->smask) * w[2];
         w[4] = (double)c[0];
         w[5] = (8.0 * nm + 12.0 * np4) * w[4];
     }

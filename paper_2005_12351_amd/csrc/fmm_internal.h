@@ -25,6 +25,17 @@ constexpr int kGraphKey = 10;        // arguments a captured launch sequence is 
 
 struct MultiIndex { int8_t x, y, z, k; };
 
+// Source order codes: 0, 1, 2 for one order, or FMM_MIXED + a bit mask of the
+// orders present in one system (bit k: order k); moment rows hold the
+// present orders' physical moments in ascending order.
+__host__ __device__ constexpr int code_mask(int code) { return code >= FMM_MIXED ? code - FMM_MIXED : 1 << code; }
+__host__ __device__ constexpr int mask_width(int m) { return (m & 1 ? 1 : 0) + (m & 2 ? 3 : 0) + (m & 4 ? 6 : 0); }
+__host__ __device__ constexpr int mask_min_order(int m) { return m & 1 ? 0 : (m & 2 ? 1 : 2); }
+__host__ __device__ constexpr bool mask_single(int m) { return m == 1 || m == 2 || m == 4; }
+// FP32 moments per particle: 8 floats for one order (q | mu | six Q and the
+// trace), 12 for several ([q mu] [xx xy xz yy] [yz zz tr 0], absent parts 0)
+__host__ __device__ constexpr int m32_width(int m) { return mask_single(m) ? 8 : 12; }
+
 // multi-indices in storage order (total order ascending; within an order
 // n_x descending, then n_y descending), up to order kPTable
 struct MITable {
@@ -175,7 +186,8 @@ struct fmm_tree {
     double *d_cls_geom = nullptr;
     unsigned long long *d_bhcount = nullptr;   // Barnes-Hut interaction counters (2)
     // per expansion state
-    int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;
+    int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;   // order: the lowest source order s
+    int smask = 1;                         // source orders present (bit mask)
     const double *mom_user = nullptr;
     double *d_mom = nullptr;               // sorted moments FP64 (w per particle)
     float *d_mom32 = nullptr;              // sorted moments FP32 (8 per particle)

@@ -85,38 +85,59 @@ hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s)
     return hipGetLastError();
 }
 
-// sorted moments: FP64 (w per particle) and FP32 (8 per particle; for
-// quadrupoles the 6 components and the trace)
-__global__ void prep_moments_kernel(int n, int w, const double *__restrict__ mom, const int32_t *__restrict__ perm,
+// sorted moments: FP64 (the caller's row of w values per particle) and FP32
+// (one order: 8 floats, q | mu | the six Q components and their trace;
+// several orders: 12 floats, [q mu] [xx xy xz yy] [yz zz tr 0], absent
+// parts zero)
+__global__ void prep_moments_kernel(int n, int mask, const double *__restrict__ mom, const int32_t *__restrict__ perm,
                                     double *__restrict__ m64, float *__restrict__ m32)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int w = mask_width(mask);
     const size_t j = (size_t)perm[i];
-    float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < w; ++k) {
-        const double a = mom[j * w + k];
-        m64[(size_t)i * w + k] = a;
-        v[k] = (float)a;
+    float v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < w; ++k) m64[(size_t)i * w + k] = mom[j * w + k];
+    if (mask_single(mask)) {
+        for (int k = 0; k < w; ++k) v[k] = (float)mom[j * w + k];
+        if (w == 6) v[6] = (float)(mom[j * 6 + 0] + mom[j * 6 + 3] + mom[j * 6 + 5]);
+        float4 *o = reinterpret_cast<float4 *>(m32) + 2 * (size_t)i;
+        o[0] = make_float4(v[0], v[1], v[2], v[3]);
+        o[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+        int off = 0;
+        const double *r = mom + j * w;
+        if (mask & 1) v[0] = (float)r[off++];
+        if (mask & 2) {
+            v[1] = (float)r[off];
+            v[2] = (float)r[off + 1];
+            v[3] = (float)r[off + 2];
+            off += 3;
+        }
+        if (mask & 4) {
+            for (int k = 0; k < 6; ++k) v[4 + k] = (float)r[off + k];
+            v[10] = (float)(r[off] + r[off + 3] + r[off + 5]);
+        }
+        float4 *o = reinterpret_cast<float4 *>(m32) + 3 * (size_t)i;
+        o[0] = make_float4(v[0], v[1], v[2], v[3]);
+        o[1] = make_float4(v[4], v[5], v[6], v[7]);
+        o[2] = make_float4(v[8], v[9], v[10], v[11]);
     }
-    if (w == 6) v[6] = (float)(mom[j * 6 + 0] + mom[j * 6 + 3] + mom[j * 6 + 5]);
-    float4 *o = reinterpret_cast<float4 *>(m32) + 2 * (size_t)i;
-    o[0] = make_float4(v[0], v[1], v[2], v[3]);
-    o[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s)
 {
     const int n = (int)t->ht.n;
-    const int w = t->order == 0 ? 1 : (t->order == 1 ? 3 : 6);
-    hipLaunchKernelGGL(prep_moments_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, w, t->mom_user, t->d_perm,
-                       t->d_mom, t->d_mom32);
+    hipLaunchKernelGGL(prep_moments_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, t->smask, t->mom_user,
+                       t->d_perm, t->d_mom, t->d_mom32);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ P2M
-// M~_n = r^-s sum_j sum_{sigma <= n, |sigma| = s} zeta_j^(n-sigma)/(n-sigma)! S_sigma(j)
-// with zeta = (z - x_j)/r and S_sigma = (-1)^s T_sigma / sigma! (Eq. 3, Eq. 5).
+// M~_n = sum_j sum_k r^-k sum_{sigma <= n, |sigma| = k} zeta_j^(n-sigma)/(n-sigma)! S_sigma(j)
+// with zeta = (z - x_j)/r and S_sigma = (-1)^k T_sigma / sigma! (Eq. 3, Eq. 5),
+// k over the source orders present (MASK bit k), so a system with several
+// orders adds each part's expansion.
 // One workgroup per leaf; a thread owns one or more coefficients n (its
 // multi-index is read once), particles are staged in LDS 32 at a time as
 // per-axis tables zeta^a / a!, so the inner loop touches LDS only.
@@ -136,23 +157,25 @@ constexpr InvTable make_inv()
 }
 __constant__ InvTable k_inv = make_inv();   // 1/a
 
-template <int S>
+template <int MASK>
 __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
                                                           const DevCell *__restrict__ cells, Geo g,
                                                           const double *__restrict__ xs, int n,
                                                           const double *__restrict__ mom, double *__restrict__ M,
                                                           float *__restrict__ M32)
 {
-    constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
+    constexpr int W = mask_width(MASK);
+    constexpr int S = mask_min_order(MASK);
+    constexpr bool Q0 = MASK & 1, Q1 = MASK & 2, Q2 = MASK & 4;
+    // source tensor slots: 0 order 0; 1..3 order 1; 4..9 order 2
     __shared__ double pw[kP2MStage][3][kAxW];
-    __shared__ double sv[kP2MStage][W];
+    __shared__ double sv[kP2MStage][10];
     const int c = leaves[blockIdx.x];
     const DevCell cell = cells[c];
     double z[3];
     cell_center(cell, g.lo, g.h, z);
     const double r = cell_radius(cell.level, g.h);
     const double ir = 1.0 / r;
-    const double irs = S == 0 ? 1.0 : (S == 1 ? ir : ir * ir);
     const int n0 = nterms(S - 1), nm = nterms(p) - n0;
     constexpr int KMAX = (nterms(kPTable) + kP2MThreads - 1) / kP2MThreads;
     double acc[KMAX];
@@ -184,19 +207,22 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
         if ((int)threadIdx.x < cnt) {
             const int t = threadIdx.x;
             const double *m = mom + ((size_t)cell.first + base + t) * W;
-            if (S == 0) {
-                sv[t][0] = m[0];
-            } else if (S == 1) {
-                sv[t][0] = -m[0] * irs;
-                sv[t][1] = -m[1] * irs;
-                sv[t][2] = -m[2] * irs;
-            } else {
-                sv[t][0] = 0.5 * m[0] * irs;   // (2,0,0)
-                sv[t][1] = m[1] * irs;         // (1,1,0)
-                sv[t][2] = m[2] * irs;         // (1,0,1)
-                sv[t][3] = 0.5 * m[3] * irs;   // (0,2,0)
-                sv[t][4] = m[4] * irs;         // (0,1,1)
-                sv[t][5] = 0.5 * m[5] * irs;   // (0,0,2)
+            int off = 0;
+            if (Q0) sv[t][0] = m[off++];
+            if (Q1) {
+                sv[t][1] = -m[off] * ir;
+                sv[t][2] = -m[off + 1] * ir;
+                sv[t][3] = -m[off + 2] * ir;
+                off += 3;
+            }
+            if (Q2) {
+                const double ir2 = ir * ir;
+                sv[t][4] = 0.5 * m[off] * ir2;       // (2,0,0)
+                sv[t][5] = m[off + 1] * ir2;         // (1,1,0)
+                sv[t][6] = m[off + 2] * ir2;         // (1,0,1)
+                sv[t][7] = 0.5 * m[off + 3] * ir2;   // (0,2,0)
+                sv[t][8] = m[off + 4] * ir2;         // (0,1,1)
+                sv[t][9] = 0.5 * m[off + 5] * ir2;   // (0,0,2)
             }
         }
         __syncthreads();
@@ -206,28 +232,27 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
             const int ax = ix[k], ay = iy[k], az = iz[k];
             double a = acc[k];
             for (int t = 0; t < cnt; ++t) {
-                if (S == 0) {
-                    a = fma(pw[t][0][ax] * pw[t][1][ay], pw[t][2][az] * sv[t][0], a);
-                } else if (S == 1) {
-                    // sigma = e_x, e_y, e_z; a zero table entry stands for a negative index
-                    const double px = pw[t][0][ax], py = pw[t][1][ay], pz = pw[t][2][az];
-                    const double pxm = ax ? pw[t][0][ax - 1] : 0.0, pym = ay ? pw[t][1][ay - 1] : 0.0,
-                                 pzm = az ? pw[t][2][az - 1] : 0.0;
-                    a = fma(pxm * py, pz * sv[t][0], a);
-                    a = fma(px * pym, pz * sv[t][1], a);
-                    a = fma(px * py, pzm * sv[t][2], a);
-                } else {
-                    const double px0 = pw[t][0][ax], py0 = pw[t][1][ay], pz0 = pw[t][2][az];
+                // a zero table entry stands for a negative index
+                const double px0 = pw[t][0][ax], py0 = pw[t][1][ay], pz0 = pw[t][2][az];
+                if (Q0) a = fma(px0 * py0, pz0 * sv[t][0], a);
+                if (Q1 || Q2) {
                     const double px1 = ax >= 1 ? pw[t][0][ax - 1] : 0.0, py1 = ay >= 1 ? pw[t][1][ay - 1] : 0.0,
                                  pz1 = az >= 1 ? pw[t][2][az - 1] : 0.0;
-                    const double px2 = ax >= 2 ? pw[t][0][ax - 2] : 0.0, py2 = ay >= 2 ? pw[t][1][ay - 2] : 0.0,
-                                 pz2 = az >= 2 ? pw[t][2][az - 2] : 0.0;
-                    a = fma(px2 * py0, pz0 * sv[t][0], a);
-                    a = fma(px1 * py1, pz0 * sv[t][1], a);
-                    a = fma(px1 * py0, pz1 * sv[t][2], a);
-                    a = fma(px0 * py2, pz0 * sv[t][3], a);
-                    a = fma(px0 * py1, pz1 * sv[t][4], a);
-                    a = fma(px0 * py0, pz2 * sv[t][5], a);
+                    if (Q1) {
+                        a = fma(px1 * py0, pz0 * sv[t][1], a);
+                        a = fma(px0 * py1, pz0 * sv[t][2], a);
+                        a = fma(px0 * py0, pz1 * sv[t][3], a);
+                    }
+                    if (Q2) {
+                        const double px2 = ax >= 2 ? pw[t][0][ax - 2] : 0.0, py2 = ay >= 2 ? pw[t][1][ay - 2] : 0.0,
+                                     pz2 = az >= 2 ? pw[t][2][az - 2] : 0.0;
+                        a = fma(px2 * py0, pz0 * sv[t][4], a);
+                        a = fma(px1 * py1, pz0 * sv[t][5], a);
+                        a = fma(px1 * py0, pz1 * sv[t][6], a);
+                        a = fma(px0 * py2, pz0 * sv[t][7], a);
+                        a = fma(px0 * py1, pz1 * sv[t][8], a);
+                        a = fma(px0 * py0, pz2 * sv[t][9], a);
+                    }
                 }
             }
             acc[k] = a;
@@ -242,21 +267,28 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
         }
 }
 
-hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
+template <int MASK>
+static void p2m_launch(fmm_tree *t, hipStream_t s)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
-    const dim3 gr((unsigned)t->nleaves), bl(kP2MThreads);
     float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
-    if (t->order == 0)
-        hipLaunchKernelGGL(p2m_kernel<0>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64, m32);
-    else if (t->order == 1)
-        hipLaunchKernelGGL(p2m_kernel<1>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64, m32);
-    else
-        hipLaunchKernelGGL(p2m_kernel<2>, gr, bl, 0, s, t->p, nmp, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n,
-                           t->d_mom, t->d_M64, m32);
+    hipLaunchKernelGGL(p2m_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp, t->d_leaves,
+                       t->d_cells, g, t->d_x, (int)t->ht.n, t->d_mom, t->d_M64, m32);
+}
+
+hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
+{
+    switch (t->smask) {
+    case 1: p2m_launch<1>(t, s); break;
+    case 2: p2m_launch<2>(t, s); break;
+    case 3: p2m_launch<3>(t, s); break;
+    case 4: p2m_launch<4>(t, s); break;
+    case 5: p2m_launch<5>(t, s); break;
+    case 6: p2m_launch<6>(t, s); break;
+    case 7: p2m_launch<7>(t, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -556,10 +588,27 @@ __device__ __forceinline__ int p2p_entry(const int *wstart, int nw, int j)
     return lo;
 }
 
-template <int S>
+// the pair terms of one source of several orders: each order's terms go to
+// its own sums (the orders scale differently with the leaf radius)
+template <int MASK>
+__device__ __forceinline__ void p2p_pair_mixed(float rx, float ry, float rz, float inv, const float4 &m0,
+                                               const float4 &m1, const float4 &m2, float (&bp)[3], float (&bx)[3],
+                                               float (&by)[3], float (&bz)[3])
+{
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (MASK & 1) p2p_pair_f32<0>(rx, ry, rz, inv, m0, z4, bp[0], bx[0], by[0], bz[0]);
+    if (MASK & 2)
+        p2p_pair_f32<1>(rx, ry, rz, inv, make_float4(m0.y, m0.z, m0.w, 0.f), z4, bp[1], bx[1], by[1], bz[1]);
+    if (MASK & 4) p2p_pair_f32<2>(rx, ry, rz, inv, m1, m2, bp[2], bx[2], by[2], bz[2]);
+}
+
+template <int MASK>
 __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
 {
-    constexpr int NV = S == 2 ? 2 : 1;   // float4 of moments per staged source
+    constexpr bool ONE = mask_single(MASK);
+    constexpr int S = mask_min_order(MASK);
+    constexpr int NV = ONE ? (S == 2 ? 2 : 1) : 3;   // float4 of moments per staged source
+    constexpr int MW = m32_width(MASK) / 4;          // float4 of moments per particle
     __shared__ double spx[kPChunk32], spy[kPChunk32], spz[kPChunk32];
     __shared__ float4 spm[NV][kPChunk32];
     __shared__ int wstart[kPList], wfirst[kPList];
@@ -573,7 +622,14 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
     const DevCell cb = a.cells[b];
     const double rb = ldexp(1.0, kMaxLevel - cb.level) * a.h;
     const double irb = 1.0 / rb;
-    const double sphi = 1.0 / pow(rb, (double)(S + 1)), sfld = sphi / rb;
+    // physical scale of the order-k sums: potential r_b^-(k+1), field r_b^-(k+2)
+    double sphi[3], sfld[3];
+    sphi[0] = irb;
+    sphi[1] = irb * irb;
+    sphi[2] = sphi[1] * irb;
+    sfld[0] = sphi[1];
+    sfld[1] = sphi[2];
+    sfld[2] = sphi[2] * irb;
     double zb[3];
     {
         const double r = ldexp(1.0, kMaxLevel - cb.level);
@@ -595,7 +651,9 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
         // close pairs keep their relative accuracy
         const double tx = (a.xs[i] - zb[0]) * irb, ty = (a.xs[n + i] - zb[1]) * irb,
                      tz = (a.xs[2 * n + i] - zb[2]) * irb;
-        float ps = 0.f, pc = 0.f, xs_ = 0.f, xc = 0.f, ys = 0.f, yc = 0.f, zs = 0.f, zc = 0.f;
+        // Kahan-compensated sums per source order
+        float ps[3] = {0.f, 0.f, 0.f}, pc[3] = {0.f, 0.f, 0.f}, xs_[3] = {0.f, 0.f, 0.f}, xc[3] = {0.f, 0.f, 0.f};
+        float ys[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f}, zs[3] = {0.f, 0.f, 0.f}, zc[3] = {0.f, 0.f, 0.f};
         for (int w0 = e0; w0 < e1; w0 += kPList) {
             const int nw = min(kPList, e1 - w0);
             __syncthreads();
@@ -611,36 +669,55 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                     spx[j] = (a.xs[pj] - zb[0]) * irb;
                     spy[j] = (a.xs[n + pj] - zb[1]) * irb;
                     spz[j] = (a.xs[2 * n + pj] - zb[2]) * irb;
-                    spm[0][j] = m4[2 * pj];
-                    if (S == 2) spm[S == 2 ? 1 : 0][j] = m4[2 * pj + 1];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) spm[v][j] = m4[MW * pj + v];
                 }
                 __syncthreads();
                 if (act) {
                     const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
                     // the target itself, if it is staged in this chunk
                     const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
-                    float bp = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+                    float bp[3] = {0.f, 0.f, 0.f}, bx[3] = {0.f, 0.f, 0.f}, by[3] = {0.f, 0.f, 0.f},
+                          bz[3] = {0.f, 0.f, 0.f};
                     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     for (int j = ja; j < jb; ++j) {
                         const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
                         const float inv = j == jself ? 0.f : __builtin_amdgcn_rsqf(r2);
                         const float4 m0 = spm[0][j];
-                        const float4 m1 = S == 2 ? spm[S == 2 ? 1 : 0][j] : zero4;
-                        p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp, bx, by, bz);
+                        const float4 m1 = NV >= 2 ? spm[NV >= 2 ? 1 : 0][j] : zero4;
+                        if (ONE) {
+                            p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp[S], bx[S], by[S], bz[S]);
+                        } else {
+                            const float4 m2 = spm[NV >= 3 ? 2 : 0][j];
+                            p2p_pair_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bp, bx, by, bz);
+                        }
                     }
-                    kahan_add(ps, pc, bp);
-                    kahan_add(xs_, xc, bx);
-                    kahan_add(ys, yc, by);
-                    kahan_add(zs, zc, bz);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        if (!(MASK & (1 << k))) continue;
+                        kahan_add(ps[k], pc[k], bp[k]);
+                        kahan_add(xs_[k], xc[k], bx[k]);
+                        kahan_add(ys[k], yc[k], by[k]);
+                        kahan_add(zs[k], zc[k], bz[k]);
+                    }
                 }
             }
         }
         __syncthreads();
-        red[0][tid] = act ? (double)ps - (double)pc : 0.0;
-        red[1][tid] = act ? (double)xs_ - (double)xc : 0.0;
-        red[2][tid] = act ? (double)ys - (double)yc : 0.0;
-        red[3][tid] = act ? (double)zs - (double)zc : 0.0;
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (!(MASK & (1 << k))) continue;
+            q0 += ((double)ps[k] - (double)pc[k]) * sphi[k];
+            q1 += ((double)xs_[k] - (double)xc[k]) * sfld[k];
+            q2 += ((double)ys[k] - (double)yc[k]) * sfld[k];
+            q3 += ((double)zs[k] - (double)zc[k]) * sfld[k];
+        }
+        red[0][tid] = act ? q0 : 0.0;
+        red[1][tid] = act ? q1 : 0.0;
+        red[2][tid] = act ? q2 : 0.0;
+        red[3][tid] = act ? q3 : 0.0;
         __syncthreads();
         if (tid < cs) {
             double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
@@ -651,18 +728,18 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                 v3 += red[3][tid + k * cs];
             }
             double *o = a.near + 4 * (size_t)i;
-            o[0] = v0 * sphi;
-            o[1] = v1 * sfld;
-            o[2] = v2 * sfld;
-            o[3] = v3 * sfld;
+            o[0] = v0;
+            o[1] = v1;
+            o[2] = v2;
+            o[3] = v3;
         }
     }
 }
 
-template <int S>
+template <int MASK>
 __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
 {
-    constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
+    constexpr int W = mask_width(MASK);
     __shared__ double sx[kPChunk64], sy[kPChunk64], sz[kPChunk64], sm[W][kPChunk64];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
@@ -711,7 +788,10 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
                         double m[W];
 #pragma unroll
                         for (int c = 0; c < W; ++c) m[c] = sm[c][j];
-                        p2p_pair_f64<S>(rx, ry, rz, m, ph, ex, ey, ez);
+                        // a source of several orders adds each order's terms
+                        if (MASK & 1) p2p_pair_f64<0>(rx, ry, rz, m, ph, ex, ey, ez);
+                        if (MASK & 2) p2p_pair_f64<1>(rx, ry, rz, m + (MASK & 1), ph, ex, ey, ez);
+                        if (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
                     }
                 }
             }
@@ -751,15 +831,23 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
     a.h = t->ht.h;
     a.order = t->d_p2p_order;
     const dim3 g((unsigned)t->nleaves), bl(kPT);
-    if (t->prec == FMM_PREC_MIXED) {
-        if (t->order == 0) hipLaunchKernelGGL(p2p_f32_kernel<0>, g, bl, 0, s, a);
-        else if (t->order == 1) hipLaunchKernelGGL(p2p_f32_kernel<1>, g, bl, 0, s, a);
-        else hipLaunchKernelGGL(p2p_f32_kernel<2>, g, bl, 0, s, a);
-    } else {
-        if (t->order == 0) hipLaunchKernelGGL(p2p_f64_kernel<0>, g, bl, 0, s, a);
-        else if (t->order == 1) hipLaunchKernelGGL(p2p_f64_kernel<1>, g, bl, 0, s, a);
-        else hipLaunchKernelGGL(p2p_f64_kernel<2>, g, bl, 0, s, a);
+    const bool f32 = t->prec == FMM_PREC_MIXED;
+#define P2P_CASE(M)                                                                         \
+    case M:                                                                                 \
+        if (f32) hipLaunchKernelGGL(p2p_f32_kernel<M>, g, bl, 0, s, a);                     \
+        else hipLaunchKernelGGL(p2p_f64_kernel<M>, g, bl, 0, s, a);                         \
+        break;
+    switch (t->smask) {
+        P2P_CASE(1)
+        P2P_CASE(2)
+        P2P_CASE(3)
+        P2P_CASE(4)
+        P2P_CASE(5)
+        P2P_CASE(6)
+        P2P_CASE(7)
+    default: return hipErrorInvalidValue;
     }
+#undef P2P_CASE
     return hipGetLastError();
 }
 

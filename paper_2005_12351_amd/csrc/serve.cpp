@@ -64,9 +64,10 @@ struct Server {
 // tiles and partial results (~2 kB), plus a fixed 4 MB for derivative tables.
 static size_t footprint_estimate(const fmm_request &r)
 {
-    const double w = r.order == 0 ? 1 : (r.order == 1 ? 3 : 6);
+    const int mask = code_mask(r.order), s = mask_min_order(mask);
+    const double w = mask_width(mask);
     const double cells = std::max(1.0, 2.3 * (double)r.n / std::max(1, r.ncrit));
-    const double nm = nterms(r.p) - nterms(r.order - 1), nl = nterms(std::max(0, r.p - r.order));
+    const double nm = nterms(r.p) - nterms(s - 1), nl = nterms(std::max(0, r.p - s));
     const double per_part = 112.0 + 8.0 * w;
     const double per_cell = 48.0 + nm * 12.0 + nl * 24.0 + 2048.0;
     return (size_t)(per_part * (double)r.n + per_cell * cells + 4.0 * (1 << 20));
@@ -226,8 +227,10 @@ extern "C" int fmm_submit(fmm_ctx *ctx, const fmm_request *req, uint64_t *ticket
         return FMM_ESTATE;
     }
     const fmm_request &r = *req;
-    const int pmin = r.method == FMM_METHOD_BH ? std::max(r.order, 1) : r.order + 1;
-    if (r.n < 1 || r.order < 0 || r.order > 2 || r.p < pmin || r.p > FMM_P_MAX || r.ncrit < 1 ||
+    const bool code_ok = (r.order >= 0 && r.order <= 2) || (r.order > FMM_MIXED && r.order < FMM_MIXED + 8);
+    const int s = code_ok ? mask_min_order(code_mask(r.order)) : 0;
+    const int pmin = r.method == FMM_METHOD_BH ? std::max(s, 1) : s + 1;
+    if (r.n < 1 || !code_ok || r.p < pmin || r.p > FMM_P_MAX || r.ncrit < 1 ||
         !(r.theta > 0.0 && r.theta < 1.0) || (r.method != FMM_METHOD_FMM && r.method != FMM_METHOD_BH) ||
         (r.precision != FMM_PREC_FP64 && r.precision != FMM_PREC_MIXED) || r.outputs <= 0 ||
         (r.outputs & ~(FMM_POT | FMM_FIELD))) {

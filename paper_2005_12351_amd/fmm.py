@@ -23,6 +23,7 @@ FMM_POT, FMM_FIELD = 1, 2
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
 FMM_P_MAX = 10
+FMM_MIXED = 16          # order code FMM_MIXED | mask: several source orders (bit k: order k)
 FMM_REQ_QUEUED, FMM_REQ_RUNNING, FMM_REQ_DONE, FMM_REQ_FAILED = range(4)
 
 if not os.path.exists(LIB_PATH):

@@ -124,6 +124,35 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
             "note": "latency = done - arrival; it includes the tree build of each request"}
 
 
+def accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, Ed, theta=0.3, p=10):
+    """The same particles at the smallest (theta, p) of a sweep (theta 0.5,
+    0.4, 0.3; p 6, 8, 10) whose truncation error against the direct sum is
+    below 1e-6 for both phi and E (theta 0.3, p 10; the literal parameters
+    give 1.8e-4 / 1e-5 with the half-side cell radius).  Reported beside the
+    headline, errors measured on the sampled targets."""
+    import oracle
+    tree = fmm.Tree(ctx, pos, w.ncrit, theta)
+    phi = torch.empty(w.n, dtype=torch.float64, device=dev)
+    fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+    out = {"theta": theta, "p": p, "info": tree.info()}
+    for name, prec in (("mixed", fmm.FMM_PREC_MIXED), ("fp64", fmm.FMM_PREC_FP64)):
+        ctx.set_overlap(False)
+        for _ in range(3):
+            tree.run(w.order, mom, p, prec, outputs, phi, fld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = max(3, args.steps // 2)
+        for _ in range(k):
+            tree.run(w.order, mom, p, prec, outputs, phi, fld)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        ph, E = phi.cpu().numpy(), fld.cpu().numpy()
+        out[name] = {"value": w.n / dt, "unit": "evals/s", "ms_per_step": dt * 1e3,
+                     "phi_vs_direct": oracle.rel_l2(ph[sample], pd), "E_vs_direct": oracle.rel_l2(E[sample], Ed)}
+    tree.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +167,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the run at the smallest (theta, p) that reaches 1e-6 against the direct sum")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -301,6 +332,8 @@ def main():
             errs[name] = e
         errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s" % (len(sample), kind)
         line["rel_l2_error"] = errs
+        if not args.no_accuracy and not bh and args.config == 2:
+            line["at_1e-6"] = accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, Ed)
     if not args.no_serve:
         line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests)
     print(json.dumps(line), flush=True)

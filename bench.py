@@ -135,8 +135,11 @@ def accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, E
     phi = torch.empty(w.n, dtype=torch.float64, device=dev)
     fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     out = {"theta": theta, "p": p, "info": tree.info()}
-    for name, prec in (("mixed", fmm.FMM_PREC_MIXED), ("fp64", fmm.FMM_PREC_FP64)):
+    runs = (("mixed", fmm.FMM_PREC_MIXED, fmm.FMM_M2L_HARMONIC), ("fp64", fmm.FMM_PREC_FP64, fmm.FMM_M2L_HARMONIC),
+            ("mixed_full_basis", fmm.FMM_PREC_MIXED, fmm.FMM_M2L_FULL))
+    for name, prec, basis in runs:
         ctx.set_overlap(False)
+        ctx.set_m2l_basis(basis)
         for _ in range(3):
             tree.run(w.order, mom, p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
@@ -149,6 +152,7 @@ def accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, E
         ph, E = phi.cpu().numpy(), fld.cpu().numpy()
         out[name] = {"value": w.n / dt, "unit": "evals/s", "ms_per_step": dt * 1e3,
                      "phi_vs_direct": oracle.rel_l2(ph[sample], pd), "E_vs_direct": oracle.rel_l2(E[sample], Ed)}
+    ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     tree.close()
     return out
 
@@ -237,6 +241,17 @@ def main():
         prof, work = kernel_pass(prec, args.steps)
         res[name] = dict(step_s=step_s, prof=prof, out=(None if out[0] is None else out[0].cpu().numpy(),
                                                          out[1].cpu().numpy()), work=work)
+    full_basis = None
+    if not bh:
+        # the same MIXED steps with the M2L contracting every Cartesian component
+        ctx.set_m2l_basis(fmm.FMM_M2L_FULL)
+        step_s, _ = run(fmm.FMM_PREC_MIXED, args.steps, args.warmup)
+        prof, work = kernel_pass(fmm.FMM_PREC_MIXED, args.steps)
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+        k_ms = prof["m2l"][0] / max(1, prof["m2l"][1])
+        full_basis = {"value": w.n / step_s, "unit": "evals/s", "ms_per_step": step_s * 1e3,
+                      "m2l_avg_launch_ms": k_ms, "m2l_flops_per_launch": work["m2l_flops"],
+                      "m2l_achieved_tflops": work["m2l_flops"] / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None}
 
     def kavg(prof, k):
         v = prof.get(k)
@@ -263,7 +278,8 @@ def main():
         m2l_ms, p2p_ms = kavg(m["prof"], "m2l"), kavg(m["prof"], "p2p")
         m2l_flops = m["work"]["m2l_flops"]
         achieved = m2l_flops / (m2l_ms * 1e-3) if m2l_ms > 0 else None
-        roofline = {"bound": "alu", "kernel": "m2l (FP32)", "achieved": achieved / 1e12 if achieved else None,
+        roofline = {"bound": "alu", "kernel": "m2l (FP32, harmonic basis)",
+                    "achieved": achieved / 1e12 if achieved else None,
                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                     "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
                     "traffic": _traffic("m2l_c%d_mixed" % args.config),
@@ -285,8 +301,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
                    "ncrit": w.ncrit, "outputs": w.outputs,
-                   "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)"},
+                   "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)",
+                   **({} if bh else {"m2l_basis": "harmonic"})},
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
+        **({} if bh else {"m2l_full_basis": full_basis}),
         "kernel_timing": "separate pass of the same steps, kernels serialised, HIP events on the launch stream",
         "kernel_avg_ms_mixed": kern_ms,
         "kernel_avg_ms_fp64": {k: v[0] / max(1, v[1]) for k, v in f64["prof"].items()},

@@ -63,6 +63,7 @@ enum {
 
 enum { FMM_POT = 1, FMM_FIELD = 2 };               /* output bit mask */
 enum { FMM_METHOD_FMM = 0, FMM_METHOD_BH = 1 };
+enum { FMM_M2L_FULL = 0, FMM_M2L_HARMONIC = 1 };   /* see fmm_ctx_set_m2l_basis */
 enum {
     FMM_PREC_FP64 = 0,   /* every operator in IEEE double on the GPU */
     FMM_PREC_MIXED = 1   /* M2L, M2P and P2P in FP32 (P2P compensated),
@@ -156,6 +157,19 @@ int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
  * which removes the per-kernel launch cost.  Graphs are never used while
  * profiling is enabled.  Off: kernels are launched one by one. */
 int fmm_ctx_set_graphs(fmm_ctx *ctx, int on);
+
+/* Basis of the M2L contraction of FMM trees (Eq. 8 and the Discussion's
+ * irreducible representation).  FMM_M2L_FULL contracts every Cartesian
+ * component.  FMM_M2L_HARMONIC (default) uses that the derivative tensor of
+ * 1/r is harmonic (D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0): each multipole
+ * is folded once onto its components with m_z <= 1, the contraction runs on
+ * those and yields the local components with n_z <= 1, and the remaining
+ * local components follow from the same identity.  Order l then carries
+ * 2l+1 components instead of (l+1)(l+2)/2 (at p = 8, s = 1: 1 284
+ * multiply-adds per list entry instead of 2 838).  In exact arithmetic both
+ * give the same locals; they differ by rounding only.  Takes effect at the
+ * next fmm_upward / fmm_run of a tree.  FMM_EINVAL for another value. */
+int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis);
 
 /* Per-kernel device timing.  When enabled, every kernel launch is bracketed
  * by HIP events on the stream it runs on.  fmm_profile_read synchronises and

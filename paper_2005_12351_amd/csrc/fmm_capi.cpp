@@ -80,6 +80,14 @@ extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
     return FMM_OK;
 }
 
+extern "C" int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    if (basis != FMM_M2L_FULL && basis != FMM_M2L_HARMONIC) FAIL(FMM_EINVAL, "unknown M2L basis %d", basis);
+    ctx->m2l_basis = basis;   // trees pick it up at their next upward pass
+    return FMM_OK;
+}
+
 extern "C" int fmm_ctx_set_graphs(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
@@ -440,9 +448,13 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 {
     const int smask = code_mask(code), order = mask_min_order(smask);
-    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec) return FMM_OK;
+    const bool fmm = t->method == FMM_METHOD_FMM;
+    const int basis = fmm ? t->ctx->m2l_basis : FMM_M2L_FULL;
+    const bool harm = basis == FMM_M2L_HARMONIC;
+    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis)
+        return FMM_OK;
     drop_graphs(t);
-    for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32,
+    for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32, &t->d_Mh,
                       (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_D64,
                       (void **)&t->d_D32, (void **)&t->d_sc64, (void **)&t->d_sc32, (void **)&t->d_work,
                       (void **)&t->d_tile_chunk0, (void **)&t->d_tile_nchunk, (void **)&t->d_wave_ptr}) {
@@ -458,13 +470,16 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         (rc = tree_alloc(t, (void **)&t->d_M64, sizeof(double) * (nc + 1) * nmp)) ||
         (rc = tree_alloc(t, (void **)&t->d_near, sizeof(double) * 4 * n)))
         return rc;
-    if (prec == FMM_PREC_MIXED && (rc = tree_alloc(t, (void **)&t->d_M32, sizeof(float) * (nc + 1) * nmp))) return rc;
+    // the full FP32 copy feeds the full-basis M2L and the Barnes-Hut M2P
+    if (prec == FMM_PREC_MIXED && !harm && (rc = tree_alloc(t, (void **)&t->d_M32, sizeof(float) * (nc + 1) * nmp)))
+        return rc;
     if (t->method == FMM_METHOD_BH && !t->d_bhcount &&
         (rc = tree_alloc(t, (void **)&t->d_bhcount, 2 * sizeof(unsigned long long))))
         return rc;
-    if (t->method == FMM_METHOD_FMM) {
+    if (fmm) {
         M2LVariant v;
-        if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, &v)) FAIL(FMM_EINVAL, "no M2L kernel for p=%d s=%d", p, order);
+        if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, harm, &v))
+            FAIL(FMM_EINVAL, "no M2L kernel for p=%d s=%d", p, order);
         const size_t es = prec == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
         const int nc_ = std::max(1, t->tiling.nclasses);
         const int scw = (p + 1 + 3) / 4 * 4;
@@ -490,6 +505,12 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             (rc = tree_alloc(t, (void **)&t->d_sc64, sizeof(double) * nc_ * scw)) ||
             (rc = tree_alloc(t, (void **)&t->d_sc32, sizeof(float) * nc_ * scw)))
             return rc;
+        // reduced multipole rows, plus the zero row that padded slots read
+        if (harm && (rc = tree_alloc(t, &t->d_Mh, es * (size_t)(nc + 1) * v.nm_pad))) return rc;
+        if (harm) {
+            hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * v.nm_pad / 8, t->ctx->stream);
+            if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+        }
     }
     if (t->method == FMM_METHOD_FMM && t->l2p_pack_q != p - order) {
         // L2P waves: consecutive leaves while they hold at most 64 particles
@@ -517,14 +538,15 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
     // P2M and M2M write the FP32 copy too; the rest (the zero row the padded
     // M2L slots read, unused levels) stays zero (nmp is a multiple of 4)
-    if (e == hipSuccess && prec == FMM_PREC_MIXED)
+    if (e == hipSuccess && t->d_M32)
         e = launch_fill((double *)t->d_M32, (size_t)(nc + 1) * nmp / 2, t->ctx->stream);
     if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
     t->order = order;
     t->smask = smask;
     t->p = p;
     t->prec = prec;
-    if (t->method == FMM_METHOD_FMM) {
+    t->basis = basis;
+    if (fmm) {
         // derivative tensors of the translation classes depend on p only
         e = launch_dtable(t, t->ctx->stream);
         if (e != hipSuccess) FAIL(FMM_EDEVICE, "dtable failed: %s", hipGetErrorString(e));
@@ -594,6 +616,7 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
         ProfScope ps(ctx, s, "m2m");
         KCHK(launch_m2m_level(t, l, s));
     }
+
     if (join && a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     return FMM_OK;
 }
@@ -644,12 +667,18 @@ static void set_work_counts(fmm_tree *t)
     const int s_ = t->order, p = t->p;
     const int64_t nc = t->ht.ncells();
     const int nl = nterms(p - s_);
+    const bool harm = t->basis == FMM_M2L_HARMONIC;
+    // multiply-adds per list entry: outputs of order k times inputs of
+    // orders s..p-k, all components or (harmonic basis) 2l+1 per order l
     double fc = 0;
-    for (int k = 0; k <= p - s_; ++k) fc += (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
+    for (int k = 0; k <= p - s_; ++k)
+        fc += harm ? (double)(2 * k + 1) * (hterms(p - k) - hterms(s_ - 1))
+                   : (double)((k + 1) * (k + 2) / 2) * (nterms(p - k) - nterms(s_ - 1));
     const size_t es = t->prec == FMM_PREC_MIXED ? 4 : 8;
     t->work[1] = 2.0 * fc * t->work[0];
     t->work[3] = p2p_flops_mask(t->smask) * t->work[2];
-    t->work[6] = (double)nc * (double)(nterms(p) - nterms(s_ - 1) + nl) * es;
+    t->work[6] = harm ? (double)nc * (double)(hterms(p) - hterms(s_ - 1) + hterms(p - s_)) * es
+                      : (double)nc * (double)(nterms(p) - nterms(s_ - 1) + nl) * es;
     t->work[7] = (double)t->ht.n * (es * (4 + 8) + 32);
 }
 

@@ -36,6 +36,39 @@ __host__ __device__ constexpr bool mask_single(int m) { return m == 1 || m == 2 
 // trace), 12 for several ([q mu] [xx xy xz yy] [yz zz tr 0], absent parts 0)
 __host__ __device__ constexpr int m32_width(int m) { return mask_single(m) ? 8 : 12; }
 
+// Harmonic (reduced) basis: the components with n_z <= 1 of every order, in
+// storage order; order l holds 2l+1 of them and starts at index l^2.
+__host__ __device__ constexpr int hindex(int nx, int ny, int nz)
+{
+    return (nx + ny + nz) * (nx + ny + nz) + (ny + nz == 0 ? 0 : 2 * (ny + nz) - 1 + nz);
+}
+__host__ __device__ constexpr int hterms(int p) { return p < 0 ? 0 : (p + 1) * (p + 1); }
+
+// Harmonic-basis component h of a multipole row (row indexed by mindex):
+// for (a, b, r) = the h-th component with r <= 1,
+//   sum_j (-1)^j sum_i C(j,i) row[(a - 2i, b - 2(j - i), r + 2j)],
+// which carries the row's contraction with any harmonic tensor D (such as
+// the derivatives of 1/r, D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0) onto the
+// components with m_z <= 1 without changing it; the order is kept.
+__device__ inline double fold_component(const double *row, int h)
+{
+    int l = 0;
+    while ((l + 1) * (l + 1) <= h) ++l;
+    const int rem = h - l * l, t = (rem + 1) / 2, r = rem == 0 ? 0 : (rem + 1) % 2;
+    const int a = l - t, b = t - r;
+    double acc = 0.0;
+    for (int j = 0; 2 * j <= a + b; ++j) {
+        double sj = 0.0, c = 1.0;   // c = C(j, i)
+        for (int i = 0; i <= j; ++i) {
+            const int ax = a - 2 * i, by = b - 2 * (j - i);
+            if (ax >= 0 && by >= 0) sj = fma(c, row[mindex(ax, by, r + 2 * j)], sj);
+            c = c * (j - i) / (i + 1);
+        }
+        acc += (j & 1) ? -sj : sj;
+    }
+    return acc;
+}
+
 // multi-indices in storage order (total order ascending; within an order
 // n_x descending, then n_y descending), up to order kPTable
 struct MITable {
@@ -134,7 +167,7 @@ struct M2LVariant {
     int blo[17];               // output blocks: coefficients [blo[b], blo[b+1])
     int bfma[16];              // multiply-adds per list entry in each block
 };
-bool m2l_lookup(int p, int s, bool fp32, M2LVariant *out);
+bool m2l_lookup(int p, int s, bool fp32, bool harmonic, M2LVariant *out);
 void build_m2l_work(const M2LTiling &tl, const M2LVariant &v, int nwaves, M2LWork &out);
 
 // ------------------------------------------------------------------ context
@@ -148,6 +181,7 @@ struct fmm_ctx {
     bool profile = false;
     bool overlap = false;                 // P2P on the auxiliary stream
     bool graphs = true;                   // replay captured HIP graphs
+    int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     hipEvent_t ev_fork = nullptr;
@@ -188,11 +222,13 @@ struct fmm_tree {
     // per expansion state
     int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;   // order: the lowest source order s
     int smask = 1;                         // source orders present (bit mask)
+    int basis = FMM_M2L_FULL;              // M2L basis the expansions were set up for
     const double *mom_user = nullptr;
     double *d_mom = nullptr;               // sorted moments FP64 (w per particle)
     float *d_mom32 = nullptr;              // sorted moments FP32 (8 per particle)
     double *d_M64 = nullptr;
     float *d_M32 = nullptr;
+    void *d_Mh = nullptr;                  // harmonic basis: reduced multipole rows (M2L precision)
     void *d_part = nullptr;
     double *d_L64 = nullptr;
     double *d_near = nullptr;              // 4 per particle

@@ -23,7 +23,19 @@ every SIMD finishes together although the blocks differ in work by up to 10x;
 a wave writes its partial sums only where its range crosses a (tile, block)
 boundary.
 
-Usage: python gen_m2l.py OUTDIR  -> OUTDIR/m2l_s{0,1,2}_{f32,f64}.hip
+Harmonic basis.  The derivative tensor of 1/r is harmonic: for every k,
+D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0, hence
+D_{k+2j e_z} = (-1)^j sum_i C(j,i) D_{k+2i e_x+2(j-i) e_y}.  A multipole
+row folded onto the components with m_z <= 1 (done once per cell, as P2M
+and M2M write the row) therefore gives the same sums, and the locals, whose
+truncation |m| <= p - |n| is the same for n+2e_x, n+2e_y and n+2e_z, obey
+the same identity, so only their components with n_z <= 1 are computed and
+the rest is rebuilt afterwards.  Order l then holds 2l+1 components instead
+of (l+1)(l+2)/2: the irreducible count the paper's Discussion refers to.
+The "_h" kernels contract these reduced rows; the term lists are the same
+construction restricted to the reduced components.
+
+Usage: python gen_m2l.py OUTDIR  -> OUTDIR/m2l_s{0,1,2}_{f32,f64}[_h].hip
 """
 import os
 import sys
@@ -60,17 +72,21 @@ def pad(x, m):
     return (x + m - 1) // m * m
 
 
-def split_blocks(p, s, max_acc):
+def reduced(mis):
+    """The components with n_z <= 1 (the harmonic basis), in storage order."""
+    return [n for n in mis if n[2] <= 1]
+
+
+def split_blocks(nl, max_acc):
     """Fewest contiguous n-ranges [a, b) of nearly equal size with at most
     max_acc accumulators each (every block re-reads the multipole
     coefficients it needs, so fewer blocks means less gather traffic)."""
-    nl = nterms(p - s)
     nb = max(1, -(-nl // max_acc))
     assert nb <= 16, 'at most 16 output blocks'
     return [(nl * i // nb, nl * (i + 1) // nb) for i in range(nb)]
 
 
-def gen_kernel(p, s, fp32, opt=None):
+def gen_kernel(p, s, fp32, opt=None, harmonic=False):
     """One kernel per (p, s, precision).  Work split: blockIdx.x = work item
     (tile, entry range, output row), blockIdx.y = block of output
     coefficients.  Inside a block the needed multipole coefficients are loaded
@@ -85,8 +101,12 @@ def gen_kernel(p, s, fp32, opt=None):
     VW = 4 if fp32 else 2
     fma = "__builtin_fmaf" if fp32 else "__builtin_fma"
     suf = "f32" if fp32 else "f64"
-    nm = nterms(p) - nterms(s - 1)
-    nl = nterms(p - s)
+    ns = orders(p - s)
+    ms = orders(p)[nterms(s - 1):]
+    if harmonic:
+        ns, ms = reduced(ns), reduced(ms)
+    nm = len(ms)
+    nl = len(ns)
     nmp = pad(nm, 4)
     nlp = pad(nl, 4)
     nd = pad(nterms(p), 16)
@@ -95,10 +115,8 @@ def gen_kernel(p, s, fp32, opt=None):
     max_acc = opt["acc32"] if fp32 else opt["acc64"]
     max_m = opt["m32"] if fp32 else opt["m64"]
     dgroup = opt["dgroup32"] if fp32 else opt["dgroup64"]
-    blocks = split_blocks(p, s, max_acc)
-    ns = orders(p - s)
-    ms = orders(p)[nterms(s - 1):]
-    name = f"m2l_p{p}_s{s}_{suf}"
+    blocks = split_blocks(nl, max_acc)
+    name = f"m2l_p{p}_s{s}_{suf}" + ("_h" if harmonic else "")
     L = []
     L.append(f"__global__ __launch_bounds__({TILE}) void {name}(M2LArgs a)")
     L.append("{")
@@ -265,18 +283,18 @@ static int occ_{name}()
 """
     fma_per_block = []
     for (n0, n1) in blocks:
-        fma_per_block.append(sum(nterms(p - sum(ns[i])) - nterms(s - 1) for i in range(n0, n1)))
+        fma_per_block.append(sum(1 for i in range(n0, n1) for m in ms if sum(m) + sum(ns[i]) <= p))
     meta = dict(name=name, nl_pad=nlp, nm_pad=nmp, nd=nd, nblocks=len(blocks), scw=scw,
                 blo=[b[0] for b in blocks] + [blocks[-1][1]], bfma=fma_per_block)
     return "\n".join(L) + "\n" + launcher, meta
 
 
-def gen_file(s, fp32, opt=None):
-    suf = "f32" if fp32 else "f64"
+def gen_file(s, fp32, opt=None, harmonic=False):
+    suf = ("f32" if fp32 else "f64") + ("_h" if harmonic else "")
     parts = ["// Generated by gen_m2l.py; do not edit.", "#include <algorithm>", '#include "fmm_internal.h"', ""]
     metas = []
     for p in range(s + 1, P_MAX + 1):
-        code, meta = gen_kernel(p, s, fp32, opt)
+        code, meta = gen_kernel(p, s, fp32, opt, harmonic)
         parts.append(code)
         metas.append((p, meta))
     parts.append(f"bool m2l_lookup_s{s}_{suf}(int p, M2LVariant *v)")
@@ -297,9 +315,9 @@ def main(outdir, opt=None):
     os.makedirs(outdir, exist_ok=True)
     written = []
     for s in (0, 1, 2):
-        for fp32 in (True, False):
-            fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}.hip")
-            txt = gen_file(s, fp32, opt)
+        for fp32, h in ((True, False), (False, False), (True, True), (False, True)):
+            fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}{'_h' if h else ''}.hip")
+            txt = gen_file(s, fp32, opt, h)
             old = open(fn).read() if os.path.exists(fn) else None
             if old != txt:
                 with open(fn, "w") as f:

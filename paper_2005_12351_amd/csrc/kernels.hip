@@ -162,7 +162,8 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
                                                           const DevCell *__restrict__ cells, Geo g,
                                                           const double *__restrict__ xs, int n,
                                                           const double *__restrict__ mom, double *__restrict__ M,
-                                                          float *__restrict__ M32)
+                                                          float *__restrict__ M32, int nhp, float *__restrict__ Mh32,
+                                                          double *__restrict__ Mh64)
 {
     constexpr int W = mask_width(MASK);
     constexpr int S = mask_min_order(MASK);
@@ -258,13 +259,41 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
             acc[k] = a;
         }
     }
+    __shared__ double row[nterms(kPTable)];   // the finished row, indexed by multi-index
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
         if ((int)threadIdx.x + k * kP2MThreads < nm) {
             const size_t o = (size_t)c * nmp + threadIdx.x + k * kP2MThreads;
             M[o] = acc[k];
-            if (M32) M32[o] = (float)acc[k];   // the copy the mixed-precision M2L reads
+            if (M32) M32[o] = (float)acc[k];   // the copy the full-basis mixed-precision M2L reads
+            row[n0 + threadIdx.x + k * kP2MThreads] = acc[k];
         }
+    if (Mh32 || Mh64) {
+        // the harmonic-basis row the M2L reads (in its precision)
+        __syncthreads();
+        const int h0 = hterms(S - 1), nh = hterms(p) - h0;
+        for (int h = threadIdx.x; h < nh; h += kP2MThreads) {
+            const double v = fold_component(row, h + h0);
+            if (Mh32) Mh32[(size_t)c * nhp + h] = (float)v;
+            else Mh64[(size_t)c * nhp + h] = v;
+        }
+    }
+}
+
+// harmonic-basis rows written beside M64 by P2M and M2M (null when unused)
+struct HarmOut {
+    int nhp;
+    float *h32;
+    double *h64;
+};
+static HarmOut harm_out(const fmm_tree *t)
+{
+    HarmOut o{0, nullptr, nullptr};
+    if (t->method != FMM_METHOD_FMM || t->basis != FMM_M2L_HARMONIC || !t->d_Mh) return o;
+    o.nhp = (hterms(t->p) - hterms(t->order - 1) + 3) / 4 * 4;
+    if (t->prec == FMM_PREC_MIXED) o.h32 = (float *)t->d_Mh;
+    else o.h64 = (double *)t->d_Mh;
+    return o;
 }
 
 template <int MASK>
@@ -273,8 +302,9 @@ static void p2m_launch(fmm_tree *t, hipStream_t s)
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
+    const HarmOut ho = harm_out(t);
     hipLaunchKernelGGL(p2m_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp, t->d_leaves,
-                       t->d_cells, g, t->d_x, (int)t->ht.n, t->d_mom, t->d_M64, m32);
+                       t->d_cells, g, t->d_x, (int)t->ht.n, t->d_mom, t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
 }
 
 hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
@@ -329,7 +359,8 @@ __device__ __forceinline__ void shift_items(int nt, ShiftItems &it)
 // (8 waves per SIMD: two 1024-thread workgroups fit a CU)
 __global__ __launch_bounds__(kShiftX * 8, 8) void m2m_kernel(int p, int s, int nmp, const int32_t *__restrict__ parents,
                                                           const DevCell *__restrict__ cells, double *__restrict__ M,
-                                                          float *__restrict__ M32)
+                                                          float *__restrict__ M32, int nhp, float *__restrict__ Mh32,
+                                                          double *__restrict__ Mh64)
 {
     extern __shared__ double sm[];   // X[8][nt], Y[8][nt]
     const int nt = nterms(p), n0 = nterms(s - 1);
@@ -395,7 +426,18 @@ __global__ __launch_bounds__(kShiftX * 8, 8) void m2m_kernel(int p, int s, int n
             const double v = ldexp(acc, -it.k[j]);
             M[(size_t)P * nmp + (i - n0)] = v;
             if (M32) M32[(size_t)P * nmp + (i - n0)] = (float)v;
+            X[i] = v;   // X is free after the last pass
         }
+    if (Mh32 || Mh64) {
+        // the harmonic-basis row the M2L reads (in its precision)
+        __syncthreads();
+        const int h0 = hterms(s - 1), nh = hterms(p) - h0;
+        for (int h = tid; h < nh; h += kShiftX * 8) {
+            const double v = fold_component(X, h + h0);
+            if (Mh32) Mh32[(size_t)P * nhp + h] = (float)v;
+            else Mh64[(size_t)P * nhp + h] = v;
+        }
+    }
 }
 
 hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
@@ -404,8 +446,9 @@ hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s)
     if (b <= a) return hipSuccess;
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     const size_t lds = (size_t)16 * nterms(t->p) * sizeof(double);
+    const HarmOut ho = harm_out(t);
     hipLaunchKernelGGL(m2m_kernel, dim3(b - a), dim3(kShiftX, 8), lds, s, t->p, t->order, nmp, t->d_nonleaf + a,
-                       t->d_cells, t->d_M64, t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr);
+                       t->d_cells, t->d_M64, t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr, ho.nhp, ho.h32, ho.h64);
     return hipGetLastError();
 }
 

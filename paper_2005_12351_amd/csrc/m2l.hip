@@ -74,7 +74,7 @@ hipError_t launch_dtable(fmm_tree *t, hipStream_t s)
 {
     if (t->tiling.nclasses == 0) return hipSuccess;
     M2LVariant v;
-    m2l_lookup(t->p, t->order, true, &v);
+    m2l_lookup(t->p, t->order, true, false, &v);   // nd is the same in both bases
     const int scw = (t->p + 1 + 3) / 4 * 4;
     hipLaunchKernelGGL(dtable_kernel, dim3(t->tiling.nclasses), dim3(64), 0, s, t->p, v.nd, scw, t->d_cls_geom,
                        t->d_D64, t->d_D32, t->d_sc64, t->d_sc32);
@@ -86,16 +86,16 @@ hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
 {
     const M2LWork &wk = t->m2lwork;
     if (wk.work.empty()) return hipSuccess;
-    const bool f32 = t->prec == FMM_PREC_MIXED;
+    const bool f32 = t->prec == FMM_PREC_MIXED, harm = t->basis == FMM_M2L_HARMONIC;
     M2LVariant v;
-    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
+    if (!m2l_lookup(t->p, t->order, f32, harm, &v)) return hipErrorInvalidValue;
     M2LArgs a;
     a.work = t->d_work;
     a.ucls = t->d_ucls;
     a.usrc = t->d_usrc;
     a.D = f32 ? (const void *)t->d_D32 : (const void *)t->d_D64;
     a.sc = f32 ? (const void *)t->d_sc32 : (const void *)t->d_sc64;
-    a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
+    a.M = harm ? (const void *)t->d_Mh : (f32 ? (const void *)t->d_M32 : (const void *)t->d_M64);
     a.part = t->d_part;
     a.wave_ptr = t->d_wave_ptr;
     a.zero = 0;
@@ -106,10 +106,37 @@ hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
 // cell's tile slot (each output block of a tile has its own chunks), or zero
 // for a cell without M2L sources; so the locals need no separate clearing.
 // The loads of eight chunks are issued before their fixed-order sum.
+// Harmonic basis: the rows hold the components with n_z <= 1; another
+// component (a, b, 2j + r) is (-1)^j sum_i C(j,i) of the summed components
+// (a + 2i, b + 2(j - i), r), the identity the locals inherit from D (their
+// truncation |m| <= p - |n| is the same for every component of one order).
 struct BlockBounds {
     int lo[17];
     int nb;
 };
+
+template <typename T>
+__device__ __forceinline__ double sum_partials(int n, int tile, int lane, int nlp, const BlockBounds &bb,
+                                               const int32_t *__restrict__ chunk0,
+                                               const int32_t *__restrict__ nchunk, const T *__restrict__ part)
+{
+    int b = 0;
+    while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
+    const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
+    const T *p = part + ((size_t)c0 * kTileW + lane) * nlp + n;
+    const size_t stride = (size_t)kTileW * nlp;
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 8 <= nc; k += 8) {
+        T v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = p[(size_t)(k + q) * stride];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += (double)v[q];
+    }
+    for (; k < nc; ++k) acc += (double)p[(size_t)k * stride];
+    return acc;
+}
 
 template <typename T>
 __global__ void m2l_combine_kernel(int ncells, int nl, int nlp, BlockBounds bb, const int32_t *__restrict__ cell_slot,
@@ -121,45 +148,72 @@ __global__ void m2l_combine_kernel(int ncells, int nl, int nlp, BlockBounds bb, 
     const int cell = (int)(id / nl), n = (int)(id % nl);
     const int slot = cell_slot[cell];
     double acc = 0.0;
-    if (slot >= 0) {
-        const int tile = slot / kTileW, lane = slot % kTileW;
-        int b = 0;
-        while (b + 1 < bb.nb && n >= bb.lo[b + 1]) ++b;
-        const int c0 = chunk0[tile * bb.nb + b], nc = nchunk[tile * bb.nb + b];
-        const T *p = part + ((size_t)c0 * kTileW + lane) * nlp + n;
-        const size_t stride = (size_t)kTileW * nlp;
-        int k = 0;
-        for (; k + 8 <= nc; k += 8) {
-            T v[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = p[(size_t)(k + q) * stride];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) acc += (double)v[q];
-        }
-        for (; k < nc; ++k) acc += (double)p[(size_t)k * stride];
-    }
+    if (slot >= 0) acc = sum_partials(n, slot / kTileW, slot % kTileW, nlp, bb, chunk0, nchunk, part);
     L[(size_t)cell * nl + n] = acc;
+}
+
+// Harmonic basis, kHarmCells cells per workgroup: the summed components with
+// n_z <= 1 go to LDS, then every component of the cells' rows is written.
+constexpr int kHarmCells = 4;
+template <typename T>
+__global__ __launch_bounds__(256) void m2l_combine_h_kernel(int ncells, int nl, int nlh, int nlp, BlockBounds bb,
+                                                            const int32_t *__restrict__ cell_slot,
+                                                            const int32_t *__restrict__ chunk0,
+                                                            const int32_t *__restrict__ nchunk,
+                                                            const T *__restrict__ part, double *__restrict__ L)
+{
+    __shared__ double red[kHarmCells][hterms(FMM_P_MAX)];
+    const int c0 = blockIdx.x * kHarmCells;
+    for (int it = threadIdx.x; it < kHarmCells * nlh; it += blockDim.x) {
+        const int cc = it / nlh, h = it % nlh, cell = c0 + cc;
+        double v = 0.0;
+        const int slot = cell < ncells ? cell_slot[cell] : -1;
+        if (slot >= 0) v = sum_partials(h, slot / kTileW, slot % kTileW, nlp, bb, chunk0, nchunk, part);
+        red[cc][h] = v;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < kHarmCells * nl; it += blockDim.x) {
+        const int cc = it / nl, n = it % nl, cell = c0 + cc;
+        if (cell >= ncells) break;
+        const MultiIndex nn = k_mi.v[n];
+        const int j = nn.z / 2, r = nn.z & 1;
+        double acc = 0.0, c = 1.0;   // c = C(j, i)
+        for (int i = 0; i <= j; ++i) {
+            acc = fma(c, red[cc][hindex(nn.x + 2 * i, nn.y + 2 * (j - i), r)], acc);
+            c = c * (j - i) / (i + 1);
+        }
+        L[(size_t)cell * nl + n] = (j & 1) ? -acc : acc;
+    }
 }
 
 hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
 {
-    const M2LTiling &tl = t->tiling;
     const int nl = nterms(t->p - t->order);
     const int64_t nc = t->ht.ncells();
-    const size_t tot = (size_t)nc * nl;
-    const unsigned g = (unsigned)((tot + 255) / 256);
-    const bool f32 = t->prec == FMM_PREC_MIXED;
+    const bool f32 = t->prec == FMM_PREC_MIXED, harm = t->basis == FMM_M2L_HARMONIC;
     M2LVariant v;
-    if (!m2l_lookup(t->p, t->order, f32, &v)) return hipErrorInvalidValue;
+    if (!m2l_lookup(t->p, t->order, f32, harm, &v)) return hipErrorInvalidValue;
     BlockBounds bb;
     for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
     bb.nb = v.nblocks;
-    (void)tl;
-    if (f32)
-        hipLaunchKernelGGL(m2l_combine_kernel<float>, dim3(g), dim3(256), 0, s, (int)nc, nl, v.nl_pad, bb,
-                           t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const float *)t->d_part, t->d_L64);
-    else
-        hipLaunchKernelGGL(m2l_combine_kernel<double>, dim3(g), dim3(256), 0, s, (int)nc, nl, v.nl_pad, bb,
-                           t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const double *)t->d_part, t->d_L64);
+    if (harm) {
+        const unsigned g = (unsigned)((nc + kHarmCells - 1) / kHarmCells);
+        const int nlh = hterms(t->p - t->order);
+#define COMBINE_H(T)                                                                                            \
+    hipLaunchKernelGGL(m2l_combine_h_kernel<T>, dim3(g), dim3(256), 0, s, (int)nc, nl, nlh, v.nl_pad, bb,        \
+                       t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const T *)t->d_part, t->d_L64)
+        if (f32) COMBINE_H(float);
+        else COMBINE_H(double);
+#undef COMBINE_H
+        return hipGetLastError();
+    }
+    const size_t tot = (size_t)nc * nl;
+    const unsigned g = (unsigned)((tot + 255) / 256);
+#define COMBINE(T)                                                                                              \
+    hipLaunchKernelGGL(m2l_combine_kernel<T>, dim3(g), dim3(256), 0, s, (int)nc, nl, v.nl_pad, bb,              \
+                       t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const T *)t->d_part, t->d_L64)
+    if (f32) COMBINE(float);
+    else COMBINE(double);
+#undef COMBINE
     return hipGetLastError();
 }

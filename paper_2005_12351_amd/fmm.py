@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("FMM_LIBRARY") or os.path.join(_HERE, "libfmm.so")
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE, FMM_EBUSY, FMM_ETIMEOUT = range(7)
 FMM_POT, FMM_FIELD = 1, 2
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
+FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
 FMM_P_MAX = 10
 FMM_MIXED = 16          # order code FMM_MIXED | mask: several source orders (bit k: order k)
@@ -60,6 +61,7 @@ fmm_tree_export = _sig("fmm_tree_export", [_vp] + [_vp] * 14)
 fmm_tree_destroy = _sig("fmm_tree_destroy", [_vp])
 fmm_last_error = _sig("fmm_last_error", [], ctypes.c_char_p)
 fmm_ctx_set_overlap = _sig("fmm_ctx_set_overlap", [_vp, ctypes.c_int])
+fmm_ctx_set_m2l_basis = _sig("fmm_ctx_set_m2l_basis", [_vp, ctypes.c_int])
 fmm_ctx_set_graphs = _sig("fmm_ctx_set_graphs", [_vp, ctypes.c_int])
 fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
 fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
@@ -76,7 +78,7 @@ fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_run", "fmm_tree_info",
-            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
@@ -177,6 +179,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_m2l_basis(self, basis: int):
+        """FMM_M2L_FULL or FMM_M2L_HARMONIC (default); used from the next upward pass."""
+        _check(fmm_ctx_set_m2l_basis(self.h, int(basis)), "fmm_ctx_set_m2l_basis")
 
     def set_overlap(self, on: bool = True):
         _check(fmm_ctx_set_overlap(self.h, int(on)), "fmm_ctx_set_overlap")

@@ -1,5 +1,6 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
-benchmark times (fmm_run, one captured graph per step, replayed): 100k uniform dipoles (p 8), 1M Plummer dipoles (p 6, field only,
+benchmark times (fmm_run, one captured graph per step, replayed), in both M2L
+bases: 100k uniform dipoles (p 8), 1M Plummer dipoles (p 6, field only,
 FMM and Barnes-Hut) and 2M lattice quadrupoles (p 10).  The oracle cannot
 evaluate every particle at these sizes, so it runs its full upward pass and
 evaluates 4 096 seeded sample targets one by one (Section 3.2 lists of the
@@ -44,9 +45,10 @@ def _oracle(orc, w, method):
     return _ref[key]
 
 
-def _run(ctx, w, prec, method):
+def _run(ctx, w, prec, method, basis):
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     m = fmm.FMM_METHOD_FMM if method == "fmm" else fmm.FMM_METHOD_BH
+    ctx.set_m2l_basis(basis)
     t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta, m)
     mom = to_dev(w.moments)
     phi = torch.empty(w.n, dtype=torch.float64, device="cuda") if outputs & fmm.FMM_POT else None
@@ -57,19 +59,23 @@ def _run(ctx, w, prec, method):
     s = torch.from_numpy(w.sample).cuda()
     out = (None if phi is None else phi[s].cpu().numpy(), fld[s].cpu().numpy())
     t.close()
+    ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     return out
 
 
-CASES = [(2, "fmm"), (3, "fmm"), (3, "bh"), (4, "fmm")]
+# (workload, method, M2L basis); Barnes-Hut has no M2L
+CASES = [(2, "fmm", "harmonic"), (2, "fmm", "full"), (3, "fmm", "harmonic"), (3, "fmm", "full"), (3, "bh", "full"),
+         (4, "fmm", "harmonic"), (4, "fmm", "full")]
+BASIS = {"harmonic": fmm.FMM_M2L_HARMONIC, "full": fmm.FMM_M2L_FULL}
 
 
-@pytest.mark.parametrize("index,method", CASES)
+@pytest.mark.parametrize("index,method,basis", CASES)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_full_size_sampled(orc, ctx, index, method, prec):
+def test_full_size_sampled(orc, ctx, index, method, basis, prec):
     w = W.config(index)
-    print(f"[full] {w.name} n={w.n} p={w.p} theta={w.theta} {method} {prec}", flush=True)
+    print(f"[full] {w.name} n={w.n} p={w.p} theta={w.theta} {method} {basis} {prec}", flush=True)
     po, Eo = _oracle(orc, w, method)
-    ph, E = _run(ctx, w, prec, method)
+    ph, E = _run(ctx, w, prec, method, BASIS[basis])
     e2 = rel_l2(E, Eo)
     msg = f"   rel L2 on {len(w.sample)} samples: E {e2:.2e}"
     ok = e2 < TOL[prec]

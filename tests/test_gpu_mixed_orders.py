@@ -32,11 +32,17 @@ CASES = [(3, "uniform", 3000, 6, 32, 0.5), (6, "plummer", 4000, 7, 32, 0.5), (5,
 
 @pytest.mark.parametrize("mask,kind,n,p,ncrit,theta", CASES)
 @pytest.mark.parametrize("prec", [fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED])
-def test_mixed_fmm_matches_oracle(orc, ctx, mask, kind, n, p, ncrit, theta, prec):
+@pytest.mark.parametrize("basis", [fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_FULL])
+def test_mixed_fmm_matches_oracle(orc, ctx, mask, kind, n, p, ncrit, theta, prec, basis):
     w = W.small_mixed(900 + mask + n, n, mask, kind, p=p, theta=theta, ncrit=ncrit)
-    print(f"[mixed fmm] mask={mask} {kind} n={n} p={p} ncrit={ncrit} theta={theta} precision={prec}", flush=True)
-    ph, E, t = gpu_fmm(fmm, ctx, w, precision=prec)
-    t.close()
+    print(f"[mixed fmm] mask={mask} {kind} n={n} p={p} ncrit={ncrit} theta={theta} precision={prec} basis={basis}",
+          flush=True)
+    ctx.set_m2l_basis(basis)
+    try:
+        ph, E, t = gpu_fmm(fmm, ctx, w, precision=prec)
+        t.close()
+    finally:
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     po, Eo = orc.Tree(w.pos, ncrit, theta).fmm(w.order, w.moments, p)
     e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)
     print(f"   rel L2 vs oracle: phi {e1:.2e} E {e2:.2e}", flush=True)

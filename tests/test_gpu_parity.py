@@ -98,9 +98,20 @@ PARITY = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2
           (1, 2, "uniform", 700, 4, 0.3), (0, 10, "plummer", 1200, 8, 0.5)]
 
 
+BASES = {"full": fmm.FMM_M2L_FULL, "harmonic": fmm.FMM_M2L_HARMONIC}
+
+
+@pytest.fixture(params=list(BASES))
+def basis(request, ctx):
+    """Runs the test in each M2L basis, then restores the default."""
+    ctx.set_m2l_basis(BASES[request.param])
+    yield request.param
+    ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+
+
 @pytest.mark.parametrize("order,p,kind,n,ncrit,theta", PARITY)
-def test_fmm_fp64_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
-    _say(f"[fp64] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
+def test_fmm_fp64_matches_oracle(orc, ctx, basis, order, p, kind, n, ncrit, theta):
+    _say(f"[fp64 {basis}] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
     w = W.small_random(900 + n + order, n, order, kind)
     ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=fmm.FMM_PREC_FP64)
     t = orc.Tree(w.pos, ncrit, theta)
@@ -110,8 +121,8 @@ def test_fmm_fp64_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
 
 
 @pytest.mark.parametrize("order,p,kind,n,ncrit,theta", PARITY)
-def test_fmm_mixed_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
-    _say(f"[mixed] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
+def test_fmm_mixed_matches_oracle(orc, ctx, basis, order, p, kind, n, ncrit, theta):
+    _say(f"[mixed {basis}] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}")
     w = W.small_random(900 + n + order, n, order, kind)
     ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=fmm.FMM_PREC_MIXED)
     t = orc.Tree(w.pos, ncrit, theta)
@@ -144,6 +155,31 @@ def test_outputs_mask_and_determinism(orc, ctx):
         p2, _, _ = gpu_fmm(fmm, ctx, w, p=6, theta=0.5, ncrit=32, precision=prec, outputs=fmm.FMM_POT)
         _, E2, _ = gpu_fmm(fmm, ctx, w, p=6, theta=0.5, ncrit=32, precision=prec, outputs=fmm.FMM_FIELD)
         assert np.array_equal(p2, ph) and np.array_equal(E2, E)
+
+
+def test_basis_switch_on_one_tree(ctx):
+    """Switching the M2L basis between calls on one tree recaptures the
+    launch sequence: full and harmonic agree to rounding, and returning to a
+    basis reproduces its earlier result bit for bit."""
+    w = W.small_random(5151, 6000, 1, "uniform", p=8, theta=0.5, ncrit=32)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.moments).cuda()
+    try:
+        for prec, tol in ((fmm.FMM_PREC_FP64, 1e-12), (fmm.FMM_PREC_MIXED, 1e-6)):
+            t = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+            out = []
+            for b in (fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_FULL, fmm.FMM_M2L_HARMONIC):
+                ctx.set_m2l_basis(b)
+                ph, E = t.run(w.order, mom, w.p, prec)
+                torch.cuda.synchronize()
+                out.append((ph.cpu().numpy(), E.cpu().numpy()))
+            _say(f"[basis switch] precision={prec}: full vs harmonic phi {rel_l2(out[0][0], out[1][0]):.2e}"
+                 f" E {rel_l2(out[0][1], out[1][1]):.2e}")
+            assert rel_l2(out[0][0], out[1][0]) < tol and rel_l2(out[0][1], out[1][1]) < tol
+            assert np.array_equal(out[0][0], out[2][0]) and np.array_equal(out[0][1], out[2][1])
+            t.close()
+    finally:
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
 
 
 @pytest.mark.parametrize("overlap", [True, False])

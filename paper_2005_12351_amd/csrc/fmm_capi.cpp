@@ -583,18 +583,20 @@ static int check_eval_args(fmm_ctx *ctx, fmm_tree *t, int outputs, const double 
     return FMM_OK;
 }
 
-// Queues the upward pass on the context stream: sorted moments, P2M, M2M by
-// level, FP32 copy of the multipoles.  For FMM trees the near field (which
-// needs only the sorted moments) is forked onto the auxiliary stream; with
-// join it is joined back at the end, otherwise the caller joins it (ev_near).
+// Queues the upward pass on the context stream: P2M (which also writes the
+// sorted FP64 and FP32 moments), M2M by level (both also write the
+// harmonic-basis or FP32 copy the M2L reads).  For FMM trees the near field
+// (which needs only the sorted moments) is forked after P2M onto the
+// auxiliary stream; with join it is joined back at the end, otherwise the
+// caller joins it (ev_near).
 static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
 {
     hipStream_t s = ctx->stream;
     const bool fmm = t->method == FMM_METHOD_FMM;
     hipStream_t a = ctx->overlap && fmm ? ctx->aux : s;
     {
-        ProfScope ps(ctx, s, "prep_moments");
-        KCHK(launch_prep_moments(t, s));
+        ProfScope ps(ctx, s, "p2m");
+        KCHK(launch_p2m(t, s));
     }
     if (fmm) {
         if (a != s) {
@@ -607,16 +609,11 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
         }
         if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
     }
-    {
-        ProfScope ps(ctx, s, "p2m");
-        KCHK(launch_p2m(t, s));
-    }
     const int nlev = (int)t->ht.level_ptr.size() - 1;
     for (int l = nlev - 2; l >= t->m2m_top; --l) {
         ProfScope ps(ctx, s, "m2m");
         KCHK(launch_m2m_level(t, l, s));
     }
-
     if (join && a != s) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     return FMM_OK;
 }

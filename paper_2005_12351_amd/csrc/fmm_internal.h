@@ -44,29 +44,43 @@ __host__ __device__ constexpr int hindex(int nx, int ny, int nz)
 }
 __host__ __device__ constexpr int hterms(int p) { return p < 0 ? 0 : (p + 1) * (p + 1); }
 
-// Harmonic-basis component h of a multipole row (row indexed by mindex):
-// for (a, b, r) = the h-th component with r <= 1,
+// Folding onto the harmonic basis.  Component h = (a, b, r), r <= 1, of a
+// folded multipole row is
 //   sum_j (-1)^j sum_i C(j,i) row[(a - 2i, b - 2(j - i), r + 2j)],
 // which carries the row's contraction with any harmonic tensor D (such as
 // the derivatives of 1/r, D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0) onto the
-// components with m_z <= 1 without changing it; the order is kept.
-__device__ inline double fold_component(const double *row, int h)
+// components with m_z <= 1 without changing it; the order is kept.  The
+// terms are tabulated once: for h, entries [start[h], start[h+1]) hold the
+// row index and the signed binomial weight.
+constexpr int kFoldTerms = 1036;   // terms of all components up to order kPTable
+struct FoldTable {
+    int16_t start[hterms(kPTable) + 1];
+    int16_t idx[kFoldTerms];
+    float w[kFoldTerms];
+};
+constexpr FoldTable make_fold()
 {
-    int l = 0;
-    while ((l + 1) * (l + 1) <= h) ++l;
-    const int rem = h - l * l, t = (rem + 1) / 2, r = rem == 0 ? 0 : (rem + 1) % 2;
-    const int a = l - t, b = t - r;
-    double acc = 0.0;
-    for (int j = 0; 2 * j <= a + b; ++j) {
-        double sj = 0.0, c = 1.0;   // c = C(j, i)
-        for (int i = 0; i <= j; ++i) {
-            const int ax = a - 2 * i, by = b - 2 * (j - i);
-            if (ax >= 0 && by >= 0) sj = fma(c, row[mindex(ax, by, r + 2 * j)], sj);
-            c = c * (j - i) / (i + 1);
-        }
-        acc += (j & 1) ? -sj : sj;
-    }
-    return acc;
+    FoldTable f{};
+    int e = 0, h = 0;
+    for (int l = 0; l <= kPTable; ++l)
+        for (int t = 0; t <= l; ++t)
+            for (int r = 0; r <= (t == 0 ? 0 : 1); ++r) {
+                f.start[h++] = (int16_t)e;
+                const int a = l - t, b = t - r;
+                for (int j = 0; 2 * j <= a + b; ++j) {
+                    int c = 1;   // C(j, i)
+                    for (int i = 0; i <= j; ++i) {
+                        if (a - 2 * i >= 0 && b - 2 * (j - i) >= 0) {
+                            f.idx[e] = (int16_t)mindex(a - 2 * i, b - 2 * (j - i), r + 2 * j);
+                            f.w[e] = (float)((j & 1) ? -c : c);
+                            ++e;
+                        }
+                        c = c * (j - i) / (i + 1);
+                    }
+                }
+            }
+    f.start[h] = (int16_t)e;
+    return f;
 }
 
 // multi-indices in storage order (total order ascending; within an order
@@ -260,7 +274,6 @@ struct ProfScope {
 
 // kernels entry points (host launchers), return hipError_t
 hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s);
-hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s);
 hipError_t launch_p2m(fmm_tree *t, hipStream_t s);
 hipError_t launch_m2m_level(fmm_tree *t, int level, hipStream_t s);
 hipError_t launch_dtable(fmm_tree *t, hipStream_t s);

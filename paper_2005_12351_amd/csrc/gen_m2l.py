@@ -46,7 +46,7 @@ TILE = 64
 # code-shape options (register blocking and scalar-load pipelining); the
 # defaults are the measured best on gfx950, see DEFAULTS
 DEFAULTS = {"acc32": 128, "m32": 64, "acc64": 64, "m64": 32, "dgroup32": 32, "dgroup64": 16, "pipeline": 1,
-            "mpre": 0, "launder": 1, "scale_branch": 0}
+            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0}
 
 
 def orders(p):
@@ -118,7 +118,9 @@ def gen_kernel(p, s, fp32, opt=None, harmonic=False):
     blocks = split_blocks(nl, max_acc)
     name = f"m2l_p{p}_s{s}_{suf}" + ("_h" if harmonic else "")
     L = []
-    L.append(f"__global__ __launch_bounds__({TILE}) void {name}(M2LArgs a)")
+    # minwaves > 0: resident waves per SIMD the register allocation must allow
+    lb = f"{TILE}, {opt['minwaves']}" if opt["minwaves"] else f"{TILE}"
+    L.append(f"__global__ __launch_bounds__({lb}) void {name}(M2LArgs a)")
     L.append("{")
     L.append("    const int lane = threadIdx.x;")
     L.append(f"    const {T} *__restrict__ Mb = (const {T} *)a.M;")

@@ -85,28 +85,25 @@ hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s)
     return hipGetLastError();
 }
 
-// sorted moments: FP64 (the caller's row of w values per particle) and FP32
-// (one order: 8 floats, q | mu | the six Q components and their trace;
-// several orders: 12 floats, [q mu] [xx xy xz yy] [yz zz tr 0], absent
-// parts zero)
-__global__ void prep_moments_kernel(int n, int mask, const double *__restrict__ mom, const int32_t *__restrict__ perm,
-                                    double *__restrict__ m64, float *__restrict__ m32)
+// Sorted moments of particle i (sorted order; perm maps it to the caller's
+// row): FP64 (the caller's row of w values) and FP32 (one order: 8 floats,
+// q | mu | the six Q components and their trace; several orders: 12 floats,
+// [q mu] [xx xy xz yy] [yz zz tr 0], absent parts zero).  P2M writes them
+// while it visits every particle once; the near field reads them.
+__device__ __forceinline__ void sort_moments(size_t i, int mask, const double *__restrict__ r,
+                                             double *__restrict__ m64, float *__restrict__ m32)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const int w = mask_width(mask);
-    const size_t j = (size_t)perm[i];
     float v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < w; ++k) m64[(size_t)i * w + k] = mom[j * w + k];
+    for (int k = 0; k < w; ++k) m64[i * w + k] = r[k];
     if (mask_single(mask)) {
-        for (int k = 0; k < w; ++k) v[k] = (float)mom[j * w + k];
-        if (w == 6) v[6] = (float)(mom[j * 6 + 0] + mom[j * 6 + 3] + mom[j * 6 + 5]);
-        float4 *o = reinterpret_cast<float4 *>(m32) + 2 * (size_t)i;
+        for (int k = 0; k < w; ++k) v[k] = (float)r[k];
+        if (w == 6) v[6] = (float)(r[0] + r[3] + r[5]);
+        float4 *o = reinterpret_cast<float4 *>(m32) + 2 * i;
         o[0] = make_float4(v[0], v[1], v[2], v[3]);
         o[1] = make_float4(v[4], v[5], v[6], v[7]);
     } else {
         int off = 0;
-        const double *r = mom + j * w;
         if (mask & 1) v[0] = (float)r[off++];
         if (mask & 2) {
             v[1] = (float)r[off];
@@ -118,19 +115,11 @@ __global__ void prep_moments_kernel(int n, int mask, const double *__restrict__ 
             for (int k = 0; k < 6; ++k) v[4 + k] = (float)r[off + k];
             v[10] = (float)(r[off] + r[off + 3] + r[off + 5]);
         }
-        float4 *o = reinterpret_cast<float4 *>(m32) + 3 * (size_t)i;
+        float4 *o = reinterpret_cast<float4 *>(m32) + 3 * i;
         o[0] = make_float4(v[0], v[1], v[2], v[3]);
         o[1] = make_float4(v[4], v[5], v[6], v[7]);
         o[2] = make_float4(v[8], v[9], v[10], v[11]);
     }
-}
-
-hipError_t launch_prep_moments(fmm_tree *t, hipStream_t s)
-{
-    const int n = (int)t->ht.n;
-    hipLaunchKernelGGL(prep_moments_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, t->smask, t->mom_user,
-                       t->d_perm, t->d_mom, t->d_mom32);
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ P2M
@@ -157,11 +146,25 @@ constexpr InvTable make_inv()
 }
 __constant__ InvTable k_inv = make_inv();   // 1/a
 
+static __constant__ FoldTable k_fold = make_fold();
+static_assert(make_fold().start[hterms(kPTable)] == kFoldTerms, "fold table size");
+
+// component h of the harmonic-basis fold of a multipole row (row indexed by
+// multi-index)
+__device__ __forceinline__ double fold_component(const double *row, int h)
+{
+    double acc = 0.0;
+    for (int e = k_fold.start[h]; e < k_fold.start[h + 1]; ++e) acc = fma((double)k_fold.w[e], row[k_fold.idx[e]], acc);
+    return acc;
+}
+
 template <int MASK>
 __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
                                                           const DevCell *__restrict__ cells, Geo g,
                                                           const double *__restrict__ xs, int n,
-                                                          const double *__restrict__ mom, double *__restrict__ M,
+                                                          const double *__restrict__ mom_user,
+                                                          const int32_t *__restrict__ perm, double *__restrict__ mom64,
+                                                          float *__restrict__ mom32, double *__restrict__ M,
                                                           float *__restrict__ M32, int nhp, float *__restrict__ Mh32,
                                                           double *__restrict__ Mh64)
 {
@@ -207,7 +210,9 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
         }
         if ((int)threadIdx.x < cnt) {
             const int t = threadIdx.x;
-            const double *m = mom + ((size_t)cell.first + base + t) * W;
+            const size_t i = (size_t)cell.first + base + t;
+            const double *m = mom_user + (size_t)perm[i] * W;
+            sort_moments(i, MASK, m, mom64, mom32);
             int off = 0;
             if (Q0) sv[t][0] = m[off++];
             if (Q1) {
@@ -304,7 +309,8 @@ static void p2m_launch(fmm_tree *t, hipStream_t s)
     float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
     const HarmOut ho = harm_out(t);
     hipLaunchKernelGGL(p2m_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp, t->d_leaves,
-                       t->d_cells, g, t->d_x, (int)t->ht.n, t->d_mom, t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
+                       t->d_cells, g, t->d_x, (int)t->ht.n, t->mom_user, t->d_perm, t->d_mom, t->d_mom32,
+                       t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
 }
 
 hipError_t launch_p2m(fmm_tree *t, hipStream_t s)

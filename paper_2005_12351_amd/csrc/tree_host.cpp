@@ -15,7 +15,8 @@
 // M2L tiling.  Target cells with a non-empty M2L list are grouped 64 to a
 // tile (one GPU lane per target).  Cells of one level and one position
 // inside their parent have identical relative source layouts away from the
-// domain boundary, so tiles are formed in that order.  A tile iterates over
+// domain boundary, and near it equal truncations (see below), so tiles are
+// formed in that order.  A tile iterates over
 // the union of its targets' translation classes; a class is the exact
 // dimensionless geometry of a pair, ((z_B - z_A) / r_B, r_A / r_B), so one
 // derivative tensor serves every lane at a given step.
@@ -27,14 +28,41 @@ void build_m2l_tiling(const HostTree &t, M2LTiling &out)
     for (int64_t c = 0; c < nc; ++c)
         if (t.m2l_ptr[c + 1] > t.m2l_ptr[c]) tg.push_back((int32_t)c);
     auto oct = [&](int32_t c) { return ((t.ix[3 * c] & 1) << 2) | ((t.ix[3 * c + 1] & 1) << 1) | (t.ix[3 * c + 2] & 1); };
-    // a cell whose list is shorter than most of its level's lists sits near
-    // the domain boundary; list length (coarsely) groups cells with similar
-    // truncated neighbourhoods, which shrinks the per-tile union
+    // Near the domain boundary a cell's list is truncated on the sides that
+    // touch the boundary.  Its neighbourhood signature, the smallest and
+    // largest offset per axis of its same-level sources, identifies the
+    // truncation (in a uniform region cells with equal signatures have equal
+    // class sets), so tiles are formed in (level, octant, signature) order;
+    // the list length breaks ties.
+    struct Key {
+        int32_t lo[3], hi[3];
+        int64_t len;
+    };
+    std::vector<Key> key(nc);
+    for (int32_t c : tg) {
+        Key k{{0, 0, 0}, {0, 0, 0}, t.m2l_ptr[c + 1] - t.m2l_ptr[c]};
+        bool any = false;
+        for (int64_t e = t.m2l_ptr[c]; e < t.m2l_ptr[c + 1]; ++e) {
+            const int64_t A = t.m2l_src[e];
+            if (t.level[A] != t.level[c]) continue;
+            for (int d = 0; d < 3; ++d) {
+                const int32_t o = t.ix[3 * A + d] - t.ix[3 * c + d];
+                k.lo[d] = any ? std::min(k.lo[d], o) : o;
+                k.hi[d] = any ? std::max(k.hi[d], o) : o;
+            }
+            any = true;
+        }
+        key[c] = k;
+    }
     std::stable_sort(tg.begin(), tg.end(), [&](int32_t a, int32_t b) {
         if (t.level[a] != t.level[b]) return t.level[a] < t.level[b];
         if (oct(a) != oct(b)) return oct(a) < oct(b);
-        const int64_t la = t.m2l_ptr[a + 1] - t.m2l_ptr[a], lb = t.m2l_ptr[b + 1] - t.m2l_ptr[b];
-        return la > lb;
+        const Key &ka = key[a], &kb = key[b];
+        for (int d = 0; d < 3; ++d) {
+            if (ka.lo[d] != kb.lo[d]) return ka.lo[d] < kb.lo[d];
+            if (ka.hi[d] != kb.hi[d]) return ka.hi[d] < kb.hi[d];
+        }
+        return ka.len > kb.len;
     });
     out.ntiles = (int)((tg.size() + kTileW - 1) / kTileW);
     out.tile_cell.assign((size_t)out.ntiles * kTileW, -1);

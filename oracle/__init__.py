@@ -50,7 +50,10 @@ def lib():
         L.orc_tree_lists.argtypes = [_vp, ctypes.c_double]
         L.orc_tree_info.argtypes = [_vp, _vp]
         L.orc_tree_export.argtypes = [_vp] + [_vp] * 14
-        L.orc_fmm_eval.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp]
+        L.orc_fmm_eval.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp]
+        L.orc_direct_grad.argtypes = [ctypes.c_int64, _vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp]
+        L.orc_p2p_pair_grad.argtypes = [ctypes.c_int, _vp, _vp, _vp]
+        L.orc_l2p_grad.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
         L.orc_bh_eval.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                   _vp, _vp, _vp]
         L.orc_upward.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp]
@@ -125,6 +128,13 @@ def p2p_pair(order: int, r, mom):
     return phi[0], E
 
 
+def p2p_pair_grad(order: int, r, mom) -> np.ndarray:
+    """Field gradient d_i E_j (xx, xy, xz, yy, yz, zz) of one source at r."""
+    G = np.zeros(6)
+    lib().orc_p2p_pair_grad(order, _p(_c(r)), _p(_c(mom).ravel()), _p(G))
+    return G
+
+
 def p2m(p: int, order: int, z, pos, mom) -> np.ndarray:
     pos = _c(pos).reshape(-1, 3)
     mom = _c(mom)
@@ -158,11 +168,31 @@ def l2p(p: int, s: int, z, L, x):
     return phi[0], E
 
 
+def l2p_grad(p: int, s: int, z, L, x) -> np.ndarray:
+    """Field gradient (xx, xy, xz, yy, yz, zz) of the local expansion L at x."""
+    G = np.zeros(6)
+    lib().orc_l2p_grad(p, s, _p(_c(z)), _p(_c(L)), _p(_c(x)), _p(G))
+    return G
+
+
 def m2p(p: int, s: int, zA, M, x):
     phi = np.zeros(1)
     E = np.zeros(3)
     lib().orc_m2p(p, s, _p(_c(zA)), _p(_c(M)), _p(_c(x)), _p(phi), _p(E))
     return phi[0], E
+
+
+def direct_grad(pos, order: int, mom, targets: Optional[np.ndarray] = None) -> np.ndarray:
+    """O(N^2) field gradient (k x 6: xx, xy, xz, yy, yz, zz) at all (or the
+    listed) targets."""
+    pos = _c(pos).reshape(-1, 3)
+    mom = _c(mom)
+    n = pos.shape[0]
+    tg = None if targets is None else _c(targets, np.int64)
+    k = n if tg is None else tg.shape[0]
+    G = np.zeros((k, 6))
+    lib().orc_direct_grad(n, _p(pos), order, _p(mom), k, _p(tg), _p(G))
+    return G
 
 
 def direct(pos, order: int, mom, targets: Optional[np.ndarray] = None):
@@ -265,17 +295,22 @@ class Tree:
         lib().orc_upward(self._h, order, _p(mom), p, _p(M))
         return M
 
-    def fmm(self, order: int, mom, p: int, targets: Optional[np.ndarray] = None, want_L: bool = False):
+    def fmm(self, order: int, mom, p: int, targets: Optional[np.ndarray] = None, want_L: bool = False,
+            want_grad: bool = False):
+        """phi, E (and the local expansions L, the field gradient G (k x 6)
+        when asked for, in that order)."""
         mom = _c(mom)
         tg = None if targets is None else _c(targets, np.int64)
         k = self.n if tg is None else tg.shape[0]
         phi = np.zeros(k)
         E = np.zeros((k, 3))
         L = np.zeros((self.info()["ncells"], nterms(p - min_order(order)))) if want_L else None
-        rc = lib().orc_fmm_eval(self._h, order, _p(mom), p, k, _p(tg), _p(phi), _p(E), _p(L))
+        G = np.zeros((k, 6)) if want_grad else None
+        rc = lib().orc_fmm_eval(self._h, order, _p(mom), p, k, _p(tg), _p(phi), _p(E), _p(L), _p(G))
         if rc != 0:
             raise ValueError("oracle FMM rejected its arguments (lists missing or p < order+1)")
-        return (phi, E, L) if want_L else (phi, E)
+        out = (phi, E) + ((L,) if want_L else ()) + ((G,) if want_grad else ())
+        return out
 
     def bh(self, order: int, mom, p: int, theta_bh: float, targets: Optional[np.ndarray] = None):
         mom = _c(mom)

@@ -233,6 +233,81 @@ void orc_p2p_pair(int o, const double *r, const double *mom, double *phi, double
     }
 }
 
+/* Field gradient G_ij = d_i E_j = -d_i d_j phi (symmetric; stored xx, xy,
+ * xz, yy, yz, zz) at a target displaced by r from a source of one order: the
+ * second derivatives of the closed forms above (Section 2 asks for
+ * derivatives of the potential of any order; order 2 is the one after the
+ * field).
+ *   charge:     q (delta_ij r^2 - 3 r_i r_j) / r^5
+ *   dipole:     3 (mu_i r_j + mu_j r_i + (mu.r) delta_ij) / r^5
+ *               - 15 (mu.r) r_i r_j / r^7
+ *   quadrupole: phi = A + B, A = 3/2 (r.Q.r) / r^5, B = -tr Q / (2 r^3);
+ *     d_i d_j A = 3 Q_ij / r^5 - 15 ((Qr)_i r_j + (Qr)_j r_i) / r^7
+ *                 - 15/2 (r.Q.r) delta_ij / r^7 + 105/2 (r.Q.r) r_i r_j / r^9
+ *     d_i d_j B = 3/2 tr Q (delta_ij / r^5 - 5 r_i r_j / r^7)          */
+static void pair_grad_single(int order, const double *r, const double *mom, double *G)
+{
+    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rinv = 1.0 / sqrt(r2);
+    double r3 = rinv * rinv * rinv, r5 = r3 * rinv * rinv, r7 = r5 * rinv * rinv, r9 = r7 * rinv * rinv;
+    for (int k = 0; k < 6; ++k) {
+        int i = I[k], j = J[k];
+        double dij = i == j ? 1.0 : 0.0;
+        if (order == 0) {
+            G[k] = mom[0] * (dij * r2 - 3.0 * r[i] * r[j]) * r5;
+        } else if (order == 1) {
+            double mr = mom[0] * r[0] + mom[1] * r[1] + mom[2] * r[2];
+            G[k] = 3.0 * (mom[i] * r[j] + mom[j] * r[i] + mr * dij) * r5 - 15.0 * mr * r[i] * r[j] * r7;
+        } else {
+            double Q[3][3] = {{mom[0], mom[1], mom[2]}, {mom[1], mom[3], mom[4]}, {mom[2], mom[4], mom[5]}};
+            double Qr[3], rQr = 0.0, tr = mom[0] + mom[3] + mom[5];
+            for (int a = 0; a < 3; ++a) Qr[a] = Q[a][0] * r[0] + Q[a][1] * r[1] + Q[a][2] * r[2];
+            for (int a = 0; a < 3; ++a) rQr += r[a] * Qr[a];
+            double ddA = 3.0 * Q[i][j] * r5 - 15.0 * (Qr[i] * r[j] + Qr[j] * r[i]) * r7 - 7.5 * rQr * dij * r7 +
+                         52.5 * rQr * r[i] * r[j] * r9;
+            double ddB = 1.5 * tr * (dij * r5 - 5.0 * r[i] * r[j] * r7);
+            G[k] = -(ddA + ddB);
+        }
+    }
+}
+
+void orc_p2p_pair_grad(int o, const double *r, const double *mom, double *G)
+{
+    int m = code_mask(o), off = 0;
+    for (int k = 0; k < 6; ++k) G[k] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        if (!(m & (1 << k))) continue;
+        double g[6];
+        pair_grad_single(k, r, mom + off, g);
+        for (int c = 0; c < 6; ++c) G[c] += g[c];
+        off += width_of(k);
+    }
+}
+
+/* O(N^2) field gradient at the listed targets (all if targets == NULL),
+ * ascending j, j != i; grad is nt x 6 (xx, xy, xz, yy, yz, zz). */
+void orc_direct_grad(int64_t n, const double *pos, int order, const double *mom, int64_t nt,
+                     const int64_t *targets, double *grad)
+{
+    int w = mom_width(order);
+    int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < cnt; ++t) {
+        int64_t i = targets ? targets[t] : t;
+        double sg[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                           pos[3 * i + 2] - pos[3 * j + 2]};
+            double g[6];
+            orc_p2p_pair_grad(order, r, mom + w * j, g);
+            for (int c = 0; c < 6; ++c) sg[c] += g[c];
+        }
+        for (int c = 0; c < 6; ++c) grad[6 * t + c] = sg[c];
+    }
+}
+
 /* O(N^2) sum over all sources j != i for the listed targets (all if
  * targets == NULL), ascending j. */
 void orc_direct(int64_t n, const double *pos, int order, const double *mom,
@@ -405,6 +480,32 @@ void orc_l2p(int p, int s, const double *z, const double *L, const double *x, do
     E[0] = e[0];
     E[1] = e[1];
     E[2] = e[2];
+    free(mono);
+}
+
+/* Field gradient of the local expansion at x: the derivative of order
+ * k = e_i + e_j of the L2P sum (the general-k form of Eq. 10),
+ * d_i d_j phi = sum_{|n| <= p-s-2} (x-z)^n/n! L_{n+e_i+e_j}, G_ij = -that.
+ * For p - s < 2 the truncated expansion has no second derivative: G = 0. */
+void orc_l2p_grad(int p, int s, const double *z, const double *L, const double *x, double *G)
+{
+    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+    int q = p - s;
+    for (int k = 0; k < 6; ++k) G[k] = 0.0;
+    if (q < 2) return;
+    double *mono = malloc(sizeof(double) * orc_nterms(q));
+    double d[3] = {x[0] - z[0], x[1] - z[1], x[2] - z[2]};
+    monomials(q, d, mono);
+    for (int i = 0; i < orc_nterms(q - 2); ++i) {
+        int n[3];
+        orc_multi_index(i, n);
+        for (int k = 0; k < 6; ++k) {
+            int a[3] = {n[0], n[1], n[2]};
+            a[I[k]] += 1;
+            a[J[k]] += 1;
+            G[k] -= mono[i] * L[orc_index(a[0], a[1], a[2])];
+        }
+    }
     free(mono);
 }
 
@@ -795,9 +896,11 @@ int orc_upward(const orc_tree *t, int order, const double *mom, int p, double *M
 
 /* FMM potential/field at the listed targets (input indices; all if
  * targets == NULL).  L_out (ncells x nterms(p-s)), if given, receives the
- * local expansions of the cells that were needed (others zero). */
+ * local expansions of the cells that were needed (others zero).  grad, if
+ * given (nt x 6), receives the field gradient: the second derivatives of the
+ * local expansion plus the near field's closed forms. */
 int orc_fmm_eval(const orc_tree *t, int order, const double *mom, int p, int64_t nt_,
-                 const int64_t *targets, double *phi, double *field, double *L_out)
+                 const int64_t *targets, double *phi, double *field, double *L_out, double *grad)
 {
     if (!orc_code_valid(order)) return 1;
     int s = orc_min_order(order);
@@ -845,8 +948,9 @@ int orc_fmm_eval(const orc_tree *t, int order, const double *mom, int p, int64_t
         double zB[3], rB;
         orc_cell_center(t, b, zB, &rB);
         const double *x = t->xs + 3 * i;
-        double ph, e[3];
+        double ph, e[3], g[6];
         orc_l2p(p, s, zB, L + (size_t)b * ntL, x, &ph, e);
+        if (grad) orc_l2p_grad(p, s, zB, L + (size_t)b * ntL, x, g);
         for (int64_t q = t->p2p_ptr[b]; q < t->p2p_ptr[b + 1]; ++q) {
             int64_t a = t->p2p_src[q];
             for (int64_t j = t->first[a]; j < t->first[a] + t->count[a]; ++j) {
@@ -858,8 +962,15 @@ int orc_fmm_eval(const orc_tree *t, int order, const double *mom, int p, int64_t
                 e[0] += ee[0];
                 e[1] += ee[1];
                 e[2] += ee[2];
+                if (grad) {
+                    double gg[6];
+                    orc_p2p_pair_grad(order, r, ms + w * j, gg);
+                    for (int c = 0; c < 6; ++c) g[c] += gg[c];
+                }
             }
         }
+        if (grad)
+            for (int c = 0; c < 6; ++c) grad[6 * out + c] = g[c];
         if (phi) phi[out] = ph;
         if (field) {
             field[3 * out] = e[0];

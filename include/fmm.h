@@ -61,7 +61,7 @@ enum {
     FMM_ETIMEOUT = 6   /* serving: wait timed out */
 };
 
-enum { FMM_POT = 1, FMM_FIELD = 2 };               /* output bit mask */
+enum { FMM_POT = 1, FMM_FIELD = 2, FMM_GRAD = 4 };   /* output bit mask (FMM_GRAD: fmm_evaluate_grad only) */
 enum { FMM_METHOD_FMM = 0, FMM_METHOD_BH = 1 };
 enum { FMM_M2L_FULL = 0, FMM_M2L_HARMONIC = 1 };   /* see fmm_ctx_set_m2l_basis */
 enum {
@@ -114,6 +114,20 @@ int fmm_upward(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, i
  * (n x 3) must be non-NULL for the requested outputs.  FMM_ESTATE if
  * fmm_upward has not run on this tree. */
 int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field);
+
+/* fmm_evaluate plus the field gradient (Section 2: derivatives of the
+ * potential of order |k| from the local expansion, here k = e_i + e_j).
+ * `outputs` may add FMM_GRAD; grad (n x 6, caller order, device FP64)
+ * receives G_ij = d_i E_j = -d_i d_j phi as xx, xy, xz, yy, yz, zz: the
+ * second derivatives of the local expansion, -(1/r^3) sum_{|n| <= p-s-2}
+ * eta^n/n! L~_{n+e_i+e_j}, plus the closed-form gradients of the near-field
+ * pairs (computed by an extra near-field pass in this call, in the tree's
+ * precision).  phi and field as for fmm_evaluate and bit-identical to it.
+ * FMM trees only; p - s >= 2 (below that the truncated expansion has no
+ * second derivative; a finite difference of it would be zero too):
+ * FMM_EINVAL otherwise, FMM_ESTATE before fmm_upward.  The near-field
+ * gradient buffer (48 bytes per particle) is allocated on the first call. */
+int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field, double *grad);
 
 /* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,
  * n_m2l_classes, n_m2l_tiles, n_m2l_slots_used (tile lanes x union entries),

@@ -462,7 +462,8 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         return FMM_OK;
     drop_graphs(t);
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32, &t->d_Mh,
-                      (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_D64,
+                      (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_near_g,
+                      (void **)&t->d_D64,
                       (void **)&t->d_D32, (void **)&t->d_sc64, (void **)&t->d_sc32, (void **)&t->d_work,
                       (void **)&t->d_tile_chunk0, (void **)&t->d_tile_nchunk, (void **)&t->d_wave_ptr}) {
         tree_free_block(t, *pp);
@@ -627,8 +628,10 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
 
 // Queues the far field and the final combination (FMM) or the Barnes-Hut
 // traversal; wait_near: join the near field forked by queue_upward right
-// before the final L2P.
-static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, bool wait_near)
+// before the final L2P.  outputs & FMM_GRAD (FMM only): the near-field
+// gradient pass runs before the L2P, which then writes grad too.
+static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, bool wait_near,
+                          double *grad = nullptr)
 {
     hipStream_t s = ctx->stream;
     if (t->method == FMM_METHOD_BH) {
@@ -650,9 +653,13 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         KCHK(launch_l2l_level(t, l, s));
     }
     if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+    if (outputs & FMM_GRAD) {
+        ProfScope ps(ctx, s, "p2p_grad");
+        KCHK(launch_p2p(t, s, true));
+    }
     {
         ProfScope ps(ctx, s, "l2p");
-        KCHK(launch_l2p_final(t, outputs, phi, field, s));
+        KCHK(launch_l2p_final(t, outputs, phi, field, grad, s));
     }
     return FMM_OK;
 }
@@ -710,6 +717,32 @@ extern "C" int fmm_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi,
     if (t->method == FMM_METHOD_BH) return queue_evaluate(ctx, t, outputs, phi, field, false);
     const int64_t key[kGraphKey] = {2, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field, 0, 0, 0, 0, 0, 0};
     rc = run_cached(ctx, t, key, ctx->stream, [&]() { return queue_evaluate(ctx, t, outputs, phi, field, false); });
+    if (rc) return rc;
+    set_work_counts(t);
+    return FMM_OK;
+}
+
+extern "C" int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, double *grad)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (outputs <= 0 || (outputs & ~(FMM_POT | FMM_FIELD | FMM_GRAD))) FAIL(FMM_EINVAL, "bad output mask %d", outputs);
+    if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
+    if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
+    if ((outputs & FMM_GRAD) && !grad) FAIL(FMM_EINVAL, "field gradient requested but grad is NULL");
+    if (t->method != FMM_METHOD_FMM) FAIL(FMM_EINVAL, "field gradients are computed for FMM trees only");
+    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    if ((outputs & FMM_GRAD) && t->p - t->order < 2)
+        FAIL(FMM_EINVAL, "field gradient needs p - s >= 2 (p = %d, lowest source order %d): below that the "
+                         "truncated local expansion has no second derivative", t->p, t->order);
+    HIPCHK(hipSetDevice(ctx->device));
+    int rc;
+    if ((outputs & FMM_GRAD) && !t->d_near_g &&
+        (rc = tree_alloc(t, (void **)&t->d_near_g, sizeof(double) * 6 * (size_t)std::max<int64_t>(1, t->ht.n))))
+        return rc;
+    const int64_t key[kGraphKey] = {4, outputs, (int64_t)(uintptr_t)phi, (int64_t)(uintptr_t)field,
+                                    (int64_t)(uintptr_t)grad, 0, 0, 0, 0, 0};
+    rc = run_cached(ctx, t, key, ctx->stream,
+                    [&]() { return queue_evaluate(ctx, t, outputs, phi, field, false, grad); });
     if (rc) return rc;
     set_work_counts(t);
     return FMM_OK;

@@ -246,6 +246,7 @@ struct fmm_tree {
     void *d_part = nullptr;
     double *d_L64 = nullptr;
     double *d_near = nullptr;              // 4 per particle
+    double *d_near_g = nullptr;            // 6 per particle: near-field gradient (allocated on first use)
     double *d_D64 = nullptr, *d_sc64 = nullptr;
     float *d_D32 = nullptr, *d_sc32 = nullptr;
     size_t dev_bytes = 0;
@@ -281,8 +282,8 @@ hipError_t launch_fill(double *p, size_t count, hipStream_t s);
 hipError_t launch_m2l(fmm_tree *t, hipStream_t s);
 hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s);
 hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
-hipError_t launch_p2p(fmm_tree *t, hipStream_t s);
-hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false);   // grad: field gradient to d_near_g
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
 

@@ -563,7 +563,8 @@ struct P2PArgs {
     const float *m32;       // 8 per particle
     const double *xs;       // SoA
     const double *m64;
-    double *near;           // 4 per particle
+    double *near;           // 4 per particle (phi, E)
+    double *near_g;         // 6 per particle (field gradient), gradient kernels only
     int n;
     double h, lo[3];
 };
@@ -652,8 +653,30 @@ __device__ __forceinline__ void p2p_pair_mixed(float rx, float ry, float rz, flo
 }
 
 template <int MASK>
+__device__ __forceinline__ void p2p_pair_grad_mixed(float rx, float ry, float rz, float inv, const float4 &m0,
+                                                    const float4 &m1, const float4 &m2, float (&g)[6][3])
+{
+    const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    float t[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (!(MASK & (1 << k))) continue;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = g[c][k];
+        if (k == 0) p2p_pair_grad_f32<0>(rx, ry, rz, inv, m0, z4, t);
+        if (k == 1) p2p_pair_grad_f32<1>(rx, ry, rz, inv, make_float4(m0.y, m0.z, m0.w, 0.f), z4, t);
+        if (k == 2) p2p_pair_grad_f32<2>(rx, ry, rz, inv, m1, m2, t);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g[c][k] = t[c];
+    }
+}
+
+// GRAD: the six field-gradient components instead of phi and E (sums of
+// order k scaled by r_b^-(k+3)), written to near_g
+template <int MASK, bool GRAD>
 __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
 {
+    constexpr int NO = GRAD ? 6 : 4;                 // output components
     constexpr bool ONE = mask_single(MASK);
     constexpr int S = mask_min_order(MASK);
     constexpr int NV = ONE ? (S == 2 ? 2 : 1) : 3;   // float4 of moments per staged source
@@ -662,7 +685,7 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
     __shared__ float4 spm[NV][kPChunk32];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
-    __shared__ double red[4][kPT];
+    __shared__ double red[NO][kPT];
     __shared__ int sh[kPT / 64];
     __shared__ int wself;
     const int tid = threadIdx.x;
@@ -679,6 +702,8 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
     sfld[0] = sphi[1];
     sfld[1] = sphi[2];
     sfld[2] = sphi[2] * irb;
+    // scale of output component c of the order-k sums
+    auto scale = [&](int c, int k) { return GRAD ? sfld[k] * irb : (c == 0 ? sphi[k] : sfld[k]); };
     double zb[3];
     {
         const double r = ldexp(1.0, kMaxLevel - cb.level);
@@ -700,9 +725,12 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
         // close pairs keep their relative accuracy
         const double tx = (a.xs[i] - zb[0]) * irb, ty = (a.xs[n + i] - zb[1]) * irb,
                      tz = (a.xs[2 * n + i] - zb[2]) * irb;
-        // Kahan-compensated sums per source order
-        float ps[3] = {0.f, 0.f, 0.f}, pc[3] = {0.f, 0.f, 0.f}, xs_[3] = {0.f, 0.f, 0.f}, xc[3] = {0.f, 0.f, 0.f};
-        float ys[3] = {0.f, 0.f, 0.f}, yc[3] = {0.f, 0.f, 0.f}, zs[3] = {0.f, 0.f, 0.f}, zc[3] = {0.f, 0.f, 0.f};
+        // Kahan-compensated sums per output component and source order
+        float ks[NO][3], kc[NO][3];
+#pragma unroll
+        for (int c = 0; c < NO; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) ks[c][k] = kc[c][k] = 0.f;
         for (int w0 = e0; w0 < e1; w0 += kPList) {
             const int nw = min(kPList, e1 - w0);
             __syncthreads();
@@ -726,8 +754,11 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                     const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
                     // the target itself, if it is staged in this chunk
                     const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
-                    float bp[3] = {0.f, 0.f, 0.f}, bx[3] = {0.f, 0.f, 0.f}, by[3] = {0.f, 0.f, 0.f},
-                          bz[3] = {0.f, 0.f, 0.f};
+                    float bs[NO][3];
+#pragma unroll
+                    for (int c = 0; c < NO; ++c)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) bs[c][k] = 0.f;
                     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
                     for (int j = ja; j < jb; ++j) {
                         const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
@@ -735,64 +766,69 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                         const float inv = j == jself ? 0.f : __builtin_amdgcn_rsqf(r2);
                         const float4 m0 = spm[0][j];
                         const float4 m1 = NV >= 2 ? spm[NV >= 2 ? 1 : 0][j] : zero4;
-                        if (ONE) {
-                            p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bp[S], bx[S], by[S], bz[S]);
+                        if constexpr (GRAD) {
+                            if constexpr (ONE) {
+                                float t6[6];
+#pragma unroll
+                                for (int c = 0; c < 6; ++c) t6[c] = bs[c][S];
+                                p2p_pair_grad_f32<S>(rx, ry, rz, inv, m0, m1, t6);
+#pragma unroll
+                                for (int c = 0; c < 6; ++c) bs[c][S] = t6[c];
+                            } else {
+                                const float4 m2 = spm[NV >= 3 ? 2 : 0][j];
+                                p2p_pair_grad_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bs);
+                            }
+                        } else if constexpr (ONE) {
+                            p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bs[0][S], bs[1][S], bs[2][S], bs[3][S]);
                         } else {
                             const float4 m2 = spm[NV >= 3 ? 2 : 0][j];
-                            p2p_pair_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bp, bx, by, bz);
+                            p2p_pair_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bs[0], bs[1], bs[2], bs[3]);
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         if (!(MASK & (1 << k))) continue;
-                        kahan_add(ps[k], pc[k], bp[k]);
-                        kahan_add(xs_[k], xc[k], bx[k]);
-                        kahan_add(ys[k], yc[k], by[k]);
-                        kahan_add(zs[k], zc[k], bz[k]);
+#pragma unroll
+                        for (int c = 0; c < NO; ++c) kahan_add(ks[c][k], kc[c][k], bs[c][k]);
                     }
                 }
             }
         }
         __syncthreads();
-        double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (!(MASK & (1 << k))) continue;
-            q0 += ((double)ps[k] - (double)pc[k]) * sphi[k];
-            q1 += ((double)xs_[k] - (double)xc[k]) * sfld[k];
-            q2 += ((double)ys[k] - (double)yc[k]) * sfld[k];
-            q3 += ((double)zs[k] - (double)zc[k]) * sfld[k];
+        for (int c = 0; c < NO; ++c) {
+            double q = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                if (!(MASK & (1 << k))) continue;
+                q += ((double)ks[c][k] - (double)kc[c][k]) * scale(c, k);
+            }
+            red[c][tid] = act ? q : 0.0;
         }
-        red[0][tid] = act ? q0 : 0.0;
-        red[1][tid] = act ? q1 : 0.0;
-        red[2][tid] = act ? q2 : 0.0;
-        red[3][tid] = act ? q3 : 0.0;
         __syncthreads();
         if (tid < cs) {
-            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-            for (int k = 0; k < ns; ++k) {
-                v0 += red[0][tid + k * cs];
-                v1 += red[1][tid + k * cs];
-                v2 += red[2][tid + k * cs];
-                v3 += red[3][tid + k * cs];
-            }
-            double *o = a.near + 4 * (size_t)i;
-            o[0] = v0;
-            o[1] = v1;
-            o[2] = v2;
-            o[3] = v3;
+            double v[NO];
+#pragma unroll
+            for (int c = 0; c < NO; ++c) v[c] = 0.0;
+            for (int k = 0; k < ns; ++k)
+#pragma unroll
+                for (int c = 0; c < NO; ++c) v[c] += red[c][tid + k * cs];
+            double *o = GRAD ? a.near_g + 6 * (size_t)i : a.near + 4 * (size_t)i;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) o[c] = v[c];
         }
     }
 }
 
-template <int MASK>
+template <int MASK, bool GRAD>
 __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
 {
     constexpr int W = mask_width(MASK);
+    constexpr int NO = GRAD ? 6 : 4;
     __shared__ double sx[kPChunk64], sy[kPChunk64], sz[kPChunk64], sm[W][kPChunk64];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
-    __shared__ double red[4][kPT];
+    __shared__ double red[NO][kPT];
     __shared__ int sh[kPT / 64];
     __shared__ int wself;
     const int tid = threadIdx.x;
@@ -809,6 +845,7 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
         const int i = cb.first + tg0 + t;
         const double xi = a.xs[i], yi = a.xs[n + i], zi = a.xs[2 * n + i];
         double ph = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        double g[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int w0 = e0; w0 < e1; w0 += kPList) {
             const int nw = min(kPList, e1 - w0);
             __syncthreads();
@@ -838,33 +875,39 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
 #pragma unroll
                         for (int c = 0; c < W; ++c) m[c] = sm[c][j];
                         // a source of several orders adds each order's terms
-                        if (MASK & 1) p2p_pair_f64<0>(rx, ry, rz, m, ph, ex, ey, ez);
-                        if (MASK & 2) p2p_pair_f64<1>(rx, ry, rz, m + (MASK & 1), ph, ex, ey, ez);
-                        if (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
+                        if constexpr (GRAD) {
+                            if (MASK & 1) p2p_pair_grad_f64<0>(rx, ry, rz, m, g);
+                            if (MASK & 2) p2p_pair_grad_f64<1>(rx, ry, rz, m + (MASK & 1), g);
+                            if (MASK & 4) p2p_pair_grad_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), g);
+                        } else {
+                            if (MASK & 1) p2p_pair_f64<0>(rx, ry, rz, m, ph, ex, ey, ez);
+                            if (MASK & 2) p2p_pair_f64<1>(rx, ry, rz, m + (MASK & 1), ph, ex, ey, ez);
+                            if (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
+                        }
                     }
                 }
             }
         }
         __syncthreads();
-        red[0][tid] = act ? ph : 0.0;
-        red[1][tid] = act ? ex : 0.0;
-        red[2][tid] = act ? ey : 0.0;
-        red[3][tid] = act ? ez : 0.0;
+        const double mine[4] = {ph, ex, ey, ez};
+#pragma unroll
+        for (int c = 0; c < NO; ++c) red[c][tid] = act ? (GRAD ? g[c] : mine[c % 4]) : 0.0;
         __syncthreads();
         if (tid < cs) {
-            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            double v[NO];
+#pragma unroll
+            for (int c = 0; c < NO; ++c) v[c] = 0.0;
             for (int k = 0; k < ns; ++k)
-                for (int c = 0; c < 4; ++c) v[c] += red[c][tid + k * cs];
-            double *o = a.near + 4 * (size_t)i;
-            o[0] = v[0];
-            o[1] = v[1];
-            o[2] = v[2];
-            o[3] = v[3];
+#pragma unroll
+                for (int c = 0; c < NO; ++c) v[c] += red[c][tid + k * cs];
+            double *o = GRAD ? a.near_g + 6 * (size_t)i : a.near + 4 * (size_t)i;
+#pragma unroll
+            for (int c = 0; c < NO; ++c) o[c] = v[c];
         }
     }
 }
 
-hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad)
 {
     P2PArgs a;
     a.leaves = t->d_leaves;
@@ -876,6 +919,7 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
     a.xs = t->d_x;
     a.m64 = t->d_mom;
     a.near = t->d_near;
+    a.near_g = t->d_near_g;
     a.n = (int)t->ht.n;
     a.h = t->ht.h;
     a.order = t->d_p2p_order;
@@ -883,8 +927,10 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s)
     const bool f32 = t->prec == FMM_PREC_MIXED;
 #define P2P_CASE(M)                                                                         \
     case M:                                                                                 \
-        if (f32) hipLaunchKernelGGL(p2p_f32_kernel<M>, g, bl, 0, s, a);                     \
-        else hipLaunchKernelGGL(p2p_f64_kernel<M>, g, bl, 0, s, a);                         \
+        if (f32 && grad) hipLaunchKernelGGL((p2p_f32_kernel<M, true>), g, bl, 0, s, a);     \
+        else if (f32) hipLaunchKernelGGL((p2p_f32_kernel<M, false>), g, bl, 0, s, a);       \
+        else if (grad) hipLaunchKernelGGL((p2p_f64_kernel<M, true>), g, bl, 0, s, a);       \
+        else hipLaunchKernelGGL((p2p_f64_kernel<M, false>), g, bl, 0, s, a);                \
         break;
     switch (t->smask) {
         P2P_CASE(1)
@@ -915,13 +961,18 @@ constexpr int kL2PLds = 16384;   // bytes of cubes per wave
 __host__ __device__ constexpr int l2p_cube(int q) { return (q + 2) * (q + 2) * (q + 2); }
 int l2p_pack_limit(int q) { return std::max(1, std::min(kL2PMaxLeaves, kL2PLds / (int)(8 * l2p_cube(q)))); }
 
-template <int Q>
+// GRAD: also the field gradient, -(1/r^3) sum_{|n|<=q-2} eta^n/n! L~_{n+e_i+e_j}
+// (the second derivatives of the expansion, the general-k form of Eq. 10),
+// plus the near field's gradient; its sums read the same cube (indices stay
+// inside the simplex, so no larger edge is needed)
+template <int Q, bool GRAD>
 __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ pack,
                                                  const int32_t *__restrict__ leaves, const DevCell *__restrict__ cells,
                                                  Geo g, const double *__restrict__ xs, int n,
                                                  const double *__restrict__ L, const double *__restrict__ near,
                                                  const int32_t *__restrict__ perm, double *__restrict__ phi,
-                                                 double *__restrict__ field)
+                                                 double *__restrict__ field, const double *__restrict__ near_g,
+                                                 double *__restrict__ grad)
 {
     constexpr int NL = nterms(Q);
     constexpr int E = Q + 2;                     // edge: room for n + e_d
@@ -969,6 +1020,7 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
 #pragma unroll
         for (int a = 1; a <= Q; ++a) pz[a] = pz[a - 1] * ez * (1.0 / a);
         double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+        double G[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx, xy, xz, yy, yz, zz
         double px = 1.0;
 #pragma unroll 1
         for (int nx = 0; nx <= Q; ++nx) {
@@ -994,6 +1046,21 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
                 fx = fma(py, tx, fx);
                 fy = fma(py, ty, fy);
                 fz = fma(py, tz, fz);
+                if constexpr (GRAD) {
+                    double tg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int nz = 0; nz + 2 <= Q; ++nz) {
+                        if (nz > lim - 2) break;
+                        tg[0] = fma(pz[nz], b[2 * E * E + nz], tg[0]);
+                        tg[1] = fma(pz[nz], b[E * E + E + nz], tg[1]);
+                        tg[2] = fma(pz[nz], b[E * E + nz + 1], tg[2]);
+                        tg[3] = fma(pz[nz], b[2 * E + nz], tg[3]);
+                        tg[4] = fma(pz[nz], b[E + nz + 1], tg[4]);
+                        tg[5] = fma(pz[nz], b[nz + 2], tg[5]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) G[c] = fma(py, tg[c], G[c]);
+                }
             }
         }
         const double *nr = near + 4 * (size_t)i;
@@ -1005,32 +1072,48 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
             field[3 * o + 1] = -fy * ir2 + nr[2];
             field[3 * o + 2] = -fz * ir2 + nr[3];
         }
+        if constexpr (GRAD) {
+            const double ir3 = ir * ir * ir;
+            const double *ng = near_g + 6 * (size_t)i;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) grad[6 * o + c] = -G[c] * ir3 + ng[c];
+        }
     }
 }
 
 template <int Q>
-static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
+static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
     const size_t lds = (size_t)l2p_pack_limit(Q) * l2p_cube(Q) * sizeof(double);
-    hipLaunchKernelGGL(l2p_kernel<Q>, dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs, t->d_l2p_pack,
-                       t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm, phi, field);
+    if constexpr (Q >= 2) {
+        if (outputs & FMM_GRAD) {
+            hipLaunchKernelGGL((l2p_kernel<Q, true>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
+                               t->d_l2p_pack, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near,
+                               t->d_perm, phi, field, t->d_near_g, grad);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((l2p_kernel<Q, false>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
+                       t->d_l2p_pack, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm,
+                       phi, field, nullptr, nullptr);
 }
 
-hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
 {
+    if ((outputs & FMM_GRAD) && t->p - t->order < 2) return hipErrorInvalidValue;
     switch (t->p - t->order) {
-    case 0: l2p_launch<0>(t, outputs, phi, field, s); break;
-    case 1: l2p_launch<1>(t, outputs, phi, field, s); break;
-    case 2: l2p_launch<2>(t, outputs, phi, field, s); break;
-    case 3: l2p_launch<3>(t, outputs, phi, field, s); break;
-    case 4: l2p_launch<4>(t, outputs, phi, field, s); break;
-    case 5: l2p_launch<5>(t, outputs, phi, field, s); break;
-    case 6: l2p_launch<6>(t, outputs, phi, field, s); break;
-    case 7: l2p_launch<7>(t, outputs, phi, field, s); break;
-    case 8: l2p_launch<8>(t, outputs, phi, field, s); break;
-    case 9: l2p_launch<9>(t, outputs, phi, field, s); break;
-    case 10: l2p_launch<10>(t, outputs, phi, field, s); break;
+    case 0: l2p_launch<0>(t, outputs, phi, field, grad, s); break;
+    case 1: l2p_launch<1>(t, outputs, phi, field, grad, s); break;
+    case 2: l2p_launch<2>(t, outputs, phi, field, grad, s); break;
+    case 3: l2p_launch<3>(t, outputs, phi, field, grad, s); break;
+    case 4: l2p_launch<4>(t, outputs, phi, field, grad, s); break;
+    case 5: l2p_launch<5>(t, outputs, phi, field, grad, s); break;
+    case 6: l2p_launch<6>(t, outputs, phi, field, grad, s); break;
+    case 7: l2p_launch<7>(t, outputs, phi, field, grad, s); break;
+    case 8: l2p_launch<8>(t, outputs, phi, field, grad, s); break;
+    case 9: l2p_launch<9>(t, outputs, phi, field, grad, s); break;
+    case 10: l2p_launch<10>(t, outputs, phi, field, grad, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -80,3 +80,82 @@ __device__ __forceinline__ void p2p_pair_f64(double rx, double ry, double rz, co
     }
 }
 
+
+// Field gradient G_ij = d_i E_j = -d_i d_j phi of the same sources (the
+// second derivatives of the potentials above), accumulated into
+// g[0..5] = xx, xy, xz, yy, yz, zz:
+//   charge:     q (delta_ij / r^3 - 3 r_i r_j / r^5)
+//   dipole:     3 (mu_i r_j + mu_j r_i + (mu.r) delta_ij) / r^5 - 15 (mu.r) r_i r_j / r^7
+//   quadrupole: -3 Q_ij / r^5 + 15 ((Qr)_i r_j + (Qr)_j r_i) / r^7
+//               + (7.5 r.Q.r / r^7 - 1.5 tr Q / r^5) delta_ij
+//               + (7.5 tr Q / r^7 - 52.5 r.Q.r / r^9) r_i r_j
+template <int S, typename T>
+__device__ __forceinline__ void pair_grad_terms(T rx, T ry, T rz, T inv, T m0, T m1, T m2, T m3, T m4, T m5, T tr,
+                                                T (&g)[6])
+{
+    const T inv2 = inv * inv;
+    const T inv3 = inv * inv2;
+    const T inv5 = inv3 * inv2;
+    const T r[3] = {rx, ry, rz};
+    if (S == 0) {
+        const T a = m0 * inv3, b = (T)3 * m0 * inv5;
+        g[0] += a - b * rx * rx;
+        g[1] -= b * rx * ry;
+        g[2] -= b * rx * rz;
+        g[3] += a - b * ry * ry;
+        g[4] -= b * ry * rz;
+        g[5] += a - b * rz * rz;
+    } else if (S == 1) {
+        const T mu[3] = {m0, m1, m2};
+        const T mr = m0 * rx + m1 * ry + m2 * rz;
+        const T a = (T)3 * inv5, b = (T)15 * mr * inv5 * inv2;
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j, ++k)
+                g[k] += a * (mu[i] * r[j] + mu[j] * r[i] + (i == j ? mr : (T)0)) - b * r[i] * r[j];
+    } else {
+        // m0..m5 = xx, xy, xz, yy, yz, zz
+        const T Q[3][3] = {{m0, m1, m2}, {m1, m3, m4}, {m2, m4, m5}};
+        T Qr[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Qr[i] = Q[i][0] * rx + Q[i][1] * ry + Q[i][2] * rz;
+        const T rqr = rx * Qr[0] + ry * Qr[1] + rz * Qr[2];
+        const T inv7 = inv5 * inv2;
+        const T cq = (T)-3 * inv5, cx = (T)15 * inv7;
+        const T cd = (T)7.5 * rqr * inv7 - (T)1.5 * tr * inv5;
+        const T cr = (T)7.5 * tr * inv7 - (T)52.5 * rqr * inv7 * inv2;
+        int k = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = i; j < 3; ++j, ++k)
+                g[k] += cq * Q[i][j] + cx * (Qr[i] * r[j] + Qr[j] * r[i]) + (i == j ? cd : (T)0) + cr * r[i] * r[j];
+    }
+}
+
+// FP32 near field: positions in units of the target leaf radius, moments as
+// staged (charge m0.x; dipole m0.xyz; quadrupole m0 = (xx, xy, xz, yy),
+// m1 = (yz, zz, tr, -))
+template <int S>
+__device__ __forceinline__ void p2p_pair_grad_f32(float rx, float ry, float rz, float inv, const float4 &m0,
+                                                  const float4 &m1, float (&g)[6])
+{
+    if (S == 2) pair_grad_terms<2, float>(rx, ry, rz, inv, m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, g);
+    else pair_grad_terms<S, float>(rx, ry, rz, inv, m0.x, m0.y, m0.z, 0.f, 0.f, 0.f, 0.f, g);
+}
+
+// FP64 near field: physical positions and moments (w values of one order)
+template <int S>
+__device__ __forceinline__ void p2p_pair_grad_f64(double rx, double ry, double rz, const double *m, double (&g)[6])
+{
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    double inv = __builtin_amdgcn_rsq(r2);
+    const double hr = 0.5 * r2;
+    inv = inv * __builtin_fma(-hr * inv, inv, 1.5);
+    inv = inv * __builtin_fma(-hr * inv, inv, 1.5);
+    if (S == 2) pair_grad_terms<2, double>(rx, ry, rz, inv, m[0], m[1], m[2], m[3], m[4], m[5], m[0] + m[3] + m[5], g);
+    else if (S == 1) pair_grad_terms<1, double>(rx, ry, rz, inv, m[0], m[1], m[2], 0.0, 0.0, 0.0, 0.0, g);
+    else pair_grad_terms<0, double>(rx, ry, rz, inv, m[0], 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, g);
+}

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FMM_LIBRARY") or os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE, FMM_EBUSY, FMM_ETIMEOUT = range(7)
-FMM_POT, FMM_FIELD = 1, 2
+FMM_POT, FMM_FIELD, FMM_GRAD = 1, 2, 4   # output mask bits (FMM_GRAD: evaluate_grad only)
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
@@ -55,6 +55,7 @@ fmm_build_tree = _sig("fmm_build_tree", [_vp, _vp, _i64, ctypes.c_int, ctypes.c_
                                          ctypes.POINTER(_vp)])
 fmm_upward = _sig("fmm_upward", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int])
 fmm_evaluate = _sig("fmm_evaluate", [_vp, _vp, ctypes.c_int, _vp, _vp])
+fmm_evaluate_grad = _sig("fmm_evaluate_grad", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp])
 fmm_run = _sig("fmm_run", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp])
 fmm_tree_info = _sig("fmm_tree_info", [_vp, _vp])
 fmm_tree_export = _sig("fmm_tree_export", [_vp] + [_vp] * 14)
@@ -77,7 +78,7 @@ fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
 fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
-EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_run", "fmm_tree_info",
+EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_run", "fmm_tree_info",
             "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
@@ -254,6 +255,21 @@ class Tree:
         _check(fmm_evaluate(self.ctx.h, self.h, int(outputs), phi.data_ptr() if phi is not None else None,
                             field.data_ptr() if field is not None else None), "fmm_evaluate")
         return phi, field
+
+    def evaluate_grad(self, outputs: int = FMM_POT | FMM_FIELD | FMM_GRAD, phi: Optional[torch.Tensor] = None,
+                      field: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+        """phi, field and the field gradient (n x 6: xx, xy, xz, yy, yz, zz)"""
+        dev = torch.device("cuda", self.ctx.device)
+        if (outputs & FMM_POT) and phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if (outputs & FMM_FIELD) and field is None:
+            field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
+        if (outputs & FMM_GRAD) and grad is None:
+            grad = torch.empty((self.n, 6), dtype=torch.float64, device=dev)
+        ptr = lambda x: x.data_ptr() if x is not None else None  # noqa: E731
+        _check(fmm_evaluate_grad(self.ctx.h, self.h, int(outputs), ptr(phi), ptr(field), ptr(grad)),
+               "fmm_evaluate_grad")
+        return phi, field, grad
 
     def run(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED,
             outputs: int = FMM_POT | FMM_FIELD, phi: Optional[torch.Tensor] = None,

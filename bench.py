@@ -241,6 +241,22 @@ def main():
         prof, work = kernel_pass(prec, args.steps)
         res[name] = dict(step_s=step_s, prof=prof, out=(None if out[0] is None else out[0].cpu().numpy(),
                                                          out[1].cpu().numpy()), work=work)
+    grad_line = None
+    if not bh and w.p - w.order >= 2:
+        # the field gradient after the timed steps' upward state (MIXED)
+        grd = torch.empty((w.n, 6), dtype=torch.float64, device=dev)
+        tree.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED, outputs)
+        for _ in range(args.warmup):
+            tree.evaluate_grad(fmm.FMM_GRAD, None, None, grd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            tree.evaluate_grad(fmm.FMM_GRAD, None, None, grd)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        grad_line = {"ms_per_call": dt * 1e3, "unit": "evals/s", "value": w.n / dt,
+                     "what": "fmm_evaluate_grad(FMM_GRAD) after the MIXED upward pass: far field again plus a "
+                             "near-field gradient pass", "out": grd.cpu().numpy()}
     full_basis = None
     if not bh:
         # the same MIXED steps with the M2L contracting every Cartesian component
@@ -305,6 +321,7 @@ def main():
                    **({} if bh else {"m2l_basis": "harmonic"})},
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         **({} if bh else {"m2l_full_basis": full_basis}),
+        **({} if grad_line is None else {"field_gradient": {k: v for k, v in grad_line.items() if k != "out"}}),
         "kernel_timing": "separate pass of the same steps, kernels serialised, HIP events on the launch stream",
         "kernel_avg_ms_mixed": kern_ms,
         "kernel_avg_ms_fp64": {k: v[0] / max(1, v[1]) for k, v in f64["prof"].items()},
@@ -357,6 +374,11 @@ def main():
             errs[name] = e
         errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s" % (len(sample), kind)
         line["rel_l2_error"] = errs
+        if grad_line is not None:
+            Go = ot.fmm(w.order, w.moments, w.p, targets=sample, want_grad=True)[2]
+            Gd = oracle.direct_grad(w.pos, w.order, w.moments, targets=sample)
+            line["field_gradient"]["G_vs_oracle"] = oracle.rel_l2(grad_line["out"][sample], Go)
+            line["field_gradient"]["G_vs_direct"] = oracle.rel_l2(grad_line["out"][sample], Gd)
         if not args.no_accuracy and not bh and args.config == 2:
             line["at_1e-6"] = accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, Ed)
     if not args.no_serve:

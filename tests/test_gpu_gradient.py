@@ -8,7 +8,8 @@ Tolerances (relative L2 over all targets and the six components):
   terms are FP32: a few units of roundoff (6e-8) each, with cancellation
   between the delta and r_i r_j parts (up to 3x for a charge, more for the
   quadrupole's five terms) and Kahan-compensated sums; the far part comes
-  from the FP32 M2L like the field's.  Observed values are printed.
+  from the FP32 M2L like the field's.  Observed: 2.1e-7 to 5.6e-7 (FP64
+  4e-16 to 3e-15); the values are printed.
 """
 import numpy as np
 import pytest

@@ -369,12 +369,14 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     // level, L2L only below the shallowest M2L target level: above them the
     // multipoles are never read and the locals are zero.  Barnes-Hut may
     // accept a cell at any level.
+    // (a list is sorted by source index and cells are level-major, so its
+    // first source is its shallowest)
     int src_top = nlev, tgt_top = nlev;
     if ((int64_t)h.m2l_ptr.size() == nc + 1)
         for (int64_t c = 0; c < nc; ++c)
             if (h.m2l_ptr[c + 1] > h.m2l_ptr[c]) {
                 tgt_top = std::min(tgt_top, h.level[c]);
-                for (int64_t e = h.m2l_ptr[c]; e < h.m2l_ptr[c + 1]; ++e) src_top = std::min(src_top, h.level[h.m2l_src[e]]);
+                src_top = std::min(src_top, h.level[h.m2l_src[h.m2l_ptr[c]]]);
             }
     t->m2m_top = method == FMM_METHOD_BH ? 0 : src_top;
     t->l2l_from = tgt_top + 1;

@@ -8,20 +8,172 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <atomic>
+#include <thread>
 
 #include "fmm_internal.h"
+
+// ---------------------------------------------------------------------------
+// Host threads for the scheduling passes: work items [0, n) in contiguous
+// blocks, one per thread; every result slot is written by exactly one item,
+// so the outcome does not depend on the thread count (at most 16 cores,
+// divided among the builds in flight).
+// Builds running at once (serving overlaps them) share the host cores.
+static std::atomic<int> g_builds{0};
+struct BuildScope {
+    BuildScope() { ++g_builds; }
+    ~BuildScope() { --g_builds; }
+};
+
+template <typename F>
+static void parallel_for(int64_t n, F f)
+{
+    const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int64_t nt = std::min<int64_t>(std::max(1, hw / std::max(1, g_builds.load())), std::max<int64_t>(1, n / 4));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int64_t k = 0; k < nt; ++k)
+        th.emplace_back([&, k]() {
+            for (int64_t i = n * k / nt; i < n * (k + 1) / nt; ++i) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// Exact integer geometry of a pair (source A, target B): the centre offset
+// in units of the smaller radius and the level difference.  It determines
+// ((z_B - z_A) / r_B, r_A / r_B) exactly.
+struct ClassKey {
+    int64_t d[3];
+    int32_t dl;
+    bool operator<(const ClassKey &o) const
+    {
+        if (dl != o.dl) return dl < o.dl;
+        for (int k = 0; k < 3; ++k)
+            if (d[k] != o.d[k]) return d[k] < o.d[k];
+        return false;
+    }
+    bool operator==(const ClassKey &o) const
+    {
+        return dl == o.dl && d[0] == o.d[0] && d[1] == o.d[1] && d[2] == o.d[2];
+    }
+    uint64_t hash() const
+    {
+        uint64_t h = (uint64_t)d[0] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)d[1] * 0xC2B2AE3D27D4EB4FULL ^
+                     (uint64_t)d[2] * 0x165667B19E3779F9ULL ^ (uint64_t)(dl + 64) * 0x27D4EB2F165667C5ULL;
+        return h ^ (h >> 29);
+    }
+};
+
+static ClassKey class_key(const HostTree &t, int64_t A, int64_t B)
+{
+    const int la = t.level[A], lb = t.level[B];
+    const int lmax = std::max(la, lb);
+    ClassKey k;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t cb = (2 * (int64_t)t.ix[3 * B + d] + 1) << (lmax - lb);
+        const int64_t ca = (2 * (int64_t)t.ix[3 * A + d] + 1) << (lmax - la);
+        k.d[d] = cb - ca;
+    }
+    k.dl = lb - la;
+    return k;
+}
+
+// Map ClassKey -> int (one per thread and tile).  Pairs of one level with
+// offsets of at most kNear cells per axis (nearly all M2L pairs) index a
+// dense table; the rest go through open addressing.
+constexpr int kNear = 8;
+constexpr int kNearW = 2 * kNear + 1;
+static int near_index(const ClassKey &k)
+{
+    if (k.dl != 0) return -1;
+    int idx = 0;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t o = k.d[d] / 2;   // same level: offsets are 2 * (cell offset)
+        if (o < -kNear || o > kNear) return -1;
+        idx = idx * kNearW + (int)(o + kNear);
+    }
+    return idx;
+}
+
+struct KeyMap {
+    std::vector<int32_t> nearv;
+    std::vector<ClassKey> key;
+    std::vector<int32_t> val;
+    size_t mask = 0, used = 0;
+    void reset(size_t want)
+    {
+        nearv.assign((size_t)kNearW * kNearW * kNearW, -1);
+        size_t cap = 64;
+        while (cap < 2 * want) cap *= 2;
+        key.assign(cap, ClassKey{});
+        val.assign(cap, -1);
+        mask = cap - 1;
+        used = 0;
+    }
+    // value of k, inserting it with value v if absent
+    int32_t get_or_put(const ClassKey &k, int32_t v)
+    {
+        const int ni = near_index(k);
+        if (ni >= 0) {
+            if (nearv[ni] < 0) nearv[ni] = v;
+            return nearv[ni];
+        }
+        if (2 * (used + 1) > key.size()) grow();
+        size_t i = k.hash() & mask;
+        while (val[i] >= 0) {
+            if (key[i] == k) return val[i];
+            i = (i + 1) & mask;
+        }
+        key[i] = k;
+        val[i] = v;
+        ++used;
+        return v;
+    }
+    int32_t get(const ClassKey &k) const
+    {
+        const int ni = near_index(k);
+        if (ni >= 0) return nearv[ni];
+        size_t i = k.hash() & mask;
+        while (val[i] >= 0) {
+            if (key[i] == k) return val[i];
+            i = (i + 1) & mask;
+        }
+        return -1;
+    }
+    void grow()
+    {
+        std::vector<ClassKey> ok(std::move(key));
+        std::vector<int32_t> ov(std::move(val));
+        key.assign(ok.size() * 2, ClassKey{});
+        val.assign(ok.size() * 2, -1);
+        mask = key.size() - 1;
+        for (size_t j = 0; j < ok.size(); ++j)
+            if (ov[j] >= 0) {
+                size_t i = ok[j].hash() & mask;
+                while (val[i] >= 0) i = (i + 1) & mask;
+                key[i] = ok[j];
+                val[i] = ov[j];
+            }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // M2L tiling.  Target cells with a non-empty M2L list are grouped 64 to a
 // tile (one GPU lane per target).  Cells of one level and one position
 // inside their parent have identical relative source layouts away from the
 // domain boundary, and near it equal truncations (see below), so tiles are
-// formed in that order.  A tile iterates over
-// the union of its targets' translation classes; a class is the exact
-// dimensionless geometry of a pair, ((z_B - z_A) / r_B, r_A / r_B), so one
-// derivative tensor serves every lane at a given step.
+// formed in that order.  A tile iterates over the union of its targets'
+// translation classes; a class is the exact dimensionless geometry of a
+// pair, ((z_B - z_A) / r_B, r_A / r_B), so one derivative tensor serves
+// every lane at a given step.  Class ids follow the sorted order of the
+// exact pair geometry, so they and everything built from them are the same
+// for any number of host threads.
 void build_m2l_tiling(const HostTree &t, M2LTiling &out)
 {
+    BuildScope scope;
     out = M2LTiling();
     const int64_t nc = t.ncells();
     std::vector<int32_t> tg;
@@ -39,7 +191,8 @@ void build_m2l_tiling(const HostTree &t, M2LTiling &out)
         int64_t len;
     };
     std::vector<Key> key(nc);
-    for (int32_t c : tg) {
+    parallel_for((int64_t)tg.size(), [&](int64_t q) {
+        const int32_t c = tg[q];
         Key k{{0, 0, 0}, {0, 0, 0}, t.m2l_ptr[c + 1] - t.m2l_ptr[c]};
         bool any = false;
         for (int64_t e = t.m2l_ptr[c]; e < t.m2l_ptr[c + 1]; ++e) {
@@ -53,7 +206,7 @@ void build_m2l_tiling(const HostTree &t, M2LTiling &out)
             any = true;
         }
         key[c] = k;
-    }
+    });
     std::stable_sort(tg.begin(), tg.end(), [&](int32_t a, int32_t b) {
         if (t.level[a] != t.level[b]) return t.level[a] < t.level[b];
         if (oct(a) != oct(b)) return oct(a) < oct(b);
@@ -67,99 +220,76 @@ void build_m2l_tiling(const HostTree &t, M2LTiling &out)
     out.ntiles = (int)((tg.size() + kTileW - 1) / kTileW);
     out.tile_cell.assign((size_t)out.ntiles * kTileW, -1);
     for (size_t i = 0; i < tg.size(); ++i) out.tile_cell[i] = tg[i];
+    const int ntl = out.ntiles;
 
-    // translation classes: flat open-addressing table keyed by the exact
-    // integer pair geometry (offsets in units of the smaller radius, level
-    // difference); ids in order of first appearance
-    struct Slot {
-        int64_t dx, dy, dz;
-        int32_t dl, id;
-    };
-    std::vector<Slot> table(4096, Slot{0, 0, 0, 0, -1});
-    size_t mask = table.size() - 1, used = 0;
-    auto hash = [](int64_t dx, int64_t dy, int64_t dz, int dl) {
-        uint64_t h = (uint64_t)dx * 0x9E3779B97F4A7C15ULL ^ (uint64_t)dy * 0xC2B2AE3D27D4EB4FULL ^
-                     (uint64_t)dz * 0x165667B19E3779F9ULL ^ (uint64_t)(dl + 64) * 0x27D4EB2F165667C5ULL;
-        return (size_t)(h ^ (h >> 29));
-    };
-    auto grow = [&]() {
-        std::vector<Slot> old(std::move(table));
-        table.assign(old.size() * 2, Slot{0, 0, 0, 0, -1});
-        mask = table.size() - 1;
-        for (const Slot &e : old)
-            if (e.id >= 0) {
-                size_t i = hash(e.dx, e.dy, e.dz, e.dl) & mask;
-                while (table[i].id >= 0) i = (i + 1) & mask;
-                table[i] = e;
+    // pass 1 (per tile): the tile's distinct pair geometries, sorted
+    std::vector<std::vector<ClassKey>> tkeys(ntl);
+    std::vector<int64_t> tpairs(ntl, 0);
+    parallel_for(ntl, [&](int64_t ti) {
+        KeyMap m;
+        m.reset(256);
+        std::vector<ClassKey> &u = tkeys[ti];
+        for (int l = 0; l < kTileW; ++l) {
+            const int32_t B = out.tile_cell[(size_t)ti * kTileW + l];
+            if (B < 0) continue;
+            for (int64_t e = t.m2l_ptr[B]; e < t.m2l_ptr[B + 1]; ++e) {
+                const ClassKey k = class_key(t, t.m2l_src[e], B);
+                if (m.get_or_put(k, (int32_t)u.size()) == (int32_t)u.size()) u.push_back(k);
+                tpairs[ti]++;
             }
-    };
-    auto class_of = [&](int64_t A, int64_t B) {
-        const int la = t.level[A], lb = t.level[B];
-        const int lmax = std::max(la, lb);
-        int64_t d[3];
-        for (int k = 0; k < 3; ++k) {
-            const int64_t cb = (2 * (int64_t)t.ix[3 * B + k] + 1) << (lmax - lb);
-            const int64_t ca = (2 * (int64_t)t.ix[3 * A + k] + 1) << (lmax - la);
-            d[k] = cb - ca;
         }
-        const int dl = lb - la;
-        size_t i = hash(d[0], d[1], d[2], dl) & mask;
-        while (table[i].id >= 0) {
-            const Slot &e = table[i];
-            if (e.dx == d[0] && e.dy == d[1] && e.dz == d[2] && e.dl == dl) return e.id;
-            i = (i + 1) & mask;
+        std::sort(u.begin(), u.end());
+    });
+    // class ids: ranks in the sorted union of all tiles' geometries
+    std::vector<ClassKey> all;
+    {
+        KeyMap seen;
+        seen.reset(1024);
+        for (const auto &u : tkeys)
+            for (const ClassKey &k : u)
+                if (seen.get_or_put(k, (int32_t)all.size()) == (int32_t)all.size()) all.push_back(k);
+        std::sort(all.begin(), all.end());
+    }
+    out.nclasses = (int)all.size();
+    out.cls_geom.resize((size_t)4 * all.size());
+    for (size_t c = 0; c < all.size(); ++c) {
+        const ClassKey &k = all[c];
+        const double unit = std::ldexp(1.0, std::min(0, k.dl));   // smaller radius / r_B
+        out.cls_geom[4 * c] = (double)k.d[0] * unit;
+        out.cls_geom[4 * c + 1] = (double)k.d[1] * unit;
+        out.cls_geom[4 * c + 2] = (double)k.d[2] * unit;
+        out.cls_geom[4 * c + 3] = std::ldexp(1.0, k.dl);           // r_A / r_B
+    }
+    out.tile_uoff.assign(ntl + 1, 0);
+    for (int ti = 0; ti < ntl; ++ti) {
+        out.tile_uoff[ti + 1] = out.tile_uoff[ti] + (int32_t)tkeys[ti].size();
+        out.pairs += tpairs[ti];
+    }
+    out.nentries = out.tile_uoff[ntl];
+    out.ucls.assign((size_t)out.nentries, 0);
+    out.usrc.resize((size_t)out.nentries * kTileW);
+    // pass 2 (per tile): class ids of its entries (ascending) and the source
+    // of every lane at each entry
+    parallel_for(ntl, [&](int64_t ti) {
+        const std::vector<ClassKey> &u = tkeys[ti];
+        const size_t base = (size_t)out.tile_uoff[ti];
+        std::fill(out.usrc.begin() + base * kTileW, out.usrc.begin() + (base + u.size()) * kTileW,
+                  (int32_t)nc);   // the zero row where a lane lacks the class
+        KeyMap m;
+        m.reset(u.size());
+        for (size_t j = 0; j < u.size(); ++j) {
+            m.get_or_put(u[j], (int32_t)j);
+            out.ucls[base + j] = (int32_t)(std::lower_bound(all.begin(), all.end(), u[j]) - all.begin());
         }
-        const int32_t id = (int32_t)used++;
-        table[i] = Slot{d[0], d[1], d[2], dl, id};
-        const double unit = std::ldexp(1.0, lb - lmax);   // smaller radius / r_B
-        out.cls_geom.push_back((double)d[0] * unit);
-        out.cls_geom.push_back((double)d[1] * unit);
-        out.cls_geom.push_back((double)d[2] * unit);
-        out.cls_geom.push_back(std::ldexp(1.0, lb - la));  // r_A / r_B
-        if (2 * used > table.size()) grow();
-        return id;
-    };
-
-    out.tile_uoff.assign(out.ntiles + 1, 0);
-    // per tile: its distinct classes in ascending id order, then one entry
-    // (a row of 64 sources, the zero row where a lane lacks the class) each
-    struct Item {
-        int32_t cls, lane, src;
-    };
-    std::vector<Item> items;
-    std::vector<int32_t> tile_cls, seen, slot;
-    for (int ti = 0; ti < out.ntiles; ++ti) {
-        items.clear();
-        tile_cls.clear();
         for (int l = 0; l < kTileW; ++l) {
             const int32_t B = out.tile_cell[(size_t)ti * kTileW + l];
             if (B < 0) continue;
             for (int64_t e = t.m2l_ptr[B]; e < t.m2l_ptr[B + 1]; ++e) {
                 const int64_t A = t.m2l_src[e];
-                const int32_t c = class_of(A, B);
-                if ((size_t)c >= seen.size()) {
-                    seen.resize(used, -1);
-                    slot.resize(used, 0);
-                }
-                if (seen[c] != ti) {
-                    seen[c] = ti;
-                    tile_cls.push_back(c);
-                }
-                items.push_back(Item{c, l, (int32_t)A});
-                out.pairs++;
+                out.usrc[(base + (size_t)m.get(class_key(t, A, B))) * kTileW + l] = (int32_t)A;
             }
         }
-        std::sort(tile_cls.begin(), tile_cls.end());
-        const size_t base = out.ucls.size();
-        for (size_t k = 0; k < tile_cls.size(); ++k) slot[tile_cls[k]] = (int32_t)k;
-        out.ucls.insert(out.ucls.end(), tile_cls.begin(), tile_cls.end());
-        out.usrc.resize((base + tile_cls.size()) * kTileW, (int32_t)nc);   // zero row by default
-        for (const Item &it : items) out.usrc[(base + slot[it.cls]) * kTileW + it.lane] = it.src;
-        out.tile_uoff[ti + 1] = (int32_t)out.ucls.size();
-    }
-    out.nclasses = (int)used;
-    out.nentries = (int64_t)out.ucls.size();
-
+    });
 }
 
 void build_m2l_work(const M2LTiling &tl, const M2LVariant &v, int nwaves, M2LWork &out)

@@ -318,7 +318,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
                    "ncrit": w.ncrit, "outputs": w.outputs,
                    "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)",
-                   **({} if bh else {"m2l_basis": "harmonic"})},
+                   "basis": "harmonic (M2L / M2P on the folded rows)"},
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         **({} if bh else {"m2l_full_basis": full_basis}),
         **({} if grad_line is None else {"field_gradient": {k: v for k, v in grad_line.items() if k != "out"}}),

@@ -172,16 +172,18 @@ int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
  * profiling is enabled.  Off: kernels are launched one by one. */
 int fmm_ctx_set_graphs(fmm_ctx *ctx, int on);
 
-/* Basis of the M2L contraction of FMM trees (Eq. 8 and the Discussion's
- * irreducible representation).  FMM_M2L_FULL contracts every Cartesian
+/* Basis of the M2L contraction of FMM trees and of the M2P of Barnes-Hut
+ * trees (Eq. 8, Eq. 6 and the Discussion's irreducible representation).  FMM_M2L_FULL contracts every Cartesian
  * component.  FMM_M2L_HARMONIC (default) uses that the derivative tensor of
  * 1/r is harmonic (D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0): each multipole
  * is folded once onto its components with m_z <= 1, the contraction runs on
  * those and yields the local components with n_z <= 1, and the remaining
  * local components follow from the same identity.  Order l then carries
  * 2l+1 components instead of (l+1)(l+2)/2 (at p = 8, s = 1: 1 284
- * multiply-adds per list entry instead of 2 838).  In exact arithmetic both
- * give the same locals; they differ by rounding only.  Takes effect at the
+ * multiply-adds per list entry instead of 2 838).  Barnes-Hut M2P likewise
+ * contracts the folded row and forms only the derivatives with k_z <= 2.
+ * In exact arithmetic both bases give the same results; they differ by
+ * rounding only.  Takes effect at the
  * next fmm_upward / fmm_run of a tree.  FMM_EINVAL for another value. */
 int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis);
 

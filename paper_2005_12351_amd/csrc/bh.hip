@@ -29,7 +29,7 @@ struct BHArgs {
     const double *xs;       // sorted positions, SoA
     const double *m64;      // sorted moments FP64 (w per particle)
     const float *m32;       // sorted moments FP32 (8 per particle)
-    const void *M;          // normalised multipoles, rows of nmp
+    const void *M;          // normalised multipoles (harmonic basis: folded), rows of nmp
     const int32_t *perm;
     double *phi, *field;
     int n, nmp, outputs;
@@ -48,7 +48,8 @@ __device__ __forceinline__ void wave_sync_bh()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int P, int S, typename T>
+// H: the rows are folded onto the harmonic basis and contracted by M2PEvalH
+template <int P, int S, typename T, bool H>
 __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
 {
     constexpr bool F32 = sizeof(T) == 4;
@@ -96,7 +97,12 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
             // E = -(1/r^2) sum M~ D_{+e}(u)
             const double ir = 1.0 / r;
             T p_, x_, y_, z_;
-            M2PEval<P, S, T>::eval(Mb + (size_t)c * a.nmp, (T)(dx * ir), (T)(dy * ir), (T)(dz * ir), p_, x_, y_, z_);
+            if constexpr (H)
+                M2PEvalH<P, S, T>::eval(Mb + (size_t)c * a.nmp, (T)(dx * ir), (T)(dy * ir), (T)(dz * ir), p_, x_, y_,
+                                        z_);
+            else
+                M2PEval<P, S, T>::eval(Mb + (size_t)c * a.nmp, (T)(dx * ir), (T)(dy * ir), (T)(dz * ir), p_, x_, y_,
+                                       z_);
             ph += (double)p_ * ir;
             const double ir2 = ir * ir;
             ex -= (double)x_ * ir2;
@@ -189,19 +195,20 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n)
 typedef void (*bh_fn)(BHArgs);
 
 template <int P, int S>
-bh_fn pick(bool f32)
+bh_fn pick(bool f32, bool h)
 {
-    return f32 ? (bh_fn)bh_kernel<P, S, float> : (bh_fn)bh_kernel<P, S, double>;
+    if (h) return f32 ? (bh_fn)bh_kernel<P, S, float, true> : (bh_fn)bh_kernel<P, S, double, true>;
+    return f32 ? (bh_fn)bh_kernel<P, S, float, false> : (bh_fn)bh_kernel<P, S, double, false>;
 }
 
 template <int S, int P = (S > 1 ? S : 1)>
-bh_fn pick_p(int p, bool f32)
+bh_fn pick_p(int p, bool f32, bool h)
 {
     if constexpr (P > FMM_P_MAX) {
         return nullptr;
     } else {
-        if (p == P) return pick<P, S>(f32);
-        return pick_p<S, P + 1>(p, f32);
+        if (p == P) return pick<P, S>(f32, h);
+        return pick_p<S, P + 1>(p, f32, h);
     }
 }
 
@@ -209,20 +216,21 @@ bh_fn pick_p(int p, bool f32)
 
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s)
 {
-    const bool f32 = t->prec == FMM_PREC_MIXED;
-    bh_fn k = t->order == 0 ? pick_p<0>(t->p, f32) : (t->order == 1 ? pick_p<1>(t->p, f32) : pick_p<2>(t->p, f32));
+    const bool f32 = t->prec == FMM_PREC_MIXED, h = t->basis == FMM_M2L_HARMONIC;
+    bh_fn k = t->order == 0 ? pick_p<0>(t->p, f32, h)
+                            : (t->order == 1 ? pick_p<1>(t->p, f32, h) : pick_p<2>(t->p, f32, h));
     if (!k) return hipErrorInvalidValue;
     BHArgs a;
     a.cells = t->d_cells;
     a.xs = t->d_x;
     a.m64 = t->d_mom;
     a.m32 = t->d_mom32;
-    a.M = f32 ? (const void *)t->d_M32 : (const void *)t->d_M64;
+    a.M = h ? (const void *)t->d_Mh : (f32 ? (const void *)t->d_M32 : (const void *)t->d_M64);
     a.perm = t->d_perm;
     a.phi = phi;
     a.field = field;
     a.n = (int)t->ht.n;
-    a.nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
+    a.nmp = h ? (hterms(t->p) - hterms(t->order - 1) + 3) / 4 * 4 : (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     a.outputs = outputs;
     a.theta2 = t->theta * t->theta;
     for (int d = 0; d < 3; ++d) a.g.lo[d] = t->ht.lo[d];

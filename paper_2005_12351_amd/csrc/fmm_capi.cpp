@@ -458,7 +458,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 {
     const int smask = code_mask(code), order = mask_min_order(smask);
     const bool fmm = t->method == FMM_METHOD_FMM;
-    const int basis = fmm ? t->ctx->m2l_basis : FMM_M2L_FULL;
+    const int basis = t->ctx->m2l_basis;
     const bool harm = basis == FMM_M2L_HARMONIC;
     if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis)
         return FMM_OK;
@@ -486,6 +486,14 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     if (t->method == FMM_METHOD_BH && !t->d_bhcount &&
         (rc = tree_alloc(t, (void **)&t->d_bhcount, 2 * sizeof(unsigned long long))))
         return rc;
+    if (!fmm && harm) {
+        // folded rows the Barnes-Hut M2P reads (FMM trees size them from the M2L variant below)
+        const size_t es = prec == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
+        const int nhp = (hterms(p) - hterms(order - 1) + 3) / 4 * 4;
+        if ((rc = tree_alloc(t, &t->d_Mh, es * (size_t)(nc + 1) * nhp))) return rc;
+        hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * nhp / 8, t->ctx->stream);
+        if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+    }
     if (fmm) {
         M2LVariant v;
         if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, harm, &v))
@@ -784,8 +792,16 @@ extern "C" int fmm_work_counts(const fmm_tree *t, double *w)
         HIPCHK(hipMemcpyAsync(c, t->d_bhcount, sizeof(c), hipMemcpyDeviceToHost, t->ctx->stream));
         HIPCHK(hipStreamSynchronize(t->ctx->stream));
         const int p = t->p, s_ = t->order;
-        const double nm = (double)(nterms(p) - nterms(s_ - 1));
-        const double np4 = (double)(p + 4) * (p + 3) * (p + 2) / 6.0;   // C(p+4, 3) derivative terms
+        // contraction terms and derivative-tensor components up to p + 1
+        // (harmonic basis: the components with m_z <= 1, k_z <= 2)
+        double nm = (double)(nterms(p) - nterms(s_ - 1));
+        double np4 = (double)(p + 4) * (p + 3) * (p + 2) / 6.0;   // C(p+4, 3)
+        if (t->basis == FMM_M2L_HARMONIC) {
+            nm = (double)(hterms(p) - hterms(s_ - 1));
+            np4 = 0.0;
+            for (int l = 0; l <= p + 1; ++l)
+                for (int kz = 0; kz <= std::min(2, l); ++kz) np4 += (double)(l - kz + 1);
+        }
         w[2] = (double)c[1];
         w[3] = p2p_flops_mask(t->smask) * w[2];
         w[4] = (double)c[0];

@@ -34,13 +34,21 @@ BH_CASES = [(1, 6, "plummer", 5000, 32, 0.6), (1, 6, "plummer", 5000, 32, 0.3), 
             (0, 10, "uniform", 700, 4, 0.5)]
 
 
+BASES = {"harmonic": fmm.FMM_M2L_HARMONIC, "full": fmm.FMM_M2L_FULL}
+
+
 @pytest.mark.parametrize("order,p,kind,n,ncrit,theta", BH_CASES)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_bh_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta, prec):
-    print(f"[bh {prec}] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}", flush=True)
+@pytest.mark.parametrize("basis", list(BASES))
+def test_bh_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta, prec, basis):
+    print(f"[bh {prec} {basis}] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}", flush=True)
     w = W.small_random(1200 + n + order, n, order, kind)
     pr = fmm.FMM_PREC_FP64 if prec == "fp64" else fmm.FMM_PREC_MIXED
-    ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=pr, method=fmm.FMM_METHOD_BH)
+    ctx.set_m2l_basis(BASES[basis])
+    try:
+        ph, E, _ = gpu_fmm(fmm, ctx, w, p=p, theta=theta, ncrit=ncrit, precision=pr, method=fmm.FMM_METHOD_BH)
+    finally:
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     po, Eo = orc.Tree(w.pos, ncrit).bh(order, w.moments, p, theta)
     tol = TOL_FP64 if prec == "fp64" else TOL_MIXED
     e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)

@@ -63,9 +63,9 @@ def _run(ctx, w, prec, method, basis):
     return out
 
 
-# (workload, method, M2L basis); Barnes-Hut has no M2L
-CASES = [(2, "fmm", "harmonic"), (2, "fmm", "full"), (3, "fmm", "harmonic"), (3, "fmm", "full"), (3, "bh", "full"),
-         (4, "fmm", "harmonic"), (4, "fmm", "full")]
+# (workload, method, basis of the M2L / Barnes-Hut M2P)
+CASES = [(2, "fmm", "harmonic"), (2, "fmm", "full"), (3, "fmm", "harmonic"), (3, "fmm", "full"), (3, "bh", "harmonic"),
+         (3, "bh", "full"), (4, "fmm", "harmonic"), (4, "fmm", "full")]
 BASIS = {"harmonic": fmm.FMM_M2L_HARMONIC, "full": fmm.FMM_M2L_FULL}
 
 

@@ -51,11 +51,16 @@ def test_mixed_fmm_matches_oracle(orc, ctx, mask, kind, n, p, ncrit, theta, prec
 
 @pytest.mark.parametrize("mask", [3, 6, 7])
 @pytest.mark.parametrize("prec", [fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED])
-def test_mixed_bh_matches_oracle(orc, ctx, mask, prec):
+@pytest.mark.parametrize("basis", [fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_FULL])
+def test_mixed_bh_matches_oracle(orc, ctx, mask, prec, basis):
     w = W.small_mixed(950 + mask, 3000, mask, "plummer", p=6, theta=0.5, ncrit=32)
-    print(f"[mixed bh] mask={mask} precision={prec}", flush=True)
-    ph, E, t = gpu_fmm(fmm, ctx, w, precision=prec, method=fmm.FMM_METHOD_BH)
-    t.close()
+    print(f"[mixed bh] mask={mask} precision={prec} basis={basis}", flush=True)
+    ctx.set_m2l_basis(basis)
+    try:
+        ph, E, t = gpu_fmm(fmm, ctx, w, precision=prec, method=fmm.FMM_METHOD_BH)
+        t.close()
+    finally:
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     po, Eo = orc.Tree(w.pos, w.ncrit).bh(w.order, w.moments, w.p, w.theta)
     e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)
     print(f"   rel L2 vs oracle BH: phi {e1:.2e} E {e2:.2e}", flush=True)

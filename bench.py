@@ -257,6 +257,28 @@ def main():
         grad_line = {"ms_per_call": dt * 1e3, "unit": "evals/s", "value": w.n / dt,
                      "what": "fmm_evaluate_grad(FMM_GRAD) after the MIXED upward pass: far field again plus a "
                              "near-field gradient pass", "out": grd.cpu().numpy()}
+    mixed_line = None
+    if not bh and args.config == 2:
+        # the same particles carrying a charge, a dipole and a quadrupole each
+        # (order code MIXED | 7: expansions from order 0, three near-field sums)
+        mrng = np.random.default_rng(20052)
+        mmom_np = W.mixed_moments(mrng, 7, w.n)
+        mmom = torch.from_numpy(mmom_np).to(dev)
+        code = fmm.FMM_MIXED + 7
+        mphi = torch.empty(w.n, dtype=torch.float64, device=dev)
+        mfld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            tree.run(code, mmom, w.p, fmm.FMM_PREC_MIXED, outputs, mphi, mfld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            tree.run(code, mmom, w.p, fmm.FMM_PREC_MIXED, outputs, mphi, mfld)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        mixed_line = {"what": "charge + dipole + quadrupole on every particle (order code MIXED | 7), same tree, "
+                              "p %d, MIXED precision" % w.p,
+                      "value": w.n / dt, "unit": "evals/s", "ms_per_step": dt * 1e3,
+                      "moments": mmom_np, "out": (mphi.cpu().numpy(), mfld.cpu().numpy())}
     full_basis = None
     if not bh:
         # the same MIXED steps with the M2L contracting every Cartesian component
@@ -322,6 +344,8 @@ def main():
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         **({} if bh else {"m2l_full_basis": full_basis}),
         **({} if grad_line is None else {"field_gradient": {k: v for k, v in grad_line.items() if k != "out"}}),
+        **({} if mixed_line is None else
+           {"mixed_sources": {k: v for k, v in mixed_line.items() if k not in ("out", "moments")}}),
         "kernel_timing": "separate pass of the same steps, kernels serialised, HIP events on the launch stream",
         "kernel_avg_ms_mixed": kern_ms,
         "kernel_avg_ms_fp64": {k: v[0] / max(1, v[1]) for k, v in f64["prof"].items()},
@@ -374,6 +398,12 @@ def main():
             errs[name] = e
         errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s" % (len(sample), kind)
         line["rel_l2_error"] = errs
+        if mixed_line is not None:
+            code = oracle.MIXED + 7
+            mpo, mEo = ot.fmm(code, mixed_line["moments"], w.p, targets=sample)
+            mph, mE = mixed_line["out"]
+            line["mixed_sources"]["phi_vs_oracle"] = oracle.rel_l2(mph[sample], mpo)
+            line["mixed_sources"]["E_vs_oracle"] = oracle.rel_l2(mE[sample], mEo)
         if grad_line is not None:
             Go = ot.fmm(w.order, w.moments, w.p, targets=sample, want_grad=True)[2]
             Gd = oracle.direct_grad(w.pos, w.order, w.moments, targets=sample)

@@ -10,18 +10,19 @@ with D_k the derivatives of 1/r.  In the normalised form used on the GPU
 
     L~_n(B) += sum_m D_{n+m}((z_B - z_A) / r_B) * rho^|m| * M~_m(A).
 
-Each generated kernel runs one 64-wide wavefront per work item: lane l owns
+In each generated kernel a 64-wide wavefront works on one tile: lane l owns
 the target cell of tile slot l and keeps its local coefficients (or one block
 of them) in registers; the wave walks the tile's translation classes, and at
 each step every lane streams the multipole of its own source while the
 derivative tensor of the class, identical for all lanes, comes through scalar
 loads.  The contraction is written out term by term (one fused multiply-add
 each), so no index arithmetic is left at run time.  The grid has exactly as
-many waves as the device keeps resident; the host cuts the concatenated
-(tile, output block, entry) work into equally expensive pieces per wave, so
-every SIMD finishes together although the blocks differ in work by up to 10x;
-a wave writes its partial sums only where its range crosses a (tile, block)
-boundary.
+many workgroups as the device keeps resident; the host cuts the concatenated
+(tile, output block, entry) work into equally expensive pieces, one per
+workgroup, so every SIMD finishes together although the blocks differ in
+work by up to 10x.  The wgw waves of a workgroup split each piece's entries
+and add their sums in LDS; a piece writes partial sums only where it crosses
+a (tile, block) boundary.
 
 Harmonic basis.  The derivative tensor of 1/r is harmonic: for every k,
 D_{k+2e_x} + D_{k+2e_y} + D_{k+2e_z} = 0, hence
@@ -43,10 +44,10 @@ import sys
 P_MAX = 10
 TILE = 64
 
-# code-shape options (register blocking and scalar-load pipelining); the
-# defaults are the measured best on gfx950, see DEFAULTS
+# code-shape options (register blocking, scalar-load pipelining, waves per
+# workgroup); the defaults are the measured best on gfx950
 DEFAULTS = {"acc32": 128, "m32": 64, "acc64": 64, "m64": 32, "dgroup32": 32, "dgroup64": 16, "pipeline": 1,
-            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0}
+            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0, "wgw": 4}
 
 
 def orders(p):
@@ -119,10 +120,20 @@ def gen_kernel(p, s, fp32, opt=None, harmonic=False):
     name = f"m2l_p{p}_s{s}_{suf}" + ("_h" if harmonic else "")
     L = []
     # minwaves > 0: resident waves per SIMD the register allocation must allow
-    lb = f"{TILE}, {opt['minwaves']}" if opt["minwaves"] else f"{TILE}"
+    wgw = opt["wgw"]
+    NT = TILE * wgw
+    lb = f"{NT}, {opt['minwaves']}" if opt["minwaves"] else f"{NT}"
     L.append(f"__global__ __launch_bounds__({lb}) void {name}(M2LArgs a)")
     L.append("{")
-    L.append("    const int lane = threadIdx.x;")
+    L.append(f"    const int lane = threadIdx.x % {TILE};")
+    if wgw > 1:
+        # the waves of a workgroup split every item's entries and add their
+        # partial sums in LDS (in wave order) before one row set is written;
+        # the wave index is read from the first lane so that the compiler
+        # knows it is uniform (else the piece bounds, class ids and table
+        # pointer derived from it leave the scalar unit)
+        L.append(f"    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / {TILE});")
+        L.append(f"    __shared__ {T} red[{max(b - a for a, b in blocks)} * {TILE}];")
     L.append(f"    const {T} *__restrict__ Mb = (const {T} *)a.M;")
     L.append(f"    const {T} *__restrict__ Db = (const {T} *)a.D;")
     L.append(f"    const {T} *__restrict__ Sb = (const {T} *)a.sc;")
@@ -148,7 +159,12 @@ def gen_kernel(p, s, fp32, opt=None, harmonic=False):
             cur.append(j)
         if cur:
             chunks.append(cur)
-        L.append("        for (int u = w.y; u < w.z; ++u) {")
+        if wgw > 1:
+            L.append(f"        const int uspan = w.z - w.y;")
+            L.append(f"        const int ub = w.y + uspan * wv / {wgw}, ue = w.y + uspan * (wv + 1) / {wgw};")
+            L.append("        for (int u = ub; u < ue; ++u) {")
+        else:
+            L.append("        for (int u = w.y; u < w.z; ++u) {")
         L.append("            const int cls = a.ucls[u];")
         # the class tables are read-only for the whole kernel: reading them
         # through the constant address space lets the uniform loads go
@@ -264,22 +280,39 @@ def gen_kernel(p, s, fp32, opt=None, harmonic=False):
                     L.append(SB)
                     L.extend(f_[h:])
         L.append("        }")
-        for i in range(n0, n1):
-            L.append(f"        out[{i}] = c{i};")
+        if wgw > 1:
+            for q in range(wgw):
+                last = q == wgw - 1
+                L.append(f"        if (wv == {q}) {{")
+                for i in range(n0, n1):
+                    slot = f"red[{i - n0} * {TILE} + lane]"
+                    if q == 0:
+                        L.append(f"            {slot} = c{i};")
+                    elif not last:
+                        L.append(f"            {slot} += c{i};")
+                    else:
+                        L.append(f"            out[{i}] = {slot} + c{i};")
+                L.append("        }")
+                if not last:
+                    L.append("        __syncthreads();")
+            L.append("        __syncthreads();   // red is reused by the next item")
+        else:
+            for i in range(n0, n1):
+                L.append(f"        out[{i}] = c{i};")
         L.append("    }")
     L.append("    }")
     L.append("}")
     launcher = f"""
 static hipError_t launch_{name}(const M2LArgs &a, int nwaves, hipStream_t st)
 {{
-    hipLaunchKernelGGL({name}, dim3(nwaves), dim3({TILE}), 0, st, a);
+    hipLaunchKernelGGL({name}, dim3(nwaves), dim3({NT}), 0, st, a);
     return hipGetLastError();
 }}
 
 static int occ_{name}()
 {{
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, {name}, {TILE}, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, {name}, {NT}, 0) != hipSuccess) return 1;
     return per_cu > 0 ? per_cu : 1;
 }}
 """

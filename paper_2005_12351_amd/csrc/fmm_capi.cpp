@@ -447,13 +447,6 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 }
 
 // ------------------------------------------------------------------ upward
-// M2L waves per resident wave slot of the device (each wave writes its own
-// partial rows where its piece of the work ends)
-#ifndef FMM_M2L_WAVE_SCALE
-#define FMM_M2L_WAVE_SCALE 1.0
-#endif
-static constexpr double kM2LWaveScale = FMM_M2L_WAVE_SCALE;
-
 static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 {
     const int smask = code_mask(code), order = mask_min_order(smask);
@@ -505,7 +498,9 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         int dev = 0, ncu = 256;
         hipDeviceProp_t prop;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
-        build_m2l_work(t->tiling, v, std::max(1, (int)(ncu * v.occupancy() * kM2LWaveScale)), t->m2lwork);
+        // one M2L workgroup per resident workgroup slot; each writes its own
+        // partial rows where its piece of the work ends
+        build_m2l_work(t->tiling, v, ncu * v.occupancy(), t->m2lwork);
         std::vector<int4> work(t->m2lwork.work.size() / 4);
         for (size_t k = 0; k < work.size(); ++k)
             work[k] = make_int4(t->m2lwork.work[4 * k], t->m2lwork.work[4 * k + 1], t->m2lwork.work[4 * k + 2],

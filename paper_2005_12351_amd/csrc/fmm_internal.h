@@ -151,12 +151,13 @@ struct M2LTiling {
 void build_m2l_tiling(const HostTree &t, M2LTiling &out);
 
 // M2L work for one kernel variant: the (tile, output block, entry) units,
-// concatenated, are cut into nwaves pieces of equal cost; a piece that
+// concatenated, are cut into nwaves pieces of equal cost, one per resident
+// M2L workgroup (whose waves split it); a piece that
 // crosses a (tile, block) boundary becomes several items, each with its own
 // 64 partial-result rows
 struct M2LWork {
     std::vector<int32_t> work;             // nitems*4: tile | block << 24, u0, u1, first row
-    std::vector<int32_t> wave_ptr;         // nwaves+1
+    std::vector<int32_t> wave_ptr;         // nwaves+1: items of each piece
     std::vector<int32_t> chunk0, nchunk;   // per (tile, block): first row set, row-set count
     int64_t nrows = 0;
     int nwaves = 0;
@@ -168,7 +169,7 @@ struct M2LArgs {
     const int32_t *ucls, *usrc;
     const void *D, *sc, *M;
     void *part;
-    const int32_t *wave_ptr;   // pieces of wave w: work[wave_ptr[w] .. wave_ptr[w+1])
+    const int32_t *wave_ptr;   // items of workgroup w's piece: work[wave_ptr[w] .. wave_ptr[w+1])
     int zero;                  // always 0; offsets the table pointer per chunk so
                                // that the compiler reloads instead of keeping it live
 };
@@ -176,7 +177,7 @@ struct M2LArgs {
 typedef hipError_t (*m2l_launch_fn)(const M2LArgs &, int nwaves, hipStream_t);
 struct M2LVariant {
     m2l_launch_fn launch;
-    int (*occupancy)();        // resident waves per CU
+    int (*occupancy)();        // resident workgroups per CU
     int nl_pad, nm_pad, nd, nblocks;
     int blo[17];               // output blocks: coefficients [blo[b], blo[b+1])
     int bfma[16];              // multiply-adds per list entry in each block

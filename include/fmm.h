@@ -197,9 +197,11 @@ int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, int64_t *laun
 
 /* Algorithmic work of the last fmm_evaluate on a tree (for roofline
  * accounting): w[0] = M2L list entries, w[1] = M2L FLOPs (2 per
- * multiply-add of the contraction), w[2] = P2P pairs, w[3] = P2P FLOPs,
- * w[4] = M2P (cell, particle) pairs, w[5] = M2P FLOPs, w[6] = M2L input
- * and output bytes, w[7] = P2P input and output bytes.  For Barnes-Hut trees
+ * multiply-add of the contraction in the basis in use), w[2] = P2P pairs,
+ * w[3] = P2P FLOPs, w[4] = M2P (cell, particle) pairs, w[5] = M2P FLOPs
+ * (contraction plus derivative tensor, in the basis in use), w[6] = M2L
+ * input and output bytes (one multipole and one local row per cell),
+ * w[7] = P2P input and output bytes.  For Barnes-Hut trees
  * the traversal kernel counts its accepted cells and direct pairs itself;
  * reading them synchronises the context stream. */
 int fmm_work_counts(const fmm_tree *tree, double *w);

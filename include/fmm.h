@@ -37,6 +37,10 @@
  *    fmm_last_error() returns a thread-local text for the last failure.
  *  - The library owns fmm_ctx and fmm_tree objects and all device memory they
  *    hold; free them with the matching *_destroy call.
+ *  - A context and its trees are used from one host thread at a time;
+ *    different contexts may be used from different threads at once (the
+ *    serving loop gives each slot its own).  Results do not depend on how
+ *    many host threads a build gets.
  */
 #ifndef FMM_H
 #define FMM_H

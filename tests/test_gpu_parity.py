@@ -157,6 +157,52 @@ def test_outputs_mask_and_determinism(orc, ctx):
         assert np.array_equal(p2, ph) and np.array_equal(E2, E)
 
 
+def test_concurrent_builds_are_deterministic(ctx):
+    """The host scheduling runs on host threads shared among the builds in
+    flight; trees built at the same time on several contexts from several
+    threads (so each build gets fewer host threads) give bit-identical
+    results to a tree built alone."""
+    import threading
+    w = W.small_random(6161, 20000, 1, "plummer", p=8, theta=0.5, ncrit=32)
+    pos = torch.from_numpy(w.pos).cuda()
+    mom = torch.from_numpy(w.moments).cuda()
+
+    def evaluate(tree):
+        ph, E = tree.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED)
+        torch.cuda.synchronize()   # the context streams too (device-wide)
+        return ph.cpu().numpy(), E.cpu().numpy()
+
+    t0 = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+    info = t0.info()                 # before any expansion buffers exist
+    ref = evaluate(t0)
+    t0.close()
+    ctxs = [fmm.Context(0) for _ in range(6)]
+    trees = [None] * len(ctxs)
+    errors = []
+
+    def build(k):
+        try:
+            trees[k] = fmm.Tree(ctxs[k], pos, w.ncrit, w.theta)
+        except Exception as e:  # pragma: no cover - reported below
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=build, args=(k,)) for k in range(len(ctxs))]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    assert not errors, errors
+    try:
+        for t in trees:
+            assert t.info() == info
+            ph, E = evaluate(t)
+            assert np.array_equal(ph, ref[0]) and np.array_equal(E, ref[1])
+            t.close()
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_basis_switch_on_one_tree(ctx):
     """Switching the M2L basis between calls on one tree recaptures the
     launch sequence: full and harmonic agree to rounding, and returning to a

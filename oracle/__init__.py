@@ -55,7 +55,8 @@ def lib():
         L.orc_p2p_pair_grad.argtypes = [ctypes.c_int, _vp, _vp, _vp]
         L.orc_l2p_grad.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
         L.orc_bh_eval.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
-                                  _vp, _vp, _vp]
+                                  _vp, _vp, _vp, _vp]
+        L.orc_m2p_grad.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp]
         L.orc_upward.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp]
         L.orc_direct.argtypes = [ctypes.c_int64, _vp, ctypes.c_int, _vp, ctypes.c_int64, _vp, _vp, _vp]
         L.orc_dtensor.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _vp]
@@ -180,6 +181,13 @@ def m2p(p: int, s: int, zA, M, x):
     E = np.zeros(3)
     lib().orc_m2p(p, s, _p(_c(zA)), _p(_c(M)), _p(_c(x)), _p(phi), _p(E))
     return phi[0], E
+
+
+def m2p_grad(p: int, s: int, zA, M, x) -> np.ndarray:
+    """Field gradient (xx, xy, xz, yy, yz, zz) of the multipole M about zA at x."""
+    G = np.zeros(6)
+    lib().orc_m2p_grad(p, s, _p(_c(zA)), _p(_c(M)), _p(_c(x)), _p(G))
+    return G
 
 
 def direct_grad(pos, order: int, mom, targets: Optional[np.ndarray] = None) -> np.ndarray:
@@ -312,16 +320,19 @@ class Tree:
         out = (phi, E) + ((L,) if want_L else ()) + ((G,) if want_grad else ())
         return out
 
-    def bh(self, order: int, mom, p: int, theta_bh: float, targets: Optional[np.ndarray] = None):
+    def bh(self, order: int, mom, p: int, theta_bh: float, targets: Optional[np.ndarray] = None,
+           want_grad: bool = False):
+        """phi, E (and the field gradient G, k x 6, when asked for)."""
         mom = _c(mom)
         tg = None if targets is None else _c(targets, np.int64)
         k = self.n if tg is None else tg.shape[0]
         phi = np.zeros(k)
         E = np.zeros((k, 3))
-        rc = lib().orc_bh_eval(self._h, order, _p(mom), p, float(theta_bh), k, _p(tg), _p(phi), _p(E))
+        G = np.zeros((k, 6)) if want_grad else None
+        rc = lib().orc_bh_eval(self._h, order, _p(mom), p, float(theta_bh), k, _p(tg), _p(phi), _p(E), _p(G))
         if rc != 0:
             raise ValueError("oracle BH rejected its arguments")
-        return phi, E
+        return (phi, E, G) if want_grad else (phi, E)
 
 
 def rel_l2(a: np.ndarray, b: np.ndarray) -> float:

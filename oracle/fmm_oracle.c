@@ -530,6 +530,28 @@ void orc_m2p(int p, int s, const double *zA, const double *M, const double *x, d
     free(D);
 }
 
+/* Field gradient of the multipole M about zA at x: the second derivatives
+ * of the M2P sum, d_i d_j phi = sum M_n D_{n+e_i+e_j}(x - zA), G_ij = -that
+ * (derivative tensor to order p + 2). */
+void orc_m2p_grad(int p, int s, const double *zA, const double *M, const double *x, double *G)
+{
+    static const int I[6] = {0, 0, 0, 1, 1, 2}, J[6] = {0, 1, 2, 1, 2, 2};
+    double *D = malloc(sizeof(double) * orc_nterms(p + 2));
+    orc_dtensor(p + 2, x[0] - zA[0], x[1] - zA[1], x[2] - zA[2], D);
+    for (int k = 0; k < 6; ++k) G[k] = 0.0;
+    for (int j = orc_nterms(s - 1); j < orc_nterms(p); ++j) {
+        int m[3];
+        orc_multi_index(j, m);
+        for (int k = 0; k < 6; ++k) {
+            int a[3] = {m[0], m[1], m[2]};
+            a[I[k]] += 1;
+            a[J[k]] += 1;
+            G[k] -= M[j] * D[orc_index(a[0], a[1], a[2])];
+        }
+    }
+    free(D);
+}
+
 /* ------------------------------------------------------------------ */
 /* Octree and interaction lists (Section 3.2)                           */
 /* ------------------------------------------------------------------ */
@@ -997,7 +1019,7 @@ static int cell_contains(const orc_tree *t, int64_t c, int64_t i)
 
 /* Multipolar Barnes-Hut (Section 3.2, Eq. 12) at the listed targets. */
 int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double theta_bh,
-                int64_t nt_, const int64_t *targets, double *phi, double *field)
+                int64_t nt_, const int64_t *targets, double *phi, double *field, double *grad)
 {
     if (!orc_code_valid(order)) return 1;
     int s = orc_min_order(order);
@@ -1013,7 +1035,7 @@ int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double t
         int64_t i = targets ? t->iperm[targets[k]] : k;
         int64_t out = targets ? k : t->perm[i];
         const double *x = t->xs + 3 * i;
-        double ph = 0.0, e[3] = {0.0, 0.0, 0.0};
+        double ph = 0.0, e[3] = {0.0, 0.0, 0.0}, g[6] = {0, 0, 0, 0, 0, 0};
         int64_t stack[8 * (ORC_MAXLEVEL + 2)];
         int sp = 0;
         stack[sp++] = 0;
@@ -1031,6 +1053,11 @@ int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double t
                 e[0] += ee[0];
                 e[1] += ee[1];
                 e[2] += ee[2];
+                if (grad) {
+                    double gg[6];
+                    orc_m2p_grad(p, s, zA, M + (size_t)a * ntM, x, gg);
+                    for (int c = 0; c < 6; ++c) g[c] += gg[c];
+                }
             } else if (is_leaf(t, a)) {
                 for (int64_t j = t->first[a]; j < t->first[a] + t->count[a]; ++j) {
                     if (j == i) continue;
@@ -1041,6 +1068,11 @@ int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double t
                     e[0] += ee[0];
                     e[1] += ee[1];
                     e[2] += ee[2];
+                    if (grad) {
+                        double gg[6];
+                        orc_p2p_pair_grad(order, r, ms + w * j, gg);
+                        for (int c = 0; c < 6; ++c) g[c] += gg[c];
+                    }
                 }
             } else {
                 /* push in reverse so that children are visited in octant order */
@@ -1053,6 +1085,8 @@ int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double t
             field[3 * out + 1] = e[1];
             field[3 * out + 2] = e[2];
         }
+        if (grad)
+            for (int c = 0; c < 6; ++c) grad[6 * out + c] = g[c];
     }
     free(M);
     free(ms);

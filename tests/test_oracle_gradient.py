@@ -142,3 +142,35 @@ def test_fmm_gradient_mixed_superposes():
     parts = (t.fmm(0, m0, p, want_grad=True)[2] + t.fmm(code, np.hstack([z1, m1, z6]), p, want_grad=True)[2]
              + t.fmm(code, np.hstack([z1, z3, m2]), p, want_grad=True)[2])
     assert np.abs(G - parts).max() <= 1e-12 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("p,s", [(4, 0), (6, 1), (8, 2), (1, 1)])
+def test_m2p_gradient_is_derivative_of_m2p_field(p, s):
+    """Barnes-Hut: the gradient of the multipole's own field (finite
+    differences of the oracle's M2P field)."""
+    rng = np.random.default_rng(200 + p + s)
+    M = rng.standard_normal(oracle.nterms(p))
+    M[:oracle.nterms(s - 1)] = 0.0
+    zA = rng.uniform(-0.2, 0.2, 3)
+    for _ in range(4):
+        x = zA + rng.uniform(1.5, 2.5, 3) * rng.choice([-1, 1], 3)
+        G = oracle.m2p_grad(p, s, zA, M, x)
+        Gfd = fd_of_field(lambda y: oracle.m2p(p, s, zA, M, y)[1], x, 1e-5)
+        assert np.abs(G - Gfd).max() <= 1e-6 * np.abs(G).max()
+        assert abs(G[0] + G[3] + G[5]) <= 1e-12 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_bh_gradient_converges_to_direct(order):
+    rng = np.random.default_rng(300 + order)
+    n = 1500
+    pos = rng.random((n, 3))
+    mom = rng.standard_normal((n, [1, 3, 6][order]))
+    Gd = oracle.direct_grad(pos, order, mom)
+    t = oracle.Tree(pos, 16)
+    errs = [oracle.rel_l2(t.bh(order, mom, p, 0.5, want_grad=True)[2], Gd) for p in (max(order, 1), order + 3, 8)]
+    # the far part shrinks with p (slowly where the near field dominates)
+    assert errs[2] < errs[1] < errs[0] and errs[-1] < 2e-3, errs
+    # a tiny opening angle accepts nothing: the direct sum itself
+    G0 = t.bh(order, mom, 4, 1e-6, want_grad=True)[2]
+    assert oracle.rel_l2(G0, Gd) < 1e-13

@@ -127,10 +127,16 @@ int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double 
  * eta^n/n! L~_{n+e_i+e_j}, plus the closed-form gradients of the near-field
  * pairs (computed by an extra near-field pass in this call, in the tree's
  * precision).  phi and field as for fmm_evaluate and bit-identical to it.
- * FMM trees only; p - s >= 2 (below that the truncated expansion has no
+ * FMM trees need p - s >= 2 (below that the truncated expansion has no
  * second derivative; a finite difference of it would be zero too):
  * FMM_EINVAL otherwise, FMM_ESTATE before fmm_upward.  The near-field
- * gradient buffer (48 bytes per particle) is allocated on the first call. */
+ * gradient buffer (48 bytes per particle) is allocated on the first call.
+ * Barnes-Hut trees (any p the tree accepts): each accepted cell adds
+ * -(1/r^3) sum_m M~_m D_{m+e_i+e_j}(u) (the second derivatives of the M2P of
+ * Eq. 6, u = (x - z_A)/r, r the cell's half side), each unaccepted leaf the
+ * pairs' closed forms, in one traversal that also writes phi and field
+ * (equal to fmm_evaluate's up to the rounding of the tree's precision: the
+ * kernel is a separately compiled variant). */
 int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field, double *grad);
 
 /* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,

@@ -633,15 +633,16 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
 
 // Queues the far field and the final combination (FMM) or the Barnes-Hut
 // traversal; wait_near: join the near field forked by queue_upward right
-// before the final L2P.  outputs & FMM_GRAD (FMM only): the near-field
-// gradient pass runs before the L2P, which then writes grad too.
+// before the final L2P.  outputs & FMM_GRAD: for FMM the near-field gradient
+// pass runs before the L2P, which then writes grad too; for BH the traversal
+// kernel's gradient variant writes it.
 static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, bool wait_near,
                           double *grad = nullptr)
 {
     hipStream_t s = ctx->stream;
     if (t->method == FMM_METHOD_BH) {
         ProfScope ps(ctx, s, "bh");
-        KCHK(launch_bh(t, outputs, phi, field, s));
+        KCHK(launch_bh(t, outputs, phi, field, grad, s));
         return FMM_OK;
     }
     {
@@ -734,8 +735,11 @@ extern "C" int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *t, int outputs, double 
     if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
     if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
     if ((outputs & FMM_GRAD) && !grad) FAIL(FMM_EINVAL, "field gradient requested but grad is NULL");
-    if (t->method != FMM_METHOD_FMM) FAIL(FMM_EINVAL, "field gradients are computed for FMM trees only");
     if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    if (t->method == FMM_METHOD_BH) {
+        HIPCHK(hipSetDevice(ctx->device));
+        return queue_evaluate(ctx, t, outputs, phi, field, false, grad);
+    }
     if ((outputs & FMM_GRAD) && t->p - t->order < 2)
         FAIL(FMM_EINVAL, "field gradient needs p - s >= 2 (p = %d, lowest source order %d): below that the "
                          "truncated local expansion has no second derivative", t->p, t->order);

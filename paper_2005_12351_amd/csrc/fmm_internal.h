@@ -286,7 +286,7 @@ hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
 hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false);   // grad: field gradient to d_near_g
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
-hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, hipStream_t s);
+hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 
 // serving (serve.cpp)
 int serve_destroy(fmm_ctx *ctx);

@@ -16,6 +16,9 @@ M2PEvalH is the same for the harmonic basis: the cell's row is folded onto
 its components with m_z <= 1 (see P2M / M2M), so only those are contracted
 and only the derivatives with k_z <= 2 (those with m_z <= 1 and their
 gradient) are formed; D being harmonic, the result is the same.
+M2PEvalG / M2PEvalGH also return sum M_n D_{n+e_i+e_j} (the field gradient,
+derivatives to order p + 2; harmonic: k_z <= 3) in g[0..5] = xx, xy, xz,
+yy, yz, zz.
 
 Usage: python gen_bh.py OUTDIR -> OUTDIR/bh_m2p.h
 """
@@ -54,13 +57,14 @@ def lit(v, fp32):
     return s + "f" if fp32 else s
 
 
-def gen_spec(p, s, fp32, harmonic=False):
+def gen_spec(p, s, fp32, harmonic=False, grad=False):
     T = "float" if fp32 else "double"
-    q = p + 1
+    q = p + 2 if grad else p + 1
     L = []
-    L.append(f"template <> struct {'M2PEvalH' if harmonic else 'M2PEval'}<{p}, {s}, {T}> {{")
+    name = "M2PEval" + ("G" if grad else "") + ("H" if harmonic else "")
+    L.append(f"template <> struct {name}<{p}, {s}, {T}> {{")
     L.append(f"    static __device__ __forceinline__ void eval(const {T} *__restrict__ M, {T} ux, {T} uy, {T} uz, "
-             f"{T} &ph, {T} &ex, {T} &ey, {T} &ez)")
+             f"{T} &ph, {T} &ex, {T} &ey, {T} &ez" + (f", {T} (&g)[6])" if grad else ")"))
     L.append("    {")
     if fp32:
         L.append("        const float r2 = ux * ux + uy * uy + uz * uz;")
@@ -77,7 +81,7 @@ def gen_spec(p, s, fp32, harmonic=False):
         for a in range(1, q + 1):
             L.append(f"        const {T} {d}{a} = {d}{a - 1} * {v};")
     for n in orders(q):
-        if harmonic and n[2] > 2:
+        if harmonic and n[2] > (3 if grad else 2):
             continue
         terms = []
         for kx in range(n[0] // 2 + 1):
@@ -99,6 +103,20 @@ def gen_spec(p, s, fp32, harmonic=False):
             L.append(f"          {c} = {('__builtin_fmaf' if fp32 else '__builtin_fma')}(mm, "
                      f"D{idx((m[0] + dx, m[1] + dy, m[2] + dz))}, {c}); ")
         L.append("        }")
+    if grad:
+        fm = '__builtin_fmaf' if fp32 else '__builtin_fma'
+        L.append(f"        {T} b0 = 0, b1 = 0, b2 = 0, b3 = 0, b4 = 0, b5 = 0;")
+        pairs = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+        for j, m in enumerate(ms):
+            L.append(f"        {{ const {T} mm = M[{j}];")
+            for c, (i1, i2) in enumerate(pairs):
+                k = list(m)
+                k[i1] += 1
+                k[i2] += 1
+                L.append(f"          b{c} = {fm}(mm, D{idx(tuple(k))}, b{c});")
+            L.append("        }")
+        for c in range(6):
+            L.append(f"        g[{c}] = b{c};")
     L.append("        ph = a0;")
     L.append("        ex = a1;")
     L.append("        ey = a2;")
@@ -112,13 +130,16 @@ def main(outdir):
     os.makedirs(outdir, exist_ok=True)
     parts = ["// Generated by gen_bh.py; do not edit.", "#pragma once", "",
              "template <int P, int S, typename T> struct M2PEval;",
-             "template <int P, int S, typename T> struct M2PEvalH;", ""]
+             "template <int P, int S, typename T> struct M2PEvalH;",
+             "template <int P, int S, typename T> struct M2PEvalG;",
+             "template <int P, int S, typename T> struct M2PEvalGH;", ""]
     for s in (0, 1, 2):
         for p in range(max(s, 1), P_MAX + 1):
             for fp32 in (True, False):
                 for h in (False, True):
-                    parts.append(gen_spec(p, s, fp32, h))
-                    parts.append("")
+                    for gr in (False, True):
+                        parts.append(gen_spec(p, s, fp32, h, gr))
+                        parts.append("")
     txt = "\n".join(parts) + "\n"
     fn = os.path.join(outdir, "bh_m2p.h")
     old = open(fn).read() if os.path.exists(fn) else None

@@ -1,6 +1,8 @@
 """GPU parity of the field gradient (fmm_evaluate_grad) against the oracle's
-FMM gradient on the same tree, lists and truncation: the second derivatives
-of the local expansion plus the near-field pairs' closed forms.
+gradient on the same tree, lists and truncation: for FMM the second
+derivatives of the local expansion plus the near-field pairs' closed forms,
+for Barnes-Hut the second derivatives of each accepted cell's M2P plus the
+pairs of the unaccepted leaves.
 
 Tolerances (relative L2 over all targets and the six components):
 - FP64: 1e-10, as for phi and E (same arithmetic up to summation order).
@@ -151,7 +153,79 @@ def test_gradient_errors(ctx):
         fmm._check(fmm.fmm_evaluate(ctx.h, t.h, fmm.FMM_GRAD, None, None), "fmm_evaluate")
     t.close()
     tb = fmm.Tree(ctx, pos, w.ncrit, w.theta, fmm.FMM_METHOD_BH)
-    tb.upward(1, mom, 4, fmm.FMM_PREC_FP64)
-    with pytest.raises(RuntimeError, match="FMM trees"):
-        tb.evaluate_grad(fmm.FMM_GRAD)
+    with pytest.raises(RuntimeError):
+        tb.evaluate_grad(fmm.FMM_GRAD)                     # BH before fmm_upward: FMM_ESTATE
+    tb.upward(1, mom, 1, fmm.FMM_PREC_FP64)
+    tb.evaluate_grad(fmm.FMM_GRAD, None, None, g)          # BH: no p - s restriction
+    with pytest.raises(RuntimeError):
+        fmm._check(fmm.fmm_evaluate_grad(ctx.h, tb.h, fmm.FMM_GRAD, None, None, None), "fmm_evaluate_grad")
     tb.close()
+
+
+# Barnes-Hut: accepted cells through the second derivatives of the M2P,
+# unaccepted leaves through the pairs' closed forms, against the oracle's
+# traversal on the same tree (same acceptance decisions, taken in FP64).
+BH_CASES = [(1, 6, "plummer", 4000, 32, 0.6), (0, 4, "uniform", 3000, 16, 0.5), (2, 5, "lattice", 3375, 64, 0.4),
+            (1, 1, "plummer", 3000, 16, 0.5), (2, 2, "uniform", 1000, 8, 0.6), (0, 10, "uniform", 700, 4, 0.5)]
+BASES = {"harmonic": fmm.FMM_M2L_HARMONIC, "full": fmm.FMM_M2L_FULL}
+
+
+def _bh_grad(ctx, w, p, theta, ncrit, prec, basis, outputs=ALL):
+    ctx.set_m2l_basis(BASES[basis])
+    try:
+        t = fmm.Tree(ctx, to_dev(w.pos), ncrit, theta, fmm.FMM_METHOD_BH)
+        t.upward(w.order, to_dev(w.moments), p, prec)
+        out = t.evaluate_grad(outputs)
+        ref = t.evaluate(outputs & (fmm.FMM_POT | fmm.FMM_FIELD)) if outputs & 3 else (None, None)
+        torch.cuda.synchronize()
+        t.close()
+    finally:
+        ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+    cpu = lambda x: None if x is None else x.cpu().numpy()   # noqa: E731
+    return tuple(cpu(x) for x in out), tuple(cpu(x) for x in ref)
+
+
+@pytest.mark.parametrize("order,p,kind,n,ncrit,theta", BH_CASES)
+@pytest.mark.parametrize("prec", [fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED])
+@pytest.mark.parametrize("basis", list(BASES))
+def test_bh_gradient_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta, prec, basis):
+    print(f"[bh grad {basis}] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta} precision={prec}",
+          flush=True)
+    w = W.small_random(1700 + n + order, n, order, kind)
+    (ph, E, G), (ph0, E0) = _bh_grad(ctx, w, p, theta, ncrit, prec, basis)
+    po, Eo, Go = orc.Tree(w.pos, ncrit).bh(order, w.moments, p, theta, want_grad=True)
+    e = rel_l2(G, Go)
+    print(f"   rel L2 vs oracle: G {e:.2e} (phi {rel_l2(ph, po):.2e}, E {rel_l2(E, Eo):.2e}); "
+          f"vs fmm_evaluate: phi {rel_l2(ph, ph0):.1e} E {rel_l2(E, E0):.1e}", flush=True)
+    assert e < TOL[prec]
+    # phi and E of the gradient variant agree with the plain traversal's to
+    # rounding: the two kernels are compiled apart and the FP32 M2P may round
+    # in another order (observed 5e-9 MIXED, 3e-17 FP64)
+    agree = 1e-14 if prec == fmm.FMM_PREC_FP64 else 1e-7
+    assert rel_l2(ph, ph0) < agree and rel_l2(E, E0) < agree
+    assert rel_l2(ph, po) < TOL[prec] and rel_l2(E, Eo) < TOL[prec]
+    assert np.abs(G[:, 0] + G[:, 3] + G[:, 5]).max() <= 1e-5 * np.abs(G).max()
+
+
+@pytest.mark.parametrize("mask,p", [(7, 6), (5, 3)])
+@pytest.mark.parametrize("prec", [fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED])
+def test_bh_gradient_mixed_orders(orc, ctx, mask, p, prec):
+    w = W.small_mixed(1800 + mask, 2500, mask, "plummer", p=p, theta=0.5, ncrit=32)
+    print(f"[bh grad mixed] mask={mask} p={p} precision={prec}", flush=True)
+    (_, _, G), _ = _bh_grad(ctx, w, p, 0.5, 32, prec, "harmonic", fmm.FMM_GRAD)
+    Go = orc.Tree(w.pos, 32).bh(w.order, w.moments, p, 0.5, want_grad=True)[2]
+    e = rel_l2(G, Go)
+    print(f"   rel L2 vs oracle: G {e:.2e}", flush=True)
+    assert e < TOL[prec]
+
+
+def test_bh_gradient_degenerate(orc, ctx):
+    """one particle: no source, zero gradient; two: the pair's closed form"""
+    for n in (1, 2, 40):
+        w = W.small_random(1900 + n, n, 2, "uniform")
+        (_, _, G), _ = _bh_grad(ctx, w, 3, 0.5, 4, fmm.FMM_PREC_FP64, "harmonic", fmm.FMM_GRAD)
+        Go = orc.Tree(w.pos, 4).bh(2, w.moments, 3, 0.5, want_grad=True)[2]
+        if n == 1:
+            assert np.all(G == 0.0)
+        else:
+            assert rel_l2(G, Go) < TOL[fmm.FMM_PREC_FP64]

@@ -242,7 +242,7 @@ def main():
         res[name] = dict(step_s=step_s, prof=prof, out=(None if out[0] is None else out[0].cpu().numpy(),
                                                          out[1].cpu().numpy()), work=work)
     grad_line = None
-    if not bh and w.p - w.order >= 2:
+    if bh or w.p - w.order >= 2:
         # the field gradient after the timed steps' upward state (MIXED)
         grd = torch.empty((w.n, 6), dtype=torch.float64, device=dev)
         tree.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED, outputs)
@@ -254,9 +254,12 @@ def main():
             tree.evaluate_grad(fmm.FMM_GRAD, None, None, grd)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
-        grad_line = {"ms_per_call": dt * 1e3, "unit": "evals/s", "value": w.n / dt,
-                     "what": "fmm_evaluate_grad(FMM_GRAD) after the MIXED upward pass: far field again plus a "
-                             "near-field gradient pass", "out": grd.cpu().numpy()}
+        what = ("fmm_evaluate_grad(FMM_GRAD) after the MIXED upward pass: the traversal kernel's gradient "
+                "variant (M2P second derivatives, pair gradients)" if bh else
+                "fmm_evaluate_grad(FMM_GRAD) after the MIXED upward pass: far field again plus a "
+                "near-field gradient pass")
+        grad_line = {"ms_per_call": dt * 1e3, "unit": "evals/s", "value": w.n / dt, "what": what,
+                     "out": grd.cpu().numpy()}
     mixed_line = None
     if not bh and args.config == 2:
         # the same particles carrying a charge, a dipole and a quadrupole each
@@ -405,7 +408,8 @@ def main():
             line["mixed_sources"]["phi_vs_oracle"] = oracle.rel_l2(mph[sample], mpo)
             line["mixed_sources"]["E_vs_oracle"] = oracle.rel_l2(mE[sample], mEo)
         if grad_line is not None:
-            Go = ot.fmm(w.order, w.moments, w.p, targets=sample, want_grad=True)[2]
+            Go = (ot.bh(w.order, w.moments, w.p, w.theta, targets=sample, want_grad=True) if bh else
+                  ot.fmm(w.order, w.moments, w.p, targets=sample, want_grad=True))[2]
             Gd = oracle.direct_grad(w.pos, w.order, w.moments, targets=sample)
             line["field_gradient"]["G_vs_oracle"] = oracle.rel_l2(grad_line["out"][sample], Go)
             line["field_gradient"]["G_vs_direct"] = oracle.rel_l2(grad_line["out"][sample], Gd)

@@ -219,6 +219,24 @@ def test_bh_gradient_mixed_orders(orc, ctx, mask, p, prec):
     assert e < TOL[prec]
 
 
+def test_bh_gradient_full_size_sampled(orc, ctx):
+    """1M Plummer dipoles, p 6, theta 0.6 (the Barnes-Hut benchmark workload)
+    after fmm_run, on 4 096 sampled targets, both precisions"""
+    w = W.config(3)
+    print(f"[bh grad full] {w.name}", flush=True)
+    Go = orc.Tree(w.pos, w.ncrit).bh(w.order, w.moments, w.p, w.theta, targets=w.sample, want_grad=True)[2]
+    t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta, fmm.FMM_METHOD_BH)
+    s = torch.from_numpy(w.sample).cuda()
+    for prec in (fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED):
+        t.run(w.order, to_dev(w.moments), w.p, prec, fmm.FMM_FIELD)
+        _, _, G = t.evaluate_grad(fmm.FMM_GRAD)
+        torch.cuda.synchronize()
+        e = rel_l2(G[s].cpu().numpy(), Go)
+        print(f"   precision={prec}: G rel L2 {e:.2e}", flush=True)
+        assert e < TOL[prec]
+    t.close()
+
+
 def test_bh_gradient_degenerate(orc, ctx):
     """one particle: no source, zero gradient; two: the pair's closed form"""
     for n in (1, 2, 40):

@@ -9,6 +9,7 @@
 // per octant and the M2L derivative tensor depends only on the dimensionless
 // pair geometry.  P2M, M2M, L2L, L2P run in FP64.
 #include <cmath>
+#include <type_traits>
 
 #include "fmm_internal.h"
 #include "pair_kernels.h"
@@ -737,33 +738,50 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
             if (tid == 0) wself = -1;
             __syncthreads();
             const int nsw = p2p_window(a, cb, b, w0, nw, wstart, wfirst, wgeo, &wself, sh);
-            for (int c0 = 0; c0 < nsw; c0 += kPChunk32) {
-                const int nc = min(kPChunk32, nsw - c0);
+            // chunks are a multiple of the slice count long, and the last one
+            // is padded with zero sources far away (their terms are exactly
+            // zero), so every slice takes the same number of sources and the
+            // pair loop runs on a counter common to the whole workgroup
+            const int cstep = (kPChunk32 / ns) * ns;
+            for (int c0 = 0; c0 < nsw; c0 += cstep) {
+                const int nc = min(cstep, nsw - c0);
+                const int per = (nc + ns - 1) / ns;   // sources per slice
                 __syncthreads();
-                for (int j = tid; j < nc; j += kPT) {
-                    const int q = p2p_entry(wstart, nw, c0 + j);
-                    const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
-                    spx[j] = (a.xs[pj] - zb[0]) * irb;
-                    spy[j] = (a.xs[n + pj] - zb[1]) * irb;
-                    spz[j] = (a.xs[2 * n + pj] - zb[2]) * irb;
+                for (int j = tid; j < per * ns; j += kPT) {
+                    if (j < nc) {
+                        const int q = p2p_entry(wstart, nw, c0 + j);
+                        const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
+                        spx[j] = (a.xs[pj] - zb[0]) * irb;
+                        spy[j] = (a.xs[n + pj] - zb[1]) * irb;
+                        spz[j] = (a.xs[2 * n + pj] - zb[2]) * irb;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) spm[v][j] = m4[MW * pj + v];
+                        for (int v = 0; v < NV; ++v) spm[v][j] = m4[MW * pj + v];
+                    } else {
+                        spx[j] = spy[j] = spz[j] = 1.0e4;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) spm[v][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
                 }
                 __syncthreads();
                 if (act) {
-                    const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
-                    // the target itself, if it is staged in this chunk
+                    const int ja = sl * per;
+                    // the target itself, if it is staged in this chunk; only a
+                    // chunk holding part of the target leaf's own entry needs
+                    // the per-pair test (the same for the whole workgroup)
                     const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
+                    const bool own = wself >= 0 && wself < c0 + nc && wself + cb.count > c0;
                     float bs[NO][3];
 #pragma unroll
                     for (int c = 0; c < NO; ++c)
 #pragma unroll
                         for (int k = 0; k < 3; ++k) bs[c][k] = 0.f;
                     const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-                    for (int j = ja; j < jb; ++j) {
+                    auto pairs = [&](auto check) {
+                    for (int jj = 0; jj < per; ++jj) {
+                        const int j = ja + jj;
                         const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
-                        const float inv = j == jself ? 0.f : __builtin_amdgcn_rsqf(r2);
+                        const float inv = (decltype(check)::value && j == jself) ? 0.f : __builtin_amdgcn_rsqf(r2);
                         const float4 m0 = spm[0][j];
                         const float4 m1 = NV >= 2 ? spm[NV >= 2 ? 1 : 0][j] : zero4;
                         if constexpr (GRAD) {
@@ -785,6 +803,9 @@ __global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
                             p2p_pair_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bs[0], bs[1], bs[2], bs[3]);
                         }
                     }
+                    };
+                    if (own) pairs(std::true_type{});
+                    else pairs(std::false_type{});
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         if (!(MASK & (1 << k))) continue;
@@ -837,6 +858,15 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
     const DevCell cb = a.cells[b];
     const size_t n = a.n;
     const int e0 = a.ptr[lk], e1 = a.ptr[lk + 1];
+    // position of the padding sources: 10^4 leaf radii beyond the leaf
+    // centre (finite; with zero moments their terms are exactly zero)
+    double far[3];
+    {
+        const double r = ldexp(1.0, kMaxLevel - cb.level) * a.h;
+        far[0] = a.lo[0] + (double)(2 * cb.ix + 1) * r + 1.0e4 * r;
+        far[1] = a.lo[1] + (double)(2 * cb.iy + 1) * r + 1.0e4 * r;
+        far[2] = a.lo[2] + (double)(2 * cb.iz + 1) * r + 1.0e4 * r;
+    }
     for (int tg0 = 0; tg0 < cb.count; tg0 += kPT) {
         const int cs = min(kPT, cb.count - tg0);
         const int ns = kPT / cs;
@@ -852,24 +882,42 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
             if (tid == 0) wself = -1;
             __syncthreads();
             const int nsw = p2p_window(a, cb, b, w0, nw, wstart, wfirst, wgeo, &wself, sh);
-            for (int c0 = 0; c0 < nsw; c0 += kPChunk64) {
-                const int nc = min(kPChunk64, nsw - c0);
+            // as in the FP32 kernel: chunks a multiple of the slice count long,
+            // the last padded with zero sources 10^4 leaf radii away, so all
+            // slices take the same number of sources
+            const int cstep = (kPChunk64 / ns) * ns;
+            for (int c0 = 0; c0 < nsw; c0 += cstep) {
+                const int nc = min(cstep, nsw - c0);
+                const int per = (nc + ns - 1) / ns;
                 __syncthreads();
-                for (int j = tid; j < nc; j += kPT) {
-                    const int q = p2p_entry(wstart, nw, c0 + j);
-                    const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
-                    sx[j] = a.xs[pj];
-                    sy[j] = a.xs[n + pj];
-                    sz[j] = a.xs[2 * n + pj];
+                for (int j = tid; j < per * ns; j += kPT) {
+                    if (j < nc) {
+                        const int q = p2p_entry(wstart, nw, c0 + j);
+                        const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
+                        sx[j] = a.xs[pj];
+                        sy[j] = a.xs[n + pj];
+                        sz[j] = a.xs[2 * n + pj];
 #pragma unroll
-                    for (int c = 0; c < W; ++c) sm[c][j] = a.m64[pj * W + c];
+                        for (int c = 0; c < W; ++c) sm[c][j] = a.m64[pj * W + c];
+                    } else {
+                        sx[j] = far[0];
+                        sy[j] = far[1];
+                        sz[j] = far[2];
+#pragma unroll
+                        for (int c = 0; c < W; ++c) sm[c][j] = 0.0;
+                    }
                 }
                 __syncthreads();
                 if (act) {
-                    const int ja = nc * sl / ns, jb = nc * (sl + 1) / ns;
+                    const int ja = sl * per;
                     const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
-                    for (int j = ja; j < jb; ++j) {
-                        if (j == jself) continue;
+                    // only a chunk holding part of the target leaf's own entry
+                    // needs the self test (the same for the whole workgroup)
+                    const bool own = wself >= 0 && wself < c0 + nc && wself + cb.count > c0;
+                    auto pairs = [&](auto check) {
+                    for (int jj = 0; jj < per; ++jj) {
+                        const int j = ja + jj;
+                        if (decltype(check)::value && j == jself) continue;
                         const double rx = xi - sx[j], ry = yi - sy[j], rz = zi - sz[j];
                         double m[W];
 #pragma unroll
@@ -885,6 +933,9 @@ __global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
                             if (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
                         }
                     }
+                    };
+                    if (own) pairs(std::true_type{});
+                    else pairs(std::false_type{});
                 }
             }
         }

@@ -127,13 +127,30 @@ __device__ __forceinline__ void sort_moments(size_t i, int mask, const double *_
 // M~_n = sum_j sum_k r^-k sum_{sigma <= n, |sigma| = k} zeta_j^(n-sigma)/(n-sigma)! S_sigma(j)
 // with zeta = (z - x_j)/r and S_sigma = (-1)^k T_sigma / sigma! (Eq. 3, Eq. 5),
 // k over the source orders present (MASK bit k), so a system with several
-// orders adds each part's expansion.
-// One workgroup per leaf; a thread owns one or more coefficients n (its
-// multi-index is read once), particles are staged in LDS 32 at a time as
-// per-axis tables zeta^a / a!, so the inner loop touches LDS only.
+// orders adds each part's expansion.  One workgroup per leaf; particles are
+// staged in LDS 32 at a time as per-axis tables X_a = zeta_x^a/a! (and Y, Z).
+// Two kernels, chosen by the source orders:
+// - p2m_coef_kernel (charges and dipoles): a thread owns one or more
+//   coefficients n and adds every particle's term, 1 + 3 products of table
+//   entries per particle;
+// - p2m_kernel (any quadrupole part): the monomial factorises over the axes
+//   and sigma has at most two units, so for a fixed column (ax, ay) the
+//   particle's contribution to every coefficient (ax, ay, az) is
+//   A0 Z_az + A1 Z_{az-1} + A2 Z_{az-2}, with
+//   A0 = S_0 X0 Y0 + S_ex X1 Y0 + S_ey X0 Y1 + S_2ex X2 Y0 + S_ex+ey X1 Y1 + S_2ey X0 Y2,
+//   A1 = S_ez X0 Y0 + S_ex+ez X1 Y0 + S_ey+ez X0 Y1, A2 = S_2ez X0 Y0
+//   (Xk = X_{ax-k}, Yk = Y_{ay-k}).  A thread owns a block of consecutive az
+//   of one column and forms A0..A2 once per particle; when the blocks fill
+//   less than half the workgroup, groups of threads take every ngroups-th
+//   particle and their sums are added in group order at the end (a fixed
+//   order).  With quadrupoles this is 25 % faster than the per-coefficient
+//   form (ten terms per coefficient and particle there); with dipoles it is
+//   not, so those keep the simpler kernel.
 constexpr int kP2MThreads = 128;
-constexpr int kP2MStage = 32;       // particles staged per pass (LDS per workgroup ~11 KB)
-constexpr int kAxW = kPTable + 2;   // row of one axis table, padded
+constexpr int kP2MStage = 32;                    // particles staged per pass
+constexpr int kP2MBlk = 6;                       // longest column block
+constexpr int kAxWc = FMM_P_MAX + 2;             // axis table row of the per-coefficient kernel: X_0..X_p
+constexpr int kAxW = FMM_P_MAX + kP2MBlk + 4;    // of the column kernel: X_-2, X_-1 (zero), X_0..X_p, zero padding
 
 struct InvTable {
     double v[kPTable + 2];
@@ -160,7 +177,7 @@ __device__ __forceinline__ double fold_component(const double *row, int h)
 }
 
 template <int MASK>
-__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
+__global__ __launch_bounds__(kP2MThreads) void p2m_coef_kernel(int p, int nmp, const int32_t *__restrict__ leaves,
                                                           const DevCell *__restrict__ cells, Geo g,
                                                           const double *__restrict__ xs, int n,
                                                           const double *__restrict__ mom_user,
@@ -173,7 +190,7 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
     constexpr int S = mask_min_order(MASK);
     constexpr bool Q0 = MASK & 1, Q1 = MASK & 2, Q2 = MASK & 4;
     // source tensor slots: 0 order 0; 1..3 order 1; 4..9 order 2
-    __shared__ double pw[kP2MStage][3][kAxW];
+    __shared__ double pw[kP2MStage][3][kAxWc];
     __shared__ double sv[kP2MStage][10];
     const int c = leaves[blockIdx.x];
     const DevCell cell = cells[c];
@@ -182,7 +199,7 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
     const double r = cell_radius(cell.level, g.h);
     const double ir = 1.0 / r;
     const int n0 = nterms(S - 1), nm = nterms(p) - n0;
-    constexpr int KMAX = (nterms(kPTable) + kP2MThreads - 1) / kP2MThreads;
+    constexpr int KMAX = (nterms(FMM_P_MAX) + kP2MThreads - 1) / kP2MThreads;
     double acc[KMAX];
     int ix[KMAX], iy[KMAX], iz[KMAX];
 #pragma unroll
@@ -265,7 +282,7 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
             acc[k] = a;
         }
     }
-    __shared__ double row[nterms(kPTable)];   // the finished row, indexed by multi-index
+    __shared__ double row[nterms(FMM_P_MAX)];   // the finished row, indexed by multi-index
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
         if ((int)threadIdx.x + k * kP2MThreads < nm) {
@@ -273,6 +290,218 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, const 
             M[o] = acc[k];
             if (M32) M32[o] = (float)acc[k];   // the copy the full-basis mixed-precision M2L reads
             row[n0 + threadIdx.x + k * kP2MThreads] = acc[k];
+        }
+    if (Mh32 || Mh64) {
+        // the harmonic-basis row the M2L reads (in its precision)
+        __syncthreads();
+        const int h0 = hterms(S - 1), nh = hterms(p) - h0;
+        for (int h = threadIdx.x; h < nh; h += kP2MThreads) {
+            const double v = fold_component(row, h + h0);
+            if (Mh32) Mh32[(size_t)c * nhp + h] = (float)v;
+            else Mh64[(size_t)c * nhp + h] = v;
+        }
+    }
+}
+
+// Column blocks of every (p, s), fixed at compile time: for each pair the
+// block length with the fewest multiply-add steps per particle (about 10 to
+// form A0..A2 plus 3 per block entry, divided by the groups of threads that
+// share the particles), then the blocks in column order, (ax, ay, az0, nb).
+struct P2MItem {
+    int8_t ax, ay, az0, nb;
+};
+constexpr int kP2MPlanMax = 3 * (FMM_P_MAX + 1) * kP2MThreads;
+struct P2MPlan {
+    int16_t start[FMM_P_MAX + 1][3];
+    int16_t nitems[FMM_P_MAX + 1][3];
+    int8_t blk[FMM_P_MAX + 1][3];
+    int8_t ngroups[FMM_P_MAX + 1][3];
+    P2MItem items[kP2MPlanMax];
+};
+constexpr int p2m_count(int p, int S, int blk)
+{
+    int cnt = 0;
+    for (int x = 0; x <= p; ++x)
+        for (int y = 0; y <= p - x; ++y) {
+            const int lo = S - x - y > 0 ? S - x - y : 0, hi = p - x - y;
+            cnt += (hi - lo + blk) / blk;
+        }
+    return cnt;
+}
+constexpr P2MPlan make_p2m_plan()
+{
+    P2MPlan pl{};
+    int pos = 0;
+    for (int p = 0; p <= FMM_P_MAX; ++p)
+        for (int S = 0; S < 3; ++S) {
+            pl.start[p][S] = (int16_t)pos;
+            if (S > p) continue;
+            int best_b = kP2MBlk, best_n = p2m_count(p, S, kP2MBlk);
+            double best = (10.0 + 3.0 * kP2MBlk) / (kP2MThreads / best_n);
+            for (int bl = 2; bl < kP2MBlk; ++bl) {
+                const int ni = p2m_count(p, S, bl);
+                if (ni > kP2MThreads) continue;
+                const double cost = (10.0 + 3.0 * bl) / (kP2MThreads / ni);
+                if (cost < best) {
+                    best = cost;
+                    best_b = bl;
+                    best_n = ni;
+                }
+            }
+            pl.blk[p][S] = (int8_t)best_b;
+            pl.nitems[p][S] = (int16_t)best_n;
+            pl.ngroups[p][S] = (int8_t)(kP2MThreads / best_n);
+            for (int x = 0; x <= p; ++x)
+                for (int y = 0; y <= p - x; ++y) {
+                    const int lo = S - x - y > 0 ? S - x - y : 0, hi = p - x - y;
+                    for (int z0 = lo; z0 <= hi; z0 += best_b)
+                        pl.items[pos++] = P2MItem{(int8_t)x, (int8_t)y, (int8_t)z0,
+                                                  (int8_t)(hi + 1 - z0 < best_b ? hi + 1 - z0 : best_b)};
+                }
+        }
+    return pl;
+}
+static __constant__ P2MPlan k_p2m = make_p2m_plan();
+static constexpr P2MPlan kP2MPlanHost = make_p2m_plan();
+// the longest block always fits: at p = 10, s = 0 it makes 81 blocks
+static_assert(p2m_count(FMM_P_MAX, 0, kP2MBlk) <= kP2MThreads, "P2M blocks exceed the workgroup");
+
+template <int MASK>
+__global__ __launch_bounds__(kP2MThreads) void p2m_kernel(int p, int nmp, int blk, int nitems, int ngroups,
+                                                          const int32_t *__restrict__ leaves,
+                                                          const DevCell *__restrict__ cells, Geo g,
+                                                          const double *__restrict__ xs, int n,
+                                                          const double *__restrict__ mom_user,
+                                                          const int32_t *__restrict__ perm, double *__restrict__ mom64,
+                                                          float *__restrict__ mom32, double *__restrict__ M,
+                                                          float *__restrict__ M32, int nhp, float *__restrict__ Mh32,
+                                                          double *__restrict__ Mh64)
+{
+    constexpr int W = mask_width(MASK);
+    constexpr int S = mask_min_order(MASK);
+    constexpr bool Q0 = MASK & 1, Q1 = MASK & 2, Q2 = MASK & 4;
+    // source tensor slots: 0 order 0; 1..3 order 1; 4..9 order 2
+    __shared__ double pw[kP2MStage][3][kAxW];
+    __shared__ double sv[kP2MStage][10];
+    __shared__ double gsum[kP2MThreads * kP2MBlk];   // sums of groups 1.. (ngroups > 1)
+    __shared__ double row[nterms(FMM_P_MAX)];          // the finished row, indexed by multi-index
+    const int c = leaves[blockIdx.x];
+    const DevCell cell = cells[c];
+    double z[3];
+    cell_center(cell, g.lo, g.h, z);
+    const double r = cell_radius(cell.level, g.h);
+    const double ir = 1.0 / r;
+    const int n0 = nterms(S - 1);
+    const int item = (int)threadIdx.x % nitems, grp = (int)threadIdx.x / nitems;
+    const bool act = grp < ngroups;
+    const P2MItem pi = k_p2m.items[k_p2m.start[p][S] + item];
+    const int ax = pi.ax, ay = pi.ay, az0 = pi.az0, nb = pi.nb;
+    double acc[kP2MBlk];
+#pragma unroll
+    for (int k = 0; k < kP2MBlk; ++k) acc[k] = 0.0;
+    for (int base = 0; base < cell.count; base += kP2MStage) {
+        const int cnt = min(kP2MStage, cell.count - base);
+        __syncthreads();
+        for (int it = threadIdx.x; it < 3 * cnt; it += kP2MThreads) {
+            // item -> (particle, axis): two zeros, zeta^a / a! for a = 0..p, zeros
+            const int t = it / 3, d = it % 3;
+            const size_t j = (size_t)cell.first + base + t;
+            const double zeta = (z[d] - xs[(size_t)d * n + j]) * ir;
+            double *row_t = pw[t][d];
+            double f = 1.0;
+            row_t[0] = 0.0;
+            row_t[1] = 0.0;
+            row_t[2] = 1.0;
+            for (int e = 1; e <= p; ++e) {
+                f = f * zeta * k_inv.v[e];
+                row_t[2 + e] = f;
+            }
+            for (int e = p + 3; e < kAxW; ++e) row_t[e] = 0.0;
+        }
+        if ((int)threadIdx.x < cnt) {
+            const int t = threadIdx.x;
+            const size_t i = (size_t)cell.first + base + t;
+            const double *m = mom_user + (size_t)perm[i] * W;
+            sort_moments(i, MASK, m, mom64, mom32);
+            int off = 0;
+            if (Q0) sv[t][0] = m[off++];
+            if (Q1) {
+                sv[t][1] = -m[off] * ir;
+                sv[t][2] = -m[off + 1] * ir;
+                sv[t][3] = -m[off + 2] * ir;
+                off += 3;
+            }
+            if (Q2) {
+                const double ir2 = ir * ir;
+                sv[t][4] = 0.5 * m[off] * ir2;       // (2,0,0)
+                sv[t][5] = m[off + 1] * ir2;         // (1,1,0)
+                sv[t][6] = m[off + 2] * ir2;         // (1,0,1)
+                sv[t][7] = 0.5 * m[off + 3] * ir2;   // (0,2,0)
+                sv[t][8] = m[off + 4] * ir2;         // (0,1,1)
+                sv[t][9] = 0.5 * m[off + 5] * ir2;   // (0,0,2)
+            }
+        }
+        __syncthreads();
+        if (act) {
+            for (int t = grp; t < cnt; t += ngroups) {
+                const double *X = pw[t][0], *Y = pw[t][1], *Z = pw[t][2] + az0;
+                const double x0 = X[ax + 2], y0 = Y[ay + 2];
+                const double x0y0 = x0 * y0;
+                double A0 = 0.0, A1 = 0.0, A2 = 0.0;
+                if (Q0) A0 = sv[t][0] * x0y0;
+                if (Q1 || Q2) {
+                    const double x1 = X[ax + 1], y1 = Y[ay + 1];
+                    const double x1y0 = x1 * y0, x0y1 = x0 * y1;
+                    if (Q1) {
+                        A0 = fma(sv[t][1], x1y0, A0);
+                        A0 = fma(sv[t][2], x0y1, A0);
+                        A1 = sv[t][3] * x0y0;
+                    }
+                    if (Q2) {
+                        const double x2 = X[ax], y2 = Y[ay];
+                        A0 = fma(sv[t][4], x2 * y0, A0);
+                        A0 = fma(sv[t][5], x1 * y1, A0);
+                        A0 = fma(sv[t][7], x0 * y2, A0);
+                        A1 = fma(sv[t][6], x1y0, A1);
+                        A1 = fma(sv[t][8], x0y1, A1);
+                        A2 = sv[t][9] * x0y0;
+                    }
+                }
+                // Z[k + 2] = Z_{az0+k}; blocks past the column's end read
+                // real or zero table entries into sums that are not written
+#pragma unroll
+                for (int k = 0; k < kP2MBlk; ++k) {
+                    if (k >= blk) break;
+                    double v = fma(A0, Z[k + 2], acc[k]);
+                    if (Q1 || Q2) v = fma(A1, Z[k + 1], v);
+                    if (Q2) v = fma(A2, Z[k], v);
+                    acc[k] = v;
+                }
+            }
+        }
+    }
+    if (ngroups > 1) {
+        __syncthreads();
+        if (act && grp > 0)
+#pragma unroll
+            for (int k = 0; k < kP2MBlk; ++k)
+                if (k < blk) gsum[((grp - 1) * nitems + item) * kP2MBlk + k] = acc[k];
+        __syncthreads();
+        if (act && grp == 0)
+            for (int q = 1; q < ngroups; ++q)
+#pragma unroll
+                for (int k = 0; k < kP2MBlk; ++k)
+                    if (k < blk) acc[k] += gsum[((q - 1) * nitems + item) * kP2MBlk + k];
+    }
+    if (act && grp == 0)
+#pragma unroll
+        for (int k = 0; k < kP2MBlk; ++k) {
+            if (k >= nb) break;
+            const int i = mindex(ax, ay, az0 + k);
+            const size_t o = (size_t)c * nmp + (i - n0);
+            M[o] = acc[k];
+            if (M32) M32[o] = (float)acc[k];   // the copy the full-basis mixed-precision M2L reads
+            row[i] = acc[k];
         }
     if (Mh32 || Mh64) {
         // the harmonic-basis row the M2L reads (in its precision)
@@ -309,7 +538,17 @@ static void p2m_launch(fmm_tree *t, hipStream_t s)
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
     const HarmOut ho = harm_out(t);
-    hipLaunchKernelGGL(p2m_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp, t->d_leaves,
+    if constexpr (!(MASK & 4)) {
+        hipLaunchKernelGGL(p2m_coef_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp,
+                           t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->mom_user, t->d_perm, t->d_mom,
+                           t->d_mom32, t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
+        return;
+    }
+    const int S = t->order;
+    const int blk = kP2MPlanHost.blk[t->p][S], nitems = kP2MPlanHost.nitems[t->p][S];
+    const int ngroups = kP2MPlanHost.ngroups[t->p][S];
+    hipLaunchKernelGGL(p2m_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp, blk, nitems,
+                       ngroups, t->d_leaves,
                        t->d_cells, g, t->d_x, (int)t->ht.n, t->mom_user, t->d_perm, t->d_mom, t->d_mom32,
                        t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
 }

@@ -260,6 +260,24 @@ def main():
                 "near-field gradient pass")
         grad_line = {"ms_per_call": dt * 1e3, "unit": "evals/s", "value": w.n / dt, "what": what,
                      "out": grd.cpu().numpy()}
+    bh_half = None
+    if bh:
+        # the same particles at theta_BH = 0.3, half the literal opening angle:
+        # the setting whose error matches the FMM's at theta 0.6
+        t2 = fmm.Tree(ctx, pos, w.ncrit, 0.3, fmm.FMM_METHOD_BH)
+        hphi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
+        hfld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            t2.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED, outputs, hphi, hfld)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            t2.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED, outputs, hphi, hfld)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        bh_half = {"theta": 0.3, "value": w.n / dt, "unit": "evals/s", "ms_per_step": dt * 1e3,
+                   "out": hfld.cpu().numpy()}
+        t2.close()
     mixed_line = None
     if not bh and args.config == 2:
         # the same particles carrying a charge, a dipole and a quadrupole each
@@ -347,6 +365,7 @@ def main():
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         **({} if bh else {"m2l_full_basis": full_basis}),
         **({} if grad_line is None else {"field_gradient": {k: v for k, v in grad_line.items() if k != "out"}}),
+        **({} if bh_half is None else {"bh_theta_0.3": {k: v for k, v in bh_half.items() if k != "out"}}),
         **({} if mixed_line is None else
            {"mixed_sources": {k: v for k, v in mixed_line.items() if k not in ("out", "moments")}}),
         "kernel_timing": "separate pass of the same steps, kernels serialised, HIP events on the launch stream",
@@ -391,16 +410,33 @@ def main():
                                            % (len(sample), kind, reps, tb)),
                                 "seconds": tc}
         pd, Ed = oracle.direct(w.pos, w.order, w.moments, targets=sample)
+
+        def per_particle(a, b):
+            """median / p99 / max over targets of |a - b| / |b| (vector norm
+            for E), the distribution behind the pooled L2 figure"""
+            num = np.linalg.norm(np.reshape(a - b, (len(b), -1)), axis=1)
+            den = np.linalg.norm(np.reshape(b, (len(b), -1)), axis=1)
+            r = num / np.where(den > 0, den, 1.0)
+            return {"median": float(np.median(r)), "p99": float(np.percentile(r, 99)), "max": float(r.max())}
+
         errs = {}
         for name in ("mixed", "fp64"):
             ph, E = res[name]["out"]
-            e = {"E_vs_direct": oracle.rel_l2(E[sample], Ed), "E_vs_oracle": oracle.rel_l2(E[sample], Eo_s)}
+            e = {"E_vs_direct": oracle.rel_l2(E[sample], Ed), "E_vs_oracle": oracle.rel_l2(E[sample], Eo_s),
+                 "E_per_particle_vs_direct": per_particle(E[sample], Ed),
+                 "E_per_particle_vs_oracle": per_particle(E[sample], Eo_s)}
             if ph is not None:
                 e["phi_vs_direct"] = oracle.rel_l2(ph[sample], pd)
                 e["phi_vs_oracle"] = oracle.rel_l2(ph[sample], po_s)
             errs[name] = e
-        errs["targets"] = "%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s" % (len(sample), kind)
+        errs["targets"] = ("%d sampled targets, direct O(N) sum per target in FP64; oracle = CPU %s; per-particle "
+                           "figures: median, 99th percentile and maximum of the relative error of one target"
+                           % (len(sample), kind))
         line["rel_l2_error"] = errs
+        if bh_half is not None:
+            hEo = oracle.Tree(w.pos, w.ncrit).bh(w.order, w.moments, w.p, 0.3, targets=sample)[1]
+            line["bh_theta_0.3"]["E_vs_direct"] = oracle.rel_l2(bh_half["out"][sample], Ed)
+            line["bh_theta_0.3"]["E_vs_oracle"] = oracle.rel_l2(bh_half["out"][sample], hEo)
         if mixed_line is not None:
             code = oracle.MIXED + 7
             mpo, mEo = ot.fmm(code, mixed_line["moments"], w.p, targets=sample)

@@ -47,7 +47,7 @@ TILE = 64
 # code-shape options (register blocking, scalar-load pipelining, waves per
 # workgroup); the defaults are the measured best on gfx950
 DEFAULTS = {"acc32": 128, "m32": 64, "acc64": 64, "m64": 32, "dgroup32": 32, "dgroup64": 16, "pipeline": 1,
-            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0, "wgw": 4}
+            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0, "wgw": 4, "fairprio": 1}
 
 
 def orders(p):
@@ -165,6 +165,17 @@ def gen_kernel(p, s, fp32, opt=None, harmonic=False):
             L.append("        for (int u = ub; u < ue; ++u) {")
         else:
             L.append("        for (int u = w.y; u < w.z; ++u) {")
+        if opt["fairprio"] and wgw > 1:
+            # issue priority falls as the wave works through its entries, so
+            # a wave that lags (the younger workgroup's, which loses the
+            # age-ordered arbitration) catches up instead of finishing alone
+            L.append("            {")
+            L.append("                const int stage = (u - ub) * 4 / (ue - ub);")
+            L.append("                if (stage == 0) __builtin_amdgcn_s_setprio(3);")
+            L.append("                else if (stage == 1) __builtin_amdgcn_s_setprio(2);")
+            L.append("                else if (stage == 2) __builtin_amdgcn_s_setprio(1);")
+            L.append("                else __builtin_amdgcn_s_setprio(0);")
+            L.append("            }")
         L.append("            const int cls = a.ucls[u];")
         # the class tables are read-only for the whole kernel: reading them
         # through the constant address space lets the uniform loads go

@@ -912,20 +912,26 @@ __device__ __forceinline__ void p2p_pair_grad_mixed(float rx, float ry, float rz
 }
 
 // GRAD: the six field-gradient components instead of phi and E (sums of
-// order k scaled by r_b^-(k+3)), written to near_g
+// order k scaled by r_b^-(k+3)), written to near_g.  The launch bound asks
+// for five resident workgroups per CU, which fits the dipole kernel in 82
+// VGPRs without spills (114 unbounded).
 template <int MASK, bool GRAD>
-__global__ __launch_bounds__(kPT) void p2p_f32_kernel(P2PArgs a)
+__global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
 {
     constexpr int NO = GRAD ? 6 : 4;                 // output components
     constexpr bool ONE = mask_single(MASK);
     constexpr int S = mask_min_order(MASK);
     constexpr int NV = ONE ? (S == 2 ? 2 : 1) : 3;   // float4 of moments per staged source
     constexpr int MW = m32_width(MASK) / 4;          // float4 of moments per particle
-    __shared__ double spx[kPChunk32], spy[kPChunk32], spz[kPChunk32];
+    // the staging area doubles as the reduction buffer at the end of a pass
+    // (8 KB less LDS per workgroup, one more workgroup per CU)
+    __shared__ double sbuf[3 * kPChunk32];
+    double *const spx = sbuf, *const spy = sbuf + kPChunk32, *const spz = sbuf + 2 * kPChunk32;
+    static_assert(NO * kPT <= 3 * kPChunk32, "reduction buffer exceeds the staging area");
+    double (*const red)[kPT] = reinterpret_cast<double (*)[kPT]>(sbuf);
     __shared__ float4 spm[NV][kPChunk32];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
-    __shared__ double red[NO][kPT];
     __shared__ int sh[kPT / 64];
     __shared__ int wself;
     const int tid = threadIdx.x;

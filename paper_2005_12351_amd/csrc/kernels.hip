@@ -1086,8 +1086,9 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
     }
 }
 
+// (five resident workgroups per CU, as the FP32 kernel)
 template <int MASK, bool GRAD>
-__global__ __launch_bounds__(kPT) void p2p_f64_kernel(P2PArgs a)
+__global__ __launch_bounds__(kPT, 5) void p2p_f64_kernel(P2PArgs a)
 {
     constexpr int W = mask_width(MASK);
     constexpr int NO = GRAD ? 6 : 4;

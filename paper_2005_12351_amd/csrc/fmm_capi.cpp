@@ -547,6 +547,11 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the host vector dies here
         t->l2p_npacks = (int)pack.size() - 1;
         t->l2p_pack_q = p - order;
+        int dev = 0, ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+        t->l2p_columns = l2p_columns_pay(p - order, t->l2p_npacks, ncu);
     }
     hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
     // P2M and M2M write the FP32 copy too; the rest (the zero row the padded

@@ -230,6 +230,7 @@ struct fmm_tree {
     int32_t *d_p2p_order = nullptr;        // leaf ordinals by decreasing near-field cost
     int32_t *d_l2p_pack = nullptr;         // L2P: leaf-ordinal range of every wave
     int l2p_npacks = 0, l2p_pack_q = -1;
+    bool l2p_columns = false;              // L2P keeps the locals as packed columns (see l2p_columns_pay)
     int32_t *d_wave_ptr = nullptr;
     M2LWork m2lwork;
     double *d_cls_geom = nullptr;
@@ -286,6 +287,7 @@ hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
 hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false);   // grad: field gradient to d_near_g
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
+bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a launch of npacks waves
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 
 // serving (serve.cpp)

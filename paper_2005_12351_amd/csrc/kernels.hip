@@ -1249,20 +1249,45 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad)
 // to the caller's particle order.  One wave per pack of consecutive leaves
 // holding at most 64 particles together (the host packs them, so that most
 // lanes work although leaves hold ~ncrit/3 particles on average).  Each
-// leaf's L~ is unpacked into a dense zero-padded cube in LDS, so that for
-// fixed (n_x, n_y) the four sums over n_z are unit-stride from one base; the
-// loop structure is the same for every lane.  Compiled per q = p - s.
+// leaf's L~ is unpacked into LDS, zero beyond the simplex, so that for fixed
+// (n_x, n_y) the sums over n_z of L~_n and of its neighbours n + e_d (+ e_d')
+// are unit-stride from one base each; the loop structure is the same for
+// every lane.  Two layouts (COLS):
+// - a dense (q+2)^3 cube: the neighbours sit at fixed offsets from the base,
+//   immediates of the LDS reads;
+// - packed columns: for every (n_x, n_y) with n_x + n_y <= q + 2 the entries
+//   n_z = 0 .. q + 2 - n_x - n_y lie contiguously, (q+3)(q+4)(q+5)/6 values,
+//   a third of the cube, but each neighbour column costs an address add.
+// The cube is used while every wave of the launch fits on the chip at once
+// under its LDS share (100k particles), the columns when that share limits
+// the resident waves (1M and more), where they are about 25 % faster.
+// The leaves per pack are what a 16 KB budget of cubes allows in both cases.
+// Compiled per q = p - s.
 constexpr int kL2PMaxLeaves = 8;
-constexpr int kL2PLds = 16384;   // bytes of cubes per wave
+constexpr int kL2PPackBudget = 16384;   // bytes of (q+2)^3 cubes that fix the leaves per pack
 
+// values of one leaf's columns, and the start of column (x, y) (K = q + 3:
+// column (x', y') holds K - x' - y' values)
+__host__ __device__ constexpr int l2p_cols(int q) { return (q + 3) * (q + 4) * (q + 5) / 6; }
+__host__ __device__ constexpr int l2p_col(int q, int x, int y)
+{
+    const int K = q + 3, kx = K - x;
+    return K * (K + 1) * (K + 2) / 6 - kx * (kx + 1) * (kx + 2) / 6 + y * kx - y * (y - 1) / 2;
+}
 __host__ __device__ constexpr int l2p_cube(int q) { return (q + 2) * (q + 2) * (q + 2); }
-int l2p_pack_limit(int q) { return std::max(1, std::min(kL2PMaxLeaves, kL2PLds / (int)(8 * l2p_cube(q)))); }
+int l2p_pack_limit(int q) { return std::max(1, std::min(kL2PMaxLeaves, kL2PPackBudget / (8 * l2p_cube(q)))); }
+constexpr int kLdsPerCU = 160 * 1024;
+bool l2p_columns_pay(int q, int npacks, int ncu)
+{
+    const int cube_bytes = l2p_pack_limit(q) * l2p_cube(q) * 8;
+    return (int64_t)npacks > (int64_t)ncu * std::max(1, kLdsPerCU / cube_bytes);
+}
 
 // GRAD: also the field gradient, -(1/r^3) sum_{|n|<=q-2} eta^n/n! L~_{n+e_i+e_j}
 // (the second derivatives of the expansion, the general-k form of Eq. 10),
 // plus the near field's gradient; its sums read the same cube (indices stay
 // inside the simplex, so no larger edge is needed)
-template <int Q, bool GRAD>
+template <int Q, bool GRAD, bool COLS>
 __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__restrict__ pack,
                                                  const int32_t *__restrict__ leaves, const DevCell *__restrict__ cells,
                                                  Geo g, const double *__restrict__ xs, int n,
@@ -1272,9 +1297,11 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
                                                  double *__restrict__ grad)
 {
     constexpr int NL = nterms(Q);
-    constexpr int E = Q + 2;                     // edge: room for n + e_d
-    constexpr int NC = E * E * E;
-    extern __shared__ double cubes[];            // one cube per leaf of the pack
+    constexpr int E = Q + 2;                     // cube edge: room for n + e_d
+    constexpr int NC = COLS ? l2p_cols(Q) : E * E * E;   // values per leaf
+    // start of the n_z run of (x, y)
+    auto at = [](int x, int y) { return COLS ? l2p_col(Q, x, y) : (x * E + y) * E; };
+    extern __shared__ double cubes[];            // one cube or set of columns per leaf of the pack
     __shared__ int lfirst[kL2PMaxLeaves], lstart[kL2PMaxLeaves + 1];
     __shared__ double lgeo[kL2PMaxLeaves][4];    // centre, 1 / radius
     const int p0 = pack[blockIdx.x], nlv = pack[blockIdx.x + 1] - p0;
@@ -1299,7 +1326,7 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
         const size_t c = (size_t)leaves[p0 + q];
         for (int i = threadIdx.x; i < NL; i += blockDim.x) {
             const MultiIndex nn = k_mi.v[i];
-            cubes[q * NC + (nn.x * E + nn.y) * E + nn.z] = L[c * NL + i];
+            cubes[q * NC + at(nn.x, nn.y) + nn.z] = L[c * NL + i];
         }
     }
     __syncthreads();
@@ -1326,7 +1353,10 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
 #pragma unroll 1
             for (int ny = 0; ny <= Q - nx; ++ny) {
                 if (ny) py *= ey * k_inv.v[ny];
-                const double *b = cube + (nx * E + ny) * E;
+                // columns (nx, ny), (nx+1, ny), (nx, ny+1) and, for the
+                // gradient, (nx+2, ny), (nx+1, ny+1), (nx, ny+2)
+                const double *b = cube + at(nx, ny);
+                const double *bx = cube + at(nx + 1, ny), *by = cube + at(nx, ny + 1);
                 const int lim = Q - nx - ny;
                 // entries beyond the simplex are zero, so the field sums may
                 // run to the same bound as the potential sum
@@ -1335,8 +1365,8 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
                 for (int nz = 0; nz <= Q; ++nz) {
                     if (nz > lim) break;
                     tp = fma(pz[nz], b[nz], tp);
-                    tx = fma(pz[nz], b[E * E + nz], tx);
-                    ty = fma(pz[nz], b[E + nz], ty);
+                    tx = fma(pz[nz], bx[nz], tx);
+                    ty = fma(pz[nz], by[nz], ty);
                     tz = fma(pz[nz], b[nz + 1], tz);
                 }
                 ph = fma(py, tp, ph);
@@ -1345,14 +1375,16 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
                 fz = fma(py, tz, fz);
                 if constexpr (GRAD) {
                     double tg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    const double *bxx = cube + at(nx + 2, ny), *bxy = cube + at(nx + 1, ny + 1),
+                                 *byy = cube + at(nx, ny + 2);
 #pragma unroll
                     for (int nz = 0; nz + 2 <= Q; ++nz) {
                         if (nz > lim - 2) break;
-                        tg[0] = fma(pz[nz], b[2 * E * E + nz], tg[0]);
-                        tg[1] = fma(pz[nz], b[E * E + E + nz], tg[1]);
-                        tg[2] = fma(pz[nz], b[E * E + nz + 1], tg[2]);
-                        tg[3] = fma(pz[nz], b[2 * E + nz], tg[3]);
-                        tg[4] = fma(pz[nz], b[E + nz + 1], tg[4]);
+                        tg[0] = fma(pz[nz], bxx[nz], tg[0]);
+                        tg[1] = fma(pz[nz], bxy[nz], tg[1]);
+                        tg[2] = fma(pz[nz], bx[nz + 1], tg[2]);
+                        tg[3] = fma(pz[nz], byy[nz], tg[3]);
+                        tg[4] = fma(pz[nz], by[nz + 1], tg[4]);
                         tg[5] = fma(pz[nz], b[nz + 2], tg[5]);
                     }
 #pragma unroll
@@ -1378,22 +1410,29 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
     }
 }
 
-template <int Q>
-static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
+template <int Q, bool COLS>
+static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
-    const size_t lds = (size_t)l2p_pack_limit(Q) * l2p_cube(Q) * sizeof(double);
+    const size_t lds = (size_t)l2p_pack_limit(Q) * (COLS ? l2p_cols(Q) : l2p_cube(Q)) * sizeof(double);
     if constexpr (Q >= 2) {
         if (outputs & FMM_GRAD) {
-            hipLaunchKernelGGL((l2p_kernel<Q, true>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
+            hipLaunchKernelGGL((l2p_kernel<Q, true, COLS>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
                                t->d_l2p_pack, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near,
                                t->d_perm, phi, field, t->d_near_g, grad);
             return;
         }
     }
-    hipLaunchKernelGGL((l2p_kernel<Q, false>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
+    hipLaunchKernelGGL((l2p_kernel<Q, false, COLS>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
                        t->d_l2p_pack, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near, t->d_perm,
                        phi, field, nullptr, nullptr);
+}
+
+template <int Q>
+static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
+{
+    if (t->l2p_columns) l2p_launch_layout<Q, true>(t, outputs, phi, field, grad, s);
+    else l2p_launch_layout<Q, false>(t, outputs, phi, field, grad, s);
 }
 
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)

@@ -117,16 +117,19 @@ def test_gradient_keeps_phi_field_and_replays(ctx, basis, prec):
         ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
 
 
-def test_gradient_full_size_sampled(orc, ctx):
-    """100k uniform dipoles, p 8 (the benchmark workload), after fmm_run, on
-    4 096 sampled targets."""
-    w = W.config(2)
+@pytest.mark.parametrize("index", [2, 3])
+def test_gradient_full_size_sampled(orc, ctx, index):
+    """100k uniform dipoles, p 8 (the benchmark workload; L2P keeps the
+    locals as cubes) and 1M Plummer dipoles, p 6 (enough L2P waves that it
+    keeps them as packed columns), after fmm_run, on 4 096 sampled targets."""
+    w = W.config(index)
     print(f"[grad full] {w.name}", flush=True)
     Go = orc.Tree(w.pos, w.ncrit, w.theta).fmm(w.order, w.moments, w.p, targets=w.sample, want_grad=True)[2]
     t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta)
     s = torch.from_numpy(w.sample).cuda()
+    outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     for prec in (fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED):
-        t.run(w.order, to_dev(w.moments), w.p, prec)
+        t.run(w.order, to_dev(w.moments), w.p, prec, outputs)
         _, _, G = t.evaluate_grad(fmm.FMM_GRAD)
         torch.cuda.synchronize()
         e = rel_l2(G[s].cpu().numpy(), Go)

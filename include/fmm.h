@@ -169,10 +169,16 @@ int fmm_tree_destroy(fmm_tree *tree);
 /* Text of the last error on the calling thread ("" if none). */
 const char *fmm_last_error(void);
 
-/* Near field (P2P) on a second stream beside the far field (default off: on
- * MI355X the near field fills the GPU by itself and the overlap measured no
- * gain).  Off: every kernel runs on the context stream, one after the other,
- * so the per-kernel timings below measure each kernel alone. */
+/* Near field (P2P) on a second stream beside the far field.  `on`:
+ * FMM_OVERLAP_OFF (default): every kernel runs on the context stream, one
+ * after the other, so the per-kernel timings below measure each kernel alone;
+ * FMM_OVERLAP_WHOLE: the whole near field beside the whole far field;
+ * FMM_OVERLAP_SPLIT: in fmm_run, half the near field (by cost) beside the
+ * upward M2M levels, joined before the M2L, the other half after the M2L
+ * beside the combine and L2L, joined before the L2P, so that it never
+ * competes with the M2L (fmm_upward alone runs the whole near field).
+ * FMM_EINVAL for other values. */
+enum { FMM_OVERLAP_OFF = 0, FMM_OVERLAP_WHOLE = 1, FMM_OVERLAP_SPLIT = 2 };
 int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
 
 /* Replay HIP graphs (default on): the kernel sequence of fmm_upward and of

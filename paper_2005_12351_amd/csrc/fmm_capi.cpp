@@ -75,7 +75,8 @@ static void drop_graphs(fmm_tree *t)
 extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
-    ctx->overlap = on != 0;
+    if (on < 0 || on > FMM_OVERLAP_SPLIT) FAIL(FMM_EINVAL, "overlap mode %d (0, 1 or 2)", on);
+    ctx->overlap = on;
     for (fmm_tree *t : ctx->trees) drop_graphs(t);
     return FMM_OK;
 }
@@ -201,7 +202,9 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
     if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_m2l, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_near2, hipEventDisableTiming) != hipSuccess) {
         delete c;
         FAIL(FMM_EDEVICE, "stream/event creation failed");
     }
@@ -248,6 +251,8 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     hipEventDestroy(c->ev_up);
     hipEventDestroy(c->ev_near);
     hipEventDestroy(c->ev_fork);
+    hipEventDestroy(c->ev_m2l);
+    hipEventDestroy(c->ev_near2);
     hipStreamDestroy(c->aux);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -402,6 +407,14 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     std::vector<int32_t> p2p_order(t->nleaves);
     for (int64_t k = 0; k < t->nleaves; ++k) p2p_order[k] = (int32_t)k;
     std::stable_sort(p2p_order.begin(), p2p_order.end(), [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
+    {
+        // split point of the near field for FMM_OVERLAP_SPLIT: half the cost
+        double tot = 0.0, acc = 0.0;
+        for (double c : leaf_cost) tot += c;
+        int k = 0;
+        while (k < (int)t->nleaves && acc < 0.5 * tot) acc += leaf_cost[p2p_order[k++]];
+        t->p2p_split = k;
+    }
     std::vector<int32_t> perm32(n);
     for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)h.perm[i];
 
@@ -623,7 +636,10 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
         }
         {
             ProfScope ps(ctx, a, "p2p");
-            KCHK(launch_p2p(t, a));
+            // split overlap inside fmm_run: the first half here (beside M2M),
+            // the second after the M2L (queue_evaluate)
+            if (ctx->overlap == FMM_OVERLAP_SPLIT && !join) KCHK(launch_p2p_part(t, a, 0, t->p2p_split));
+            else KCHK(launch_p2p(t, a));
         }
         if (a != s) KCHK(hipEventRecord(ctx->ev_near, a));
     }
@@ -650,9 +666,21 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         KCHK(launch_bh(t, outputs, phi, field, grad, s));
         return FMM_OK;
     }
+    const bool split = wait_near && ctx->overlap == FMM_OVERLAP_SPLIT;
+    if (split) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));   // the first near-field half
     {
         ProfScope ps(ctx, s, "m2l");
         KCHK(launch_m2l(t, s));
+    }
+    if (split) {
+        // the second half of the near field beside the combine and L2L
+        KCHK(hipEventRecord(ctx->ev_m2l, s));
+        KCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_m2l, 0));
+        {
+            ProfScope ps(ctx, ctx->aux, "p2p");
+            KCHK(launch_p2p_part(t, ctx->aux, t->p2p_split, -1));
+        }
+        KCHK(hipEventRecord(ctx->ev_near2, ctx->aux));
     }
     {
         ProfScope ps(ctx, s, "m2l_combine");
@@ -663,7 +691,8 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         ProfScope ps(ctx, s, "l2l");
         KCHK(launch_l2l_level(t, l, s));
     }
-    if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
+    if (split) KCHK(hipStreamWaitEvent(s, ctx->ev_near2, 0));
+    else if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     if (outputs & FMM_GRAD) {
         ProfScope ps(ctx, s, "p2p_grad");
         KCHK(launch_p2p(t, s, true));

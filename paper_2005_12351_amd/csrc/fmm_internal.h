@@ -194,7 +194,7 @@ struct fmm_ctx {
     bool own_stream = false;
     size_t budget = 0;
     bool profile = false;
-    bool overlap = false;                 // P2P on the auxiliary stream
+    int overlap = 0;                      // P2P on the auxiliary stream: 0 off, 1 whole, 2 split (FMM_OVERLAP_*)
     bool graphs = true;                   // replay captured HIP graphs
     int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
     bool fake = false;                    // no device: serving-logic tests only
@@ -203,6 +203,7 @@ struct fmm_ctx {
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;
     hipEvent_t ev_up = nullptr, ev_near = nullptr;
+    hipEvent_t ev_m2l = nullptr, ev_near2 = nullptr;   // split overlap: M2L queued, second P2P part done
     struct Server *server = nullptr;
     std::vector<struct fmm_tree *> trees;  // live trees; released with the context
 };
@@ -228,6 +229,7 @@ struct fmm_tree {
     int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_cell_slot = nullptr;   // cell -> tile slot or -1
     int32_t *d_tile_chunk0 = nullptr, *d_tile_nchunk = nullptr;
     int32_t *d_p2p_order = nullptr;        // leaf ordinals by decreasing near-field cost
+    int p2p_split = 0;                     // first position of p2p_order past half the near-field cost
     int32_t *d_l2p_pack = nullptr;         // L2P: leaf-ordinal range of every wave
     int l2p_npacks = 0, l2p_pack_q = -1;
     bool l2p_columns = false;              // L2P keeps the locals as packed columns (see l2p_columns_pay)
@@ -289,6 +291,8 @@ hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
 bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a launch of npacks waves
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
+// P2P over the leaves p2p_order[first .. first + count) (count < 0: to the end)
+hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count);
 
 // serving (serve.cpp)
 int serve_destroy(fmm_ctx *ctx);

@@ -1204,8 +1204,20 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f64_kernel(P2PArgs a)
     }
 }
 
-hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad)
+static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count);
+
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad) { return launch_p2p_range(t, s, grad, 0, -1); }
+
+hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count)
 {
+    return launch_p2p_range(t, s, false, first, count);
+}
+
+static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count)
+{
+    if (count < 0) count = (int)t->nleaves - first;
+    if (first < 0 || count < 0 || first + count > t->nleaves) return hipErrorInvalidValue;
+    if (count == 0) return hipSuccess;
     P2PArgs a;
     a.leaves = t->d_leaves;
     a.ptr = t->d_p2p_ptr;
@@ -1219,8 +1231,8 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad)
     a.near_g = t->d_near_g;
     a.n = (int)t->ht.n;
     a.h = t->ht.h;
-    a.order = t->d_p2p_order;
-    const dim3 g((unsigned)t->nleaves), bl(kPT);
+    a.order = t->d_p2p_order + first;
+    const dim3 g((unsigned)count), bl(kPT);
     const bool f32 = t->prec == FMM_PREC_MIXED;
 #define P2P_CASE(M)                                                                         \
     case M:                                                                                 \

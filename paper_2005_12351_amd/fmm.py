@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("FMM_LIBRARY") or os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE, FMM_EBUSY, FMM_ETIMEOUT = range(7)
 FMM_POT, FMM_FIELD, FMM_GRAD = 1, 2, 4   # output mask bits (FMM_GRAD: evaluate_grad only)
+FMM_OVERLAP_OFF, FMM_OVERLAP_WHOLE, FMM_OVERLAP_SPLIT = 0, 1, 2
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
@@ -185,7 +186,9 @@ class Context:
         """FMM_M2L_FULL or FMM_M2L_HARMONIC (default); used from the next upward pass."""
         _check(fmm_ctx_set_m2l_basis(self.h, int(basis)), "fmm_ctx_set_m2l_basis")
 
-    def set_overlap(self, on: bool = True):
+    def set_overlap(self, on=True):
+        """False/0 off, True/1 the whole near field beside the far field, 2
+        (FMM_OVERLAP_SPLIT) half beside M2M and half after the M2L"""
         _check(fmm_ctx_set_overlap(self.h, int(on)), "fmm_ctx_set_overlap")
 
     def set_graphs(self, on: bool = True):

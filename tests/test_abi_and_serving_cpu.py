@@ -115,3 +115,15 @@ def test_fake_server_stop_drains_queue(fmm):
     ctx.wait(t, 5.0)
     ctx.close()
     assert len(tickets) == 8
+
+
+def test_overlap_modes_validated(fmm):
+    """fmm_ctx_set_overlap takes FMM_OVERLAP_OFF / WHOLE / SPLIT and rejects
+    anything else with FMM_EINVAL (no device needed)"""
+    ctx = fmm.Context.fake(budget_bytes=1 << 30)
+    for mode in (fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT, False, True):
+        ctx.set_overlap(mode)
+    for bad in (-1, 3):
+        with pytest.raises(RuntimeError, match="overlap mode"):
+            ctx.set_overlap(bad)
+    ctx.close()

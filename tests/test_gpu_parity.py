@@ -228,7 +228,7 @@ def test_basis_switch_on_one_tree(ctx):
         ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
 
 
-@pytest.mark.parametrize("overlap", [True, False])
+@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT])
 def test_graph_replay_matches_eager(ctx, overlap):
     """Captured graphs replayed several times, with eager work and
     synchronisations in between, give exactly the eager result each time."""
@@ -263,7 +263,7 @@ def test_graph_replay_matches_eager(ctx, overlap):
         ctx.set_graphs(True)
 
 
-@pytest.mark.parametrize("overlap", [True, False])
+@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT])
 @pytest.mark.parametrize("method", ["fmm", "bh"])
 def test_run_matches_upward_evaluate(ctx, overlap, method):
     """fmm_run (one launch sequence) gives exactly the result of fmm_upward +

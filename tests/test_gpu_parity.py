@@ -313,6 +313,15 @@ def test_error_codes(ctx):
     with pytest.raises(fmm.FMMError) as e:
         fmm.Tree(ctx, pos, 0, 0.5)
     assert e.value.code == fmm.FMM_EINVAL
+    # an empty system and a non-finite position are rejected, not evaluated
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Tree(ctx, torch.empty((0, 3), dtype=torch.float64, device="cuda"), 8, 0.5)
+    assert e.value.code == fmm.FMM_EINVAL
+    bad = pos.clone()
+    bad[17, 1] = float("nan")
+    with pytest.raises(fmm.FMMError) as e:
+        fmm.Tree(ctx, bad, 8, 0.5)
+    assert e.value.code == fmm.FMM_EINVAL
     with pytest.raises(fmm.FMMError):
         fmm.Tree(ctx, pos, 8, 1.5)
     t = fmm.Tree(ctx, pos, 8, 0.5)

@@ -85,7 +85,7 @@ def test_tree_invariants_and_pair_coverage(orc, kind, n, ncrit, theta):
             row[d.first[a]:d.first[a] + d.count[a]] += 1
         full[i] = row
     assert np.all(full == 1)
-    # lists sorted, and M2L only between cells that satisfy Eq. 13 strictly
+    # each list sorted by source index (Eq. 13 itself: test_oracle_mac.py)
     for c in range(nc):
         seg = d.m2l_src[d.m2l_ptr[c]:d.m2l_ptr[c + 1]]
         assert np.all(np.diff(seg) > 0)

@@ -1,11 +1,14 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the
 benchmark times (fmm_run, one captured graph per step, replayed), in both M2L
 bases: 100k uniform dipoles (p 8), 1M Plummer dipoles (p 6, field only,
-FMM and Barnes-Hut) and 2M lattice quadrupoles (p 10).  The oracle cannot
-evaluate every particle at these sizes, so it runs its full upward pass and
-evaluates 4 096 seeded sample targets one by one (Section 3.2 lists of the
-sampled leaves only); the GPU values at those targets are compared with the
-same bounds as the small cases: FP64 1e-10, MIXED 1e-6 (relative L2)."""
+FMM and Barnes-Hut) and 2M lattice quadrupoles (p 10).  At 100k particles the
+oracle evaluates every target, at the literal parameters (theta 0.5, p 8) and
+at the benchmark's headline parameters (theta 0.3, p 10, the smallest sweep
+point whose error against the direct sum is below 1e-6).  At 1M and 2M it
+runs its full upward pass and evaluates 4 096 seeded sample targets (Section
+3.2 lists of the sampled leaves only).  The bounds are those of the small
+cases (pooled relative L2 and largest per-target error, tests/gpu_helpers.py).
+"""
 import numpy as np
 import pytest
 
@@ -17,9 +20,8 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2005_12351_amd import fmm  # noqa: E402
 from paper_2005_12351_amd import workloads as W  # noqa: E402
-from tests.gpu_helpers import rel_l2, to_dev  # noqa: E402
+from tests.gpu_helpers import PHI_FLOOR, to_dev, within  # noqa: E402
 
-TOL = {"fp64": 1e-10, "mixed": 1e-6}
 PREC = {"fp64": fmm.FMM_PREC_FP64, "mixed": fmm.FMM_PREC_MIXED}
 
 
@@ -76,13 +78,36 @@ def test_full_size_sampled(orc, ctx, index, method, basis, prec):
     print(f"[full] {w.name} n={w.n} p={w.p} theta={w.theta} {method} {basis} {prec}", flush=True)
     po, Eo = _oracle(orc, w, method)
     ph, E = _run(ctx, w, prec, method, BASIS[basis])
-    e2 = rel_l2(E, Eo)
-    msg = f"   rel L2 on {len(w.sample)} samples: E {e2:.2e}"
-    ok = e2 < TOL[prec]
+    ok = within(E, Eo, prec, f"E on {len(w.sample)} samples")
     if ph is not None:
-        e1 = rel_l2(ph, po)
-        msg += f" phi {e1:.2e}"
-        ok = ok and e1 < TOL[prec]
-    print(msg, flush=True)
+        ok &= within(ph, po, prec, f"phi on {len(w.sample)} samples", floor=PHI_FLOOR)
     assert ok
     assert np.all(np.isfinite(E))
+
+
+_all = {}
+
+
+@pytest.mark.parametrize("theta,p", [(0.5, 8), (0.3, 10)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c2_every_target(orc, ctx, theta, p, prec):
+    """100k uniform dipoles: every target against the oracle FMM, through
+    fmm_run replays (harmonic basis, as the benchmark times it)"""
+    w = W.config(2)
+    w.theta, w.p = theta, p
+    print(f"[full, all targets] {w.name} theta={theta} p={p} {prec}", flush=True)
+    if (theta, p) not in _all:
+        _all[(theta, p)] = orc.Tree(w.pos, w.ncrit, theta).fmm(w.order, w.moments, p)
+    po, Eo = _all[(theta, p)]
+    t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, theta)
+    mom = to_dev(w.moments)
+    phi = torch.empty(w.n, dtype=torch.float64, device="cuda")
+    fld = torch.empty((w.n, 3), dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        t.run(w.order, mom, p, PREC[prec], fmm.FMM_POT | fmm.FMM_FIELD, phi, fld)
+    torch.cuda.synchronize()
+    ph, E = phi.cpu().numpy(), fld.cpu().numpy()
+    t.close()
+    ok = within(ph, po, prec, f"phi on all {w.n} targets", floor=PHI_FLOOR)
+    ok &= within(E, Eo, prec, f"E on all {w.n} targets")
+    assert ok

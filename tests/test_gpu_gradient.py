@@ -12,6 +12,9 @@ Tolerances (relative L2 over all targets and the six components):
   quadrupole's five terms) and Kahan-compensated sums; the far part comes
   from the FP32 M2L like the field's.  Observed: 2.1e-7 to 5.6e-7 (FP64
   4e-16 to 3e-15); the values are printed.
+Largest per-target error (tests/gpu_helpers.py): FP64 1e-12 as for phi and
+E; MIXED 1e-4, since a target's gradient is dominated by its nearest pairs,
+whose r^-3 and r^-5 terms cancel most among the outputs.
 """
 import numpy as np
 import pytest
@@ -24,9 +27,9 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2005_12351_amd import fmm  # noqa: E402
 from paper_2005_12351_amd import workloads as W  # noqa: E402
-from tests.gpu_helpers import rel_l2, to_dev  # noqa: E402
+from tests.gpu_helpers import PHI_FLOOR, rel_l2, to_dev, within  # noqa: E402
 
-TOL = {fmm.FMM_PREC_FP64: 1e-10, fmm.FMM_PREC_MIXED: 2e-6}
+TOL = {fmm.FMM_PREC_FP64: (1e-10, 1e-12), fmm.FMM_PREC_MIXED: (2e-6, 1e-4)}
 ALL = fmm.FMM_POT | fmm.FMM_FIELD | fmm.FMM_GRAD
 
 
@@ -60,9 +63,10 @@ def test_gradient_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta, prec
     (ph, E, G), t = _gpu_grad(ctx, w, prec)
     t.close()
     po, Eo, Go = orc.Tree(w.pos, ncrit, theta).fmm(order, w.moments, p, want_grad=True)
-    e = rel_l2(G, Go)
-    print(f"   rel L2 vs oracle: G {e:.2e} (phi {rel_l2(ph, po):.2e}, E {rel_l2(E, Eo):.2e})", flush=True)
-    assert e < TOL[prec]
+    ok = within(G, Go, prec, "G vs oracle", TOL[prec])
+    ok &= within(ph, po, prec, "phi vs oracle", floor=PHI_FLOOR)
+    ok &= within(E, Eo, prec, "E vs oracle")
+    assert ok
     assert np.abs(G[:, 0] + G[:, 3] + G[:, 5]).max() <= 1e-5 * np.abs(G).max()   # Laplace: trace ~ 0
 
 
@@ -74,9 +78,7 @@ def test_gradient_mixed_orders(orc, ctx, mask, p, prec):
     (_, _, G), t = _gpu_grad(ctx, w, prec)
     t.close()
     Go = orc.Tree(w.pos, w.ncrit, w.theta).fmm(w.order, w.moments, p, want_grad=True)[2]
-    e = rel_l2(G, Go)
-    print(f"   rel L2 vs oracle: G {e:.2e}", flush=True)
-    assert e < TOL[prec]
+    assert within(G, Go, prec, "G vs oracle", TOL[prec])
 
 
 @pytest.mark.parametrize("basis", [fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_FULL])
@@ -132,9 +134,7 @@ def test_gradient_full_size_sampled(orc, ctx, index):
         t.run(w.order, to_dev(w.moments), w.p, prec, outputs)
         _, _, G = t.evaluate_grad(fmm.FMM_GRAD)
         torch.cuda.synchronize()
-        e = rel_l2(G[s].cpu().numpy(), Go)
-        print(f"   precision={prec}: G rel L2 {e:.2e}", flush=True)
-        assert e < TOL[prec]
+        assert within(G[s].cpu().numpy(), Go, prec, f"precision={prec}: G vs oracle", TOL[prec])
     t.close()
 
 
@@ -197,16 +197,16 @@ def test_bh_gradient_matches_oracle(orc, ctx, order, p, kind, n, ncrit, theta, p
     w = W.small_random(1700 + n + order, n, order, kind)
     (ph, E, G), (ph0, E0) = _bh_grad(ctx, w, p, theta, ncrit, prec, basis)
     po, Eo, Go = orc.Tree(w.pos, ncrit).bh(order, w.moments, p, theta, want_grad=True)
-    e = rel_l2(G, Go)
-    print(f"   rel L2 vs oracle: G {e:.2e} (phi {rel_l2(ph, po):.2e}, E {rel_l2(E, Eo):.2e}); "
-          f"vs fmm_evaluate: phi {rel_l2(ph, ph0):.1e} E {rel_l2(E, E0):.1e}", flush=True)
-    assert e < TOL[prec]
+    print(f"   vs fmm_evaluate: phi {rel_l2(ph, ph0):.1e} E {rel_l2(E, E0):.1e}", flush=True)
+    assert within(G, Go, prec, "G vs oracle BH", TOL[prec])
     # phi and E of the gradient variant agree with the plain traversal's to
     # rounding: the two kernels are compiled apart and the FP32 M2P may round
     # in another order (observed 5e-9 MIXED, 3e-17 FP64)
     agree = 1e-14 if prec == fmm.FMM_PREC_FP64 else 1e-7
     assert rel_l2(ph, ph0) < agree and rel_l2(E, E0) < agree
-    assert rel_l2(ph, po) < TOL[prec] and rel_l2(E, Eo) < TOL[prec]
+    ok = within(ph, po, prec, "phi vs oracle BH", floor=PHI_FLOOR)
+    ok &= within(E, Eo, prec, "E vs oracle BH")
+    assert ok
     assert np.abs(G[:, 0] + G[:, 3] + G[:, 5]).max() <= 1e-5 * np.abs(G).max()
 
 
@@ -217,9 +217,7 @@ def test_bh_gradient_mixed_orders(orc, ctx, mask, p, prec):
     print(f"[bh grad mixed] mask={mask} p={p} precision={prec}", flush=True)
     (_, _, G), _ = _bh_grad(ctx, w, p, 0.5, 32, prec, "harmonic", fmm.FMM_GRAD)
     Go = orc.Tree(w.pos, 32).bh(w.order, w.moments, p, 0.5, want_grad=True)[2]
-    e = rel_l2(G, Go)
-    print(f"   rel L2 vs oracle: G {e:.2e}", flush=True)
-    assert e < TOL[prec]
+    assert within(G, Go, prec, "G vs oracle BH", TOL[prec])
 
 
 def test_bh_gradient_full_size_sampled(orc, ctx):
@@ -234,9 +232,7 @@ def test_bh_gradient_full_size_sampled(orc, ctx):
         t.run(w.order, to_dev(w.moments), w.p, prec, fmm.FMM_FIELD)
         _, _, G = t.evaluate_grad(fmm.FMM_GRAD)
         torch.cuda.synchronize()
-        e = rel_l2(G[s].cpu().numpy(), Go)
-        print(f"   precision={prec}: G rel L2 {e:.2e}", flush=True)
-        assert e < TOL[prec]
+        assert within(G[s].cpu().numpy(), Go, prec, f"precision={prec}: G vs oracle BH", TOL[prec])
     t.close()
 
 
@@ -249,4 +245,4 @@ def test_bh_gradient_degenerate(orc, ctx):
         if n == 1:
             assert np.all(G == 0.0)
         else:
-            assert rel_l2(G, Go) < TOL[fmm.FMM_PREC_FP64]
+            assert within(G, Go, "fp64", f"n={n} G vs oracle BH", TOL[fmm.FMM_PREC_FP64])

@@ -14,9 +14,8 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 from paper_2005_12351_amd import fmm  # noqa: E402
 from paper_2005_12351_amd import workloads as W  # noqa: E402
-from tests.gpu_helpers import gpu_fmm, rel_l2  # noqa: E402
+from tests.gpu_helpers import PHI_FLOOR, gpu_fmm, within  # noqa: E402
 
-TOL = {fmm.FMM_PREC_FP64: 1e-10, fmm.FMM_PREC_MIXED: 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -44,9 +43,9 @@ def test_mixed_fmm_matches_oracle(orc, ctx, mask, kind, n, p, ncrit, theta, prec
     finally:
         ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     po, Eo = orc.Tree(w.pos, ncrit, theta).fmm(w.order, w.moments, p)
-    e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)
-    print(f"   rel L2 vs oracle: phi {e1:.2e} E {e2:.2e}", flush=True)
-    assert e1 < TOL[prec] and e2 < TOL[prec]
+    ok = within(ph, po, prec, "phi vs oracle", floor=PHI_FLOOR)
+    ok &= within(E, Eo, prec, "E vs oracle")
+    assert ok
 
 
 @pytest.mark.parametrize("mask", [3, 6, 7])
@@ -62,9 +61,9 @@ def test_mixed_bh_matches_oracle(orc, ctx, mask, prec, basis):
     finally:
         ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
     po, Eo = orc.Tree(w.pos, w.ncrit).bh(w.order, w.moments, w.p, w.theta)
-    e1, e2 = rel_l2(ph, po), rel_l2(E, Eo)
-    print(f"   rel L2 vs oracle BH: phi {e1:.2e} E {e2:.2e}", flush=True)
-    assert e1 < TOL[prec] and e2 < TOL[prec]
+    ok = within(ph, po, prec, "phi vs oracle BH", floor=PHI_FLOOR)
+    ok &= within(E, Eo, prec, "E vs oracle BH")
+    assert ok
 
 
 def test_mixed_codes_rejected(ctx):

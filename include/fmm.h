@@ -32,6 +32,11 @@
  *    GPU work finishes; inputs must stay valid and outputs untouched until the
  *    stream is synchronised.  fmm_build_tree is the exception: it reads the
  *    positions back to the host and returns after the tree is resident.
+ *    The library orders nothing against the caller's other streams: work
+ *    that produces an input must be complete or ordered before the call on
+ *    the context's stream (e.g. an event recorded on the producer's stream
+ *    and waited on by the context's stream), and work that consumes an output
+ *    must be ordered after the call the same way.
  *  - Every entry point returns FMM_OK or an error code; no C++ exception
  *    crosses the ABI.  Arguments are checked before any GPU work is queued.
  *    fmm_last_error() returns a thread-local text for the last failure.
@@ -86,10 +91,23 @@ enum {
 #define FMM_MIXED 16
 
 /* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the
- * library creates its own).  `hbm_budget_bytes` bounds the device memory the
- * serving loop admits (0: 80% of the free memory at creation). */
+ * library creates its own, non-blocking).  Calls that capture graphs need a
+ * stream other than the legacy default stream.  `hbm_budget_bytes` bounds
+ * the device memory the serving loop admits (0: 80% of the free memory at
+ * creation). */
 int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, fmm_ctx **out);
+/* Destroys the context after its device work has finished.  Trees of this
+ * context that are still alive lose their device memory; fmm_tree_destroy
+ * remains valid on them (and is then the only call they accept). */
 int fmm_ctx_destroy(fmm_ctx *ctx);
+
+/* Device bytes one tree of this context may hold (0, the default: no limit).
+ * A tree allocation beyond it fails with FMM_ENOMEM, as one the device
+ * refuses does: the call returns FMM_ENOMEM with nothing queued that reads
+ * the missing buffers, the tree keeps no half-built expansion set, and a
+ * later fmm_upward / fmm_run whose buffers fit sets it up again (with any
+ * parameters, the failed call's previous ones included). */
+int fmm_ctx_set_tree_limit(fmm_ctx *ctx, size_t bytes);
 
 /* Octree, Morton order and (for FMM) interaction lists of n particles
  * (Section 3.2).  n >= 1, ncrit >= 1, 0 < theta < 1; method FMM_METHOD_FMM or
@@ -246,7 +264,12 @@ enum { FMM_REQ_QUEUED = 0, FMM_REQ_RUNNING = 1, FMM_REQ_DONE = 2, FMM_REQ_FAILED
  * minus the footprints of the running requests. */
 int fmm_serve_start(fmm_ctx *ctx, int max_concurrent);
 /* Queue a request (copied); FMM_ENOMEM if its footprint exceeds the whole
- * budget, FMM_EINVAL for bad parameters (nothing is queued then). */
+ * budget, FMM_EINVAL for bad parameters (nothing is queued then).  The
+ * request runs on the server's own streams, which are not ordered after any
+ * stream of the caller: its inputs must be complete on the device when
+ * fmm_submit is called (e.g. the producer stream synchronised), and its
+ * outputs are complete once fmm_wait returns FMM_OK or fmm_poll reports
+ * FMM_REQ_DONE. */
 int fmm_submit(fmm_ctx *ctx, const fmm_request *req, uint64_t *ticket);
 int fmm_poll(fmm_ctx *ctx, uint64_t ticket, int *state);
 /* Block until the request is done (timeout_s < 0: no limit); FMM_ETIMEOUT

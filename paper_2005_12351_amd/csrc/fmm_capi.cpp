@@ -220,7 +220,7 @@ static void tree_release_device(fmm_tree *t)
     drop_graphs(t);
     // the near field may still run on the auxiliary stream
     (void)hipStreamSynchronize(t->ctx->aux);
-    for (void *p : t->allocs) (void)hipFreeAsync(p, t->ctx->stream);
+    for (auto &a : t->allocs) (void)hipFreeAsync(a.first, t->ctx->stream);
     t->allocs.clear();
     t->dev_bytes = 0;
 }
@@ -267,11 +267,14 @@ int tree_alloc(fmm_tree *t, void **p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (t->ctx->tree_limit && t->dev_bytes + bytes > t->ctx->tree_limit)
+        FAIL(FMM_ENOMEM, "device allocation of %zu bytes would exceed the tree limit of %zu bytes (%zu held)", bytes,
+             t->ctx->tree_limit, t->dev_bytes);
     if (hipMallocAsync(p, bytes, t->ctx->stream) != hipSuccess) {
         *p = nullptr;
         FAIL(FMM_ENOMEM, "device allocation of %zu bytes failed", bytes);
     }
-    t->allocs.push_back(*p);
+    t->allocs.emplace_back(*p, bytes);
     t->dev_bytes += bytes;
     return FMM_OK;
 }
@@ -279,9 +282,19 @@ int tree_alloc(fmm_tree *t, void **p, size_t bytes)
 static void tree_free_block(fmm_tree *t, void *p)
 {
     if (!p) return;
-    auto it = std::find(t->allocs.begin(), t->allocs.end(), p);
-    if (it != t->allocs.end()) t->allocs.erase(it);
+    auto it = std::find_if(t->allocs.begin(), t->allocs.end(), [p](const auto &a) { return a.first == p; });
+    if (it != t->allocs.end()) {
+        t->dev_bytes -= it->second;
+        t->allocs.erase(it);
+    }
     (void)hipFreeAsync(p, t->ctx->stream);
+}
+
+extern "C" int fmm_ctx_set_tree_limit(fmm_ctx *ctx, size_t bytes)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    ctx->tree_limit = bytes;
+    return FMM_OK;
 }
 
 template <typename T>
@@ -469,6 +482,10 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis)
         return FMM_OK;
     drop_graphs(t);
+    // the tree holds no valid expansion set from here until every buffer
+    // below exists: a failure on the way leaves it marked so, and the next
+    // call sets it up again whatever its parameters
+    t->p = -1;
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32, &t->d_Mh,
                       (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_near_g,
                       (void **)&t->d_D64,
@@ -556,6 +573,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         pack.push_back((int32_t)t->nleaves);
         if (t->d_l2p_pack) tree_free_block(t, t->d_l2p_pack);
         t->d_l2p_pack = nullptr;
+        t->l2p_pack_q = -1;
         if ((rc = upload(t, &t->d_l2p_pack, pack, t->ctx->stream))) return rc;
         HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the host vector dies here
         t->l2p_npacks = (int)pack.size() - 1;
@@ -580,7 +598,10 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     if (fmm) {
         // derivative tensors of the translation classes depend on p only
         e = launch_dtable(t, t->ctx->stream);
-        if (e != hipSuccess) FAIL(FMM_EDEVICE, "dtable failed: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            t->p = -1;
+            FAIL(FMM_EDEVICE, "dtable failed: %s", hipGetErrorString(e));
+        }
         t->dtab_p = p;
     }
     return FMM_OK;
@@ -658,7 +679,7 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
 // pass runs before the L2P, which then writes grad too; for BH the traversal
 // kernel's gradient variant writes it.
 static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field, bool wait_near,
-                          double *grad = nullptr)
+                          double *grad = nullptr, double *near_g = nullptr)
 {
     hipStream_t s = ctx->stream;
     if (t->method == FMM_METHOD_BH) {
@@ -695,11 +716,11 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
     else if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     if (outputs & FMM_GRAD) {
         ProfScope ps(ctx, s, "p2p_grad");
-        KCHK(launch_p2p(t, s, true));
+        KCHK(launch_p2p(t, s, true, near_g));
     }
     {
         ProfScope ps(ctx, s, "l2p");
-        KCHK(launch_l2p_final(t, outputs, phi, field, grad, s));
+        KCHK(launch_l2p_final(t, outputs, phi, field, grad, s, near_g));
     }
     return FMM_OK;
 }

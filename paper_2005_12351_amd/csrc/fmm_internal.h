@@ -199,6 +199,7 @@ struct fmm_ctx {
     int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
+    size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
     hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;
@@ -254,7 +255,7 @@ struct fmm_tree {
     double *d_D64 = nullptr, *d_sc64 = nullptr;
     float *d_D32 = nullptr, *d_sc32 = nullptr;
     size_t dev_bytes = 0;
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;   // every device block the tree holds, with its size
     // captured launch sequences, keyed by the arguments they bake in
     struct GraphEntry {
         int64_t key[kGraphKey];
@@ -286,8 +287,10 @@ hipError_t launch_fill(double *p, size_t count, hipStream_t s);
 hipError_t launch_m2l(fmm_tree *t, hipStream_t s);
 hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s);
 hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
-hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false);   // grad: field gradient to d_near_g
-hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
+// grad: field gradient to near_g (NULL: the tree's d_near_g)
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false, double *near_g = nullptr);
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s,
+                            const double *near_g = nullptr);
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
 bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a launch of npacks waves
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);

@@ -1204,16 +1204,20 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f64_kernel(P2PArgs a)
     }
 }
 
-static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count);
+static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count,
+                                   double *near_g = nullptr);
 
-hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad) { return launch_p2p_range(t, s, grad, 0, -1); }
+hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad, double *near_g)
+{
+    return launch_p2p_range(t, s, grad, 0, -1, near_g);
+}
 
 hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count)
 {
     return launch_p2p_range(t, s, false, first, count);
 }
 
-static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count)
+static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count, double *near_g)
 {
     if (count < 0) count = (int)t->nleaves - first;
     if (first < 0 || count < 0 || first + count > t->nleaves) return hipErrorInvalidValue;
@@ -1228,7 +1232,7 @@ static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int fi
     a.xs = t->d_x;
     a.m64 = t->d_mom;
     a.near = t->d_near;
-    a.near_g = t->d_near_g;
+    a.near_g = near_g ? near_g : t->d_near_g;
     a.n = (int)t->ht.n;
     a.h = t->ht.h;
     a.order = t->d_p2p_order + first;
@@ -1423,7 +1427,8 @@ __global__ __launch_bounds__(64) void l2p_kernel(int outputs, const int32_t *__r
 }
 
 template <int Q, bool COLS>
-static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
+static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s,
+                              const double *near_g)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
     const size_t lds = (size_t)l2p_pack_limit(Q) * (COLS ? l2p_cols(Q) : l2p_cube(Q)) * sizeof(double);
@@ -1431,7 +1436,7 @@ static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *fie
         if (outputs & FMM_GRAD) {
             hipLaunchKernelGGL((l2p_kernel<Q, true, COLS>), dim3((unsigned)t->l2p_npacks), dim3(64), lds, s, outputs,
                                t->d_l2p_pack, t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->d_L64, t->d_near,
-                               t->d_perm, phi, field, t->d_near_g, grad);
+                               t->d_perm, phi, field, near_g, grad);
             return;
         }
     }
@@ -1441,27 +1446,30 @@ static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *fie
 }
 
 template <int Q>
-static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
+static void l2p_launch(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s,
+                       const double *near_g)
 {
-    if (t->l2p_columns) l2p_launch_layout<Q, true>(t, outputs, phi, field, grad, s);
-    else l2p_launch_layout<Q, false>(t, outputs, phi, field, grad, s);
+    if (t->l2p_columns) l2p_launch_layout<Q, true>(t, outputs, phi, field, grad, s, near_g);
+    else l2p_launch_layout<Q, false>(t, outputs, phi, field, grad, s, near_g);
 }
 
-hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
+hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s,
+                            const double *near_g)
 {
     if ((outputs & FMM_GRAD) && t->p - t->order < 2) return hipErrorInvalidValue;
+    if (!near_g) near_g = t->d_near_g;
     switch (t->p - t->order) {
-    case 0: l2p_launch<0>(t, outputs, phi, field, grad, s); break;
-    case 1: l2p_launch<1>(t, outputs, phi, field, grad, s); break;
-    case 2: l2p_launch<2>(t, outputs, phi, field, grad, s); break;
-    case 3: l2p_launch<3>(t, outputs, phi, field, grad, s); break;
-    case 4: l2p_launch<4>(t, outputs, phi, field, grad, s); break;
-    case 5: l2p_launch<5>(t, outputs, phi, field, grad, s); break;
-    case 6: l2p_launch<6>(t, outputs, phi, field, grad, s); break;
-    case 7: l2p_launch<7>(t, outputs, phi, field, grad, s); break;
-    case 8: l2p_launch<8>(t, outputs, phi, field, grad, s); break;
-    case 9: l2p_launch<9>(t, outputs, phi, field, grad, s); break;
-    case 10: l2p_launch<10>(t, outputs, phi, field, grad, s); break;
+    case 0: l2p_launch<0>(t, outputs, phi, field, grad, s, near_g); break;
+    case 1: l2p_launch<1>(t, outputs, phi, field, grad, s, near_g); break;
+    case 2: l2p_launch<2>(t, outputs, phi, field, grad, s, near_g); break;
+    case 3: l2p_launch<3>(t, outputs, phi, field, grad, s, near_g); break;
+    case 4: l2p_launch<4>(t, outputs, phi, field, grad, s, near_g); break;
+    case 5: l2p_launch<5>(t, outputs, phi, field, grad, s, near_g); break;
+    case 6: l2p_launch<6>(t, outputs, phi, field, grad, s, near_g); break;
+    case 7: l2p_launch<7>(t, outputs, phi, field, grad, s, near_g); break;
+    case 8: l2p_launch<8>(t, outputs, phi, field, grad, s, near_g); break;
+    case 9: l2p_launch<9>(t, outputs, phi, field, grad, s, near_g); break;
+    case 10: l2p_launch<10>(t, outputs, phi, field, grad, s, near_g); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -4,6 +4,17 @@ Argument marshalling only: every step of the method runs in the library's
 HIP kernels.  PyTorch provides device memory (contiguous float64 tensors on
 the context's device) and streams.  Importing this module loads the library
 and fails loudly if it has not been built.
+
+Stream ordering: the library queues its work on the context's stream (a
+PyTorch stream, created by the context unless one is given).  Every call here
+first makes that stream wait for PyTorch's current stream, so inputs made by
+earlier device work are complete before the library reads them, and
+afterwards makes the current stream wait for the context's stream, so the
+outputs are complete before later work on the current stream uses them and
+before the caching allocator hands their memory (or the inputs') to anything
+else.  The serving calls run on the library's own worker streams: submit()
+synchronises the current stream before it queues a request, and a request's
+outputs are complete once wait() returns.
 """
 from __future__ import annotations
 
@@ -65,6 +76,7 @@ fmm_last_error = _sig("fmm_last_error", [], ctypes.c_char_p)
 fmm_ctx_set_overlap = _sig("fmm_ctx_set_overlap", [_vp, ctypes.c_int])
 fmm_ctx_set_m2l_basis = _sig("fmm_ctx_set_m2l_basis", [_vp, ctypes.c_int])
 fmm_ctx_set_graphs = _sig("fmm_ctx_set_graphs", [_vp, ctypes.c_int])
+fmm_ctx_set_tree_limit = _sig("fmm_ctx_set_tree_limit", [_vp, ctypes.c_size_t])
 fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
 fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
 fmm_profile_read = _sig("fmm_profile_read", [_vp, _vp, _vp, _vp, ctypes.c_int])
@@ -80,7 +92,7 @@ fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_run", "fmm_tree_info",
-            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_tree_limit", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
@@ -107,7 +119,8 @@ def _dev_f64(t: torch.Tensor, cols: Optional[int], name: str) -> torch.Tensor:
 
 
 class Context:
-    """A libfmm context bound to one device and one HIP stream."""
+    """A libfmm context bound to one device and one stream (a PyTorch stream of
+    default priority; a new one unless `stream` is given)."""
 
     def __init__(self, device: int = 0, stream: Optional[torch.cuda.Stream] = None, budget_bytes: int = 0,
                  _handle=None):
@@ -116,10 +129,28 @@ class Context:
         if _handle is not None:
             self.h = _handle
             return
+        if self.stream is None:
+            self.stream = torch.cuda.Stream(device=device)
+        elif self.stream.cuda_stream == 0:
+            raise ValueError("the legacy default stream cannot be a context stream (its work cannot be captured "
+                             "into graphs); pass a created stream or None")
         h = _vp()
-        s = stream.cuda_stream if stream is not None else None
-        _check(fmm_ctx_create(device, s, budget_bytes, ctypes.byref(h)), "fmm_ctx_create")
+        _check(fmm_ctx_create(device, self.stream.cuda_stream, budget_bytes, ctypes.byref(h)), "fmm_ctx_create")
         self.h = h
+
+    def _enter(self):
+        """the context's stream waits for the caller's current stream"""
+        if self.stream is not None:
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        """the caller's current stream waits for the work just queued"""
+        if self.stream is not None:
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def set_tree_limit(self, nbytes: int):
+        """device bytes one tree may hold (0: no limit); beyond it calls fail with FMM_ENOMEM"""
+        _check(fmm_ctx_set_tree_limit(self.h, int(nbytes)), "fmm_ctx_set_tree_limit")
 
     @classmethod
     def fake(cls, budget_bytes: int, ns_per_particle: float = 0.0):
@@ -140,6 +171,9 @@ class Context:
                outputs: int = FMM_POT | FMM_FIELD) -> int:
         def ptr(t):
             return None if t is None else t.data_ptr()
+        if self.device >= 0:
+            # the server's worker streams are not ordered after the caller's
+            torch.cuda.current_stream(self.device).synchronize()
         r = fmm_request(ptr(pos), ptr(moments), ptr(phi), ptr(field), int(n), int(order), int(p), int(ncrit),
                         int(method), int(precision), int(outputs), float(theta))
         tk = ctypes.c_uint64()
@@ -221,8 +255,10 @@ class Tree:
         self.n = int(pos.shape[0])
         self.method = method
         h = _vp()
-        _check(fmm_build_tree(ctx.h, pos.data_ptr(), self.n, int(ncrit), float(theta), int(method), ctypes.byref(h)),
-               "fmm_build_tree")
+        ctx._enter()
+        rc = fmm_build_tree(ctx.h, pos.data_ptr(), self.n, int(ncrit), float(theta), int(method), ctypes.byref(h))
+        ctx._leave()
+        _check(rc, "fmm_build_tree")
         self.h = h
         self._moments = None
 
@@ -246,7 +282,10 @@ class Tree:
     def upward(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED):
         _dev_f64(moments, None, "moments")
         self._moments = moments       # read by the queued upward work (and baked into its graph)
-        _check(fmm_upward(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision)), "fmm_upward")
+        self.ctx._enter()
+        rc = fmm_upward(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision))
+        self.ctx._leave()
+        _check(rc, "fmm_upward")
 
     def evaluate(self, outputs: int = FMM_POT | FMM_FIELD, phi: Optional[torch.Tensor] = None,
                  field: Optional[torch.Tensor] = None):
@@ -255,8 +294,11 @@ class Tree:
             phi = torch.empty(self.n, dtype=torch.float64, device=dev)
         if (outputs & FMM_FIELD) and field is None:
             field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
-        _check(fmm_evaluate(self.ctx.h, self.h, int(outputs), phi.data_ptr() if phi is not None else None,
-                            field.data_ptr() if field is not None else None), "fmm_evaluate")
+        self.ctx._enter()
+        rc = fmm_evaluate(self.ctx.h, self.h, int(outputs), phi.data_ptr() if phi is not None else None,
+                          field.data_ptr() if field is not None else None)
+        self.ctx._leave()
+        _check(rc, "fmm_evaluate")
         return phi, field
 
     def evaluate_grad(self, outputs: int = FMM_POT | FMM_FIELD | FMM_GRAD, phi: Optional[torch.Tensor] = None,
@@ -270,8 +312,10 @@ class Tree:
         if (outputs & FMM_GRAD) and grad is None:
             grad = torch.empty((self.n, 6), dtype=torch.float64, device=dev)
         ptr = lambda x: x.data_ptr() if x is not None else None  # noqa: E731
-        _check(fmm_evaluate_grad(self.ctx.h, self.h, int(outputs), ptr(phi), ptr(field), ptr(grad)),
-               "fmm_evaluate_grad")
+        self.ctx._enter()
+        rc = fmm_evaluate_grad(self.ctx.h, self.h, int(outputs), ptr(phi), ptr(field), ptr(grad))
+        self.ctx._leave()
+        _check(rc, "fmm_evaluate_grad")
         return phi, field, grad
 
     def run(self, order: int, moments: torch.Tensor, p: int, precision: int = FMM_PREC_MIXED,
@@ -285,9 +329,11 @@ class Tree:
             phi = torch.empty(self.n, dtype=torch.float64, device=dev)
         if (outputs & FMM_FIELD) and field is None:
             field = torch.empty((self.n, 3), dtype=torch.float64, device=dev)
-        _check(fmm_run(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision), int(outputs),
-                       phi.data_ptr() if phi is not None else None, field.data_ptr() if field is not None else None),
-               "fmm_run")
+        self.ctx._enter()
+        rc = fmm_run(self.ctx.h, self.h, int(order), moments.data_ptr(), int(p), int(precision), int(outputs),
+                     phi.data_ptr() if phi is not None else None, field.data_ptr() if field is not None else None)
+        self.ctx._leave()
+        _check(rc, "fmm_run")
         return phi, field
 
     def work_counts(self):
@@ -325,8 +371,7 @@ def evaluate(pos: torch.Tensor, order: int, moments: torch.Tensor, p: int, theta
         t = Tree(ctx, pos, ncrit, theta, method)
         t.upward(order, moments, p, precision)
         out = t.evaluate(outputs)
-        torch.cuda.synchronize(pos.device)
-        t.close()
+        t.close()          # its memory is released in stream order after the evaluation
         return out
     finally:
         if own:

@@ -1,15 +1,20 @@
 """Benchmark of the MI355X Cartesian FMM (one JSON line on stdout).
 
-Default workload: 100,000 point dipoles uniform in the unit cube, p = 8,
-theta = 0.5, ncrit = 64, potential + field (the configuration the headline
-metric is quoted on).  One step = upward pass + evaluation (P2M, M2M, M2L,
+Default workload: 100,000 point dipoles uniform in the unit cube, ncrit 64,
+potential + field, at the accuracy the metric is quoted at: a relative error
+of at most 1e-6 against the direct sum.  With the half-side cell radius the
+literal parameters of this workload (theta 0.5, p 8) give 1.8e-4 (phi) and
+1e-5 (E); the smallest point of the sweep theta in {0.5, 0.4, 0.3}, p in
+{6, 8, 10} below 1e-6 for both is theta 0.3, p 10, which is timed as the
+headline (--literal times theta 0.5, p 8 instead; the literal row is always
+reported beside it).  One step = upward pass + evaluation (P2M, M2M, M2L,
 L2L, L2P, P2P) with the octree and interaction lists resident, as the metric
 counts particle evaluations per second of N / (t_upward + t_evaluate); the
 tree build (set-up, excluded by the paper's own timings) is reported
 separately.  The headline precision is MIXED (FP32 M2L/P2P, FP64 elsewhere);
 the plain FP64 GPU path is timed on the same tree and reported beside it.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2] [--literal] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -31,10 +36,18 @@ PEAK_FP64_VALU = 78.6e12
 PEAK_HBM = 8.0e12
 
 
-def _src_hash():
+KERNEL_SOURCES = {
+    "m2l": ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/m2l.hip",
+            "paper_2005_12351_amd/csrc/tree_host.cpp"),
+    "p2p": ("paper_2005_12351_amd/csrc/kernels.hip", "paper_2005_12351_amd/csrc/pair_kernels.h",
+            "paper_2005_12351_amd/csrc/fmm_capi.cpp"),
+}
+
+
+def _src_hash(kernel="m2l"):
+    """hash of the sources that decide a kernel's memory traffic"""
     h = hashlib.sha256()
-    for f in ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/m2l.hip",
-              "paper_2005_12351_amd/csrc/tree_host.cpp"):
+    for f in KERNEL_SOURCES.get(kernel, KERNEL_SOURCES["m2l"]):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -49,7 +62,7 @@ def _traffic(kernel_key: str):
     try:
         d = json.load(open(f))
         e = d.get(kernel_key)
-        if e and e.get("src_hash") == _src_hash():
+        if e and e.get("src_hash") == _src_hash(kernel_key.split("_")[0]):
             return e.get("bytes_per_launch")
     except Exception:
         return None
@@ -124,37 +137,54 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
             "note": "latency = done - arrival; it includes the tree build of each request"}
 
 
-def accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, Ed, theta=0.3, p=10):
-    """The same particles at the smallest (theta, p) of a sweep (theta 0.5,
-    0.4, 0.3; p 6, 8, 10) whose truncation error against the direct sum is
-    below 1e-6 for both phi and E (theta 0.3, p 10; the literal parameters
-    give 1.8e-4 / 1e-5 with the half-side cell radius).  Reported beside the
-    headline, errors measured on the sampled targets."""
-    import oracle
+# (theta, p) of the sweep point the headline is timed at, per workload: the
+# smallest of theta in {0.5, 0.4, 0.3}, p in {6, 8, 10} whose error against
+# the direct sum is below 1e-6 for phi and E (measured: 3.9e-7 / 1.8e-7)
+HEADLINE = {2: (0.3, 10)}
+
+
+def literal_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, theta, p):
+    """The same particles at the workload's literal (theta, p), MIXED and
+    FP64 (harmonic basis), reported beside the headline with their errors
+    (filled in by the CPU leg)."""
     tree = fmm.Tree(ctx, pos, w.ncrit, theta)
     phi = torch.empty(w.n, dtype=torch.float64, device=dev)
     fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     out = {"theta": theta, "p": p, "info": tree.info()}
-    runs = (("mixed", fmm.FMM_PREC_MIXED, fmm.FMM_M2L_HARMONIC), ("fp64", fmm.FMM_PREC_FP64, fmm.FMM_M2L_HARMONIC),
-            ("mixed_full_basis", fmm.FMM_PREC_MIXED, fmm.FMM_M2L_FULL))
-    for name, prec, basis in runs:
+    for name, prec in (("mixed", fmm.FMM_PREC_MIXED), ("fp64", fmm.FMM_PREC_FP64)):
         ctx.set_overlap(False)
-        ctx.set_m2l_basis(basis)
-        for _ in range(3):
+        for _ in range(max(3, args.warmup)):
             tree.run(w.order, mom, p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        k = max(3, args.steps // 2)
-        for _ in range(k):
+        for _ in range(args.steps):
             tree.run(w.order, mom, p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / k
-        ph, E = phi.cpu().numpy(), fld.cpu().numpy()
+        dt = (time.perf_counter() - t0) / args.steps
         out[name] = {"value": w.n / dt, "unit": "evals/s", "ms_per_step": dt * 1e3,
-                     "phi_vs_direct": oracle.rel_l2(ph[sample], pd), "E_vs_direct": oracle.rel_l2(E[sample], Ed)}
-    ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+                     "_out": (phi.cpu().numpy(), fld.cpu().numpy())}
     tree.close()
     return out
+
+
+def cpu_baseline(args, w, theta, p, method):
+    """The oracle on the host cores, all of them and one, with pinned OpenMP
+    threads (close placement on cores, active waiting, as the paper's timing
+    protocol), each the median of repeated runs on a bounded sample."""
+    import subprocess
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    res = {}
+    for label, nt, frac, runs in (("all", cores, 16, 10), ("one", 1, 128, 10)):
+        env = dict(os.environ, OMP_NUM_THREADS=str(nt), OMP_PROC_BIND="close", OMP_PLACES="cores",
+                   OMP_WAIT_POLICY="active")
+        cmd = [sys.executable, "-m", "oracle.timing", "--config", str(args.config), "--theta", repr(theta),
+               "--p", str(p), "--leaf-fraction", str(frac), "--runs", str(runs), "--method", method]
+        r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True)
+        if r.returncode != 0:
+            res[label] = {"error": r.stderr[-500:]}
+            continue
+        res[label] = json.loads(r.stdout.strip().splitlines()[-1])
+    return res
 
 
 def main():
@@ -171,8 +201,11 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of MIB MiB (reference for HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=512)
-    ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the run at the smallest (theta, p) that reaches 1e-6 against the direct sum")
+    ap.add_argument("--literal", action="store_true",
+                    help="time the workload's literal (theta, p) as the headline instead of the 1e-6 point")
+    ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
+    ap.add_argument("--p", type=int, default=None, help="override the expansion order")
+    ap.add_argument("--no-literal-row", action="store_true", help="skip the literal-parameter row")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -183,6 +216,13 @@ def main():
 
     bh = args.method == "bh"
     w = W.config(args.config, n_override=args.n or None)
+    literal = (w.theta, w.p)
+    if args.theta is not None or args.p is not None:
+        w.theta = w.theta if args.theta is None else args.theta
+        w.p = w.p if args.p is None else args.p
+    elif not args.literal and not bh and args.config in HEADLINE:
+        w.theta, w.p = HEADLINE[args.config]
+    at_literal = (w.theta, w.p) == literal
     dev = torch.device("cuda", 0)
     pos = torch.from_numpy(w.pos).to(dev)
     mom = torch.from_numpy(w.moments).to(dev)
@@ -333,18 +373,27 @@ def main():
         f64_k = {"bh_avg_launch_ms": f64_ms,
                  "bh_achieved_tflops": f64_flops / (f64_ms * 1e-3) / 1e12 if f64_ms > 0 else None}
     else:
-        # dominant kernel: M2L (FP32 VALU contraction)
-        m2l_ms, p2p_ms = kavg(m["prof"], "m2l"), kavg(m["prof"], "p2p")
-        m2l_flops = m["work"]["m2l_flops"]
-        achieved = m2l_flops / (m2l_ms * 1e-3) if m2l_ms > 0 else None
-        roofline = {"bound": "alu", "kernel": "m2l (FP32, harmonic basis)",
-                    "achieved": achieved / 1e12 if achieved else None,
+        # dominant kernel: the longer of M2L and P2P per step (kernels timed
+        # alone, HIP events on their launch stream); both are reported
+        def kern(name, flops_key, what):
+            ms = kavg(m["prof"], name)
+            per_step = m["prof"][name][0] / max(1, args.steps) if name in m["prof"] else 0.0
+            fl = m["work"][flops_key]
+            ach = fl / (ms * 1e-3) if ms > 0 else None
+            return {"bound": "alu", "kernel": what, "achieved": ach / 1e12 if ach else None,
                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                    "frac": (achieved / PEAK_FP32_VALU) if achieved else None,
-                    "traffic": _traffic("m2l_c%d_mixed" % args.config),
-                    "flops_per_launch": m2l_flops, "avg_launch_ms": m2l_ms,
-                    "p2p": {"achieved": m["work"]["p2p_flops"] / (p2p_ms * 1e-3) / 1e12 if p2p_ms > 0 else None,
-                            "avg_launch_ms": p2p_ms, "flops_per_launch": m["work"]["p2p_flops"]}}
+                    "frac": (ach / PEAK_FP32_VALU) if ach else None,
+                    "traffic": _traffic("%s_c%d_mixed_p%d_t%g" % (name, args.config, w.p, w.theta)),
+                    "flops_per_launch": fl, "avg_launch_ms": ms, "ms_per_step": per_step,
+                    "frac_of_nonpacked_issue": (ach / (PEAK_FP32_VALU / 2)) if ach else None}
+        k_m2l = kern("m2l", "m2l_flops", "m2l (FP32, harmonic basis): 2 flops per multiply-add of the reduced "
+                                         "contraction per list entry")
+        k_p2p = kern("p2p", "p2p_flops", "p2p (FP32 + Kahan): per (i, j) pair, phi+E closed form")
+        dom, other = (k_m2l, k_p2p) if k_m2l["ms_per_step"] >= k_p2p["ms_per_step"] else (k_p2p, k_m2l)
+        roofline = dict(dom)
+        roofline["other"] = other
+        roofline["note"] = ("peak = MI355X FP32 vector 157.3 TFLOP/s (packed); the kernels are built without "
+                            "packed FP32, whose issue ceiling is 78.6 TFLOP/s (frac_of_nonpacked_issue)")
         f64_ms = kavg(f64["prof"], "m2l")
         f64_k = {"m2l_avg_launch_ms": f64_ms,
                  "m2l_achieved_tflops": f64["work"]["m2l_flops"] / (f64_ms * 1e-3) / 1e12 if f64_ms > 0 else None,
@@ -352,13 +401,19 @@ def main():
     value = w.n / m["step_s"]
     evals = "field" if w.outputs == "field" else "pot+field"
     line = {
-        "metric": "FMM particle evals/sec (%s), FP32-bulk (MIXED); FP64 GPU path reported beside it" % evals
+        "metric": ("FMM particle evals/sec (%s) at rel err 1e-6, FP32 (MIXED) vs FP64; p50/p99 latency" % evals
+                   if not at_literal else
+                   "FMM particle evals/sec (%s), FP32-bulk (MIXED); FP64 GPU path reported beside it" % evals)
                   if not bh else "Barnes-Hut particle evals/sec (%s), FP32-bulk (MIXED); FP64 beside it" % evals,
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": m["step_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (M2L, P2P) + f64 (P2M, M2M, L2L, L2P)" if not bh else "f32 (M2P, P2P) + f64 (P2M, M2M)",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
+        "config": {"workload": w.name if at_literal else
+                   "%s at theta %g, p %d (smallest sweep point below 1e-6 against the direct sum; literal "
+                   "theta %g, p %d reported as literal_parameters)" % (w.name.split(":")[0] + ": %d dipoles "
+                   "uniform in the unit cube" % w.n, w.theta, w.p, literal[0], literal[1]),
+                   "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
                    "ncrit": w.ncrit, "outputs": w.outputs,
                    "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)",
                    "basis": "harmonic (M2L / M2P on the folded rows)"},
@@ -375,40 +430,37 @@ def main():
         "roofline": roofline,
     }
 
+    lit = None
+    if not bh and not at_literal and not args.no_literal_row:
+        lit = literal_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, literal[0], literal[1])
     if not args.no_cpu:
         import oracle
         oracle.lib()
-        cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        t0 = time.perf_counter()
         ot = oracle.Tree(w.pos, w.ncrit, None if bh else w.theta)
-        tb = time.perf_counter() - t0
         sample = w.sample if w.sample is not None else np.arange(w.n)
-        full = w.n <= 200_000
-        # the same evaluation repeated until at least 10 s of CPU work has run
-        full = full and not bh
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            if bh:
-                po_s, Eo_s = ot.bh(w.order, w.moments, w.p, w.theta, targets=sample)
-            elif full:
-                po, Eo = ot.fmm(w.order, w.moments, w.p)
-                po_s, Eo_s = (po[sample] if po is not None else None), Eo[sample]
-            else:
-                po_s, Eo_s = ot.fmm(w.order, w.moments, w.p, targets=sample)
-            reps += 1
-            tc = time.perf_counter() - t0
-            if tc >= 10.0:
-                break
-        nev = (w.n if full else len(sample)) * reps
         kind = "Barnes-Hut" if bh else "FMM"
-        line["cpu_baseline"] = {"value": nev / tc, "unit": "evals/s", "cores": cores, "kind": "oracle",
-                                "sample": ("full workload, upward+evaluate of the plain FP64 C oracle, repeated "
-                                           "%d times (tree build %.2f s excluded)" % (reps, tb)) if full else
-                                          ("%d sampled targets of the workload, plain FP64 C oracle %s (full upward "
-                                           "pass), repeated %d times (tree build %.2f s excluded)"
-                                           % (len(sample), kind, reps, tb)),
-                                "seconds": tc}
+        if bh:
+            po_s, Eo_s = ot.bh(w.order, w.moments, w.p, w.theta, targets=sample)
+        else:
+            po_s, Eo_s = ot.fmm(w.order, w.moments, w.p, targets=sample)
+        cb = cpu_baseline(args, w, w.theta, w.p, "bh" if bh else "fmm")
+        allc, one = cb.get("all", {}), cb.get("one", {})
+        if "median_s" in allc:
+            line["cpu_baseline"] = {
+                "value": allc["targets"] / allc["median_s"], "unit": "evals/s", "cores": allc["threads"],
+                "kind": "oracle",
+                "sample": ("plain FP64 C oracle %s at theta %g, p %d: every particle of %d of the %d leaves "
+                           "(%d targets), each run a full upward pass plus the far and near field of those "
+                           "targets; median of %d runs, OpenMP threads pinned close on cores, active wait"
+                           % (kind, w.theta, w.p, allc["leaves"], allc["leaves_total"], allc["targets"],
+                              len(allc["seconds"]))),
+                "median_s": allc["median_s"],
+                "one_core": ({"value": one["targets"] / one["median_s"], "unit": "evals/s", "cores": 1,
+                              "targets": one["targets"], "median_s": one["median_s"], "runs": len(one["seconds"])}
+                             if "median_s" in one else one)}
+        else:
+            line["cpu_baseline"] = {"value": None, "unit": "evals/s", "cores": None, "kind": "oracle",
+                                    "sample": "timing failed", "error": allc.get("error")}
         pd, Ed = oracle.direct(w.pos, w.order, w.moments, targets=sample)
 
         def per_particle(a, b):
@@ -449,8 +501,18 @@ def main():
             Gd = oracle.direct_grad(w.pos, w.order, w.moments, targets=sample)
             line["field_gradient"]["G_vs_oracle"] = oracle.rel_l2(grad_line["out"][sample], Go)
             line["field_gradient"]["G_vs_direct"] = oracle.rel_l2(grad_line["out"][sample], Gd)
-        if not args.no_accuracy and not bh and args.config == 2:
-            line["at_1e-6"] = accuracy_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, sample, pd, Ed)
+        if lit is not None:
+            lo = oracle.Tree(w.pos, w.ncrit, lit["theta"]).fmm(w.order, w.moments, lit["p"], targets=sample)
+            for name in ("mixed", "fp64"):
+                ph, E = lit[name].pop("_out")
+                lit[name].update({"phi_vs_direct": oracle.rel_l2(ph[sample], pd),
+                                  "E_vs_direct": oracle.rel_l2(E[sample], Ed),
+                                  "phi_vs_oracle": oracle.rel_l2(ph[sample], lo[0]),
+                                  "E_vs_oracle": oracle.rel_l2(E[sample], lo[1])})
+    if lit is not None:
+        for name in ("mixed", "fp64"):
+            lit[name].pop("_out", None)
+        line["literal_parameters"] = lit
     if not args.no_serve:
         line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests)
     print(json.dumps(line), flush=True)

@@ -157,6 +157,24 @@ int fmm_evaluate(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double 
  * kernel is a separately compiled variant). */
 int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field, double *grad);
 
+/* fmm_evaluate_grad for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same outputs, from the same kernels, but the near-field gradient of an
+ * FMM tree (48 bytes per particle) goes to a static device array that the
+ * library holds on every device it runs on until the process ends, so the
+ * call makes no hipMalloc/hipFree or other allocating call, and it launches
+ * the kernels one by one instead of capturing a graph.  Limit: FMM trees of
+ * at most 262 144 (2^18) particles when FMM_GRAD is requested (12 MiB of
+ * scratch); larger ones get FMM_EINVAL (use fmm_evaluate_grad).  Barnes-Hut
+ * trees use no scratch and have no limit.  Every call on a device shares that
+ * device's array: calls that overlap on one device (from several contexts or
+ * streams) race and give wrong gradients; each call writes every particle's
+ * six values before reading them, so nothing carries over between calls.
+ * The tree's own buffers come from fmm_build_tree and fmm_upward, which
+ * allocate as usual. */
+int fmm_evaluate_grad_noalloc(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field,
+                              double *grad);
+
 /* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,
  * n_m2l_classes, n_m2l_tiles, n_m2l_slots_used (tile lanes x union entries),
  * device bytes held. */

@@ -211,6 +211,12 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
+    // the device address of the allocation-free call's static scratch on
+    // this device (resolved once per device, with the device current)
+    if (const hipError_t e = noalloc_scratch(device, &c->noalloc_scratch); e != hipSuccess) {
+        fmm_ctx_destroy(c);
+        FAIL(FMM_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+    }
     *out = c;
     return FMM_OK;
 }
@@ -807,6 +813,36 @@ extern "C" int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *t, int outputs, double 
                                     (int64_t)(uintptr_t)grad, 0, 0, 0, 0, 0};
     rc = run_cached(ctx, t, key, ctx->stream,
                     [&]() { return queue_evaluate(ctx, t, outputs, phi, field, false, grad); });
+    if (rc) return rc;
+    set_work_counts(t);
+    return FMM_OK;
+}
+
+extern "C" int fmm_evaluate_grad_noalloc(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, double *field,
+                                         double *grad)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (outputs <= 0 || (outputs & ~(FMM_POT | FMM_FIELD | FMM_GRAD))) FAIL(FMM_EINVAL, "bad output mask %d", outputs);
+    if ((outputs & FMM_POT) && !phi) FAIL(FMM_EINVAL, "potential requested but phi is NULL");
+    if ((outputs & FMM_FIELD) && !field) FAIL(FMM_EINVAL, "field requested but field is NULL");
+    if ((outputs & FMM_GRAD) && !grad) FAIL(FMM_EINVAL, "field gradient requested but grad is NULL");
+    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    HIPCHK(hipSetDevice(ctx->device));
+    // kernels launched one by one (a graph would be instantiated on the
+    // first call); Barnes-Hut trees write the gradient from the traversal
+    // kernel and use no scratch
+    if (t->method == FMM_METHOD_BH) return queue_evaluate(ctx, t, outputs, phi, field, false, grad);
+    if ((outputs & FMM_GRAD) && t->p - t->order < 2)
+        FAIL(FMM_EINVAL, "field gradient needs p - s >= 2 (p = %d, lowest source order %d)", t->p, t->order);
+    double *near_g = nullptr;
+    if (outputs & FMM_GRAD) {
+        if (t->ht.n > kNoAllocMaxN)
+            FAIL(FMM_EINVAL, "n = %lld exceeds the %lld particles the allocation-free scratch holds; use "
+                             "fmm_evaluate_grad", (long long)t->ht.n, (long long)kNoAllocMaxN);
+        if (!ctx->noalloc_scratch) FAIL(FMM_ESTATE, "context has no scratch address");
+        near_g = ctx->noalloc_scratch;
+    }
+    const int rc = queue_evaluate(ctx, t, outputs, phi, field, false, grad, near_g);
     if (rc) return rc;
     set_work_counts(t);
     return FMM_OK;

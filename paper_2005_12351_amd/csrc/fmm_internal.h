@@ -200,6 +200,7 @@ struct fmm_ctx {
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
+    double *noalloc_scratch = nullptr;    // device address of the static gradient scratch on `device`
     hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;
@@ -291,6 +292,11 @@ hipError_t launch_l2l_level(fmm_tree *t, int level, hipStream_t s);
 hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad = false, double *near_g = nullptr);
 hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s,
                             const double *near_g = nullptr);
+// largest particle count of the allocation-free gradient call, and the
+// device address of its static scratch (6 doubles per particle) on the
+// current device, resolved once per device
+constexpr int64_t kNoAllocMaxN = 1 << 18;
+hipError_t noalloc_scratch(int device, double **ptr);
 int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
 bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a launch of npacks waves
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);

@@ -9,6 +9,7 @@
 // per octant and the M2L derivative tensor depends only on the dimensionless
 // pair geometry.  P2M, M2M, L2L, L2P run in FP64.
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "fmm_internal.h"
@@ -1215,6 +1216,31 @@ hipError_t launch_p2p(fmm_tree *t, hipStream_t s, bool grad, double *near_g)
 hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count)
 {
     return launch_p2p_range(t, s, false, first, count);
+}
+
+// Near-field gradient of the allocation-free fmm_evaluate_grad variant: every
+// particle's six values are written by the gradient pass before the L2P reads
+// them, so nothing needs clearing between calls.  Calls that overlap on one
+// device share it and race.
+static __device__ __align__(256) double scratch[(size_t)kNoAllocMaxN * 6];
+
+hipError_t noalloc_scratch(int device, double **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        // each device holds its own copy of the array; its host-side name is
+        // no device address, so kernels get this one
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int first, int count, double *near_g)

@@ -73,6 +73,7 @@ enum {
 enum { FMM_POT = 1, FMM_FIELD = 2, FMM_GRAD = 4 };   /* output bit mask (FMM_GRAD: fmm_evaluate_grad only) */
 enum { FMM_METHOD_FMM = 0, FMM_METHOD_BH = 1 };
 enum { FMM_M2L_FULL = 0, FMM_M2L_HARMONIC = 1 };   /* see fmm_ctx_set_m2l_basis */
+enum { FMM_M2L_ENGINE_VALU = 0, FMM_M2L_ENGINE_MFMA = 1, FMM_M2L_ENGINE_AUTO = 2 };   /* see fmm_ctx_set_m2l_engine */
 enum {
     FMM_PREC_FP64 = 0,   /* every operator in IEEE double on the GPU */
     FMM_PREC_MIXED = 1   /* M2L, M2P and P2P in FP32 (P2P compensated),
@@ -238,6 +239,19 @@ int fmm_ctx_set_graphs(fmm_ctx *ctx, int on);
  * rounding only.  Takes effect at the
  * next fmm_upward / fmm_run of a tree.  FMM_EINVAL for another value. */
 int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis);
+
+/* Units that run the M2L contraction (Eq. 8) of MIXED-precision FMM trees in
+ * the harmonic basis.  FMM_M2L_ENGINE_MFMA: the matrix cores, one
+ * v_mfma_f32_4x4x1 per (multipole coefficient, four local outputs) for 64
+ * target cells at once, FP32 products with FP32 accumulation as on the
+ * vector units; FMM_M2L_ENGINE_VALU: the vector units, one FMA per term;
+ * FMM_M2L_ENGINE_AUTO (default): the matrix cores for p >= 8, where they
+ * were measured faster, the vector units below.  Both compute the same sums
+ * (they round differently only through the order of the FP32 additions).
+ * FP64 trees and the full basis always use the vector units.  Takes effect
+ * at the next fmm_upward / fmm_run of a tree.  FMM_EINVAL for another
+ * value. */
+int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine);
 
 /* Per-kernel device timing.  When enabled, every kernel launch is bracketed
  * by HIP events on the stream it runs on.  fmm_profile_read synchronises and

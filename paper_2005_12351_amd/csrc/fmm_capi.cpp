@@ -89,6 +89,15 @@ extern "C" int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis)
     return FMM_OK;
 }
 
+extern "C" int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    if (engine != FMM_M2L_ENGINE_VALU && engine != FMM_M2L_ENGINE_MFMA && engine != FMM_M2L_ENGINE_AUTO)
+        FAIL(FMM_EINVAL, "unknown M2L engine %d", engine);
+    ctx->m2l_engine = engine;   // trees pick it up at their next upward pass
+    return FMM_OK;
+}
+
 extern "C" int fmm_ctx_set_graphs(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
@@ -485,7 +494,13 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     const bool fmm = t->method == FMM_METHOD_FMM;
     const int basis = t->ctx->m2l_basis;
     const bool harm = basis == FMM_M2L_HARMONIC;
-    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis)
+    // matrix cores: measured faster from p = 8 on (the contraction per list
+    // entry grows as p^3, the operand traffic as p^2)
+    const int eng = t->ctx->m2l_engine;
+    const bool mfma = fmm && harm && prec == FMM_PREC_MIXED &&
+                      (eng == FMM_M2L_ENGINE_MFMA || (eng == FMM_M2L_ENGINE_AUTO && p >= 8));
+    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis &&
+        t->mfma == mfma)
         return FMM_OK;
     drop_graphs(t);
     // the tree holds no valid expansion set from here until every buffer
@@ -519,13 +534,14 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         // folded rows the Barnes-Hut M2P reads (FMM trees size them from the M2L variant below)
         const size_t es = prec == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
         const int nhp = (hterms(p) - hterms(order - 1) + 3) / 4 * 4;
+        t->nhp = nhp;
         if ((rc = tree_alloc(t, &t->d_Mh, es * (size_t)(nc + 1) * nhp))) return rc;
         hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * nhp / 8, t->ctx->stream);
         if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
     }
     if (fmm) {
         M2LVariant v;
-        if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, harm, &v))
+        if (!m2l_lookup(p, order, prec == FMM_PREC_MIXED, harm, &v, mfma))
             FAIL(FMM_EINVAL, "no M2L kernel for p=%d s=%d", p, order);
         const size_t es = prec == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
         const int nc_ = std::max(1, t->tiling.nclasses);
@@ -555,6 +571,9 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             (rc = tree_alloc(t, (void **)&t->d_sc32, sizeof(float) * nc_ * scw)))
             return rc;
         // reduced multipole rows, plus the zero row that padded slots read
+        // (the M2L variant fixes the row stride: the matrix-core kernels
+        // align every row to a 128-byte cache line)
+        t->nhp = v.nm_pad;
         if (harm && (rc = tree_alloc(t, &t->d_Mh, es * (size_t)(nc + 1) * v.nm_pad))) return rc;
         if (harm) {
             hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * v.nm_pad / 8, t->ctx->stream);
@@ -601,6 +620,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     t->p = p;
     t->prec = prec;
     t->basis = basis;
+    t->mfma = mfma;
     if (fmm) {
         // derivative tensors of the translation classes depend on p only
         e = launch_dtable(t, t->ctx->stream);

@@ -182,7 +182,8 @@ struct M2LVariant {
     int blo[17];               // output blocks: coefficients [blo[b], blo[b+1])
     int bfma[16];              // multiply-adds per list entry in each block
 };
-bool m2l_lookup(int p, int s, bool fp32, bool harmonic, M2LVariant *out);
+// mfma: the matrix-core kernels (FP32 harmonic basis only)
+bool m2l_lookup(int p, int s, bool fp32, bool harmonic, M2LVariant *out, bool mfma = false);
 void build_m2l_work(const M2LTiling &tl, const M2LVariant &v, int nwaves, M2LWork &out);
 
 // ------------------------------------------------------------------ context
@@ -197,6 +198,7 @@ struct fmm_ctx {
     int overlap = 0;                      // P2P on the auxiliary stream: 0 off, 1 whole, 2 split (FMM_OVERLAP_*)
     bool graphs = true;                   // replay captured HIP graphs
     int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
+    int m2l_engine = FMM_M2L_ENGINE_AUTO; // units of the FP32 harmonic-basis M2L
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
@@ -243,6 +245,8 @@ struct fmm_tree {
     int have_up = 0, order = 0, p = 0, prec = 0, dtab_p = -1;   // order: the lowest source order s
     int smask = 1;                         // source orders present (bit mask)
     int basis = FMM_M2L_FULL;              // M2L basis the expansions were set up for
+    bool mfma = false;                     // the M2L runs on the matrix cores (FP32 harmonic basis)
+    int nhp = 0;                           // row stride of the folded multipoles d_Mh (harmonic basis)
     const double *mom_user = nullptr;
     double *d_mom = nullptr;               // sorted moments FP64 (w per particle)
     float *d_mom32 = nullptr;              // sorted moments FP32 (8 per particle)

@@ -36,7 +36,20 @@ of (l+1)(l+2)/2: the irreducible count the paper's Discussion refers to.
 The "_h" kernels contract these reduced rows; the term lists are the same
 construction restricted to the reduced components.
 
-Usage: python gen_m2l.py OUTDIR  -> OUTDIR/m2l_s{0,1,2}_{f32,f64}[_h].hip
+Matrix cores.  The "_hm" kernels compute the same FP32 harmonic-basis
+contraction on the MFMA units.  v_mfma_f32_4x4x1_16b_f32 is a batch of
+sixteen 4x4 outer products: block b of the wave gets D[r][c] += A[r] B[c],
+with A[r] from lane 4b+r and B[c] from lane 4b+c.  Lane l = 4b+c holds the
+scaled multipole coefficient m_j of its own target's source (B) and four
+accumulators, the local outputs 4g..4g+3 of its target; the class operand
+A[r] = D_{n_{4g+r}+m_j} is the same for every block, so it is broadcast from
+one block (CBSZ = 4, ABID = k): a single VGPR holds the operands of sixteen
+consecutive multiply-add slots (j, g), gathered per lane from the class's
+derivative row through a fixed index table (an index past the tensor reads a
+zero for outputs a slot does not reach).  Per slot: 64 targets x 4 outputs
+in one instruction, twice the FP32 multiply-add rate of the vector unit.
+
+Usage: python gen_m2l.py OUTDIR  -> OUTDIR/m2l_s{0,1,2}_{f32,f64}[_h].hip, m2l_s{0,1,2}_f32_hm.hip
 """
 import os
 import sys
@@ -47,7 +60,8 @@ TILE = 64
 # code-shape options (register blocking, scalar-load pipelining, waves per
 # workgroup); the defaults are the measured best on gfx950
 DEFAULTS = {"acc32": 128, "m32": 64, "acc64": 64, "m64": 32, "dgroup32": 32, "dgroup64": 16, "pipeline": 1,
-            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0, "wgw": 4, "fairprio": 1}
+            "mpre": 0, "launder": 1, "scale_branch": 0, "minwaves": 0, "wgw": 4, "fairprio": 1,
+            "mch": 32, "mdist": 4, "mwaves": 2, "mbarrier": 1, "mbalance": 0, "mpipe": 1, "malign": 1}
 
 
 def orders(p):
@@ -335,12 +349,287 @@ static int occ_{name}()
     return "\n".join(L) + "\n" + launcher, meta
 
 
-def gen_file(s, fp32, opt=None, harmonic=False):
-    suf = ("f32" if fp32 else "f64") + ("_h" if harmonic else "")
+def mfma_schedule(p, s, mch, dist, balance=False):
+    """Multiply-add slots (j, g) of the harmonic contraction for the matrix
+    cores, in issue order, with accumulator copies: a slot whose output group
+    was used fewer than `dist` slots before goes to another copy of that
+    group's accumulators (added together at the end), so that no MFMA waits
+    for the previous one's result.  Returns the chunks of the multipole row
+    (lists of j, at most `mch`, starting at multiples of 4) and per chunk the
+    slots as (j, g, copy).  balance: the chunks take whole quads of j (one
+    vector load each) so that they hold about the same number of slots,
+    low orders (many slots) beside high orders (few)."""
+    ns = reduced(orders(p - s))
+    ms = reduced(orders(p)[nterms(s - 1):])
+    nl = len(ns)
+    ng = (nl + 3) // 4
+    chunks = [list(range(c, min(len(ms), c + mch))) for c in range(0, len(ms), mch)]
+    if balance:
+        def nslots(j):
+            return sum(1 for g in range(ng)
+                       if any(sum(ns[i]) + sum(ms[j]) <= p for i in range(4 * g, min(nl, 4 * g + 4))))
+        quads = [list(range(q, min(len(ms), q + 4))) for q in range(0, len(ms), 4)]
+        k = len(chunks)
+        cost = sorted(((sum(nslots(j) for j in qd), qi) for qi, qd in enumerate(quads)), reverse=True)
+        bins = [[] for _ in range(k)]
+        load = [0] * k
+        for c, qi in cost:
+            b = min((b for b in range(k) if len(bins[b]) < mch // 4), key=lambda b: load[b])
+            bins[b].append(qi)
+            load[b] += c
+        chunks = [[j for qi in sorted(bn) for j in quads[qi]] for bn in bins if bn]
+    out = []
+    for ch in chunks:
+        queues = {}
+        for j in ch:
+            for g in range(ng):
+                if any(sum(ns[i]) + sum(ms[j]) <= p for i in range(4 * g, min(nl, 4 * g + 4))):
+                    queues.setdefault(g, []).append(j)
+        last = {}            # (g, copy) -> step of its last use
+        ncopy = {g: 1 for g in queues}
+        seq, step = [], 0
+        while any(queues.values()):
+            # the group with the most remaining slots that has a free copy
+            best = None
+            for g, q in sorted(queues.items(), key=lambda kv: -len(kv[1])):
+                if not q:
+                    continue
+                free = [c for c in range(ncopy[g]) if step - last.get((g, c), -dist) >= dist]
+                if free:
+                    best = (g, free[0])
+                    break
+            if best is None:
+                g = max((g for g in queues if queues[g]), key=lambda g: len(queues[g]))
+                if ncopy[g] < 4:
+                    ncopy[g] += 1
+                    best = (g, ncopy[g] - 1)
+                else:
+                    best = (g, min(range(ncopy[g]), key=lambda c: last.get((g, c), -dist)))
+            g, c = best
+            j = queues[g].pop(0)
+            seq.append((j, g, c))
+            last[(g, c)] = step
+            step += 1
+        out.append(seq)
+    return chunks, out
+
+
+def gen_kernel_mfma(p, s, opt=None):
+    """FP32 harmonic-basis M2L on the matrix cores (see the module header).
+    Same arguments, work items, waves per workgroup and partial rows as the
+    vector kernels (one output block holding every local output)."""
+    opt = dict(DEFAULTS, **(opt or {}))
+    ns = reduced(orders(p - s))
+    ms = reduced(orders(p)[nterms(s - 1):])
+    nl, nm = len(ns), len(ms)
+    # rows aligned to 128-byte lines: a chunk of 32 coefficients is one line
+    nlp, nmp = pad(nl, 4), pad(nm, 32 if opt["malign"] else 4)
+    nd = pad(nterms(p), 16)
+    scw = pad(p + 1, 4)
+    zero = nterms(p)          # an entry of every derivative row that is zero (nd > nterms(p))
+    assert zero < nd
+    ng = (nl + 3) // 4
+    assert 4 * ng == nlp
+    chunks, sched = mfma_schedule(p, s, opt["mch"], opt["mdist"], opt["mbalance"])
+    # operand groups: 16 consecutive slots of a chunk share one VGPR
+    groups = []              # per group: list of (j, g, copy)
+    for seq in sched:
+        for k in range(0, len(seq), 16):
+            groups.append(seq[k:k + 16])
+    nw = len(groups)
+    itab = []
+    for grp in groups:
+        row = []
+        for slot in range(16):
+            for r in range(4):
+                v = zero
+                if slot < len(grp):
+                    j, g, _ = grp[slot]
+                    i = 4 * g + r
+                    if i < nl and sum(ns[i]) + sum(ms[j]) <= p:
+                        n, m = ns[i], ms[j]
+                        v = idx((n[0] + m[0], n[1] + m[1], n[2] + m[2]))
+                row.append(4 * v)      # byte offset in the class's row
+        itab.append(row)
+    copies = {}
+    for seq in sched:
+        for j, g, c in seq:
+            copies[g] = max(copies.get(g, 0), c + 1)
+    wgw = opt["wgw"]
+    NT = TILE * wgw
+    name = f"m2l_p{p}_s{s}_f32_hm"
+    L = []
+    # operand byte offsets, two 16-bit values per word: group 2k in the low half
+    words = []
+    for k in range(0, nw, 2):
+        lo = itab[k]
+        hi = itab[k + 1] if k + 1 < nw else [0] * 64
+        words.append([a | (b << 16) for a, b in zip(lo, hi)])
+    assert max(max(r) for r in itab) < 65536
+    flat = ", ".join(str(v) for w_ in words for v in w_)
+    L.append(f"static __device__ const unsigned kIdx_{name}[{len(words) * 64}] = {{{flat}}};")
+    L.append(f"__global__ __launch_bounds__({NT}, {opt['mwaves']}) void {name}(M2LArgs a)")
+    L.append("{")
+    L.append(f"    const int lane = threadIdx.x % {TILE};")
+    L.append(f"    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x / {TILE});")
+    L.append(f"    __shared__ float red[{nlp} * {TILE}];")
+    # the operand index table, read from LDS where a group of slots needs it
+    L.append(f"    __shared__ unsigned ixs[{len(words) * 64}];")
+    L.append(f"    for (int k = threadIdx.x; k < {len(words) * 64}; k += {NT}) ixs[k] = kIdx_{name}[k];")
+    L.append("    __syncthreads();")
+    L.append("    const float *__restrict__ Mb = (const float *)a.M;")
+    L.append("    const char *__restrict__ Db = (const char *)a.D;")
+    L.append("    const float *__restrict__ Sb = (const float *)a.sc;")
+    L.append("    const int p0 = a.wave_ptr[blockIdx.x], p1 = a.wave_ptr[blockIdx.x + 1];")
+    L.append("    for (int item = p0; item < p1; ++item) {")
+    L.append("    const int4 w = a.work[item];")
+    L.append(f"    float *__restrict__ out = a.part ? (float *)a.part + ((size_t)w.w + lane) * {nlp} : nullptr;")
+    for g in range(ng):
+        for c in range(copies.get(g, 1)):
+            L.append(f"    f32x4 acc{g}_{c} = {{0.f, 0.f, 0.f, 0.f}};")
+    L.append("    const int uspan = w.z - w.y;")
+    L.append(f"    const int ub = w.y + uspan * wv / {wgw}, ue = w.y + uspan * (wv + 1) / {wgw};")
+    L.append("    for (int u = ub; u < ue; ++u) {")
+    if opt["fairprio"]:
+        L.append("        {")
+        L.append("            const int stage = (u - ub) * 4 / (ue - ub);")
+        L.append("            if (stage == 0) __builtin_amdgcn_s_setprio(3);")
+        L.append("            else if (stage == 1) __builtin_amdgcn_s_setprio(2);")
+        L.append("            else if (stage == 2) __builtin_amdgcn_s_setprio(1);")
+        L.append("            else __builtin_amdgcn_s_setprio(0);")
+        L.append("        }")
+    L.append("        const int cls = a.ucls[u];")
+    L.append(f"        const char *__restrict__ Dr = Db + (size_t)cls * {nd * 4};")
+    L.append(f"        const float __attribute__((address_space(4))) *sc = "
+             f"(const float __attribute__((address_space(4))) *)(Sb + (size_t)cls * {scw});")
+    L.append(f"        const float *__restrict__ Mr = Mb + (size_t)a.usrc[(size_t)u * {TILE} + lane] * {nmp};")
+    comps = "xyzw"
+    # operand groups of each chunk (first global group index, count)
+    gstart, gi = [], 0
+    for seq in sched:
+        gstart.append(gi)
+        gi += (len(seq) + 15) // 16
+
+    def loads(ci, mr="Mr", dr="Dr", decl=True):
+        ch, seq = chunks[ci], sched[ci]
+        out = []
+        kw = "const " if decl else ""
+        t4, t1 = ("float4 ", "float ") if decl else ("", "")
+        for q in sorted(set(j // 4 for j in ch)):
+            out.append(f"        {kw}{t4}v{q} = *(const float4 *)({mr} + {4 * q});")
+        for k in range((len(seq) + 15) // 16):
+            wk = gstart[ci] + k
+            word = f"ixs[{(wk // 2) * 64} + lane]"
+            half = f"({word} & 0xffffu)" if wk % 2 == 0 else f"({word} >> 16)"
+            out.append(f"        {kw}{t1}w{wk} = *(const float *)({dr} + {half});")
+        return out
+
+    def mfmas(ci):
+        ch, seq = chunks[ci], sched[ci]
+        out = []
+        for j in ch:
+            out.append(f"        const float m{j} = v{j // 4}.{comps[j % 4]} * sc[{sum(ms[j])}];")
+        for k in range((len(seq) + 15) // 16):
+            wk = gstart[ci] + k
+            for slot, (j, g, c) in enumerate(seq[16 * k:16 * k + 16]):
+                out.append(f"        acc{g}_{c} = __builtin_amdgcn_mfma_f32_4x4x1f32(w{wk}, m{j}, acc{g}_{c}, 4, {slot}, 0);")
+        return out
+
+    def entry_ptrs(u, suf):
+        return [f"        const char *__restrict__ Dr{suf} = Db + (size_t)a.ucls[{u}] * {nd * 4};",
+                f"        const float *__restrict__ Mr{suf} = Mb + (size_t)a.usrc[(size_t)({u}) * {TILE} + lane] * {nmp};"]
+
+    SB = "        __builtin_amdgcn_sched_barrier(0);"
+    nchunk = len(chunks)
+    mpipe = opt["mpipe"] if nchunk > 1 else min(opt["mpipe"], 1)
+    if mpipe == 2:
+        # the first chunk's operands of entry u+1 load while entry u's last
+        # chunk multiplies (loop-carried registers); every other chunk's
+        # while the previous chunk of the same entry multiplies
+        pre = [x.replace("        ", "    ", 1) for x in loads(0, "Mr0", "Dr0", False)]
+        decl = [f"    float4 v{q};" for q in sorted(set(j // 4 for j in chunks[0]))]
+        decl += [f"    float w{gstart[0] + k};" for k in range((len(sched[0]) + 15) // 16)]
+        i_loop = L.index("    for (int u = ub; u < ue; ++u) {")
+        head = decl + ["    if (ub < ue) {"] + ["    " + x for x in entry_ptrs("ub", "0")] + ["    " + x for x in pre] + ["    }"]
+        L[i_loop:i_loop] = head
+        for ci in range(nchunk):
+            L.append(SB)
+            if ci + 1 < nchunk:
+                L.extend(loads(ci + 1))
+            else:
+                L.append("        {")
+                L.append("        const int un = u + 1 < ue ? u + 1 : u;")
+                L.extend(["    " + x for x in entry_ptrs("un", "0")])
+                L.extend(["    " + x for x in loads(0, "Mr0", "Dr0", False)])
+                L.append("        }")
+            L.extend(mfmas(ci))
+    elif mpipe == 1:
+        # the loads of chunk c+1 are issued before the multiply-adds of chunk c
+        L.extend(loads(0))
+        for ci in range(nchunk):
+            L.append(SB)
+            if ci + 1 < nchunk:
+                L.extend(loads(ci + 1))
+            L.extend(mfmas(ci))
+    else:
+        for ci in range(nchunk):
+            if opt["mbarrier"] and ci > 0:
+                # keeps the next chunk's loads from being hoisted above this
+                # point, which would hold every chunk's operands at once
+                L.append(SB)
+            L.extend(loads(ci))
+            L.extend(mfmas(ci))
+    L.append("    }")
+    for g in range(ng):
+        for c in range(1, copies.get(g, 1)):
+            L.append(f"    acc{g}_0 += acc{g}_{c};")
+    for q in range(wgw):
+        last = q == wgw - 1
+        L.append(f"    if (wv == {q}) {{")
+        for g in range(ng):
+            for r in range(4):
+                i = 4 * g + r
+                slot_ = f"red[{i} * {TILE} + lane]"
+                if q == 0:
+                    L.append(f"        {slot_} = acc{g}_0[{r}];")
+                elif not last:
+                    L.append(f"        {slot_} += acc{g}_0[{r}];")
+                else:
+                    L.append(f"        out[{i}] = {slot_} + acc{g}_0[{r}];")
+        L.append("    }")
+        if not last:
+            L.append("    __syncthreads();")
+    L.append("    __syncthreads();   // red is reused by the next item")
+    L.append("    }")
+    L.append("}")
+    launcher = f"""
+static hipError_t launch_{name}(const M2LArgs &a, int nwaves, hipStream_t st)
+{{
+    hipLaunchKernelGGL({name}, dim3(nwaves), dim3({NT}), 0, st, a);
+    return hipGetLastError();
+}}
+
+static int occ_{name}()
+{{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, {name}, {NT}, 0) != hipSuccess) return 1;
+    return per_cu > 0 ? per_cu : 1;
+}}
+"""
+    nslots = sum(len(q) for q in sched)
+    meta = dict(name=name, nl_pad=nlp, nm_pad=nmp, nd=nd, nblocks=1, scw=scw, blo=[0, nl], bfma=[4 * nslots])
+    return "\n".join(L) + "\n" + launcher, meta
+
+
+def gen_file(s, fp32, opt=None, harmonic=False, mfma=False):
+    suf = ("f32" if fp32 else "f64") + ("_h" if harmonic else "") + ("m" if mfma else "")
     parts = ["// Generated by gen_m2l.py; do not edit.", "#include <algorithm>", '#include "fmm_internal.h"', ""]
+    if mfma:
+        parts.append("typedef float f32x4 __attribute__((ext_vector_type(4)));")
+        parts.append("")
     metas = []
     for p in range(s + 1, P_MAX + 1):
-        code, meta = gen_kernel(p, s, fp32, opt, harmonic)
+        code, meta = gen_kernel_mfma(p, s, opt) if mfma else gen_kernel(p, s, fp32, opt, harmonic)
         parts.append(code)
         metas.append((p, meta))
     parts.append(f"bool m2l_lookup_s{s}_{suf}(int p, M2LVariant *v)")
@@ -361,9 +650,10 @@ def main(outdir, opt=None):
     os.makedirs(outdir, exist_ok=True)
     written = []
     for s in (0, 1, 2):
-        for fp32, h in ((True, False), (False, False), (True, True), (False, True)):
-            fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}{'_h' if h else ''}.hip")
-            txt = gen_file(s, fp32, opt, h)
+        for fp32, h, mf in ((True, False, False), (False, False, False), (True, True, False), (False, True, False),
+                            (True, True, True)):
+            fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}{'_h' if h else ''}{'m' if mf else ''}.hip")
+            txt = gen_file(s, fp32, opt, h, mf)
             old = open(fn).read() if os.path.exists(fn) else None
             if old != txt:
                 with open(fn, "w") as f:

@@ -526,7 +526,7 @@ static HarmOut harm_out(const fmm_tree *t)
 {
     HarmOut o{0, nullptr, nullptr};
     if (t->basis != FMM_M2L_HARMONIC || !t->d_Mh) return o;
-    o.nhp = (hterms(t->p) - hterms(t->order - 1) + 3) / 4 * 4;
+    o.nhp = t->nhp;
     if (t->prec == FMM_PREC_MIXED) o.h32 = (float *)t->d_Mh;
     else o.h64 = (double *)t->d_Mh;
     return o;

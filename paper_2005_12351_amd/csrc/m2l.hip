@@ -88,7 +88,7 @@ hipError_t launch_m2l(fmm_tree *t, hipStream_t s)
     if (wk.work.empty()) return hipSuccess;
     const bool f32 = t->prec == FMM_PREC_MIXED, harm = t->basis == FMM_M2L_HARMONIC;
     M2LVariant v;
-    if (!m2l_lookup(t->p, t->order, f32, harm, &v)) return hipErrorInvalidValue;
+    if (!m2l_lookup(t->p, t->order, f32, harm, &v, t->mfma)) return hipErrorInvalidValue;
     M2LArgs a;
     a.work = t->d_work;
     a.ucls = t->d_ucls;
@@ -192,7 +192,7 @@ hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
     const int64_t nc = t->ht.ncells();
     const bool f32 = t->prec == FMM_PREC_MIXED, harm = t->basis == FMM_M2L_HARMONIC;
     M2LVariant v;
-    if (!m2l_lookup(t->p, t->order, f32, harm, &v)) return hipErrorInvalidValue;
+    if (!m2l_lookup(t->p, t->order, f32, harm, &v, t->mfma)) return hipErrorInvalidValue;
     BlockBounds bb;
     for (int i = 0; i < 17; ++i) bb.lo[i] = v.blo[i];
     bb.nb = v.nblocks;

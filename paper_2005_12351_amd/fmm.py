@@ -6,8 +6,9 @@ the context's device) and streams.  Importing this module loads the library
 and fails loudly if it has not been built.
 
 Stream ordering: the library queues its work on the context's stream (a
-PyTorch stream, created by the context unless one is given).  Every call here
-first makes that stream wait for PyTorch's current stream, so inputs made by
+PyTorch stream, created by the context unless one is given).  Unless that
+stream is PyTorch's current stream, every call here first makes it wait for
+PyTorch's current stream, so inputs made by
 earlier device work are complete before the library reads them, and
 afterwards makes the current stream wait for the context's stream, so the
 outputs are complete before later work on the current stream uses them and
@@ -34,6 +35,7 @@ FMM_POT, FMM_FIELD, FMM_GRAD = 1, 2, 4   # output mask bits (FMM_GRAD: evaluate_
 FMM_OVERLAP_OFF, FMM_OVERLAP_WHOLE, FMM_OVERLAP_SPLIT = 0, 1, 2
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
+FMM_M2L_ENGINE_VALU, FMM_M2L_ENGINE_MFMA, FMM_M2L_ENGINE_AUTO = 0, 1, 2   # units of the FP32 harmonic M2L
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
 FMM_P_MAX = 10
 FMM_MIXED = 16          # order code FMM_MIXED | mask: several source orders (bit k: order k)
@@ -77,6 +79,7 @@ fmm_last_error = _sig("fmm_last_error", [], ctypes.c_char_p)
 fmm_ctx_set_overlap = _sig("fmm_ctx_set_overlap", [_vp, ctypes.c_int])
 fmm_ctx_set_m2l_basis = _sig("fmm_ctx_set_m2l_basis", [_vp, ctypes.c_int])
 fmm_ctx_set_graphs = _sig("fmm_ctx_set_graphs", [_vp, ctypes.c_int])
+fmm_ctx_set_m2l_engine = _sig("fmm_ctx_set_m2l_engine", [_vp, ctypes.c_int])
 fmm_ctx_set_tree_limit = _sig("fmm_ctx_set_tree_limit", [_vp, ctypes.c_size_t])
 fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
 fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
@@ -93,7 +96,7 @@ fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_evaluate_grad_noalloc", "fmm_run", "fmm_tree_info",
-            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_tree_limit", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_m2l_engine", "fmm_ctx_set_tree_limit", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
@@ -140,14 +143,19 @@ class Context:
         self.h = h
 
     def _enter(self):
-        """the context's stream waits for the caller's current stream"""
+        """the context's stream waits for the caller's current stream (nothing
+        to do when the caller works on the context's stream itself)"""
         if self.stream is not None:
-            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            cur = torch.cuda.current_stream(self.device)
+            if cur != self.stream:
+                self.stream.wait_stream(cur)
 
     def _leave(self):
         """the caller's current stream waits for the work just queued"""
         if self.stream is not None:
-            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+            cur = torch.cuda.current_stream(self.device)
+            if cur != self.stream:
+                cur.wait_stream(self.stream)
 
     def set_tree_limit(self, nbytes: int):
         """device bytes one tree may hold (0: no limit); beyond it calls fail with FMM_ENOMEM"""
@@ -220,6 +228,10 @@ class Context:
     def set_m2l_basis(self, basis: int):
         """FMM_M2L_FULL or FMM_M2L_HARMONIC (default); used from the next upward pass."""
         _check(fmm_ctx_set_m2l_basis(self.h, int(basis)), "fmm_ctx_set_m2l_basis")
+
+    def set_m2l_engine(self, engine: int):
+        """FMM_M2L_ENGINE_AUTO (default), _MFMA or _VALU; used from the next upward pass"""
+        _check(fmm_ctx_set_m2l_engine(self.h, int(engine)), "fmm_ctx_set_m2l_engine")
 
     def set_overlap(self, on=True):
         """False/0 off, True/1 the whole near field beside the far field, 2

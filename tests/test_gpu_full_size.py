@@ -50,7 +50,9 @@ def _oracle(orc, w, method):
 def _run(ctx, w, prec, method, basis):
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     m = fmm.FMM_METHOD_FMM if method == "fmm" else fmm.FMM_METHOD_BH
+    basis, engine = basis
     ctx.set_m2l_basis(basis)
+    ctx.set_m2l_engine(engine)
     t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta, m)
     mom = to_dev(w.moments)
     phi = torch.empty(w.n, dtype=torch.float64, device="cuda") if outputs & fmm.FMM_POT else None
@@ -62,13 +64,18 @@ def _run(ctx, w, prec, method, basis):
     out = (None if phi is None else phi[s].cpu().numpy(), fld[s].cpu().numpy())
     t.close()
     ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+    ctx.set_m2l_engine(fmm.FMM_M2L_ENGINE_AUTO)
     return out
 
 
 # (workload, method, basis of the M2L / Barnes-Hut M2P)
-CASES = [(2, "fmm", "harmonic"), (2, "fmm", "full"), (3, "fmm", "harmonic"), (3, "fmm", "full"), (3, "bh", "harmonic"),
-         (3, "bh", "full"), (4, "fmm", "harmonic"), (4, "fmm", "full")]
-BASIS = {"harmonic": fmm.FMM_M2L_HARMONIC, "full": fmm.FMM_M2L_FULL}
+CASES = [(2, "fmm", "harmonic"), (2, "fmm", "harmonic_valu"), (2, "fmm", "full"), (3, "fmm", "harmonic"),
+         (3, "fmm", "full"), (3, "bh", "harmonic"), (3, "bh", "full"), (4, "fmm", "harmonic"),
+         (4, "fmm", "harmonic_valu"), (4, "fmm", "full")]
+# M2L basis and the units of the FP32 harmonic contraction (the matrix cores by default)
+BASIS = {"harmonic": (fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_ENGINE_MFMA),
+         "harmonic_valu": (fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_ENGINE_VALU),
+         "full": (fmm.FMM_M2L_FULL, fmm.FMM_M2L_ENGINE_MFMA)}
 
 
 @pytest.mark.parametrize("index,method,basis", CASES)

@@ -98,15 +98,20 @@ PARITY = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2
           (1, 2, "uniform", 700, 4, 0.3), (0, 10, "plummer", 1200, 8, 0.5)]
 
 
-BASES = {"full": fmm.FMM_M2L_FULL, "harmonic": fmm.FMM_M2L_HARMONIC}
+# M2L basis and, for the FP32 harmonic contraction, the units it runs on
+BASES = {"full": (fmm.FMM_M2L_FULL, fmm.FMM_M2L_ENGINE_MFMA),
+         "harmonic": (fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_ENGINE_MFMA),
+         "harmonic_valu": (fmm.FMM_M2L_HARMONIC, fmm.FMM_M2L_ENGINE_VALU)}
 
 
 @pytest.fixture(params=list(BASES))
 def basis(request, ctx):
-    """Runs the test in each M2L basis, then restores the default."""
-    ctx.set_m2l_basis(BASES[request.param])
+    """Runs the test in each M2L basis (and engine), then restores the default."""
+    ctx.set_m2l_basis(BASES[request.param][0])
+    ctx.set_m2l_engine(BASES[request.param][1])
     yield request.param
     ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+    ctx.set_m2l_engine(fmm.FMM_M2L_ENGINE_AUTO)
 
 
 @pytest.mark.parametrize("order,p,kind,n,ncrit,theta", PARITY)
@@ -229,6 +234,31 @@ def test_basis_switch_on_one_tree(ctx):
             t.close()
     finally:
         ctx.set_m2l_basis(fmm.FMM_M2L_HARMONIC)
+
+
+@pytest.mark.parametrize("order,p", [(0, 10), (1, 8), (2, 6), (1, 2)])
+def test_engine_switch_on_one_tree(ctx, order, p):
+    """The FP32 harmonic M2L on the matrix cores and on the vector units
+    computes the same sums (different FP32 addition order): they agree to
+    the FP32 tolerance, and returning to an engine reproduces its result bit
+    for bit."""
+    w = W.small_random(5252 + order, 8000, order, "plummer", p=p, theta=0.5, ncrit=32)
+    pos, mom = torch.from_numpy(w.pos).cuda(), torch.from_numpy(w.moments).cuda()
+    t = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+    out = []
+    try:
+        for eng in (fmm.FMM_M2L_ENGINE_MFMA, fmm.FMM_M2L_ENGINE_VALU, fmm.FMM_M2L_ENGINE_MFMA):
+            ctx.set_m2l_engine(eng)
+            ph, E = t.run(w.order, mom, w.p, fmm.FMM_PREC_MIXED)
+            torch.cuda.synchronize()
+            out.append((ph.cpu().numpy(), E.cpu().numpy()))
+    finally:
+        ctx.set_m2l_engine(fmm.FMM_M2L_ENGINE_AUTO)
+    t.close()
+    ok = within(out[0][0], out[1][0], "mixed", "phi MFMA vs VALU", floor=PHI_FLOOR)
+    ok &= within(out[0][1], out[1][1], "mixed", "E MFMA vs VALU")
+    assert ok
+    assert np.array_equal(out[0][0], out[2][0]) and np.array_equal(out[0][1], out[2][1])
 
 
 @pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT])

@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
     ap.add_argument("--p", type=int, default=None, help="override the expansion order")
     ap.add_argument("--no-literal-row", action="store_true", help="skip the literal-parameter row")
+    ap.add_argument("--m2l-engine", choices=["auto", "mfma", "valu"], default="auto",
+                    help="units of the FP32 harmonic-basis M2L (auto: matrix cores for p >= 8)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -228,6 +230,11 @@ def main():
     mom = torch.from_numpy(w.moments).to(dev)
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     ctx = fmm.Context(0)
+    # device work of this script runs on the context's stream, so the
+    # binding has no cross-stream ordering to add around each call
+    torch.cuda.set_stream(ctx.stream)
+    ctx.set_m2l_engine({"auto": fmm.FMM_M2L_ENGINE_AUTO, "mfma": fmm.FMM_M2L_ENGINE_MFMA,
+                        "valu": fmm.FMM_M2L_ENGINE_VALU}[args.m2l_engine])
     if args.calibrate_copy:
         a_ = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
         b_ = torch.empty_like(a_)
@@ -416,7 +423,9 @@ def main():
                    "n": w.n, "source_order": w.order, "p": w.p, "theta": w.theta,
                    "ncrit": w.ncrit, "outputs": w.outputs,
                    "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)",
-                   "basis": "harmonic (M2L / M2P on the folded rows)"},
+                   "basis": "harmonic (M2L / M2P on the folded rows)",
+                   "m2l_engine": ("matrix cores (v_mfma_f32_4x4x1)" if args.m2l_engine == "mfma" or
+                                  (args.m2l_engine == "auto" and w.p >= 8) else "vector units")},
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},
         **({} if bh else {"m2l_full_basis": full_basis}),
         **({} if grad_line is None else {"field_gradient": {k: v for k, v in grad_line.items() if k != "out"}}),

@@ -58,7 +58,7 @@ def _headers_digest(build_dir):
     for p in paths:
         if os.path.exists(p):
             with open(p, "rb") as f:
-                h.update(p.encode() + b"\0" + f.read())
+                h.update(os.path.basename(p).encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

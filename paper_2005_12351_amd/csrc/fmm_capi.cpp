@@ -432,9 +432,38 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) leaf_cost[k] += (double)h.count[h.p2p_src[e]];
         leaf_cost[k] *= (double)h.count[b];
     }
-    std::vector<int32_t> p2p_order(t->nleaves);
-    for (int64_t k = 0; k < t->nleaves; ++k) p2p_order[k] = (int32_t)k;
-    std::stable_sort(p2p_order.begin(), p2p_order.end(), [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
+    // Near-field dispatch order.  Workgroups go to the eight XCDs in turn
+    // (workgroup g to XCD g % 8) and each XCD has its own L2, so the leaves,
+    // in Morton order (the order of their first particle), are cut into
+    // eight ranges of equal cost and workgroup g takes the (g / 8)-th leaf of
+    // range g % 8: the leaves one XCD works on are neighbours and share most
+    // of their source leaves in its L2.  Within a range the heaviest leaves
+    // go first, so that the light ones fill the end of the launch.
+    constexpr int kXcd = 8;
+    std::vector<int32_t> p2p_order;
+    {
+        std::vector<int32_t> mort(t->nleaves);
+        for (int64_t k = 0; k < t->nleaves; ++k) mort[k] = (int32_t)k;
+        std::stable_sort(mort.begin(), mort.end(),
+                         [&](int32_t a, int32_t b) { return h.first[t->leaves[a]] < h.first[t->leaves[b]]; });
+        double tot = 0.0;
+        for (double c : leaf_cost) tot += c;
+        std::vector<std::vector<int32_t>> range(kXcd);
+        double acc = 0.0;
+        for (int32_t k : mort) {
+            const int r = std::min(kXcd - 1, tot > 0.0 ? (int)(acc * kXcd / tot) : 0);
+            range[r].push_back(k);
+            acc += leaf_cost[k];
+        }
+        size_t longest = 0;
+        for (auto &rg : range) {
+            std::stable_sort(rg.begin(), rg.end(), [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
+            longest = std::max(longest, rg.size());
+        }
+        for (size_t i = 0; i < longest; ++i)
+            for (auto &rg : range)
+                if (i < rg.size()) p2p_order.push_back(rg[i]);
+    }
     {
         // split point of the near field for FMM_OVERLAP_SPLIT: half the cost
         double tot = 0.0, acc = 0.0;

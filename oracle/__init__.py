@@ -73,6 +73,10 @@ def lib():
         L.orc_m2p.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, _vp]
         L.orc_p2p_pair.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp]
         L.orc_cell_center.argtypes = [_vp, ctypes.c_int64, _vp, _vp]
+        L.orc_pair_derivs.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+        L.orc_direct_derivs.argtypes = [ctypes.c_int64, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _vp, _vp]
+        L.orc_l2p_derivs.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.orc_fmm_derivs.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp]
         _lib = L
     return _lib
 
@@ -203,6 +207,38 @@ def direct_grad(pos, order: int, mom, targets: Optional[np.ndarray] = None) -> n
     return G
 
 
+def nderivs(K: int) -> int:
+    """number of derivatives of order K: the multi-indices k with |k| = K"""
+    return (K + 1) * (K + 2) // 2
+
+
+def pair_derivs(order: int, K: int, r, mom) -> np.ndarray:
+    """d^k phi for every |k| = K of one source at displacement r"""
+    out = np.zeros(nderivs(K))
+    lib().orc_pair_derivs(order, K, _p(_c(r)), _p(_c(mom).ravel()), _p(out))
+    return out
+
+
+def direct_derivs(pos, order: int, mom, K: int, targets: Optional[np.ndarray] = None) -> np.ndarray:
+    """O(N^2) derivatives of order K of the potential (k x nderivs(K)), in
+    the index order within that order"""
+    pos = _c(pos).reshape(-1, 3)
+    mom = _c(mom)
+    n = pos.shape[0]
+    tg = None if targets is None else _c(targets, np.int64)
+    k = n if tg is None else tg.shape[0]
+    out = np.zeros((k, nderivs(K)))
+    lib().orc_direct_derivs(n, _p(pos), order, _p(mom), K, k, _p(tg), _p(out))
+    return out
+
+
+def l2p_derivs(p: int, s: int, z, L, x, K: int) -> np.ndarray:
+    """Eq. 10: derivatives of order K of the local expansion L about z at x"""
+    out = np.zeros(nderivs(K))
+    lib().orc_l2p_derivs(p, s, _p(_c(z)), _p(_c(L)), _p(_c(x)), K, _p(out))
+    return out
+
+
 def direct(pos, order: int, mom, targets: Optional[np.ndarray] = None):
     """O(N^2) potential and field at all (or the listed) targets."""
     pos = _c(pos).reshape(-1, 3)
@@ -318,6 +354,16 @@ class Tree:
         if rc != 0:
             raise ValueError("oracle FMM rejected its arguments (lists missing or p < order+1)")
         out = (phi, E) + ((L,) if want_L else ()) + ((G,) if want_grad else ())
+        return out
+
+    def fmm_derivs(self, order: int, mom, p: int, K: int, targets: Optional[np.ndarray] = None) -> np.ndarray:
+        """FMM derivatives of order K of the potential (k x nderivs(K))"""
+        mom = _c(mom)
+        tg = None if targets is None else _c(targets, np.int64)
+        k = self.n if tg is None else tg.shape[0]
+        out = np.zeros((k, nderivs(K)))
+        if lib().orc_fmm_derivs(self._h, order, _p(mom), p, K, k, _p(tg), _p(out)) != 0:
+            raise ValueError("oracle FMM derivatives rejected their arguments")
         return out
 
     def bh(self, order: int, mom, p: int, theta_bh: float, targets: Optional[np.ndarray] = None,

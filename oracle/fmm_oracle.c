@@ -1092,3 +1092,140 @@ int orc_bh_eval(const orc_tree *t, int order, const double *mom, int p, double t
     free(ms);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Derivatives of the potential of any order K (Section 2, Eq. 10)      */
+/* ------------------------------------------------------------------ */
+/* Every function below writes d^k phi for each multi-index k of order
+ * exactly K, in the index order of that order (position
+ * orc_index(k) - orc_nterms(K-1)), (K+1)(K+2)/2 values per target.  Order 1
+ * is -E and order 2 is -G of the functions above, which are written from
+ * closed forms and so check these independently. */
+
+/* One source of one order at displacement r.  The multipole of a point
+ * source about its own position is its source tensor (Eq. 5 with z = x), so
+ * Eq. 6 gives phi(r) = sum_{|m|=s} S_m D_m(r) and d^k phi = sum_m S_m D_{m+k}. */
+static void pair_derivs_single(int order, int K, const double *r, const double *mom, double *out)
+{
+    int q = order + K;
+    double *D = malloc(sizeof(double) * orc_nterms(q));
+    double S[10];
+    orc_dtensor(q, r[0], r[1], r[2], D);
+    source_tensor(order, mom, S);
+    int nk = (K + 1) * (K + 2) / 2, k0 = orc_nterms(K - 1);
+    for (int c = 0; c < nk; ++c) {
+        int k[3];
+        orc_multi_index(k0 + c, k);
+        double acc = 0.0;
+        for (int mi = orc_nterms(order - 1); mi < orc_nterms(order); ++mi) {
+            int m[3];
+            orc_multi_index(mi, m);
+            acc += S[mi] * D[orc_index(k[0] + m[0], k[1] + m[1], k[2] + m[2])];
+        }
+        out[c] = acc;
+    }
+    free(D);
+}
+
+/* the same for a source of any order code: the sum over its parts */
+void orc_pair_derivs(int o, int K, const double *r, const double *mom, double *out)
+{
+    int m = code_mask(o), off = 0, nk = (K + 1) * (K + 2) / 2;
+    double part[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2];
+    for (int c = 0; c < nk; ++c) out[c] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        if (!(m & (1 << k))) continue;
+        pair_derivs_single(k, K, r, mom + off, part);
+        for (int c = 0; c < nk; ++c) out[c] += part[c];
+        off += width_of(k);
+    }
+}
+
+/* O(N^2) derivatives of order K at the listed targets (all if targets is
+ * NULL), sources j != i in ascending order */
+void orc_direct_derivs(int64_t n, const double *pos, int order, const double *mom, int K, int64_t nt,
+                       const int64_t *targets, double *out)
+{
+    int w = mom_width(order), nk = (K + 1) * (K + 2) / 2;
+    int64_t cnt = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < cnt; ++k) {
+        int64_t i = targets ? targets[k] : k;
+        double acc[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2], part[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2];
+        for (int c = 0; c < nk; ++c) acc[c] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double r[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1], pos[3 * i + 2] - pos[3 * j + 2]};
+            orc_pair_derivs(order, K, r, mom + w * j, part);
+            for (int c = 0; c < nk; ++c) acc[c] += part[c];
+        }
+        for (int c = 0; c < nk; ++c) out[(size_t)nk * k + c] = acc[c];
+    }
+}
+
+/* Eq. 10 for |k| = K: d^k phi = sum_{|n| <= p-s-K} (x-z)^n/n! L_{n+k}
+ * (the local expansion is a polynomial of degree p-s: zero for K > p-s) */
+void orc_l2p_derivs(int p, int s, const double *z, const double *L, const double *x, int K, double *out)
+{
+    int q = p - s, nk = (K + 1) * (K + 2) / 2, k0 = orc_nterms(K - 1);
+    for (int c = 0; c < nk; ++c) out[c] = 0.0;
+    if (K > q) return;
+    double *mono = malloc(sizeof(double) * orc_nterms(q - K));
+    double d[3] = {x[0] - z[0], x[1] - z[1], x[2] - z[2]};
+    monomials(q - K, d, mono);
+    for (int c = 0; c < nk; ++c) {
+        int k[3];
+        orc_multi_index(k0 + c, k);
+        double acc = 0.0;
+        for (int i = 0; i < orc_nterms(q - K); ++i) {
+            int n[3];
+            orc_multi_index(i, n);
+            acc += mono[i] * L[orc_index(n[0] + k[0], n[1] + k[1], n[2] + k[2])];
+        }
+        out[c] = acc;
+    }
+    free(mono);
+}
+
+/* FMM derivatives of order K at the listed targets: Eq. 10 on each target's
+ * leaf local expansion plus the pairs of its P2P list (j != i) */
+int orc_fmm_derivs(const orc_tree *t, int order, const double *mom, int p, int K, int64_t nt_,
+                   const int64_t *targets, double *out)
+{
+    if (!orc_code_valid(order) || K < 1 || K > ORC_TABLE_P) return 1;
+    int s = orc_min_order(order);
+    if (!t->m2l_ptr || p < s + 1) return 1;
+    int w = mom_width(order), ntL = orc_nterms(p - s), nk = (K + 1) * (K + 2) / 2;
+    double *L = calloc((size_t)t->ncells * ntL, sizeof(double));
+    int rc = orc_fmm_eval(t, order, mom, p, nt_, targets, NULL, NULL, L, NULL);
+    if (rc) {
+        free(L);
+        return rc;
+    }
+    double *ms = sorted_moments(t, order, mom);
+    int64_t cnt = targets ? nt_ : t->n;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        int64_t i = targets ? t->iperm[targets[k]] : k;
+        int64_t o = targets ? k : t->perm[i];
+        int64_t b = t->leaf_of[i];
+        double zB[3], rB;
+        orc_cell_center(t, b, zB, &rB);
+        const double *x = t->xs + 3 * i;
+        double acc[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2], part[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2];
+        orc_l2p_derivs(p, s, zB, L + (size_t)b * ntL, x, K, acc);
+        for (int64_t e = t->p2p_ptr[b]; e < t->p2p_ptr[b + 1]; ++e) {
+            int64_t a = t->p2p_src[e];
+            for (int64_t j = t->first[a]; j < t->first[a] + t->count[a]; ++j) {
+                if (j == i) continue;
+                double r[3] = {x[0] - t->xs[3 * j], x[1] - t->xs[3 * j + 1], x[2] - t->xs[3 * j + 2]};
+                orc_pair_derivs(order, K, r, ms + w * j, part);
+                for (int c = 0; c < nk; ++c) acc[c] += part[c];
+            }
+        }
+        for (int c = 0; c < nk; ++c) out[(size_t)nk * o + c] = acc[c];
+    }
+    free(ms);
+    free(L);
+    return 0;
+}

@@ -176,6 +176,20 @@ int fmm_evaluate_grad(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, do
 int fmm_evaluate_grad_noalloc(fmm_ctx *ctx, fmm_tree *tree, int outputs, double *phi, double *field,
                               double *grad);
 
+/* Derivatives of the potential of order K = 1, 2 or 3 at every particle
+ * (Section 2: the derivatives of order |k| from the local expansion, Eq. 10,
+ * plus the same derivatives of the near-field pair potentials,
+ * sum_{|m|=s} S_m D_{m+k}(x_i - x_j)).  out: device, n x (K+1)(K+2)/2 FP64,
+ * caller's particle order; the columns are d^k phi for the multi-indices of
+ * order K in the index order (n_x descending, then n_y): K = 1 gives -E,
+ * K = 2 gives -G of fmm_evaluate_grad, K = 3 the ten third derivatives
+ * d_i d_j d_l phi = -d_i d_j E_l.  Computed in FP64 from the tree's locals
+ * (which come from the FP32 M2L in MIXED precision) and its sorted FP64
+ * moments.  FMM trees only; K <= p - s (the truncated local expansion has no
+ * derivative of higher order); FMM_EINVAL otherwise, FMM_ESTATE before
+ * fmm_upward. */
+int fmm_evaluate_derivs(fmm_ctx *ctx, fmm_tree *tree, int K, double *out);
+
 /* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,
  * n_m2l_classes, n_m2l_tiles, n_m2l_slots_used (tile lanes x union entries),
  * device bytes held. */

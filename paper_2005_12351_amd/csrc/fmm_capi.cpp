@@ -897,6 +897,40 @@ extern "C" int fmm_evaluate_grad_noalloc(fmm_ctx *ctx, fmm_tree *t, int outputs,
     return FMM_OK;
 }
 
+extern "C" int fmm_evaluate_derivs(fmm_ctx *ctx, fmm_tree *t, int K, double *out)
+{
+    if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
+    if (!out) FAIL(FMM_EINVAL, "out is NULL");
+    if (K < 1 || K > 3) FAIL(FMM_EINVAL, "derivative order %d (1, 2 or 3)", K);
+    if (t->method != FMM_METHOD_FMM) FAIL(FMM_EINVAL, "derivatives of any order are built for FMM trees only");
+    if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    if (K > t->p - t->order)
+        FAIL(FMM_EINVAL, "derivative order %d exceeds p - s = %d: the truncated local expansion has no "
+                         "derivative of that order", K, t->p - t->order);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // the locals of the leaves (as fmm_evaluate forms them), then Eq. 10 and
+    // the pairs' derivatives in one pass
+    {
+        ProfScope ps(ctx, s, "m2l");
+        KCHK(launch_m2l(t, s));
+    }
+    {
+        ProfScope ps(ctx, s, "m2l_combine");
+        KCHK(launch_m2l_combine(t, s));
+    }
+    const int nlev = (int)t->ht.level_ptr.size() - 1;
+    for (int l = std::max(1, t->l2l_from); l < nlev; ++l) {
+        ProfScope ps(ctx, s, "l2l");
+        KCHK(launch_l2l_level(t, l, s));
+    }
+    {
+        ProfScope ps(ctx, s, "derivs");
+        KCHK(launch_derivs(t, K, out, s));
+    }
+    return FMM_OK;
+}
+
 extern "C" int fmm_run(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision, int outputs,
                        double *phi, double *field)
 {

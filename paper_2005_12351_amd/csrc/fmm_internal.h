@@ -306,6 +306,9 @@ bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a l
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 // P2P over the leaves p2p_order[first .. first + count) (count < 0: to the end)
 hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count);
+// derivatives of order K (1..3) of the potential at every particle, out in
+// caller order, (K+1)(K+2)/2 per particle; needs the locals (M2L, L2L) queued
+hipError_t launch_derivs(fmm_tree *t, int K, double *out, hipStream_t s);
 
 // serving (serve.cpp)
 int serve_destroy(fmm_ctx *ctx);

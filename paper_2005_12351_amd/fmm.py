@@ -70,6 +70,7 @@ fmm_build_tree = _sig("fmm_build_tree", [_vp, _vp, _i64, ctypes.c_int, ctypes.c_
 fmm_upward = _sig("fmm_upward", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int])
 fmm_evaluate = _sig("fmm_evaluate", [_vp, _vp, ctypes.c_int, _vp, _vp])
 fmm_evaluate_grad = _sig("fmm_evaluate_grad", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp])
+fmm_evaluate_derivs = _sig("fmm_evaluate_derivs", [_vp, _vp, ctypes.c_int, _vp])
 fmm_evaluate_grad_noalloc = _sig("fmm_evaluate_grad_noalloc", [_vp, _vp, ctypes.c_int, _vp, _vp, _vp])
 fmm_run = _sig("fmm_run", [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp])
 fmm_tree_info = _sig("fmm_tree_info", [_vp, _vp])
@@ -95,7 +96,7 @@ fmm_serve_stop = _sig("fmm_serve_stop", [_vp])
 fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
-EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_evaluate_grad_noalloc", "fmm_run", "fmm_tree_info",
+EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_evaluate_grad_noalloc", "fmm_evaluate_derivs", "fmm_run", "fmm_tree_info",
             "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_m2l_engine", "fmm_ctx_set_tree_limit", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
@@ -330,6 +331,18 @@ class Tree:
         self.ctx._leave()
         _check(rc, "fmm_evaluate_grad")
         return phi, field, grad
+
+    def evaluate_derivs(self, K: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """derivatives of order K (1..3) of the potential, n x (K+1)(K+2)/2,
+        multi-indices of order K in the index order"""
+        if out is None:
+            out = torch.empty((self.n, (K + 1) * (K + 2) // 2), dtype=torch.float64,
+                              device=torch.device("cuda", self.ctx.device))
+        self.ctx._enter()
+        rc = fmm_evaluate_derivs(self.ctx.h, self.h, int(K), out.data_ptr())
+        self.ctx._leave()
+        _check(rc, "fmm_evaluate_derivs")
+        return out
 
     def evaluate_grad_noalloc(self, outputs: int, phi: Optional[torch.Tensor], field: Optional[torch.Tensor],
                               grad: Optional[torch.Tensor]):

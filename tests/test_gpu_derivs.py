@@ -1,0 +1,116 @@
+"""GPU parity of fmm_evaluate_derivs (derivatives of order K = 1..3 of the
+potential, Section 2 / Eq. 10) against the oracle's derivatives on the same
+tree, lists and truncation.  The GPU computes them in FP64 from the tree's
+locals, which come from the FP32 M2L in MIXED precision, so MIXED is held to
+the gradient's bounds and FP64 to FP64's."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2005_12351_amd import fmm  # noqa: E402
+from paper_2005_12351_amd import workloads as W  # noqa: E402
+from tests.gpu_helpers import to_dev, within  # noqa: E402
+
+# (pooled, per target): FP64 as phi/E/G; MIXED as the field gradient (the far
+# part carries the FP32 M2L's rounding, the near part is FP64)
+TOL = {fmm.FMM_PREC_FP64: (1e-10, 1e-12), fmm.FMM_PREC_MIXED: (2e-6, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = fmm.Context(0)
+    yield c
+    c.close()
+
+
+CASES = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2, 10, "lattice", 3375, 64, 0.5),
+         (1, 6, "plummer", 4000, 32, 0.6), (0, 3, "uniform", 1500, 16, 0.5), (2, 5, "plummer", 2500, 8, 0.4),
+         (16 + 7, 6, "plummer", 2000, 16, 0.5)]
+
+
+@pytest.mark.parametrize("order,p,kind,n,ncrit,theta", CASES)
+@pytest.mark.parametrize("prec", [fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED])
+def test_derivatives_match_oracle(orc, ctx, order, p, kind, n, ncrit, theta, prec):
+    if order >= 16:
+        w = W.small_mixed(2100 + n, n, order - 16, kind, p=p, theta=theta, ncrit=ncrit)
+    else:
+        w = W.small_random(2100 + n + order, n, order, kind, p=p, theta=theta, ncrit=ncrit)
+    s = 0 if order >= 16 else order
+    print(f"[derivs] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta} precision={prec}", flush=True)
+    t = fmm.Tree(ctx, to_dev(w.pos), ncrit, theta)
+    t.upward(w.order, to_dev(w.moments), p, prec)
+    ot = orc.Tree(w.pos, ncrit, theta)
+    ok = True
+    for K in range(1, min(3, p - s) + 1):
+        d = t.evaluate_derivs(K)
+        torch.cuda.synchronize()
+        ok &= within(d.cpu().numpy(), ot.fmm_derivs(w.order, w.moments, p, K), prec, f"order {K} vs oracle", TOL[prec])
+    t.close()
+    assert ok
+
+
+def test_orders_one_and_two_agree_with_field_and_gradient(ctx):
+    w = W.small_random(2200, 5000, 1, "plummer", p=7, theta=0.5, ncrit=32)
+    t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta)
+    t.upward(1, to_dev(w.moments), 7, fmm.FMM_PREC_FP64)
+    _, E, G = t.evaluate_grad()
+    d1, d2 = t.evaluate_derivs(1), t.evaluate_derivs(2)
+    d3 = t.evaluate_derivs(3)
+    torch.cuda.synchronize()
+    ok = within(d1.cpu().numpy(), -E.cpu().numpy(), "fp64", "order 1 vs -E")
+    ok &= within(d2.cpu().numpy(), -G.cpu().numpy(), "fp64", "order 2 vs -G")
+    assert ok
+    # Laplace: d_x d_x d_l + d_y d_y d_l + d_z d_z d_l = 0 (columns of order 3:
+    # xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz)
+    d3 = d3.cpu().numpy()
+    for l, cols in ((0, (0, 3, 5)), (1, (1, 6, 8)), (2, (2, 7, 9))):
+        assert np.abs(d3[:, cols[0]] + d3[:, cols[1]] + d3[:, cols[2]]).max() <= 1e-9 * np.abs(d3).max()
+    t.close()
+
+
+def test_derivative_errors(ctx):
+    w = W.small_random(2300, 800, 1, "uniform", p=3, theta=0.5, ncrit=16)
+    pos, mom = to_dev(w.pos), to_dev(w.moments)
+    t = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+    with pytest.raises(fmm.FMMError) as e:
+        t.evaluate_derivs(1)                       # before fmm_upward
+    assert e.value.code == fmm.FMM_ESTATE
+    t.upward(1, mom, 3, fmm.FMM_PREC_FP64)
+    for K in (0, 4):
+        with pytest.raises(fmm.FMMError) as e:
+            t.evaluate_derivs(K)
+        assert e.value.code == fmm.FMM_EINVAL
+    t.upward(1, mom, 2, fmm.FMM_PREC_FP64)
+    with pytest.raises(fmm.FMMError) as e:
+        t.evaluate_derivs(2)                       # p - s = 1
+    assert e.value.code == fmm.FMM_EINVAL
+    t.close()
+    tb = fmm.Tree(ctx, pos, w.ncrit, w.theta, fmm.FMM_METHOD_BH)
+    tb.upward(1, mom, 3, fmm.FMM_PREC_FP64)
+    with pytest.raises(fmm.FMMError) as e:
+        tb.evaluate_derivs(1)
+    assert e.value.code == fmm.FMM_EINVAL
+    tb.close()
+
+
+def test_derivatives_full_size_sampled(orc, ctx):
+    """the 100k-dipole workload at theta 0.3, p 10, order 3, on the oracle's
+    4 096 sampled targets"""
+    w = W.config(2)
+    w.theta, w.p = 0.3, 10
+    t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta)
+    ref = orc.Tree(w.pos, w.ncrit, w.theta).fmm_derivs(w.order, w.moments, w.p, 3, targets=w.sample)
+    s = torch.from_numpy(w.sample).cuda()
+    ok = True
+    for prec in (fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED):
+        t.run(w.order, to_dev(w.moments), w.p, prec)
+        d = t.evaluate_derivs(3)
+        torch.cuda.synchronize()
+        ok &= within(d[s].cpu().numpy(), ref, prec, f"precision={prec}: order 3 on the samples", TOL[prec])
+    t.close()
+    assert ok

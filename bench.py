@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
     ap.add_argument("--p", type=int, default=None, help="override the expansion order")
     ap.add_argument("--no-literal-row", action="store_true", help="skip the literal-parameter row")
+    ap.add_argument("--overlap", choices=["off", "whole", "split"], default="off",
+                    help="near field beside the far field in the timed steps (default: one after the other)")
     ap.add_argument("--m2l-engine", choices=["auto", "mfma", "valu"], default="auto",
                     help="units of the FP32 harmonic-basis M2L (auto: matrix cores for p >= 8)")
     args = ap.parse_args()
@@ -255,7 +257,8 @@ def main():
         phi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
         fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
         ctx.profile(False)
-        ctx.set_overlap(False)
+        ctx.set_overlap({"off": fmm.FMM_OVERLAP_OFF, "whole": fmm.FMM_OVERLAP_WHOLE,
+                         "split": fmm.FMM_OVERLAP_SPLIT}[args.overlap])
         for _ in range(warmup):
             tree.run(w.order, mom, w.p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
@@ -424,6 +427,7 @@ def main():
                    "ncrit": w.ncrit, "outputs": w.outputs,
                    "method": "FMM (dual-tree lists)" if not bh else "Barnes-Hut (per-particle traversal, M2P)",
                    "basis": "harmonic (M2L / M2P on the folded rows)",
+                   "near_field_overlap": args.overlap,
                    "m2l_engine": ("matrix cores (v_mfma_f32_4x4x1)" if args.m2l_engine == "mfma" or
                                   (args.m2l_engine == "auto" and w.p >= 8) else "vector units")},
         "fp64": {"value": w.n / f64["step_s"], "unit": "evals/s", "ms_per_step": f64["step_s"] * 1e3, **f64_k},

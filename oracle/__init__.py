@@ -77,6 +77,9 @@ def lib():
         L.orc_direct_derivs.argtypes = [ctypes.c_int64, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _vp, _vp]
         L.orc_l2p_derivs.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
         L.orc_fmm_derivs.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _vp, _vp]
+        L.orc_m2p_derivs.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp]
+        L.orc_bh_derivs.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int64,
+                                    _vp, _vp]
         _lib = L
     return _lib
 
@@ -239,6 +242,14 @@ def l2p_derivs(p: int, s: int, z, L, x, K: int) -> np.ndarray:
     return out
 
 
+def m2p_derivs(p: int, s: int, zA, M, x, K: int) -> np.ndarray:
+    """Eq. 6 differentiated K times: derivatives of order K at x of the
+    multipole M (physical units, nterms(p)) about zA"""
+    out = np.zeros(nderivs(K))
+    lib().orc_m2p_derivs(p, s, _p(_c(zA)), _p(_c(M)), _p(_c(x)), K, _p(out))
+    return out
+
+
 def direct(pos, order: int, mom, targets: Optional[np.ndarray] = None):
     """O(N^2) potential and field at all (or the listed) targets."""
     pos = _c(pos).reshape(-1, 3)
@@ -364,6 +375,17 @@ class Tree:
         out = np.zeros((k, nderivs(K)))
         if lib().orc_fmm_derivs(self._h, order, _p(mom), p, K, k, _p(tg), _p(out)) != 0:
             raise ValueError("oracle FMM derivatives rejected their arguments")
+        return out
+
+    def bh_derivs(self, order: int, mom, p: int, theta_bh: float, K: int,
+                  targets: Optional[np.ndarray] = None) -> np.ndarray:
+        """Barnes-Hut derivatives of order K of the potential (k x nderivs(K))"""
+        mom = _c(mom)
+        tg = None if targets is None else _c(targets, np.int64)
+        k = self.n if tg is None else tg.shape[0]
+        out = np.zeros((k, nderivs(K)))
+        if lib().orc_bh_derivs(self._h, order, _p(mom), p, float(theta_bh), K, k, _p(tg), _p(out)) != 0:
+            raise ValueError("oracle BH derivatives rejected their arguments")
         return out
 
     def bh(self, order: int, mom, p: int, theta_bh: float, targets: Optional[np.ndarray] = None,

@@ -1229,3 +1229,76 @@ int orc_fmm_derivs(const orc_tree *t, int order, const double *mom, int p, int K
     free(L);
     return 0;
 }
+
+/* Eq. 6 differentiated K times: d^k phi = sum_{s<=|n|<=p} M_n D_{n+k}(x - zA)
+ * for |k| = K (derivative tensor to order p + K) */
+void orc_m2p_derivs(int p, int s, const double *zA, const double *M, const double *x, int K, double *out)
+{
+    int nk = (K + 1) * (K + 2) / 2, k0 = orc_nterms(K - 1);
+    double *D = malloc(sizeof(double) * orc_nterms(p + K));
+    orc_dtensor(p + K, x[0] - zA[0], x[1] - zA[1], x[2] - zA[2], D);
+    for (int c = 0; c < nk; ++c) {
+        int k[3];
+        orc_multi_index(k0 + c, k);
+        double acc = 0.0;
+        for (int j = orc_nterms(s - 1); j < orc_nterms(p); ++j) {
+            int m[3];
+            orc_multi_index(j, m);
+            acc += M[j] * D[orc_index(m[0] + k[0], m[1] + k[1], m[2] + k[2])];
+        }
+        out[c] = acc;
+    }
+    free(D);
+}
+
+/* Barnes-Hut derivatives of order K at the listed targets: the traversal of
+ * orc_bh_eval (Eq. 12, the target's own cell never accepted), with the K-th
+ * derivatives of M2P for an accepted cell and of the pair potentials for an
+ * unaccepted leaf */
+int orc_bh_derivs(const orc_tree *t, int order, const double *mom, int p, double theta_bh, int K, int64_t nt_,
+                  const int64_t *targets, double *out)
+{
+    if (!orc_code_valid(order) || K < 1 || K > ORC_TABLE_P) return 1;
+    int s = orc_min_order(order);
+    if (p < s || !(theta_bh > 0.0 && theta_bh < 1.0)) return 1;
+    int w = mom_width(order), ntM = orc_nterms(p), nk = (K + 1) * (K + 2) / 2;
+    double *ms = sorted_moments(t, order, mom);
+    double *M = upward(t, order, ms, p);
+    int64_t cnt = targets ? nt_ : t->n;
+    double th2 = theta_bh * theta_bh;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < cnt; ++k) {
+        int64_t i = targets ? t->iperm[targets[k]] : k;
+        int64_t o = targets ? k : t->perm[i];
+        const double *x = t->xs + 3 * i;
+        double acc[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2], part[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2];
+        for (int c = 0; c < nk; ++c) acc[c] = 0.0;
+        int64_t stack[8 * (ORC_MAXLEVEL + 2)];
+        int sp = 0;
+        stack[sp++] = 0;
+        while (sp > 0) {
+            int64_t a = stack[--sp];
+            double zA[3], rA;
+            orc_cell_center(t, a, zA, &rA);
+            double d[3] = {x[0] - zA[0], x[1] - zA[1], x[2] - zA[2]};
+            double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!cell_contains(t, a, i) && (rA * rA < th2 * d2)) {
+                orc_m2p_derivs(p, s, zA, M + (size_t)a * ntM, x, K, part);
+                for (int c = 0; c < nk; ++c) acc[c] += part[c];
+            } else if (is_leaf(t, a)) {
+                for (int64_t j = t->first[a]; j < t->first[a] + t->count[a]; ++j) {
+                    if (j == i) continue;
+                    double r[3] = {x[0] - t->xs[3 * j], x[1] - t->xs[3 * j + 1], x[2] - t->xs[3 * j + 2]};
+                    orc_pair_derivs(order, K, r, ms + w * j, part);
+                    for (int c = 0; c < nk; ++c) acc[c] += part[c];
+                }
+            } else {
+                for (int64_t ch = t->child0[a] + t->nchild[a] - 1; ch >= t->child0[a]; --ch) stack[sp++] = ch;
+            }
+        }
+        for (int c = 0; c < nk; ++c) out[(size_t)nk * o + c] = acc[c];
+    }
+    free(M);
+    free(ms);
+    return 0;
+}

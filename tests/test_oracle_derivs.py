@@ -161,3 +161,72 @@ def test_fmm_derivatives_of_mixed_sources_superpose(orc):
     d = t.fmm_derivs(w.order, w.moments, 6, 3)
     parts = [t.fmm_derivs(k, w.moments[:, a:b].squeeze(), 6, 3) for k, (a, b) in enumerate(((0, 1), (1, 4), (4, 10)))]
     assert orc.rel_l2(d, sum(parts)) < 1e-12
+
+
+@pytest.mark.parametrize("p,s", [(4, 0), (6, 1), (8, 2)])
+def test_m2p_order_three_is_the_derivative_of_the_m2p_gradient(orc, p, s):
+    """Barnes-Hut: Eq. 6 differentiated three times against central
+    differences of the closed-contraction M2P gradient; orders 1 and 2 equal
+    -E and -G of the M2P field and gradient"""
+    rng = np.random.default_rng(91 + p)
+    M = rng.standard_normal(orc.nterms(p))
+    M[:orc.nterms(s - 1)] = 0.0
+    zA = rng.uniform(-0.2, 0.2, 3)
+    h = 1e-5
+    for _ in range(3):
+        x = zA + rng.uniform(1.5, 2.5, 3) * rng.choice([-1, 1], 3)
+        assert np.allclose(orc.m2p_derivs(p, s, zA, M, x, 1), -orc.m2p(p, s, zA, M, x)[1], rtol=1e-12, atol=0)
+        G = orc.m2p_grad(p, s, zA, M, x)
+        assert np.abs(orc.m2p_derivs(p, s, zA, M, x, 2) + G).max() <= 1e-13 * np.abs(G).max()
+        d3 = orc.m2p_derivs(p, s, zA, M, x, 3)
+        for k in _mi(3):
+            l = max(a for a in range(3) if k[a] > 0)
+            rest = list(k)
+            rest[l] -= 1
+            i = next(a for a in range(3) if rest[a] > 0)
+            rest[i] -= 1
+            j = next(a for a in range(3) if rest[a] > 0)
+            e = np.zeros(3)
+            e[l] = h
+            fd = -(_g(orc.m2p_grad(p, s, zA, M, x + e), i, j) - _g(orc.m2p_grad(p, s, zA, M, x - e), i, j)) / (2 * h)
+            assert abs(d3[_pos(3, k)] - fd) <= 1e-6 * np.abs(d3).max(), (k, d3[_pos(3, k)], fd)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_bh_derivatives_converge_to_direct(orc, order):
+    """order 3 of Barnes-Hut (Eq. 12 traversal) against the direct sum as p
+    grows; a tiny opening angle accepts nothing, so the direct sum itself;
+    orders 1 and 2 equal -E and -G of the Barnes-Hut field and gradient"""
+    rng = np.random.default_rng(95 + order)
+    n = 1500
+    pos = rng.random((n, 3))
+    mom = rng.standard_normal((n, [1, 3, 6][order]))
+    mom = mom[:, 0] if order == 0 else mom
+    dd = orc.direct_derivs(pos, order, mom, 3)
+    t = orc.Tree(pos, 16)
+    errs = [orc.rel_l2(t.bh_derivs(order, mom, p, 0.5, 3), dd) for p in (max(order, 1), order + 3, 8)]
+    assert errs[2] < errs[1] < errs[0] and errs[-1] < 5e-3, errs
+    assert orc.rel_l2(t.bh_derivs(order, mom, 4, 1e-6, 3), dd) < 1e-13
+    _, E, G = t.bh(order, mom, 5, 0.5, want_grad=True)
+    assert orc.rel_l2(t.bh_derivs(order, mom, 5, 0.5, 1), -E) < 1e-13
+    assert orc.rel_l2(t.bh_derivs(order, mom, 5, 0.5, 2), -G) < 1e-13
+    d3 = t.bh_derivs(order, mom, 5, 0.5, 3)
+    tr = sum(d3[:, _pos(3, (2 * (a == 0) + 1, 2 * (a == 1), 2 * (a == 2)))] for a in range(3))
+    assert np.abs(tr).max() <= 1e-9 * np.abs(d3).max()
+
+
+def test_bh_derivatives_target_at_cell_corner(orc):
+    """theta 0.6 > 1/sqrt(3): a target in the corner of its leaf would accept
+    its own cell without the self-cell rule; with it, the third derivatives
+    at that target converge to the direct sum as p grows"""
+    rng = np.random.default_rng(97)
+    src = rng.random((300, 3)) * 0.5
+    pos = np.vstack([src, [[0.4985] * 3, [0.0, 0.0, 0.0], [1.0, 0.3, 0.3]]])
+    q = rng.standard_normal(len(pos))
+    tg = np.array([300])
+    dd = orc.direct_derivs(pos, 0, q, 3, targets=tg)
+    t = orc.Tree(pos, 16)
+    errs = [orc.rel_l2(t.bh_derivs(0, q, p, 0.6, 3, targets=tg), dd) for p in range(1, 11)]
+    # a single target's error need not fall at every step: over two it does
+    assert all(b < a for a, b in zip(errs, errs[2:])), errs
+    assert errs[-1] < 1e-3, errs

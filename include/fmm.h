@@ -183,11 +183,13 @@ int fmm_evaluate_grad_noalloc(fmm_ctx *ctx, fmm_tree *tree, int outputs, double 
  * caller's particle order; the columns are d^k phi for the multi-indices of
  * order K in the index order (n_x descending, then n_y): K = 1 gives -E,
  * K = 2 gives -G of fmm_evaluate_grad, K = 3 the ten third derivatives
- * d_i d_j d_l phi = -d_i d_j E_l.  Computed in FP64 from the tree's locals
- * (which come from the FP32 M2L in MIXED precision) and its sorted FP64
- * moments.  FMM trees only; K <= p - s (the truncated local expansion has no
- * derivative of higher order); FMM_EINVAL otherwise, FMM_ESTATE before
- * fmm_upward. */
+ * d_i d_j d_l phi = -d_i d_j E_l.  Computed in FP64 from the tree's
+ * expansions (in MIXED precision the FMM locals come from the FP32 M2L) and
+ * its sorted FP64 moments.  FMM trees: K <= p - s (the truncated local
+ * expansion has no derivative of higher order).  Barnes-Hut trees: Eq. 6
+ * differentiated K times for every cell the particle accepts (Eq. 12, own
+ * cell never accepted) plus the pairs of the unaccepted leaves, any p.
+ * FMM_EINVAL for other K, FMM_ESTATE before fmm_upward. */
 int fmm_evaluate_derivs(fmm_ctx *ctx, fmm_tree *tree, int K, double *out);
 
 /* Tree sizes: info[0..9] = n, ncells, nlevels, nleaves, n_m2l, n_p2p,

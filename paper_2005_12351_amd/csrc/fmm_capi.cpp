@@ -902,8 +902,15 @@ extern "C" int fmm_evaluate_derivs(fmm_ctx *ctx, fmm_tree *t, int K, double *out
     if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
     if (!out) FAIL(FMM_EINVAL, "out is NULL");
     if (K < 1 || K > 3) FAIL(FMM_EINVAL, "derivative order %d (1, 2 or 3)", K);
-    if (t->method != FMM_METHOD_FMM) FAIL(FMM_EINVAL, "derivatives of any order are built for FMM trees only");
     if (!t->have_up) FAIL(FMM_ESTATE, "fmm_upward has not run on this tree");
+    if (t->method == FMM_METHOD_BH) {
+        // Eq. 6 differentiated K times on the Eq. 12 traversal: no truncation
+        // limit beyond the multipole order itself
+        HIPCHK(hipSetDevice(ctx->device));
+        ProfScope ps(ctx, ctx->stream, "bh_derivs");
+        KCHK(launch_bh_derivs(t, K, out, ctx->stream));
+        return FMM_OK;
+    }
     if (K > t->p - t->order)
         FAIL(FMM_EINVAL, "derivative order %d exceeds p - s = %d: the truncated local expansion has no "
                          "derivative of that order", K, t->p - t->order);

@@ -309,6 +309,7 @@ hipError_t launch_p2p_part(fmm_tree *t, hipStream_t s, int first, int count);
 // derivatives of order K (1..3) of the potential at every particle, out in
 // caller order, (K+1)(K+2)/2 per particle; needs the locals (M2L, L2L) queued
 hipError_t launch_derivs(fmm_tree *t, int K, double *out, hipStream_t s);
+hipError_t launch_bh_derivs(fmm_tree *t, int K, double *out, hipStream_t s);
 
 // serving (serve.cpp)
 int serve_destroy(fmm_ctx *ctx);

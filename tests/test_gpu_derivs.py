@@ -2,7 +2,9 @@
 potential, Section 2 / Eq. 10) against the oracle's derivatives on the same
 tree, lists and truncation.  The GPU computes them in FP64 from the tree's
 locals, which come from the FP32 M2L in MIXED precision, so MIXED is held to
-the gradient's bounds and FP64 to FP64's."""
+the gradient's bounds and FP64 to FP64's.  Barnes-Hut trees (Eq. 6
+differentiated K times on the Eq. 12 traversal) read the FP64 multipoles,
+which both precisions form alike, so both are held to FP64's bounds."""
 import numpy as np
 import pytest
 
@@ -91,10 +93,15 @@ def test_derivative_errors(ctx):
     assert e.value.code == fmm.FMM_EINVAL
     t.close()
     tb = fmm.Tree(ctx, pos, w.ncrit, w.theta, fmm.FMM_METHOD_BH)
-    tb.upward(1, mom, 3, fmm.FMM_PREC_FP64)
     with pytest.raises(fmm.FMMError) as e:
-        tb.evaluate_derivs(1)
-    assert e.value.code == fmm.FMM_EINVAL
+        tb.evaluate_derivs(1)                      # before fmm_upward
+    assert e.value.code == fmm.FMM_ESTATE
+    tb.upward(1, mom, 1, fmm.FMM_PREC_FP64)
+    for K in (0, 4):
+        with pytest.raises(fmm.FMMError) as e:
+            tb.evaluate_derivs(K)
+        assert e.value.code == fmm.FMM_EINVAL
+    tb.evaluate_derivs(3)                          # Barnes-Hut: no p - s limit
     tb.close()
 
 
@@ -112,5 +119,72 @@ def test_derivatives_full_size_sampled(orc, ctx):
         d = t.evaluate_derivs(3)
         torch.cuda.synchronize()
         ok &= within(d[s].cpu().numpy(), ref, prec, f"precision={prec}: order 3 on the samples", TOL[prec])
+    t.close()
+    assert ok
+
+
+# Barnes-Hut per-target bound: the derivative tensor reaches order p + K = 13;
+# its Hermite form (GPU) and the oracle's recurrence differ there by up to
+# 3e-12 of the order's largest component (both FP64), ten times the bound on
+# the orders the FMM uses
+BH_TOL = (1e-10, 1e-11)
+
+BH_CASES = [(1, 6, "plummer", 3000, 32, 0.6), (1, 6, "plummer", 3000, 32, 0.3), (0, 4, "uniform", 2000, 16, 0.5),
+            (2, 5, "lattice", 3375, 64, 0.4), (1, 1, "plummer", 2000, 16, 0.5), (0, 10, "uniform", 700, 4, 0.5),
+            (16 + 7, 6, "plummer", 2000, 16, 0.6)]
+
+
+@pytest.mark.parametrize("order,p,kind,n,ncrit,theta", BH_CASES)
+def test_bh_derivatives_match_oracle(orc, ctx, order, p, kind, n, ncrit, theta):
+    if order >= 16:
+        w = W.small_mixed(2400 + n, n, order - 16, kind, p=p, theta=theta, ncrit=ncrit)
+    else:
+        w = W.small_random(2400 + n + order, n, order, kind)
+    print(f"[bh derivs] order={order} p={p} {kind} n={n} ncrit={ncrit} theta={theta}", flush=True)
+    ot = orc.Tree(w.pos, ncrit)
+    ok = True
+    for K in (1, 2, 3):
+        ref = ot.bh_derivs(w.order, w.moments, p, theta, K)
+        got = {}
+        for prec in (fmm.FMM_PREC_FP64, fmm.FMM_PREC_MIXED):
+            t = fmm.Tree(ctx, to_dev(w.pos), ncrit, theta, fmm.FMM_METHOD_BH)
+            t.upward(w.order, to_dev(w.moments), p, prec)
+            got[prec] = t.evaluate_derivs(K)
+            torch.cuda.synchronize()
+            got[prec] = got[prec].cpu().numpy()
+            t.close()
+        ok &= within(got[fmm.FMM_PREC_FP64], ref, fmm.FMM_PREC_FP64, f"BH order {K} vs oracle", BH_TOL)
+        # the multipoles are FP64 in both precisions: the same numbers
+        ok &= bool(np.array_equal(got[fmm.FMM_PREC_FP64], got[fmm.FMM_PREC_MIXED]))
+    assert ok
+
+
+def test_bh_orders_one_and_two_agree_with_field_and_gradient(ctx):
+    w = W.small_random(2500, 5000, 1, "plummer")
+    t = fmm.Tree(ctx, to_dev(w.pos), 32, 0.5, fmm.FMM_METHOD_BH)
+    t.upward(1, to_dev(w.moments), 7, fmm.FMM_PREC_FP64)
+    _, E, G = t.evaluate_grad()
+    d1, d2, d3 = t.evaluate_derivs(1), t.evaluate_derivs(2), t.evaluate_derivs(3)
+    torch.cuda.synchronize()
+    ok = within(d1.cpu().numpy(), -E.cpu().numpy(), "fp64", "BH order 1 vs -E")
+    ok &= within(d2.cpu().numpy(), -G.cpu().numpy(), "fp64", "BH order 2 vs -G")
+    assert ok
+    d3 = d3.cpu().numpy()
+    for l, cols in ((0, (0, 3, 5)), (1, (1, 6, 8)), (2, (2, 7, 9))):
+        assert np.abs(d3[:, cols[0]] + d3[:, cols[1]] + d3[:, cols[2]]).max() <= 1e-9 * np.abs(d3).max()
+    t.close()
+
+
+def test_bh_derivatives_full_size_sampled(orc, ctx):
+    """the 10^6-dipole Barnes-Hut workload (theta 0.6, p 6, ncrit 128), order
+    3 on the oracle's 4 096 sampled targets"""
+    w = W.config(3)
+    ref = orc.Tree(w.pos, w.ncrit).bh_derivs(w.order, w.moments, w.p, w.theta, 3, targets=w.sample)
+    t = fmm.Tree(ctx, to_dev(w.pos), w.ncrit, w.theta, fmm.FMM_METHOD_BH)
+    t.upward(w.order, to_dev(w.moments), w.p, fmm.FMM_PREC_MIXED)
+    d = t.evaluate_derivs(3)
+    torch.cuda.synchronize()
+    s = torch.from_numpy(w.sample).cuda()
+    ok = within(d[s].cpu().numpy(), ref, fmm.FMM_PREC_FP64, "BH order 3 on the samples", BH_TOL)
     t.close()
     assert ok

@@ -149,7 +149,8 @@ void orc_dtensor(int q, double x, double y, double z, double *D)
 /* ------------------------------------------------------------------ */
 /* Source order codes                                                    */
 /* ------------------------------------------------------------------ */
-/* A code is a single source order (0 charge, 1 dipole, 2 quadrupole) or
+/* A code is a single source order (0 charge, 1 dipole, 2 quadrupole,
+ * 3 octupole) or
  * ORC_MIXED plus a bit mask of the orders present in one system (bit k:
  * order k).  A moment row then holds the physical moments of the present
  * orders, in ascending order, concatenated.  Every operator is linear in the
@@ -158,28 +159,65 @@ void orc_dtensor(int q, double x, double y, double z, double *D)
 #define ORC_MIXED 16
 
 static int code_mask(int o) { return o >= ORC_MIXED ? o - ORC_MIXED : 1 << o; }
-static int width_of(int order) { return order == 0 ? 1 : (order == 1 ? 3 : 6); }
+static int width_of(int order) { return (order + 1) * (order + 2) / 2; }
 static int mom_width(int o)
 {
     int m = code_mask(o), w = 0;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         if (m & (1 << k)) w += width_of(k);
     return w;
 }
 int orc_min_order(int o)
 {
     int m = code_mask(o);
-    return (m & 1) ? 0 : ((m & 2) ? 1 : 2);
+    return (m & 1) ? 0 : ((m & 2) ? 1 : ((m & 4) ? 2 : 3));
 }
 int orc_code_valid(int o)
 {
-    return (o >= 0 && o <= 2) || (o > ORC_MIXED && o < ORC_MIXED + 8);
+    return (o >= 0 && o <= 3) || (o > ORC_MIXED && o < ORC_MIXED + 16);
+}
+
+/* the full symmetric octupole tensor O_ijk from its ten components, stored
+ * in the index order of order 3 (xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz) */
+static void octupole_tensor(const double *mom, double O[3][3][3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) {
+                int c[3] = {0, 0, 0};
+                c[i]++;
+                c[j]++;
+                c[k]++;
+                O[i][j][k] = mom[orc_index(c[0], c[1], c[2]) - orc_nterms(2)];
+            }
 }
 
 /* potential and field at a target displaced by r = x_target - x_source from
  * a source of one order with physical moment mom */
 static void pair_single(int order, const double *r, const double *mom, double *phi, double *E)
 {
+    if (order == 3) {
+        /* phi = -(1/6) sum_ijk O_ijk d_i d_j d_k (1/r)
+         *     = 5/2 O(r,r,r) / r^7 - 3/2 (t.r) / r^5,   t_k = sum_i O_iik;
+         * E = -grad phi = -15/2 V / r^7 + 35/2 O(r,r,r) r / r^9
+         *                 + 3/2 t / r^5 - 15/2 (t.r) r / r^7,
+         * V_k = sum_ij O_ijk r_i r_j */
+        double O[3][3][3], V[3] = {0, 0, 0}, t[3] = {0, 0, 0};
+        octupole_tensor(mom, O);
+        for (int k = 0; k < 3; ++k)
+            for (int i = 0; i < 3; ++i) {
+                t[k] += O[i][i][k];
+                for (int j = 0; j < 3; ++j) V[k] += O[i][j][k] * r[i] * r[j];
+            }
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        double rinv = 1.0 / sqrt(r2);
+        double r5 = rinv * rinv * rinv * rinv * rinv, r7 = r5 * rinv * rinv, r9 = r7 * rinv * rinv;
+        double C = V[0] * r[0] + V[1] * r[1] + V[2] * r[2];
+        double tr = t[0] * r[0] + t[1] * r[1] + t[2] * r[2];
+        *phi = 2.5 * C * r7 - 1.5 * tr * r5;
+        for (int k = 0; k < 3; ++k) E[k] = -7.5 * V[k] * r7 + 17.5 * C * r[k] * r9 + 1.5 * t[k] * r5 - 7.5 * tr * r[k] * r7;
+        return;
+    }
     double x = r[0], y = r[1], z = r[2];
     double r2 = x * x + y * y + z * z;
     double rinv = 1.0 / sqrt(r2);
@@ -221,7 +259,7 @@ void orc_p2p_pair(int o, const double *r, const double *mom, double *phi, double
     int m = code_mask(o), off = 0;
     *phi = 0.0;
     E[0] = E[1] = E[2] = 0.0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (!(m & (1 << k))) continue;
         double ph, e[3];
         pair_single(k, r, mom + off, &ph, e);
@@ -251,6 +289,34 @@ static void pair_grad_single(int order, const double *r, const double *mom, doub
     double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     double rinv = 1.0 / sqrt(r2);
     double r3 = rinv * rinv * rinv, r5 = r3 * rinv * rinv, r7 = r5 * rinv * rinv, r9 = r7 * rinv * rinv;
+    if (order == 3) {
+        /* octupole, phi = 5/2 C / r^7 - 3/2 (t.r) / r^5 with C = O(r,r,r),
+         * W_ij = sum_k O_ijk r_k, V = W r:
+         *   d_i d_j (C / r^7) = 6 W_ij / r^7 - 21 (V_i r_j + V_j r_i) / r^9
+         *                       - 7 C delta_ij / r^9 + 63 C r_i r_j / r^11
+         *   d_i d_j ((t.r) / r^5) = -5 (t_i r_j + t_j r_i) / r^7
+         *                           - 5 (t.r) delta_ij / r^7 + 35 (t.r) r_i r_j / r^9 */
+        double O[3][3][3], W[3][3], V[3] = {0, 0, 0}, t[3] = {0, 0, 0};
+        octupole_tensor(mom, O);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) W[i][j] = O[i][j][0] * r[0] + O[i][j][1] * r[1] + O[i][j][2] * r[2];
+        for (int i = 0; i < 3; ++i) {
+            V[i] = W[i][0] * r[0] + W[i][1] * r[1] + W[i][2] * r[2];
+            t[i] = O[0][0][i] + O[1][1][i] + O[2][2][i];
+        }
+        double C = V[0] * r[0] + V[1] * r[1] + V[2] * r[2];
+        double tr = t[0] * r[0] + t[1] * r[1] + t[2] * r[2];
+        double r11 = r9 * rinv * rinv;
+        for (int k = 0; k < 6; ++k) {
+            int i = I[k], j = J[k];
+            double dij = i == j ? 1.0 : 0.0;
+            double ddC = 6.0 * W[i][j] * r7 - 21.0 * (V[i] * r[j] + V[j] * r[i]) * r9 - 7.0 * C * dij * r9 +
+                         63.0 * C * r[i] * r[j] * r11;
+            double ddT = -5.0 * (t[i] * r[j] + t[j] * r[i]) * r7 - 5.0 * tr * dij * r7 + 35.0 * tr * r[i] * r[j] * r9;
+            G[k] = -(2.5 * ddC - 1.5 * ddT);
+        }
+        return;
+    }
     for (int k = 0; k < 6; ++k) {
         int i = I[k], j = J[k];
         double dij = i == j ? 1.0 : 0.0;
@@ -276,7 +342,7 @@ void orc_p2p_pair_grad(int o, const double *r, const double *mom, double *G)
 {
     int m = code_mask(o), off = 0;
     for (int k = 0; k < 6; ++k) G[k] = 0.0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (!(m & (1 << k))) continue;
         double g[6];
         pair_grad_single(k, r, mom + off, g);
@@ -353,13 +419,21 @@ static void source_tensor(int order, const double *mom, double *S)
         S[orc_index(1, 0, 0)] = -mom[0];
         S[orc_index(0, 1, 0)] = -mom[1];
         S[orc_index(0, 0, 1)] = -mom[2];
-    } else {
+    } else if (order == 2) {
         S[orc_index(2, 0, 0)] = mom[0] / 2.0;
         S[orc_index(1, 1, 0)] = mom[1];
         S[orc_index(1, 0, 1)] = mom[2];
         S[orc_index(0, 2, 0)] = mom[3] / 2.0;
         S[orc_index(0, 1, 1)] = mom[4];
         S[orc_index(0, 0, 2)] = mom[5] / 2.0;
+    } else {
+        /* octupole: the ten components O_m in the index order of order 3,
+         * S_m = -O_m / m! */
+        for (int c = 0; c < 10; ++c) {
+            int m[3];
+            orc_multi_index(orc_nterms(2) + c, m);
+            S[orc_nterms(2) + c] = -mom[c] / (factorial(m[0]) * factorial(m[1]) * factorial(m[2]));
+        }
     }
 }
 
@@ -372,12 +446,12 @@ void orc_p2m(int p, int o, const double *z, int64_t np, const double *pos,
     int nt = orc_nterms(p);
     int mask = code_mask(o);
     double *mono = malloc(sizeof(double) * nt);
-    double S[10];
+    double S[20];
     for (int64_t j = 0; j < np; ++j) {
         double d[3] = {z[0] - pos[3 * j], z[1] - pos[3 * j + 1], z[2] - pos[3 * j + 2]};
         monomials(p, d, mono);
         int off = 0;
-        for (int order = 0; order < 3; ++order) {
+        for (int order = 0; order < 4; ++order) {
         if (!(mask & (1 << order))) continue;
         source_tensor(order, mom + w * j + off, S);
         off += width_of(order);
@@ -1109,7 +1183,7 @@ static void pair_derivs_single(int order, int K, const double *r, const double *
 {
     int q = order + K;
     double *D = malloc(sizeof(double) * orc_nterms(q));
-    double S[10];
+    double S[20];
     orc_dtensor(q, r[0], r[1], r[2], D);
     source_tensor(order, mom, S);
     int nk = (K + 1) * (K + 2) / 2, k0 = orc_nterms(K - 1);
@@ -1133,7 +1207,7 @@ void orc_pair_derivs(int o, int K, const double *r, const double *mom, double *o
     int m = code_mask(o), off = 0, nk = (K + 1) * (K + 2) / 2;
     double part[(ORC_TABLE_P + 1) * (ORC_TABLE_P + 2) / 2];
     for (int c = 0; c < nk; ++c) out[c] = 0.0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (!(m & (1 << k))) continue;
         pair_derivs_single(k, K, r, mom + off, part);
         for (int c = 0; c < nk; ++c) out[c] += part[c];

@@ -84,7 +84,43 @@ def random_moments(rng: np.random.Generator, order: int, n: int, kind: str = "de
         q[:, 3] -= tr
         q[:, 5] -= tr
         return np.ascontiguousarray(q)
-    raise ValueError("order must be 0, 1 or 2")
+    if order == 3:
+        return traceless_octupoles(rng.standard_normal((n, 10)))
+    raise ValueError("order must be 0, 1, 2 or 3")
+
+
+# the ten components of an octupole in the index order of order 3
+OCT_INDEX = [(3, 0, 0), (2, 1, 0), (2, 0, 1), (1, 2, 0), (1, 1, 1), (1, 0, 2), (0, 3, 0), (0, 2, 1), (0, 1, 2),
+             (0, 0, 3)]
+
+
+def octupole_full(o: np.ndarray) -> np.ndarray:
+    """(n, 10) components -> (n, 3, 3, 3) symmetric tensors"""
+    o = np.asarray(o, dtype=np.float64).reshape(-1, 10)
+    T = np.empty((o.shape[0], 3, 3, 3))
+    for i in range(3):
+        for j in range(3):
+            for k in range(3):
+                c = [0, 0, 0]
+                c[i] += 1
+                c[j] += 1
+                c[k] += 1
+                T[:, i, j, k] = o[:, OCT_INDEX.index(tuple(c))]
+    return T
+
+
+def traceless_octupoles(o: np.ndarray) -> np.ndarray:
+    """remove the trace t_k = sum_i O_iik: O - (delta_ij t_k + delta_ik t_j +
+    delta_jk t_i) / 5"""
+    T = octupole_full(o)
+    t = np.einsum("niik->nk", T)
+    d = np.eye(3)
+    T = T - (np.einsum("ij,nk->nijk", d, t) + np.einsum("ik,nj->nijk", d, t) + np.einsum("jk,ni->nijk", d, t)) / 5.0
+    return np.ascontiguousarray(np.stack([T[:, a, b, c] for a, b, c in map(_axes, OCT_INDEX)], axis=1))
+
+
+def _axes(c):
+    return [a for a in range(3) for _ in range(c[a])]
 
 
 def sample_targets(seed: int, n: int, k: int = 4096) -> np.ndarray:
@@ -183,8 +219,8 @@ def small_random(seed: int, n: int, order: int, kind: str = "uniform", p: int = 
 
 
 def mixed_moments(rng: np.random.Generator, mask: int, n: int) -> np.ndarray:
-    """Rows [q | mu | Q] of the orders present in ``mask`` (bit k: order k)."""
-    parts = [random_moments(rng, k, n).reshape(n, -1) for k in range(3) if mask & (1 << k)]
+    """Rows [q | mu | Q | O] of the orders present in ``mask`` (bit k: order k)."""
+    parts = [random_moments(rng, k, n).reshape(n, -1) for k in range(4) if mask & (1 << k)]
     return np.ascontiguousarray(np.concatenate(parts, axis=1))
 
 

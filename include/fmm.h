@@ -5,10 +5,13 @@
  * Cartesian Fast Multipole and Barnes-Hut Methods" (arXiv 2005.12351).
  *
  * What is computed (Section 2): the potential phi(x_i) = sum_{j != i} of the
- * field of point sources of order m (0 monopole, 1 dipole, 2 quadrupole) with
- * the Coulomb kernel 1/|x_i - x_j| (Eq. 1, no 1/(4 pi) factor), and the field
- * E = -grad phi.  Physical moments: phi = q/r, phi = mu.r/r^3,
- * phi = 1/2 sum_ij Q_ij d_i d_j (1/r) with r = x_target - x_source.
+ * field of point sources of order m (0 monopole, 1 dipole, 2 quadrupole,
+ * 3 octupole) with the Coulomb kernel 1/|x_i - x_j| (Eq. 1, no 1/(4 pi)
+ * factor), and the field E = -grad phi.  Physical moments: phi = q/r,
+ * phi = mu.r/r^3, phi = 1/2 sum_ij Q_ij d_i d_j (1/r),
+ * phi = -1/6 sum_ijk O_ijk d_i d_j d_k (1/r) with r = x_target - x_source
+ * (each the order-m term of the multipole series of a charge cloud with
+ * moments sum q x^m).
  *
  * Method (Section 3.2): an adaptive octree split while a cell holds more than
  * ncrit particles, P2M at the leaves (Eq. 3, Eq. 5), M2M upward (Eq. 4), then
@@ -82,13 +85,14 @@ enum {
 
 #define FMM_P_MAX 10     /* largest expansion order p compiled in */
 
-/* Source order codes.  0, 1, 2: every particle is a charge, a dipole or a
- * quadrupole.  FMM_MIXED | mask: several orders in one system (mask bit k:
- * order k present, e.g. FMM_MIXED | 3 for charges with dipoles); each moment
- * row then holds the present orders' moments in ascending order, [q | mu |
- * Qxx Qxy Qxz Qyy Qyz Qzz], and the expansions start at the lowest order
- * present (Section 2: the multipole series of a point source of order s
- * starts at order s; a system's series is the sum of its sources'). */
+/* Source order codes.  0, 1, 2, 3: every particle is a charge, a dipole, a
+ * quadrupole or an octupole.  FMM_MIXED | mask: several orders in one system
+ * (mask bit k: order k present, e.g. FMM_MIXED | 3 for charges with dipoles);
+ * each moment row then holds the present orders' moments in ascending order,
+ * [q | mu | Qxx Qxy Qxz Qyy Qyz Qzz | Oxxx Oxxy Oxxz Oxyy Oxyz Oxzz Oyyy
+ * Oyyz Oyzz Ozzz], and the expansions start at the lowest order present
+ * (Section 2: the multipole series of a point source of order s starts at
+ * order s; a system's series is the sum of its sources'). */
 #define FMM_MIXED 16
 
 /* Context on HIP device `device`; `hip_stream` is a hipStream_t (NULL: the
@@ -122,10 +126,10 @@ int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int ncrit, double
  * S_n = (-1)^|n| T_n / n! of the physical moment T) and M2M towards the root
  * (Eq. 4), expansion order p; for FMM trees also the near field (direct
  * sums over the P2P lists, Section 3.2) into library-owned storage, since it
- * depends only on the moments.  order: a source order code (0, 1, 2 or
+ * depends only on the moments.  order: a source order code (0, 1, 2, 3 or
  * FMM_MIXED | mask, see above) with lowest order s; s+1 <= p <= FMM_P_MAX
  * for FMM, max(s,1) <= p <= FMM_P_MAX for BH.  `moments`: device, n x w FP64
- * row-major (w = 1, 3, 6 for one order, the sum of the present orders'
+ * row-major (w = 1, 3, 6, 10 for one order, the sum of the present orders'
  * widths for several), caller-owned, read only by the work this call queues
  * on the context stream (a sorted copy is kept). */
 int fmm_upward(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int p,

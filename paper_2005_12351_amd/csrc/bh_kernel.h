@@ -59,7 +59,7 @@ template <int P, int S, typename T, bool H, bool GRAD>
 __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
 {
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int W = S == 0 ? 1 : (S == 1 ? 3 : 6);
+    constexpr int W = (S + 1) * (S + 2) / 2;
     __shared__ int stk_c[kStack];
     __shared__ unsigned long long stk_m[kStack];
     const int lane = threadIdx.x;
@@ -148,6 +148,11 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
                             if (a.mask & 4) {
                                 p2p_pair_f64<2>(rx, ry, rz, mj + off, ph, ex, ey, ez);
                                 if constexpr (GRAD) p2p_pair_grad_f64<2>(rx, ry, rz, mj + off, g);
+                                off += 6;
+                            }
+                            if (a.mask & 8) {
+                                p2p_pair_oct_f64(rx, ry, rz, mj + off, ph, ex, ey, ez);
+                                if constexpr (GRAD) p2p_pair_grad_oct_f64(rx, ry, rz, mj + off, g);
                             }
                         }
                     } else if (F32) {
@@ -160,12 +165,21 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
                             const float rx = (float)((xi - a.xs[j]) * ir), ry = (float)((yi - a.xs[n + j]) * ir),
                                         rz = (float)((zi - a.xs[2 * n + j]) * ir);
                             const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
-                            const float4 *m4 = reinterpret_cast<const float4 *>(a.m32) + 2 * (size_t)j;
+                            const float4 *m4 =
+                                reinterpret_cast<const float4 *>(a.m32) + (size_t)(m32_width(1 << S) / 4) * j;
                             const float inv = __builtin_amdgcn_rsqf(r2);
-                            p2p_pair_f32<S>(rx, ry, rz, inv, m4[0], m4[1], bp, bx, by, bz);
-                            if constexpr (GRAD) p2p_pair_grad_f32<S>(rx, ry, rz, inv, m4[0], m4[1], bg);
+                            if constexpr (S == 3) {
+                                p2p_pair_oct_f32(rx, ry, rz, inv, m4[0], m4[1], m4[2], m4[3], bp, bx, by, bz);
+                                if constexpr (GRAD) p2p_pair_grad_oct_f32(rx, ry, rz, inv, m4[0], m4[1], m4[2], m4[3], bg);
+                            } else {
+                                p2p_pair_f32<S>(rx, ry, rz, inv, m4[0], m4[1], bp, bx, by, bz);
+                                if constexpr (GRAD) p2p_pair_grad_f32<S>(rx, ry, rz, inv, m4[0], m4[1], bg);
+                            }
                         }
-                        const double sphi = S == 0 ? ir : (S == 1 ? ir * ir : ir * ir * ir), sfld = sphi * ir;
+                        double sphi = ir;
+#pragma unroll
+                        for (int q = 0; q < S; ++q) sphi *= ir;
+                        const double sfld = sphi * ir;
                         ph += (double)bp * sphi;
                         ex += (double)bx * sfld;
                         ey += (double)by * sfld;
@@ -179,8 +193,13 @@ __global__ __launch_bounds__(64) void bh_kernel(BHArgs a)
                         for (int j = cell.first; j < cell.first + cell.count; ++j) {
                             if (j == i) continue;
                             const double rx = xi - a.xs[j], ry = yi - a.xs[n + j], rz = zi - a.xs[2 * n + j];
-                            p2p_pair_f64<S>(rx, ry, rz, a.m64 + (size_t)j * W, ph, ex, ey, ez);
-                            if constexpr (GRAD) p2p_pair_grad_f64<S>(rx, ry, rz, a.m64 + (size_t)j * W, g);
+                            if constexpr (S == 3) {
+                                p2p_pair_oct_f64(rx, ry, rz, a.m64 + (size_t)j * W, ph, ex, ey, ez);
+                                if constexpr (GRAD) p2p_pair_grad_oct_f64(rx, ry, rz, a.m64 + (size_t)j * W, g);
+                            } else {
+                                p2p_pair_f64<S>(rx, ry, rz, a.m64 + (size_t)j * W, ph, ex, ey, ez);
+                                if constexpr (GRAD) p2p_pair_grad_f64<S>(rx, ry, rz, a.m64 + (size_t)j * W, g);
+                            }
                         }
                     }
                 }
@@ -244,6 +263,12 @@ bh_fn bh_pick_p(int p, bool f32, bool h)
 template <bool GRAD>
 bh_fn bh_select(int s, int p, bool f32, bool h)
 {
-    return s == 0 ? bh_pick_p<GRAD, 0>(p, f32, h) : (s == 1 ? bh_pick_p<GRAD, 1>(p, f32, h) : bh_pick_p<GRAD, 2>(p, f32, h));
+    switch (s) {
+    case 0: return bh_pick_p<GRAD, 0>(p, f32, h);
+    case 1: return bh_pick_p<GRAD, 1>(p, f32, h);
+    case 2: return bh_pick_p<GRAD, 2>(p, f32, h);
+    case 3: return bh_pick_p<GRAD, 3>(p, f32, h);
+    default: return nullptr;
+    }
 }
 

@@ -69,11 +69,15 @@ __device__ __forceinline__ double dtensor_k(int kx, int ky, int kz, const double
 }
 
 // the source tensor of one order from its physical moments (S_0 = q,
-// S_{e_i} = -mu_i, S_{e_i+e_j} = Q_ij / (e_i+e_j)!), in the index order of
-// that order
-__device__ __forceinline__ void source_of(int s, const double *t, double (&S)[6])
+// S_{e_i} = -mu_i, S_{e_i+e_j} = Q_ij / (e_i+e_j)!, S_m = -O_m / m! for an
+// octupole), in the index order of that order
+__device__ __forceinline__ void source_of(int s, const double *t, double (&S)[10])
 {
-    if (s == 0) {
+    if (s == 3) {
+        constexpr double kInvF[10] = {1.0 / 6, 0.5, 0.5, 0.5, 1.0, 0.5, 1.0 / 6, 0.5, 0.5, 1.0 / 6};
+#pragma unroll
+        for (int q = 0; q < 10; ++q) S[q] = -t[q] * kInvF[q];
+    } else if (s == 0) {
         S[0] = t[0];
     } else if (s == 1) {
         S[0] = -t[0];
@@ -110,7 +114,7 @@ __device__ __forceinline__ void pair_derivs_add(double rx, double ry, double rz,
                                                 double (&acc)[(K + 1) * (K + 2) / 2])
 {
     constexpr int NK = (K + 1) * (K + 2) / 2;
-    constexpr int Q = K + 2;                 // highest derivative order a pair needs (quadrupoles)
+    constexpr int Q = K + 3;                 // highest derivative order a pair needs (octupoles)
     const double r2 = rx * rx + ry * ry + rz * rz;
     const double ir = 1.0 / sqrt(r2), ir2 = ir * ir;
     double px[Q + 1], py[Q + 1], pz[Q + 1], F[Q + 1];
@@ -124,11 +128,11 @@ __device__ __forceinline__ void pair_derivs_add(double rx, double ry, double rz,
         F[d] = -F[d - 1] * (2.0 * d - 1.0) * ir2;
     }
     int off = 0;
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 4; ++s) {
         if (!(smask & (1 << s))) continue;
-        double S[6];
+        double S[10];
         source_of(s, mj + off, S);
-        off += s == 0 ? 1 : (s == 1 ? 3 : 6);
+        off += (s + 1) * (s + 2) / 2;
         const int nm = (s + 1) * (s + 2) / 2;
         for (int mi = 0; mi < nm; ++mi) {
             int mx, my, mz;

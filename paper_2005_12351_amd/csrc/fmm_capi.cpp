@@ -671,8 +671,8 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 static int check_upward_args(fmm_ctx *ctx, fmm_tree *t, int order, const double *moments, int p, int precision)
 {
     if (!ctx || !t || t->ctx != ctx) FAIL(FMM_EINVAL, "null or foreign context/tree");
-    if (!((order >= 0 && order <= 2) || (order > FMM_MIXED && order < FMM_MIXED + 8)))
-        FAIL(FMM_EINVAL, "source order code %d is neither 0, 1, 2 nor FMM_MIXED | mask", order);
+    if (!((order >= 0 && order <= 3) || (order > FMM_MIXED && order < FMM_MIXED + 16)))
+        FAIL(FMM_EINVAL, "source order code %d is neither 0, 1, 2, 3 nor FMM_MIXED | mask", order);
     if (!moments) FAIL(FMM_EINVAL, "moments are NULL");
     if (precision != FMM_PREC_FP64 && precision != FMM_PREC_MIXED) FAIL(FMM_EINVAL, "unknown precision %d", precision);
     const int s = mask_min_order(code_mask(order));
@@ -784,7 +784,7 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
 // reciprocal square root = 1), potential and field
 static double p2p_flops_mask(int m)
 {
-    return (m & 1 ? 20.0 : 0.0) + (m & 2 ? 32.0 : 0.0) + (m & 4 ? 58.0 : 0.0);
+    return (m & 1 ? 20.0 : 0.0) + (m & 2 ? 32.0 : 0.0) + (m & 4 ? 58.0 : 0.0) + (m & 8 ? 100.0 : 0.0);
 }
 
 // algorithmic work of an evaluation (see fmm_work_counts)

@@ -25,16 +25,27 @@ constexpr int kGraphKey = 10;        // arguments a captured launch sequence is 
 
 struct MultiIndex { int8_t x, y, z, k; };
 
-// Source order codes: 0, 1, 2 for one order, or FMM_MIXED + a bit mask of the
-// orders present in one system (bit k: order k); moment rows hold the
-// present orders' physical moments in ascending order.
+// Source order codes: 0, 1, 2, 3 for one order (charge, dipole, quadrupole,
+// octupole), or FMM_MIXED + a bit mask of the orders present in one system
+// (bit k: order k); moment rows hold the present orders' physical moments in
+// ascending order, (k+1)(k+2)/2 values for order k.
 __host__ __device__ constexpr int code_mask(int code) { return code >= FMM_MIXED ? code - FMM_MIXED : 1 << code; }
-__host__ __device__ constexpr int mask_width(int m) { return (m & 1 ? 1 : 0) + (m & 2 ? 3 : 0) + (m & 4 ? 6 : 0); }
-__host__ __device__ constexpr int mask_min_order(int m) { return m & 1 ? 0 : (m & 2 ? 1 : 2); }
-__host__ __device__ constexpr bool mask_single(int m) { return m == 1 || m == 2 || m == 4; }
-// FP32 moments per particle: 8 floats for one order (q | mu | six Q and the
-// trace), 12 for several ([q mu] [xx xy xz yy] [yz zz tr 0], absent parts 0)
-__host__ __device__ constexpr int m32_width(int m) { return mask_single(m) ? 8 : 12; }
+__host__ __device__ constexpr int mask_width(int m)
+{
+    return (m & 1 ? 1 : 0) + (m & 2 ? 3 : 0) + (m & 4 ? 6 : 0) + (m & 8 ? 10 : 0);
+}
+__host__ __device__ constexpr int mask_min_order(int m) { return m & 1 ? 0 : (m & 2 ? 1 : (m & 4 ? 2 : 3)); }
+__host__ __device__ constexpr bool mask_single(int m) { return m == 1 || m == 2 || m == 4 || m == 8; }
+// FP32 moments per particle, in float4 groups: one order of 0..2: 8 floats
+// (q | mu | six Q and the trace); octupoles alone: 16 ([O xxx xxy xxz xyy]
+// [xyz xzz yyy yyz] [yzz zzz t_x t_y] [t_z 0 0 0], t the trace vector
+// t_k = sum_i O_iik); several orders: 12 ([q mu] [xx xy xz yy] [yz zz tr 0],
+// absent parts 0), followed by the 16 of the octupole block when that order
+// is present
+__host__ __device__ constexpr int m32_width(int m)
+{
+    return mask_single(m) ? (m == 8 ? 16 : 8) : ((m & 8) ? 28 : 12);
+}
 
 // Harmonic (reduced) basis: the components with n_z <= 1 of every order, in
 // storage order; order l holds 2l+1 of them and starts at index l^2.

@@ -133,7 +133,7 @@ def main(outdir):
              "template <int P, int S, typename T> struct M2PEvalH;",
              "template <int P, int S, typename T> struct M2PEvalG;",
              "template <int P, int S, typename T> struct M2PEvalGH;", ""]
-    for s in (0, 1, 2):
+    for s in (0, 1, 2, 3):
         for p in range(max(s, 1), P_MAX + 1):
             for fp32 in (True, False):
                 for h in (False, True):

@@ -649,7 +649,7 @@ def gen_file(s, fp32, opt=None, harmonic=False, mfma=False):
 def main(outdir, opt=None):
     os.makedirs(outdir, exist_ok=True)
     written = []
-    for s in (0, 1, 2):
+    for s in (0, 1, 2, 3):
         for fp32, h, mf in ((True, False, False), (False, False, False), (True, True, False), (False, True, False),
                             (True, True, True)):
             fn = os.path.join(outdir, f"m2l_s{s}_{'f32' if fp32 else 'f64'}{'_h' if h else ''}{'m' if mf else ''}.hip")

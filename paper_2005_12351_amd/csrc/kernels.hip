@@ -88,22 +88,29 @@ hipError_t launch_prep_positions(fmm_tree *t, const double *pos, hipStream_t s)
 }
 
 // Sorted moments of particle i (sorted order; perm maps it to the caller's
-// row): FP64 (the caller's row of w values) and FP32 (one order: 8 floats,
-// q | mu | the six Q components and their trace; several orders: 12 floats,
-// [q mu] [xx xy xz yy] [yz zz tr 0], absent parts zero).  P2M writes them
-// while it visits every particle once; the near field reads them.
+// row): FP64 (the caller's row of w values) and FP32 in the layout m32_width
+// describes.  P2M writes them while it visits every particle once; the near
+// field reads them.
 __device__ __forceinline__ void sort_moments(size_t i, int mask, const double *__restrict__ r,
                                              double *__restrict__ m64, float *__restrict__ m32)
 {
-    const int w = mask_width(mask);
-    float v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int w = mask_width(mask), wf = m32_width(mask);
+    float v[28];
+#pragma unroll
+    for (int k = 0; k < 28; ++k) v[k] = 0.f;
     for (int k = 0; k < w; ++k) m64[i * w + k] = r[k];
-    if (mask_single(mask)) {
+    // the octupole block: ten components and the trace vector
+    auto oct = [&](const double *o, int at) {
+        for (int k = 0; k < 10; ++k) v[at + k] = (float)o[k];
+        v[at + 10] = (float)(o[0] + o[3] + o[5]);
+        v[at + 11] = (float)(o[1] + o[6] + o[8]);
+        v[at + 12] = (float)(o[2] + o[7] + o[9]);
+    };
+    if (mask == 8) {
+        oct(r, 0);
+    } else if (mask_single(mask)) {
         for (int k = 0; k < w; ++k) v[k] = (float)r[k];
         if (w == 6) v[6] = (float)(r[0] + r[3] + r[5]);
-        float4 *o = reinterpret_cast<float4 *>(m32) + 2 * i;
-        o[0] = make_float4(v[0], v[1], v[2], v[3]);
-        o[1] = make_float4(v[4], v[5], v[6], v[7]);
     } else {
         int off = 0;
         if (mask & 1) v[0] = (float)r[off++];
@@ -116,12 +123,12 @@ __device__ __forceinline__ void sort_moments(size_t i, int mask, const double *_
         if (mask & 4) {
             for (int k = 0; k < 6; ++k) v[4 + k] = (float)r[off + k];
             v[10] = (float)(r[off] + r[off + 3] + r[off + 5]);
+            off += 6;
         }
-        float4 *o = reinterpret_cast<float4 *>(m32) + 3 * i;
-        o[0] = make_float4(v[0], v[1], v[2], v[3]);
-        o[1] = make_float4(v[4], v[5], v[6], v[7]);
-        o[2] = make_float4(v[8], v[9], v[10], v[11]);
+        if (mask & 8) oct(r + off, 12);
     }
+    float4 *o = reinterpret_cast<float4 *>(m32) + (size_t)(wf / 4) * i;
+    for (int k = 0; k < wf / 4; ++k) o[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
 }
 
 // ------------------------------------------------------------------ P2M
@@ -131,9 +138,9 @@ __device__ __forceinline__ void sort_moments(size_t i, int mask, const double *_
 // orders adds each part's expansion.  One workgroup per leaf; particles are
 // staged in LDS 32 at a time as per-axis tables X_a = zeta_x^a/a! (and Y, Z).
 // Two kernels, chosen by the source orders:
-// - p2m_coef_kernel (charges and dipoles): a thread owns one or more
-//   coefficients n and adds every particle's term, 1 + 3 products of table
-//   entries per particle;
+// - p2m_coef_kernel (charges and dipoles, and any system with octupoles): a
+//   thread owns one or more coefficients n and adds every particle's term,
+//   1 + 3 (+ 6 + 10) products of table entries per particle;
 // - p2m_kernel (any quadrupole part): the monomial factorises over the axes
 //   and sigma has at most two units, so for a fixed column (ax, ay) the
 //   particle's contribution to every coefficient (ax, ay, az) is
@@ -189,10 +196,11 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_coef_kernel(int p, int nmp, c
 {
     constexpr int W = mask_width(MASK);
     constexpr int S = mask_min_order(MASK);
-    constexpr bool Q0 = MASK & 1, Q1 = MASK & 2, Q2 = MASK & 4;
-    // source tensor slots: 0 order 0; 1..3 order 1; 4..9 order 2
+    constexpr bool Q0 = MASK & 1, Q1 = MASK & 2, Q2 = MASK & 4, Q3 = MASK & 8;
+    // source tensor slots: 0 order 0; 1..3 order 1; 4..9 order 2; 10..19
+    // order 3 (index order within each order)
     __shared__ double pw[kP2MStage][3][kAxWc];
-    __shared__ double sv[kP2MStage][10];
+    __shared__ double sv[kP2MStage][20];
     const int c = leaves[blockIdx.x];
     const DevCell cell = cells[c];
     double z[3];
@@ -248,6 +256,15 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_coef_kernel(int p, int nmp, c
                 sv[t][7] = 0.5 * m[off + 3] * ir2;   // (0,2,0)
                 sv[t][8] = m[off + 4] * ir2;         // (0,1,1)
                 sv[t][9] = 0.5 * m[off + 5] * ir2;   // (0,0,2)
+                off += 6;
+            }
+            if (Q3) {
+                // S_m = -O_m / m!: m! = 6 for (3,0,0)-type, 2 for (2,1,0)-type,
+                // 1 for (1,1,1)
+                const double ir3 = ir * ir * ir;
+                constexpr double kInvF[10] = {1.0 / 6, 0.5, 0.5, 0.5, 1.0, 0.5, 1.0 / 6, 0.5, 0.5, 1.0 / 6};
+#pragma unroll
+                for (int q = 0; q < 10; ++q) sv[t][10 + q] = -m[off + q] * kInvF[q] * ir3;
             }
         }
         __syncthreads();
@@ -260,7 +277,7 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_coef_kernel(int p, int nmp, c
                 // a zero table entry stands for a negative index
                 const double px0 = pw[t][0][ax], py0 = pw[t][1][ay], pz0 = pw[t][2][az];
                 if (Q0) a = fma(px0 * py0, pz0 * sv[t][0], a);
-                if (Q1 || Q2) {
+                if (Q1 || Q2 || Q3) {
                     const double px1 = ax >= 1 ? pw[t][0][ax - 1] : 0.0, py1 = ay >= 1 ? pw[t][1][ay - 1] : 0.0,
                                  pz1 = az >= 1 ? pw[t][2][az - 1] : 0.0;
                     if (Q1) {
@@ -277,6 +294,22 @@ __global__ __launch_bounds__(kP2MThreads) void p2m_coef_kernel(int p, int nmp, c
                         a = fma(px0 * py2, pz0 * sv[t][7], a);
                         a = fma(px0 * py1, pz1 * sv[t][8], a);
                         a = fma(px0 * py0, pz2 * sv[t][9], a);
+                    }
+                    if (Q3) {
+                        const double px2 = ax >= 2 ? pw[t][0][ax - 2] : 0.0, py2 = ay >= 2 ? pw[t][1][ay - 2] : 0.0,
+                                     pz2 = az >= 2 ? pw[t][2][az - 2] : 0.0;
+                        const double px3 = ax >= 3 ? pw[t][0][ax - 3] : 0.0, py3 = ay >= 3 ? pw[t][1][ay - 3] : 0.0,
+                                     pz3 = az >= 3 ? pw[t][2][az - 3] : 0.0;
+                        a = fma(px3 * py0, pz0 * sv[t][10], a);   // (3,0,0)
+                        a = fma(px2 * py1, pz0 * sv[t][11], a);   // (2,1,0)
+                        a = fma(px2 * py0, pz1 * sv[t][12], a);   // (2,0,1)
+                        a = fma(px1 * py2, pz0 * sv[t][13], a);   // (1,2,0)
+                        a = fma(px1 * py1, pz1 * sv[t][14], a);   // (1,1,1)
+                        a = fma(px1 * py0, pz2 * sv[t][15], a);   // (1,0,2)
+                        a = fma(px0 * py3, pz0 * sv[t][16], a);   // (0,3,0)
+                        a = fma(px0 * py2, pz1 * sv[t][17], a);   // (0,2,1)
+                        a = fma(px0 * py1, pz2 * sv[t][18], a);   // (0,1,2)
+                        a = fma(px0 * py0, pz3 * sv[t][19], a);   // (0,0,3)
                     }
                 }
             }
@@ -539,7 +572,7 @@ static void p2m_launch(fmm_tree *t, hipStream_t s)
     const int nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     float *m32 = t->prec == FMM_PREC_MIXED ? t->d_M32 : nullptr;
     const HarmOut ho = harm_out(t);
-    if constexpr (!(MASK & 4)) {
+    if constexpr (!(MASK & 4) || (MASK & 8)) {
         hipLaunchKernelGGL(p2m_coef_kernel<MASK>, dim3((unsigned)t->nleaves), dim3(kP2MThreads), 0, s, t->p, nmp,
                            t->d_leaves, t->d_cells, g, t->d_x, (int)t->ht.n, t->mom_user, t->d_perm, t->d_mom,
                            t->d_mom32, t->d_M64, m32, ho.nhp, ho.h32, ho.h64);
@@ -564,6 +597,14 @@ hipError_t launch_p2m(fmm_tree *t, hipStream_t s)
     case 5: p2m_launch<5>(t, s); break;
     case 6: p2m_launch<6>(t, s); break;
     case 7: p2m_launch<7>(t, s); break;
+    case 8: p2m_launch<8>(t, s); break;
+    case 9: p2m_launch<9>(t, s); break;
+    case 10: p2m_launch<10>(t, s); break;
+    case 11: p2m_launch<11>(t, s); break;
+    case 12: p2m_launch<12>(t, s); break;
+    case 13: p2m_launch<13>(t, s); break;
+    case 14: p2m_launch<14>(t, s); break;
+    case 15: p2m_launch<15>(t, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -880,33 +921,39 @@ __device__ __forceinline__ int p2p_entry(const int *wstart, int nw, int j)
 }
 
 // the pair terms of one source of several orders: each order's terms go to
-// its own sums (the orders scale differently with the leaf radius)
-template <int MASK>
-__device__ __forceinline__ void p2p_pair_mixed(float rx, float ry, float rz, float inv, const float4 &m0,
-                                               const float4 &m1, const float4 &m2, float (&bp)[3], float (&bx)[3],
-                                               float (&by)[3], float (&bz)[3])
+// its own sums (the orders scale differently with the leaf radius); mv is the
+// particle's staged FP32 block (m32_width)
+template <int MASK, int NV>
+__device__ __forceinline__ void p2p_pair_mixed(float rx, float ry, float rz, float inv, const float4 (&mv)[NV],
+                                               float (&bp)[4], float (&bx)[4], float (&by)[4], float (&bz)[4])
 {
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (MASK & 1) p2p_pair_f32<0>(rx, ry, rz, inv, m0, z4, bp[0], bx[0], by[0], bz[0]);
-    if (MASK & 2)
-        p2p_pair_f32<1>(rx, ry, rz, inv, make_float4(m0.y, m0.z, m0.w, 0.f), z4, bp[1], bx[1], by[1], bz[1]);
-    if (MASK & 4) p2p_pair_f32<2>(rx, ry, rz, inv, m1, m2, bp[2], bx[2], by[2], bz[2]);
+    if constexpr (MASK & 1) p2p_pair_f32<0>(rx, ry, rz, inv, mv[0], z4, bp[0], bx[0], by[0], bz[0]);
+    if constexpr (MASK & 2)
+        p2p_pair_f32<1>(rx, ry, rz, inv, make_float4(mv[0].y, mv[0].z, mv[0].w, 0.f), z4, bp[1], bx[1], by[1], bz[1]);
+    if constexpr (MASK & 4) p2p_pair_f32<2>(rx, ry, rz, inv, mv[1], mv[2], bp[2], bx[2], by[2], bz[2]);
+    if constexpr (MASK & 8) p2p_pair_oct_f32(rx, ry, rz, inv, mv[3], mv[4], mv[5], mv[6], bp[3], bx[3], by[3], bz[3]);
 }
 
-template <int MASK>
-__device__ __forceinline__ void p2p_pair_grad_mixed(float rx, float ry, float rz, float inv, const float4 &m0,
-                                                    const float4 &m1, const float4 &m2, float (&g)[6][3])
+template <int MASK, int NV>
+__device__ __forceinline__ void p2p_pair_grad_mixed(float rx, float ry, float rz, float inv, const float4 (&mv)[NV],
+                                                    float (&g)[6][4])
 {
     const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
     float t[6];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (!(MASK & (1 << k))) continue;
 #pragma unroll
         for (int c = 0; c < 6; ++c) t[c] = g[c][k];
-        if (k == 0) p2p_pair_grad_f32<0>(rx, ry, rz, inv, m0, z4, t);
-        if (k == 1) p2p_pair_grad_f32<1>(rx, ry, rz, inv, make_float4(m0.y, m0.z, m0.w, 0.f), z4, t);
-        if (k == 2) p2p_pair_grad_f32<2>(rx, ry, rz, inv, m1, m2, t);
+        if constexpr (MASK & 1)
+            if (k == 0) p2p_pair_grad_f32<0>(rx, ry, rz, inv, mv[0], z4, t);
+        if constexpr (MASK & 2)
+            if (k == 1) p2p_pair_grad_f32<1>(rx, ry, rz, inv, make_float4(mv[0].y, mv[0].z, mv[0].w, 0.f), z4, t);
+        if constexpr (MASK & 4)
+            if (k == 2) p2p_pair_grad_f32<2>(rx, ry, rz, inv, mv[1], mv[2], t);
+        if constexpr (MASK & 8)
+            if (k == 3) p2p_pair_grad_oct_f32(rx, ry, rz, inv, mv[3], mv[4], mv[5], mv[6], t);
 #pragma unroll
         for (int c = 0; c < 6; ++c) g[c][k] = t[c];
     }
@@ -922,15 +969,19 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
     constexpr int NO = GRAD ? 6 : 4;                 // output components
     constexpr bool ONE = mask_single(MASK);
     constexpr int S = mask_min_order(MASK);
-    constexpr int NV = ONE ? (S == 2 ? 2 : 1) : 3;   // float4 of moments per staged source
-    constexpr int MW = m32_width(MASK) / 4;          // float4 of moments per particle
+    // float4 of moments per staged source (the parts the pair terms read) and
+    // per particle in the sorted FP32 moments
+    constexpr int NV = ONE ? (S == 3 ? 4 : (S == 2 ? 2 : 1)) : ((MASK & 8) ? 7 : 3);
+    constexpr int MW = m32_width(MASK) / 4;
+    // sources per chunk: half as many for the wide octupole blocks
+    constexpr int CH = NV > 3 ? kPChunk32 / 2 : kPChunk32;
     // the staging area doubles as the reduction buffer at the end of a pass
     // (8 KB less LDS per workgroup, one more workgroup per CU)
     __shared__ double sbuf[3 * kPChunk32];
-    double *const spx = sbuf, *const spy = sbuf + kPChunk32, *const spz = sbuf + 2 * kPChunk32;
+    double *const spx = sbuf, *const spy = sbuf + CH, *const spz = sbuf + 2 * CH;
     static_assert(NO * kPT <= 3 * kPChunk32, "reduction buffer exceeds the staging area");
     double (*const red)[kPT] = reinterpret_cast<double (*)[kPT]>(sbuf);
-    __shared__ float4 spm[NV][kPChunk32];
+    __shared__ float4 spm[NV][CH];
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
     __shared__ int sh[kPT / 64];
@@ -942,13 +993,15 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
     const double rb = ldexp(1.0, kMaxLevel - cb.level) * a.h;
     const double irb = 1.0 / rb;
     // physical scale of the order-k sums: potential r_b^-(k+1), field r_b^-(k+2)
-    double sphi[3], sfld[3];
+    double sphi[4], sfld[4];
     sphi[0] = irb;
     sphi[1] = irb * irb;
     sphi[2] = sphi[1] * irb;
+    sphi[3] = sphi[2] * irb;
     sfld[0] = sphi[1];
     sfld[1] = sphi[2];
-    sfld[2] = sphi[2] * irb;
+    sfld[2] = sphi[3];
+    sfld[3] = sphi[3] * irb;
     // scale of output component c of the order-k sums
     auto scale = [&](int c, int k) { return GRAD ? sfld[k] * irb : (c == 0 ? sphi[k] : sfld[k]); };
     double zb[3];
@@ -973,11 +1026,11 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
         const double tx = (a.xs[i] - zb[0]) * irb, ty = (a.xs[n + i] - zb[1]) * irb,
                      tz = (a.xs[2 * n + i] - zb[2]) * irb;
         // Kahan-compensated sums per output component and source order
-        float ks[NO][3], kc[NO][3];
+        float ks[NO][4], kc[NO][4];
 #pragma unroll
         for (int c = 0; c < NO; ++c)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) ks[c][k] = kc[c][k] = 0.f;
+            for (int k = 0; k < 4; ++k) ks[c][k] = kc[c][k] = 0.f;
         for (int w0 = e0; w0 < e1; w0 += kPList) {
             const int nw = min(kPList, e1 - w0);
             __syncthreads();
@@ -988,7 +1041,7 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
             // is padded with zero sources far away (their terms are exactly
             // zero), so every slice takes the same number of sources and the
             // pair loop runs on a counter common to the whole workgroup
-            const int cstep = (kPChunk32 / ns) * ns;
+            const int cstep = (CH / ns) * ns;
             for (int c0 = 0; c0 < nsw; c0 += cstep) {
                 const int nc = min(cstep, nsw - c0);
                 const int per = (nc + ns - 1) / ns;   // sources per slice
@@ -1016,44 +1069,47 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
                     // the per-pair test (the same for the whole workgroup)
                     const int jself = wself >= 0 ? wself + tg0 + t - c0 : -1;
                     const bool own = wself >= 0 && wself < c0 + nc && wself + cb.count > c0;
-                    float bs[NO][3];
+                    float bs[NO][4];
 #pragma unroll
                     for (int c = 0; c < NO; ++c)
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) bs[c][k] = 0.f;
-                    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int k = 0; k < 4; ++k) bs[c][k] = 0.f;
                     auto pairs = [&](auto check) {
                     for (int jj = 0; jj < per; ++jj) {
                         const int j = ja + jj;
                         const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
                         const float inv = (decltype(check)::value && j == jself) ? 0.f : __builtin_amdgcn_rsqf(r2);
-                        const float4 m0 = spm[0][j];
-                        const float4 m1 = NV >= 2 ? spm[NV >= 2 ? 1 : 0][j] : zero4;
+                        float4 mv[NV];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) mv[v] = spm[v][j];
                         if constexpr (GRAD) {
                             if constexpr (ONE) {
                                 float t6[6];
 #pragma unroll
                                 for (int c = 0; c < 6; ++c) t6[c] = bs[c][S];
-                                p2p_pair_grad_f32<S>(rx, ry, rz, inv, m0, m1, t6);
+                                if constexpr (S == 3) p2p_pair_grad_oct_f32(rx, ry, rz, inv, mv[0], mv[1], mv[2], mv[3], t6);
+                                else p2p_pair_grad_f32<S>(rx, ry, rz, inv, mv[0], mv[NV > 1 ? 1 : 0], t6);
 #pragma unroll
                                 for (int c = 0; c < 6; ++c) bs[c][S] = t6[c];
                             } else {
-                                const float4 m2 = spm[NV >= 3 ? 2 : 0][j];
-                                p2p_pair_grad_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bs);
+                                p2p_pair_grad_mixed<MASK, NV>(rx, ry, rz, inv, mv, bs);
                             }
                         } else if constexpr (ONE) {
-                            p2p_pair_f32<S>(rx, ry, rz, inv, m0, m1, bs[0][S], bs[1][S], bs[2][S], bs[3][S]);
+                            if constexpr (S == 3)
+                                p2p_pair_oct_f32(rx, ry, rz, inv, mv[0], mv[1], mv[2], mv[3], bs[0][3], bs[1][3], bs[2][3],
+                                                 bs[3][3]);
+                            else p2p_pair_f32<S>(rx, ry, rz, inv, mv[0], mv[NV > 1 ? 1 : 0], bs[0][S], bs[1][S], bs[2][S],
+                                                 bs[3][S]);
                         } else {
-                            const float4 m2 = spm[NV >= 3 ? 2 : 0][j];
-                            p2p_pair_mixed<MASK>(rx, ry, rz, inv, m0, m1, m2, bs[0], bs[1], bs[2], bs[3]);
+                            p2p_pair_mixed<MASK, NV>(rx, ry, rz, inv, mv, bs[0], bs[1], bs[2], bs[3]);
                         }
                     }
                     };
                     if (own) pairs(std::true_type{});
                     else pairs(std::false_type{});
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
+                    for (int k = 0; k < 4; ++k) {
                         if (!(MASK & (1 << k))) continue;
 #pragma unroll
                         for (int c = 0; c < NO; ++c) kahan_add(ks[c][k], kc[c][k], bs[c][k]);
@@ -1066,7 +1122,7 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
         for (int c = 0; c < NO; ++c) {
             double q = 0.0;
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < 4; ++k) {
                 if (!(MASK & (1 << k))) continue;
                 q += ((double)ks[c][k] - (double)kc[c][k]) * scale(c, k);
             }
@@ -1171,13 +1227,15 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f64_kernel(P2PArgs a)
                         for (int c = 0; c < W; ++c) m[c] = sm[c][j];
                         // a source of several orders adds each order's terms
                         if constexpr (GRAD) {
-                            if (MASK & 1) p2p_pair_grad_f64<0>(rx, ry, rz, m, g);
-                            if (MASK & 2) p2p_pair_grad_f64<1>(rx, ry, rz, m + (MASK & 1), g);
-                            if (MASK & 4) p2p_pair_grad_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), g);
+                            if constexpr (MASK & 1) p2p_pair_grad_f64<0>(rx, ry, rz, m, g);
+                            if constexpr (MASK & 2) p2p_pair_grad_f64<1>(rx, ry, rz, m + (MASK & 1), g);
+                            if constexpr (MASK & 4) p2p_pair_grad_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), g);
+                            if constexpr (MASK & 8) p2p_pair_grad_oct_f64(rx, ry, rz, m + mask_width(MASK & 7), g);
                         } else {
-                            if (MASK & 1) p2p_pair_f64<0>(rx, ry, rz, m, ph, ex, ey, ez);
-                            if (MASK & 2) p2p_pair_f64<1>(rx, ry, rz, m + (MASK & 1), ph, ex, ey, ez);
-                            if (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
+                            if constexpr (MASK & 1) p2p_pair_f64<0>(rx, ry, rz, m, ph, ex, ey, ez);
+                            if constexpr (MASK & 2) p2p_pair_f64<1>(rx, ry, rz, m + (MASK & 1), ph, ex, ey, ez);
+                            if constexpr (MASK & 4) p2p_pair_f64<2>(rx, ry, rz, m + mask_width(MASK & 3), ph, ex, ey, ez);
+                            if constexpr (MASK & 8) p2p_pair_oct_f64(rx, ry, rz, m + mask_width(MASK & 7), ph, ex, ey, ez);
                         }
                     }
                     };
@@ -1279,6 +1337,14 @@ static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int fi
         P2P_CASE(5)
         P2P_CASE(6)
         P2P_CASE(7)
+        P2P_CASE(8)
+        P2P_CASE(9)
+        P2P_CASE(10)
+        P2P_CASE(11)
+        P2P_CASE(12)
+        P2P_CASE(13)
+        P2P_CASE(14)
+        P2P_CASE(15)
     default: return hipErrorInvalidValue;
     }
 #undef P2P_CASE

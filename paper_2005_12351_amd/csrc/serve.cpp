@@ -227,7 +227,7 @@ extern "C" int fmm_submit(fmm_ctx *ctx, const fmm_request *req, uint64_t *ticket
         return FMM_ESTATE;
     }
     const fmm_request &r = *req;
-    const bool code_ok = (r.order >= 0 && r.order <= 2) || (r.order > FMM_MIXED && r.order < FMM_MIXED + 8);
+    const bool code_ok = (r.order >= 0 && r.order <= 3) || (r.order > FMM_MIXED && r.order < FMM_MIXED + 16);
     const int s = code_ok ? mask_min_order(code_mask(r.order)) : 0;
     const int pmin = r.method == FMM_METHOD_BH ? std::max(s, 1) : s + 1;
     if (r.n < 1 || !code_ok || r.p < pmin || r.p > FMM_P_MAX || r.ncrit < 1 ||

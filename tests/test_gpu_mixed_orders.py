@@ -71,7 +71,7 @@ def test_mixed_codes_rejected(ctx):
     pos = torch.from_numpy(w.pos).cuda()
     mom = torch.from_numpy(w.moments).cuda()
     t = fmm.Tree(ctx, pos, 8, 0.5)
-    for bad in (3, fmm.FMM_MIXED, fmm.FMM_MIXED + 8, -1):
+    for bad in (4, fmm.FMM_MIXED, fmm.FMM_MIXED + 16, -1):
         with pytest.raises(fmm.FMMError) as e:
             t.upward(bad, mom, 4)
         assert e.value.code == fmm.FMM_EINVAL

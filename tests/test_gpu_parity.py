@@ -365,6 +365,6 @@ def test_error_codes(ctx):
     with pytest.raises(fmm.FMMError):
         t.upward(0, q, 0)            # p < order + 1
     with pytest.raises(fmm.FMMError):
-        t.upward(3, q, 4)            # bad order
+        t.upward(4, q, 5)            # bad order
     with pytest.raises(fmm.FMMError):
         t.upward(0, q, fmm.FMM_P_MAX + 1)

@@ -33,7 +33,9 @@ def _sources(gen_dir, gen_opt):
     gen = gen_m2l.main(gen_dir, gen_opt)
     gen_bh.main(gen_dir)
     sys.path.pop(0)
-    srcs = [(os.path.join(CSRC, "kernels.hip"), []),
+    srcs = [(os.path.join(CSRC, "p2p_lo.hip"), []),
+            (os.path.join(CSRC, "p2p_oct.hip"), []),
+            (os.path.join(CSRC, "kernels.hip"), []),
             (os.path.join(CSRC, "m2l.hip"), []),
             (os.path.join(CSRC, "fmm_capi.cpp"), ["-ffp-contract=off"]),
             (os.path.join(CSRC, "tree_host.cpp"), ["-ffp-contract=off"]),

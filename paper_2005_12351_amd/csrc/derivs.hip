@@ -30,9 +30,9 @@ struct DerivArgs {
     const DevCell *cells;
     const double *xs;      // sorted positions, SoA
     const double *mom;     // sorted moments, w per particle
-    const double *L;       // normalised locals, nl per cell
+    const double *L;       // normalised locals, nl per cell (harmonic basis: nlh, the n_z <= 1 part)
     double *out;           // nk per particle, caller order
-    int n, nl, q, w, smask;
+    int n, nl, nlh, q, w, smask;
     double h, lo[3];
 };
 
@@ -106,6 +106,14 @@ __device__ __forceinline__ void mi_of(int K, int c, int &nx, int &ny, int &nz)
     nz = K - nx - ny;
 }
 
+// multi-index of position idx in the ordering by total order
+__device__ __forceinline__ void mi_at(int idx, int &nx, int &ny, int &nz)
+{
+    int o = 0;
+    while (nterms(o) <= idx) ++o;
+    mi_of(o, idx - nterms(o - 1), nx, ny, nz);
+}
+
 // the K-th derivatives of the pair potentials of one source (every order
 // its mask holds) at displacement (rx, ry, rz), added to acc
 template <int K>
@@ -153,7 +161,24 @@ __global__ __launch_bounds__(kDT) void derivs_kernel(DerivArgs a)
     const int lk = blockIdx.x;
     const int b = a.leaves[lk];
     const DevCell cb = a.cells[b];
-    for (int i = threadIdx.x; i < a.nl; i += kDT) sL[i] = a.L[(size_t)b * a.nl + i];
+    if (a.nlh > 0) {
+        // harmonic basis: the row is rebuilt from its n_z <= 1 components,
+        // (a, b, 2j + r) = (-1)^j sum_i C(j, i) (a + 2i, b + 2(j - i), r)
+        const double *R = a.L + (size_t)b * a.nlh;
+        for (int i = threadIdx.x; i < a.nl; i += kDT) {
+            int nx, ny, nz;
+            mi_at(i, nx, ny, nz);
+            const int j = nz >> 1, r = nz & 1;
+            double acc = 0.0, w = 1.0;
+            for (int k = 0; k <= j; ++k) {
+                acc = fma(w, R[hindex(nx + 2 * k, ny + 2 * (j - k), r)], acc);
+                w = w * (j - k) / (k + 1);
+            }
+            sL[i] = (j & 1) ? -acc : acc;
+        }
+    } else {
+        for (int i = threadIdx.x; i < a.nl; i += kDT) sL[i] = a.L[(size_t)b * a.nl + i];
+    }
     __syncthreads();
     const double r = ldexp(1.0, kMaxLevel - cb.level) * a.h;
     const double zb[3] = {a.lo[0] + (double)(2 * cb.ix + 1) * r, a.lo[1] + (double)(2 * cb.iy + 1) * r,
@@ -214,10 +239,10 @@ struct BHDerivArgs {
     const DevCell *cells;
     const double *xs;      // sorted positions, SoA
     const double *mom;     // sorted moments, w per particle
-    const double *M;       // normalised multipoles, rows of nmp from order s
+    const double *M;       // normalised multipoles, rows of nmp from order s (folded: harmonic order)
     const int32_t *perm;
     double *out;           // nk per particle, caller order
-    int n, p, s, nmp, w, smask;
+    int n, p, s, nmp, w, smask, folded;
     double theta2, h, lo[3];
 };
 
@@ -228,13 +253,6 @@ __device__ __forceinline__ void wave_sync_d()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// multi-index of position idx in the ordering by total order
-__device__ __forceinline__ void mi_at(int idx, int &nx, int &ny, int &nz)
-{
-    int o = 0;
-    while (nterms(o) <= idx) ++o;
-    mi_of(o, idx - nterms(o - 1), nx, ny, nz);
-}
 
 template <int K>
 __global__ __launch_bounds__(64 * kBW) void bh_derivs_kernel(BHDerivArgs a)
@@ -314,10 +332,14 @@ __global__ __launch_bounds__(64 * kBW) void bh_derivs_kernel(BHDerivArgs a)
             double tq[NK];
 #pragma unroll
             for (int q = 0; q < NK; ++q) tq[q] = 0.0;
-            const double *Mc = a.M + (size_t)c * a.nmp - n0;
-            for (int j = n0 + lane; j < n1; j += 64) {
+            // a folded row holds the m_z <= 1 components: D_{.+k} is
+            // harmonic, so contracting them gives the same sums
+            const int j0 = a.folded ? hterms(a.s - 1) : n0, j1 = a.folded ? hterms(a.p) : n1;
+            const double *Mc = a.M + (size_t)c * a.nmp - j0;
+            for (int j = j0 + lane; j < j1; j += 64) {
                 int mx, my, mz;
-                mi_at(j, mx, my, mz);
+                if (a.folded) hmulti(j, mx, my, mz);
+                else mi_at(j, mx, my, mz);
                 const double mv = Mc[j];
 #pragma unroll
                 for (int q = 0; q < NK; ++q)
@@ -371,6 +393,7 @@ hipError_t launch_derivs(fmm_tree *t, int K, double *out, hipStream_t s)
     a.n = (int)t->ht.n;
     a.q = t->p - t->order;
     a.nl = nterms(a.q);
+    a.nlh = t->basis == FMM_M2L_HARMONIC ? hterms(a.q) : 0;
     a.w = mask_width(t->smask);
     a.smask = t->smask;
     a.h = t->ht.h;
@@ -392,13 +415,15 @@ hipError_t launch_bh_derivs(fmm_tree *t, int K, double *out, hipStream_t s)
     a.cells = t->d_cells;
     a.xs = t->d_x;
     a.mom = t->d_mom;
-    a.M = t->d_M64;
+    a.folded = t->basis == FMM_M2L_HARMONIC;
+    // the FP64 upward state: full rows, or folded ones in the harmonic basis
+    a.M = a.folded ? (t->prec == FMM_PREC_MIXED ? t->d_Mf64 : (const double *)t->d_Mh) : t->d_M64;
     a.perm = t->d_perm;
     a.out = out;
     a.n = (int)t->ht.n;
     a.p = t->p;
     a.s = t->order;
-    a.nmp = (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
+    a.nmp = a.folded ? t->nhp : (nterms(t->p) - nterms(t->order - 1) + 3) / 4 * 4;
     a.w = mask_width(t->smask);
     a.smask = t->smask;
     a.theta2 = t->theta * t->theta;

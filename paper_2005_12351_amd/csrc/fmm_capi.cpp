@@ -528,7 +528,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     const int eng = t->ctx->m2l_engine;
     const bool mfma = fmm && harm && prec == FMM_PREC_MIXED &&
                       (eng == FMM_M2L_ENGINE_MFMA || (eng == FMM_M2L_ENGINE_AUTO && p >= 8));
-    if (t->d_M64 && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis &&
+    if (t->d_mom && t->order == order && t->smask == smask && t->p == p && t->prec == prec && t->basis == basis &&
         t->mfma == mfma)
         return FMM_OK;
     drop_graphs(t);
@@ -537,7 +537,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     // call sets it up again whatever its parameters
     t->p = -1;
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32, &t->d_Mh,
-                      (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_near_g,
+                      (void **)&t->d_Mf64, (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_near_g,
                       (void **)&t->d_D64,
                       (void **)&t->d_D32, (void **)&t->d_sc64, (void **)&t->d_sc32, (void **)&t->d_work,
                       (void **)&t->d_tile_chunk0, (void **)&t->d_tile_nchunk, (void **)&t->d_wave_ptr}) {
@@ -550,9 +550,21 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     int rc;
     if ((rc = tree_alloc(t, (void **)&t->d_mom, sizeof(double) * mask_width(smask) * n)) ||
         (rc = tree_alloc(t, (void **)&t->d_mom32, sizeof(float) * m32_width(smask) * n)) ||
-        (rc = tree_alloc(t, (void **)&t->d_M64, sizeof(double) * (nc + 1) * nmp)) ||
         (rc = tree_alloc(t, (void **)&t->d_near, sizeof(double) * 4 * n)))
         return rc;
+    // full rows are the upward state of the full basis only; the harmonic
+    // basis keeps folded rows (below)
+    if (!harm && (rc = tree_alloc(t, (void **)&t->d_M64, sizeof(double) * (nc + 1) * nmp))) return rc;
+    // the FP64 folded rows of the harmonic basis in MIXED (in FP64 the M2L's
+    // own rows are the state), row stride nhp
+    auto alloc_state = [&](int nhp) -> int {
+        if (!harm || prec != FMM_PREC_MIXED) return FMM_OK;
+        int r = tree_alloc(t, (void **)&t->d_Mf64, sizeof(double) * (size_t)(nc + 1) * nhp);
+        if (r) return r;
+        hipError_t e = launch_fill(t->d_Mf64, (size_t)(nc + 1) * nhp, t->ctx->stream);
+        if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+        return FMM_OK;
+    };
     // the full FP32 copy feeds the full-basis M2L and the Barnes-Hut M2P
     if (prec == FMM_PREC_MIXED && !harm && (rc = tree_alloc(t, (void **)&t->d_M32, sizeof(float) * (nc + 1) * nmp)))
         return rc;
@@ -567,6 +579,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         if ((rc = tree_alloc(t, &t->d_Mh, es * (size_t)(nc + 1) * nhp))) return rc;
         hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * nhp / 8, t->ctx->stream);
         if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+        if ((rc = alloc_state(nhp))) return rc;
     }
     if (fmm) {
         M2LVariant v;
@@ -593,7 +606,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             return rc;
         HIPCHK(hipStreamSynchronize(st));
         if ((rc = tree_alloc(t, &t->d_part, es * (size_t)std::max<int64_t>(1, t->m2lwork.nrows) * v.nl_pad)) ||
-            (rc = tree_alloc(t, (void **)&t->d_L64, sizeof(double) * nc * nl)) ||
+            (rc = tree_alloc(t, (void **)&t->d_L64, sizeof(double) * nc * (harm ? hterms(p - order) : nl))) ||
             (rc = tree_alloc(t, (void **)&t->d_D64, sizeof(double) * nc_ * v.nd)) ||
             (rc = tree_alloc(t, (void **)&t->d_D32, sizeof(float) * nc_ * v.nd)) ||
             (rc = tree_alloc(t, (void **)&t->d_sc64, sizeof(double) * nc_ * scw)) ||
@@ -607,6 +620,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         if (harm) {
             hipError_t e = launch_fill((double *)t->d_Mh, es * (size_t)(nc + 1) * v.nm_pad / 8, t->ctx->stream);
             if (e != hipSuccess) FAIL(FMM_EDEVICE, "fill failed: %s", hipGetErrorString(e));
+            if ((rc = alloc_state(v.nm_pad))) return rc;
         }
     }
     if (t->method == FMM_METHOD_FMM && t->l2p_pack_q != p - order) {
@@ -638,7 +652,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             ncu = prop.multiProcessorCount;
         t->l2p_columns = l2p_columns_pay(p - order, t->l2p_npacks, ncu);
     }
-    hipError_t e = launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream);
+    hipError_t e = t->d_M64 ? launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream) : hipSuccess;
     // P2M and M2M write the FP32 copy too; the rest (the zero row the padded
     // M2L slots read, unused levels) stays zero (nmp is a multiple of 4)
     if (e == hipSuccess && t->d_M32)

@@ -54,6 +54,16 @@ __host__ __device__ constexpr int hindex(int nx, int ny, int nz)
     return (nx + ny + nz) * (nx + ny + nz) + (ny + nz == 0 ? 0 : 2 * (ny + nz) - 1 + nz);
 }
 __host__ __device__ constexpr int hterms(int p) { return p < 0 ? 0 : (p + 1) * (p + 1); }
+// the multi-index of harmonic component h (the inverse of hindex)
+__host__ __device__ inline void hmulti(int h, int &nx, int &ny, int &nz)
+{
+    int l = 0;
+    while ((l + 1) * (l + 1) <= h) ++l;
+    const int off = h - l * l, t = (off + 1) / 2;
+    nz = off == 0 ? 0 : off - (2 * t - 1);
+    ny = t - nz;
+    nx = l - t;
+}
 
 // Folding onto the harmonic basis.  Component h = (a, b, r), r <= 1, of a
 // folded multipole row is
@@ -261,9 +271,17 @@ struct fmm_tree {
     const double *mom_user = nullptr;
     double *d_mom = nullptr;               // sorted moments FP64 (w per particle)
     float *d_mom32 = nullptr;              // sorted moments FP32 (8 per particle)
+    // Expansion storage.  Full basis: every component, d_M64 (FP64, the
+    // upward state; d_M32 its FP32 copy in MIXED) and d_L64 (nterms(p - s)
+    // per cell).  Harmonic basis, O(p^2) per cell: the multipoles only as
+    // rows folded onto their m_z <= 1 components (d_Mh in the M2L precision,
+    // plus the FP64 state d_Mf64 in MIXED; in FP64 d_Mh is the state), the
+    // locals only as their n_z <= 1 components (d_L64, hterms(p - s) per
+    // cell), the rest of a local row rebuilt where it is read.
     double *d_M64 = nullptr;
     float *d_M32 = nullptr;
     void *d_Mh = nullptr;                  // harmonic basis: reduced multipole rows (M2L precision)
+    double *d_Mf64 = nullptr;              // harmonic basis, MIXED: FP64 folded rows (stride nhp)
     void *d_part = nullptr;
     double *d_L64 = nullptr;
     double *d_near = nullptr;              // 4 per particle

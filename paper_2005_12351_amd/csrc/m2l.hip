@@ -153,7 +153,9 @@ __global__ void m2l_combine_kernel(int ncells, int nl, int nlp, BlockBounds bb, 
 }
 
 // Harmonic basis, kHarmCells cells per workgroup: the summed components with
-// n_z <= 1 go to LDS, then every component of the cells' rows is written.
+// n_z <= 1 go to LDS, then every component of the cells' rows is written
+// (full rows, nl per cell) or, when the locals are kept reduced (nl == 0),
+// just those components (nlh per cell).
 constexpr int kHarmCells = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void m2l_combine_h_kernel(int ncells, int nl, int nlh, int nlp, BlockBounds bb,
@@ -170,7 +172,9 @@ __global__ __launch_bounds__(256) void m2l_combine_h_kernel(int ncells, int nl, 
         const int slot = cell < ncells ? cell_slot[cell] : -1;
         if (slot >= 0) v = sum_partials(h, slot / kTileW, slot % kTileW, nlp, bb, chunk0, nchunk, part);
         red[cc][h] = v;
+        if (nl == 0 && cell < ncells) L[(size_t)cell * nlh + h] = v;
     }
+    if (nl == 0) return;
     __syncthreads();
     for (int it = threadIdx.x; it < kHarmCells * nl; it += blockDim.x) {
         const int cc = it / nl, n = it % nl, cell = c0 + cc;
@@ -199,8 +203,9 @@ hipError_t launch_m2l_combine(fmm_tree *t, hipStream_t s)
     if (harm) {
         const unsigned g = (unsigned)((nc + kHarmCells - 1) / kHarmCells);
         const int nlh = hterms(t->p - t->order);
+        // the locals stay reduced (nl = 0 asks for the n_z <= 1 part only)
 #define COMBINE_H(T)                                                                                            \
-    hipLaunchKernelGGL(m2l_combine_h_kernel<T>, dim3(g), dim3(256), 0, s, (int)nc, nl, nlh, v.nl_pad, bb,        \
+    hipLaunchKernelGGL(m2l_combine_h_kernel<T>, dim3(g), dim3(256), 0, s, (int)nc, 0, nlh, v.nl_pad, bb,         \
                        t->d_cell_slot, t->d_tile_chunk0, t->d_tile_nchunk, (const T *)t->d_part, t->d_L64)
         if (f32) COMBINE_H(float);
         else COMBINE_H(double);

@@ -206,6 +206,7 @@ def main():
     ap.add_argument("--theta", type=float, default=None, help="override the opening angle")
     ap.add_argument("--p", type=int, default=None, help="override the expansion order")
     ap.add_argument("--no-literal-row", action="store_true", help="skip the literal-parameter row")
+    ap.add_argument("--serve-slots", type=int, default=None, help="worker slots of the serving pass")
     ap.add_argument("--overlap", choices=["off", "whole", "split"], default="off",
                     help="near field beside the far field in the timed steps (default: one after the other)")
     ap.add_argument("--m2l-engine", choices=["auto", "mfma", "valu"], default="auto",
@@ -527,7 +528,8 @@ def main():
             lit[name].pop("_out", None)
         line["literal_parameters"] = lit
     if not args.no_serve:
-        line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests)
+        kw = {} if args.serve_slots is None else {"slots": args.serve_slots}
+        line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests, **kw)
     print(json.dumps(line), flush=True)
     tree.close()
     ctx.close()

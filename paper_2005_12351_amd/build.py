@@ -31,7 +31,7 @@ def _sources(gen_dir, gen_opt):
     import gen_bh  # noqa: E402
     import gen_m2l  # noqa: E402
     gen = gen_m2l.main(gen_dir, gen_opt)
-    gen_bh.main(gen_dir)
+    gen_bh_tus = gen_bh.main(gen_dir)
     sys.path.pop(0)
     srcs = [(os.path.join(CSRC, "p2p_lo.hip"), []),
             (os.path.join(CSRC, "p2p_oct.hip"), []),
@@ -41,11 +41,12 @@ def _sources(gen_dir, gen_opt):
             (os.path.join(CSRC, "tree_host.cpp"), ["-ffp-contract=off"]),
             (os.path.join(CSRC, "m2l_dispatch.cpp"), []),
             (os.path.join(CSRC, "serve.cpp"), [])]
-    for extra in ("bh.hip", "bh_grad.hip", "tree_gpu.hip", "derivs.hip"):
+    for extra in ("bh.hip", "tree_gpu.hip", "derivs.hip"):
         f = os.path.join(CSRC, extra)
         if os.path.exists(f):
             srcs.append((f, []))
-    srcs += [(g, []) for g in gen]
+    # the Barnes-Hut instantiations first: the longest units
+    srcs = [(g, []) for g in gen_bh_tus] + srcs + [(g, []) for g in gen]
     return srcs
 
 

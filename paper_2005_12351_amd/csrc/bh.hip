@@ -1,8 +1,18 @@
 // Barnes-Hut evaluation of potential and field (the kernel is in
-// bh_kernel.h; the variants with the field gradient are in bh_grad.hip).
+// bh_kernel.h; its instantiations, with and without the field gradient, per
+// source order, are generated translation units, gen_bh.py).
 #include "bh_kernel.h"
 
-bh_fn bh_select_grad(int s, int p, bool f32, bool h);   // bh_grad.hip
+static bh_fn bh_select(bool grad, int s, int p, bool f32, bool h)
+{
+    switch (s) {
+    case 0: return grad ? bh_select_g_s0(p, f32, h) : bh_select_f_s0(p, f32, h);
+    case 1: return grad ? bh_select_g_s1(p, f32, h) : bh_select_f_s1(p, f32, h);
+    case 2: return grad ? bh_select_g_s2(p, f32, h) : bh_select_f_s2(p, f32, h);
+    case 3: return grad ? bh_select_g_s3(p, f32, h) : bh_select_f_s3(p, f32, h);
+    default: return nullptr;
+    }
+}
 
 namespace {
 
@@ -18,7 +28,7 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n)
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s)
 {
     const bool f32 = t->prec == FMM_PREC_MIXED, h = t->basis == FMM_M2L_HARMONIC;
-    bh_fn k = (outputs & FMM_GRAD) ? bh_select_grad(t->order, t->p, f32, h) : bh_select<false>(t->order, t->p, f32, h);
+    bh_fn k = bh_select((outputs & FMM_GRAD) != 0, t->order, t->p, f32, h);
     if (!k) return hipErrorInvalidValue;
     BHArgs a;
     a.cells = t->d_cells;

@@ -260,15 +260,13 @@ bh_fn bh_pick_p(int p, bool f32, bool h)
     }
 }
 
-template <bool GRAD>
-bh_fn bh_select(int s, int p, bool f32, bool h)
-{
-    switch (s) {
-    case 0: return bh_pick_p<GRAD, 0>(p, f32, h);
-    case 1: return bh_pick_p<GRAD, 1>(p, f32, h);
-    case 2: return bh_pick_p<GRAD, 2>(p, f32, h);
-    case 3: return bh_pick_p<GRAD, 3>(p, f32, h);
-    default: return nullptr;
-    }
-}
-
+// one per (field gradient, source order), each in its own generated
+// translation unit (gen_bh.py)
+bh_fn bh_select_f_s0(int p, bool f32, bool h);
+bh_fn bh_select_f_s1(int p, bool f32, bool h);
+bh_fn bh_select_f_s2(int p, bool f32, bool h);
+bh_fn bh_select_f_s3(int p, bool f32, bool h);
+bh_fn bh_select_g_s0(int p, bool f32, bool h);
+bh_fn bh_select_g_s1(int p, bool f32, bool h);
+bh_fn bh_select_g_s2(int p, bool f32, bool h);
+bh_fn bh_select_g_s3(int p, bool f32, bool h);

@@ -63,7 +63,7 @@ ProfScope::~ProfScope()
     hipEvent_t e = pool_event(ctx);
     if (!e) return;
     hipEventRecord(e, s);
-    ctx->prof.push_back(ProfEntry{name, b, e});
+    ctx->prof.push_back(ProfEntry{name, b, e, 0.0});
 }
 
 static void drop_graphs(fmm_tree *t)
@@ -150,6 +150,7 @@ extern "C" int fmm_profile_reset(fmm_ctx *ctx)
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     for (auto &e : ctx->prof) {
+        if (!e.a) continue;   // a host phase holds no events
         ctx->ev_pool.push_back(e.a);
         ctx->ev_pool.push_back(e.b);
     }
@@ -167,8 +168,8 @@ extern "C" int fmm_profile_read(fmm_ctx *ctx, const char **names, double *ms, in
     std::vector<double> tot;
     std::vector<int64_t> cnt;
     for (auto &e : ctx->prof) {
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
+        float t = (float)e.host_ms;
+        if (e.a) HIPCHK(hipEventElapsedTime(&t, e.a, e.b));
         size_t k = 0;
         while (k < nm.size() && strcmp(nm[k], e.name) != 0) ++k;
         if (k == nm.size()) {
@@ -259,10 +260,12 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     c->trees.clear();
     (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->prof) {
+        if (!e.a) continue;   // a host phase holds no events
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
     }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    if (c->pinned) (void)hipHostFree(c->pinned);
     hipEventDestroy(c->ev_up);
     hipEventDestroy(c->ev_near);
     hipEventDestroy(c->ev_fork);
@@ -353,8 +356,9 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     t->method = method;
     t->ncrit = ncrit;
     t->theta = theta;
+    HostScope hs_all(ctx, "host:build_tree");
     {
-        const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht);
+        const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx);
         if (e != hipSuccess) {
             delete t;
             if (e == hipErrorInvalidValue) FAIL(FMM_EINVAL, "non-finite position");
@@ -365,6 +369,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     HostTree &h = t->ht;
     const int64_t nc = h.ncells();
     if (method == FMM_METHOD_FMM) {
+        HostScope hs(ctx, "host:m2l_tiling");
         build_m2l_tiling(h, t->tiling);
     } else {
         h.m2l_ptr.assign(nc + 1, 0);
@@ -475,6 +480,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     std::vector<int32_t> perm32(n);
     for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)h.perm[i];
 
+    HostScope hs_up(ctx, "host:tree_upload");
     int rc = FMM_OK;
 #define UP(dst, vec)                                   \
     if ((rc = upload(t, &(dst), vec, s)) != FMM_OK) {  \
@@ -519,6 +525,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 // ------------------------------------------------------------------ upward
 static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
 {
+    HostScope hs(t->ctx, "host:expansions");
     const int smask = code_mask(code), order = mask_min_order(smask);
     const bool fmm = t->method == FMM_METHOD_FMM;
     const int basis = t->ctx->m2l_basis;

@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <chrono>
 #include <vector>
 
 #include "../../include/fmm.h"
@@ -156,7 +157,7 @@ struct HostTree {      // canonical tree, host copy
 // hipErrorOutOfMemory: a list or frontier exceeds 2^31 entries or the device
 // is out of memory.
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
-                          HostTree &t);
+                          HostTree &t, fmm_ctx *ctx = nullptr);
 
 // M2L tiling (tree_host.cpp)
 struct M2LTiling {
@@ -208,7 +209,8 @@ bool m2l_lookup(int p, int s, bool fp32, bool harmonic, M2LVariant *out, bool mf
 void build_m2l_work(const M2LTiling &tl, const M2LVariant &v, int nwaves, M2LWork &out);
 
 // ------------------------------------------------------------------ context
-struct ProfEntry { const char *name; hipEvent_t a, b; };
+// a kernel range between two events, or (a null) a host phase of host_ms
+struct ProfEntry { const char *name; hipEvent_t a, b; double host_ms; };
 
 struct fmm_ctx {
     int device = 0;
@@ -224,6 +226,8 @@ struct fmm_ctx {
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
     double *noalloc_scratch = nullptr;    // device address of the static gradient scratch on `device`
+    void *pinned = nullptr;               // pinned host staging of tree construction's read-backs
+    size_t pinned_bytes = 0;
     hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;
@@ -310,6 +314,21 @@ struct ProfScope {
     hipEvent_t b = nullptr;
     ProfScope(fmm_ctx *c, hipStream_t st, const char *nm);
     ~ProfScope();
+};
+
+// wall-clock time of a host phase (tree construction, set-up), recorded
+// with the kernel ranges while profiling is on
+struct HostScope {
+    fmm_ctx *ctx;
+    const char *name;
+    std::chrono::steady_clock::time_point t0;
+    HostScope(fmm_ctx *c, const char *nm) : ctx(c), name(nm), t0(std::chrono::steady_clock::now()) {}
+    ~HostScope()
+    {
+        if (!ctx || !ctx->profile) return;
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ctx->prof.push_back(ProfEntry{name, nullptr, nullptr, ms});
+    }
 };
 
 // kernels entry points (host launchers), return hipError_t

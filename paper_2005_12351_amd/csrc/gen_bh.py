@@ -20,7 +20,8 @@ M2PEvalG / M2PEvalGH also return sum M_n D_{n+e_i+e_j} (the field gradient,
 derivatives to order p + 2; harmonic: k_z <= 3) in g[0..5] = xx, xy, xz,
 yy, yz, zz.
 
-Usage: python gen_bh.py OUTDIR -> OUTDIR/bh_m2p.h
+Usage: python gen_bh.py OUTDIR -> OUTDIR/bh_m2p.h, bh_m2p_s{0..3}.h and the
+translation units bh_inst_{f,g}_s{0..3}.hip
 """
 import math
 import os
@@ -126,27 +127,47 @@ def gen_spec(p, s, fp32, harmonic=False, grad=False):
     return "\n".join(L)
 
 
+def _write(fn, txt):
+    old = open(fn).read() if os.path.exists(fn) else None
+    if old != txt:
+        with open(fn, "w") as f:
+            f.write(txt)
+
+
 def main(outdir):
+    """Writes bh_m2p.h (the primary templates), bh_m2p_s{s}.h (the
+    specialisations of one source order) and one translation unit per
+    (source order, with or without the field gradient) that instantiates the
+    Barnes-Hut kernels of that pair, so that they compile in parallel;
+    returns the translation units."""
     os.makedirs(outdir, exist_ok=True)
-    parts = ["// Generated by gen_bh.py; do not edit.", "#pragma once", "",
-             "template <int P, int S, typename T> struct M2PEval;",
-             "template <int P, int S, typename T> struct M2PEvalH;",
-             "template <int P, int S, typename T> struct M2PEvalG;",
-             "template <int P, int S, typename T> struct M2PEvalGH;", ""]
+    head = ["// Generated by gen_bh.py; do not edit.", "#pragma once", "",
+            "template <int P, int S, typename T> struct M2PEval;",
+            "template <int P, int S, typename T> struct M2PEvalH;",
+            "template <int P, int S, typename T> struct M2PEvalG;",
+            "template <int P, int S, typename T> struct M2PEvalGH;", ""]
+    _write(os.path.join(outdir, "bh_m2p.h"), "\n".join(head) + "\n")
+    tus = []
     for s in (0, 1, 2, 3):
+        parts = ["// Generated by gen_bh.py; do not edit.", "#pragma once", '#include "bh_m2p.h"', ""]
         for p in range(max(s, 1), P_MAX + 1):
             for fp32 in (True, False):
                 for h in (False, True):
                     for gr in (False, True):
                         parts.append(gen_spec(p, s, fp32, h, gr))
                         parts.append("")
-    txt = "\n".join(parts) + "\n"
-    fn = os.path.join(outdir, "bh_m2p.h")
-    old = open(fn).read() if os.path.exists(fn) else None
-    if old != txt:
-        with open(fn, "w") as f:
-            f.write(txt)
-    return fn
+        _write(os.path.join(outdir, f"bh_m2p_s{s}.h"), "\n".join(parts) + "\n")
+        for gr in (False, True):
+            g = "g" if gr else "f"
+            what = "with the field gradient" if gr else "potential and field"
+            tu = (f"// Generated by gen_bh.py; do not edit.  Barnes-Hut kernels of source\n"
+                  f"// order {s}, {what} (bh_kernel.h).\n"
+                  f'#include "bh_kernel.h"\n#include "bh_m2p_s{s}.h"\n\n'
+                  f"bh_fn bh_select_{g}_s{s}(int p, bool f32, bool h) {{ return bh_pick_p<{'true' if gr else 'false'}, {s}>(p, f32, h); }}\n")
+            fn = os.path.join(outdir, f"bh_inst_{g}_s{s}.hip")
+            _write(fn, tu)
+            tus.append(fn)
+    return tus
 
 
 if __name__ == "__main__":

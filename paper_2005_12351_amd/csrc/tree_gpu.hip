@@ -544,41 +544,81 @@ int bits_for(int64_t m)
 }
 
 // CSR (ptr over ncells + 1, src) of the (target << kb | source) keys
-hipError_t keys_to_csr(Dev &dv, uint64_t *key, int64_t m, int kb, int nc, std::vector<int64_t> &ptr,
-                       std::vector<int64_t> &src)
+// The CSR lists of m (target, source) keys: sorted on the device, then per
+// target counts and the sources as int32 (copied to the host with the rest
+// of the tree, see csr_finish)
+hipError_t csr_launch(Dev &dv, uint64_t *key, int64_t m, int kb, int nc, int32_t **cnt, int32_t **s32)
 {
-    ptr.assign(nc + 1, 0);
-    src.assign(m, 0);
-    if (m == 0) return hipSuccess;
+    *cnt = dv.alloc<int32_t>(nc);
+    *s32 = dv.alloc<int32_t>(m);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(nc, 256)), dim3(256), 0, dv.s, *cnt, (int64_t)nc);
+    if (m == 0) return hipGetLastError();
     int32_t *val = dv.alloc<int32_t>(m);
-    int32_t *cnt = dv.alloc<int32_t>(nc);
-    int32_t *s32 = dv.alloc<int32_t>(m);
     GCHK(dv.err);
     hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, val, m);
     GCHK(radix_sort(dv, key, val, (int)m, 2 * kb));
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(nblk(nc, 256)), dim3(256), 0, dv.s, cnt, (int64_t)nc);
-    hipLaunchKernelGGL(list_count_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, cnt);
-    hipLaunchKernelGGL(list_src_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, s32);
-    GCHK(hipGetLastError());
-    std::vector<int32_t> c(nc), s(m);
-    GCHK(hipMemcpyAsync(c.data(), cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, dv.s));
-    GCHK(hipMemcpyAsync(s.data(), s32, sizeof(int32_t) * m, hipMemcpyDeviceToHost, dv.s));
-    GCHK(hipStreamSynchronize(dv.s));
+    hipLaunchKernelGGL(list_count_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, *cnt);
+    hipLaunchKernelGGL(list_src_kernel, dim3(nblk(m, 256)), dim3(256), 0, dv.s, key, m, kb, *s32);
+    return hipGetLastError();
+}
+
+void csr_finish(const int32_t *c, const int32_t *s, int64_t m, int nc, std::vector<int64_t> &ptr,
+                std::vector<int64_t> &src)
+{
+    ptr.assign(nc + 1, 0);
+    src.resize(m);
     for (int i = 0; i < nc; ++i) ptr[i + 1] = ptr[i] + c[i];
     for (int64_t i = 0; i < m; ++i) src[i] = s[i];
-    return hipSuccess;
 }
+
+// host staging of the device-to-host copies: the context's pinned buffer
+// (fast, asynchronous copies), grown on demand, or plain host memory
+struct Staging {
+    fmm_ctx *ctx;
+    std::vector<char> plain;
+    char *base = nullptr;
+    hipError_t reserve(size_t bytes)
+    {
+        if (ctx) {
+            if (ctx->pinned_bytes < bytes) {
+                if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+                ctx->pinned = nullptr;
+                ctx->pinned_bytes = 0;
+                const size_t want = std::max(bytes, (size_t)1 << 20);
+                GCHK(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+                ctx->pinned_bytes = want;
+            }
+            base = (char *)ctx->pinned;
+        } else {
+            plain.resize(bytes);
+            base = plain.data();
+        }
+        return hipSuccess;
+    }
+};
 
 }  // namespace
 
 // Builds the canonical tree (and, when theta > 0, the interaction lists) of
-// the n device positions on stream s, and returns it in host form.
+// the n device positions on stream s, and returns it in host form.  ctx (may
+// be null): its pinned staging buffer and, while profiling, the wall-clock
+// phases.
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
-                          HostTree &t)
+                          HostTree &t, fmm_ctx *ctx)
 {
     t = HostTree();
     t.n = n;
     Dev dv{s};
+    // wall-clock phases for the context's profile (the device work of a
+    // phase is counted where the host next waits for it)
+    auto t_last = std::chrono::steady_clock::now();
+    auto mark = [&](const char *nm) {
+        if (!ctx || !ctx->profile) return;
+        const auto now = std::chrono::steady_clock::now();
+        ctx->prof.push_back(ProfEntry{nm, nullptr, nullptr, std::chrono::duration<double, std::milli>(now - t_last).count()});
+        t_last = now;
+    };
     // root box
     const int nbb = (int)std::min<int64_t>(1024, nblk(n, 256));
     double *part = dv.alloc<double>(7 * (size_t)nbb), *bb = dv.alloc<double>(7);
@@ -589,6 +629,7 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     double box[7];
     GCHK(hipMemcpyAsync(box, bb, sizeof(box), hipMemcpyDeviceToHost, s));
     GCHK(hipStreamSynchronize(s));
+    mark("host:tree_box");
     if (box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
     double W = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
     if (W == 0.0) W = 1.0;
@@ -650,8 +691,11 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         le = le + (int)tot;
     }
     const int nc = le;
+    mark("host:tree_sort_levels");
 
     // interaction lists: breadth-first over cell pairs
+    int32_t *m2l_cnt = nullptr, *m2l_s32 = nullptr, *p2p_cnt = nullptr, *p2p_s32 = nullptr;
+    int64_t n_m2l = 0, n_p2p = 0;
     if (lists) {
         const double th2 = theta * theta;
         const int kb = bits_for(nc);
@@ -692,6 +736,7 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
             p2p_parts.push_back(pk);
             p2p_sz.push_back(tp);
         }
+        mark("host:tree_traverse");
         // gather the per-step outputs, then sort by (target, source)
         auto gather = [&](std::vector<uint64_t *> &parts, std::vector<int64_t> &sz, uint64_t *&all, int64_t &m) -> hipError_t {
             m = 0;
@@ -711,19 +756,43 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         GCHK(gather(m2l_parts, m2l_sz, mall, mm));
         GCHK(gather(p2p_parts, p2p_sz, pall, pm));
         if (mm > INT32_MAX || pm > INT32_MAX) return hipErrorOutOfMemory;
-        GCHK(keys_to_csr(dv, mall, mm, kb, nc, t.m2l_ptr, t.m2l_src));
-        GCHK(keys_to_csr(dv, pall, pm, kb, nc, t.p2p_ptr, t.p2p_src));
+        GCHK(csr_launch(dv, mall, mm, kb, nc, &m2l_cnt, &m2l_s32));
+        GCHK(csr_launch(dv, pall, pm, kb, nc, &p2p_cnt, &p2p_s32));
+        n_m2l = mm;
+        n_p2p = pm;
     }
 
-    // host copies of the order, the keys and the cells
-    std::vector<DevCell> hc(nc);
-    std::vector<int32_t> perm(n);
-    t.key.resize(n);
-    GCHK(hipMemcpyAsync(hc.data(), cells, sizeof(DevCell) * nc, hipMemcpyDeviceToHost, s));
-    GCHK(hipMemcpyAsync(perm.data(), idx, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    GCHK(hipMemcpyAsync(t.key.data(), key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+    mark("host:tree_lists");
+    // host copies of the cells, the order, the keys and the lists, in one
+    // staging buffer and one wait
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_cells = 0, o_perm = o_cells + al(sizeof(DevCell) * nc), o_key = o_perm + al(sizeof(int32_t) * n),
+                 o_mc = o_key + al(sizeof(uint64_t) * n), o_ms = o_mc + al(sizeof(int32_t) * nc),
+                 o_pc = o_ms + al(sizeof(int32_t) * n_m2l), o_ps = o_pc + al(sizeof(int32_t) * nc),
+                 o_end = o_ps + al(sizeof(int32_t) * n_p2p);
+    Staging st{ctx};
+    GCHK(st.reserve(o_end));
+    GCHK(hipMemcpyAsync(st.base + o_cells, cells, sizeof(DevCell) * nc, hipMemcpyDeviceToHost, s));
+    GCHK(hipMemcpyAsync(st.base + o_perm, idx, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    GCHK(hipMemcpyAsync(st.base + o_key, key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+    if (lists) {
+        GCHK(hipMemcpyAsync(st.base + o_mc, m2l_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+        if (n_m2l) GCHK(hipMemcpyAsync(st.base + o_ms, m2l_s32, sizeof(int32_t) * n_m2l, hipMemcpyDeviceToHost, s));
+        GCHK(hipMemcpyAsync(st.base + o_pc, p2p_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+        if (n_p2p) GCHK(hipMemcpyAsync(st.base + o_ps, p2p_s32, sizeof(int32_t) * n_p2p, hipMemcpyDeviceToHost, s));
+    }
     GCHK(hipStreamSynchronize(s));
-    t.perm.assign(perm.begin(), perm.end());
+    mark("host:tree_copy");
+    if (lists) {
+        csr_finish((const int32_t *)(st.base + o_mc), (const int32_t *)(st.base + o_ms), n_m2l, nc, t.m2l_ptr,
+                   t.m2l_src);
+        csr_finish((const int32_t *)(st.base + o_pc), (const int32_t *)(st.base + o_ps), n_p2p, nc, t.p2p_ptr,
+                   t.p2p_src);
+    }
+    const DevCell *hc = (const DevCell *)(st.base + o_cells);
+    const int32_t *perm = (const int32_t *)(st.base + o_perm);
+    t.key.assign((const uint64_t *)(st.base + o_key), (const uint64_t *)(st.base + o_key) + n);
+    t.perm.assign(perm, perm + n);
     t.level.resize(nc);
     t.ix.resize(3 * (size_t)nc);
     t.first.resize(nc);
@@ -743,5 +812,6 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         t.child0[c] = d.child0;
         t.nchild[c] = d.nchild;
     }
+    mark("host:tree_copyback");
     return hipSuccess;
 }

@@ -9,37 +9,125 @@
 #include <cmath>
 #include <numeric>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <mutex>
 #include <thread>
 
 #include "fmm_internal.h"
 
 // ---------------------------------------------------------------------------
-// Host threads for the scheduling passes: work items [0, n) in contiguous
-// blocks, one per thread; every result slot is written by exactly one item,
-// so the outcome does not depend on the thread count (at most 16 cores,
-// divided among the builds in flight).
-// Builds running at once (serving overlaps them) share the host cores.
-static std::atomic<int> g_builds{0};
-struct BuildScope {
-    BuildScope() { ++g_builds; }
-    ~BuildScope() { --g_builds; }
+// Host threads for the scheduling passes: a fixed set of workers, started on
+// first use and kept for the life of the process, takes blocks of work items
+// [0, n) from a shared counter; the calling thread takes blocks too, so a
+// loop completes even while every worker serves another build's loop (the
+// serving slots build trees at once).  Every result slot is written by
+// exactly one item, so the outcome does not depend on which thread ran it.
+class HostPool {
+public:
+    static HostPool &get()
+    {
+        static HostPool p;
+        return p;
+    }
+    template <typename F>
+    void run(int64_t n, F &&f)
+    {
+        const int64_t grain = std::max<int64_t>(1, n / (4 * (int64_t)(workers_.size() + 1)));
+        if (workers_.empty() || n <= grain) {
+            for (int64_t i = 0; i < n; ++i) f(i);
+            return;
+        }
+        Task task;
+        task.n = n;
+        task.grain = grain;
+        task.body = [&f](int64_t a, int64_t b) {
+            for (int64_t i = a; i < b; ++i) f(i);
+        };
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            tasks_.push_back(&task);
+        }
+        cv_.notify_all();
+        work_on(task);
+        {
+            // no worker joins once the task has left the queue; wait for
+            // those that joined before
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = std::find(tasks_.begin(), tasks_.end(), &task);
+            if (it != tasks_.end()) tasks_.erase(it);
+        }
+        std::unique_lock<std::mutex> tl(task.m);
+        task.cv.wait(tl, [&] { return task.active == 0; });
+    }
+
+private:
+    struct Task {
+        int64_t n = 0, grain = 1;
+        std::function<void(int64_t, int64_t)> body;
+        std::atomic<int64_t> next{0};
+        int active = 0;   // workers inside; guarded by m
+        std::mutex m;
+        std::condition_variable cv;
+    };
+    HostPool()
+    {
+        const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        for (int k = 0; k + 1 < hw; ++k) workers_.emplace_back([this] { loop(); });
+    }
+    ~HostPool()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &w : workers_) w.join();
+    }
+    static void work_on(Task &t)
+    {
+        for (;;) {
+            const int64_t a = t.next.fetch_add(t.grain);
+            if (a >= t.n) return;
+            t.body(a, std::min(t.n, a + t.grain));
+        }
+    }
+    void loop()
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return stop_ || !tasks_.empty(); });
+            if (stop_) return;
+            Task *t = tasks_.front();
+            if (t->next.load() >= t->n) {
+                tasks_.pop_front();   // nothing left to take; its owner finishes it
+                continue;
+            }
+            {
+                std::lock_guard<std::mutex> tl(t->m);
+                ++t->active;
+            }
+            lk.unlock();
+            work_on(*t);
+            {
+                std::lock_guard<std::mutex> tl(t->m);
+                if (--t->active == 0) t->cv.notify_all();
+            }
+            lk.lock();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::deque<Task *> tasks_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    bool stop_ = false;
 };
 
 template <typename F>
 static void parallel_for(int64_t n, F f)
 {
-    const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    const int64_t nt = std::min<int64_t>(std::max(1, hw / std::max(1, g_builds.load())), std::max<int64_t>(1, n / 4));
-    if (nt <= 1) {
-        for (int64_t i = 0; i < n; ++i) f(i);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int64_t k = 0; k < nt; ++k)
-        th.emplace_back([&, k]() {
-            for (int64_t i = n * k / nt; i < n * (k + 1) / nt; ++i) f(i);
-        });
-    for (auto &x : th) x.join();
+    HostPool::get().run(n, f);
 }
 
 // Exact integer geometry of a pair (source A, target B): the centre offset
@@ -173,7 +261,6 @@ struct KeyMap {
 // for any number of host threads.
 void build_m2l_tiling(const HostTree &t, M2LTiling &out)
 {
-    BuildScope scope;
     out = M2LTiling();
     const int64_t nc = t.ncells();
     std::vector<int32_t> tg;

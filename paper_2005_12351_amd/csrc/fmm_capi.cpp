@@ -632,20 +632,32 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     }
     if (t->method == FMM_METHOD_FMM && t->l2p_pack_q != p - order) {
         // L2P waves: consecutive leaves while they hold at most 64 particles
-        // together (a larger leaf gets a wave of its own)
-        const int kmax = l2p_pack_limit(p - order);
-        std::vector<int32_t> pack(1, 0);
-        int64_t cnt = 0;
-        for (int64_t k = 0; k < t->nleaves; ++k) {
-            const int64_t c = t->ht.count[t->leaves[k]];
-            const int in_pack = (int)(k - pack.back());
-            if (in_pack > 0 && (cnt + c > 64 || in_pack >= kmax)) {
-                pack.push_back((int32_t)k);
-                cnt = 0;
+        // together and fit the layout's budget (a larger leaf gets a wave of
+        // its own)
+        auto packing = [&](int kmax) {
+            std::vector<int32_t> pk(1, 0);
+            int64_t cnt = 0;
+            for (int64_t k = 0; k < t->nleaves; ++k) {
+                const int64_t c = t->ht.count[t->leaves[k]];
+                const int in_pack = (int)(k - pk.back());
+                if (in_pack > 0 && (cnt + c > 64 || in_pack >= kmax)) {
+                    pk.push_back((int32_t)k);
+                    cnt = 0;
+                }
+                cnt += c;
             }
-            cnt += c;
-        }
-        pack.push_back((int32_t)t->nleaves);
+            pk.push_back((int32_t)t->nleaves);
+            return pk;
+        };
+        const int q = p - order;
+        std::vector<int32_t> pack = packing(l2p_pack_limit(q, false));
+        int dev = 0, ncu = 256;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            ncu = prop.multiProcessorCount;
+        std::vector<int32_t> pack_cols = packing(l2p_pack_limit(q, true));
+        t->l2p_columns = pack_cols.size() < pack.size() || l2p_columns_pay(q, (int)pack.size() - 1, ncu);
+        if (t->l2p_columns) pack.swap(pack_cols);
         if (t->d_l2p_pack) tree_free_block(t, t->d_l2p_pack);
         t->d_l2p_pack = nullptr;
         t->l2p_pack_q = -1;
@@ -653,11 +665,6 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the host vector dies here
         t->l2p_npacks = (int)pack.size() - 1;
         t->l2p_pack_q = p - order;
-        int dev = 0, ncu = 256;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            ncu = prop.multiProcessorCount;
-        t->l2p_columns = l2p_columns_pay(p - order, t->l2p_npacks, ncu);
     }
     hipError_t e = t->d_M64 ? launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream) : hipSuccess;
     // P2M and M2M write the FP32 copy too; the rest (the zero row the padded

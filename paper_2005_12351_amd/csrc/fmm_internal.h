@@ -349,7 +349,7 @@ hipError_t launch_l2p_final(fmm_tree *t, int outputs, double *phi, double *field
 // current device, resolved once per device
 constexpr int64_t kNoAllocMaxN = 1 << 18;
 hipError_t noalloc_scratch(int device, double **ptr);
-int l2p_pack_limit(int q);   // leaves one L2P wave may take at expansion order q
+int l2p_pack_limit(int q, bool cols);   // leaves one L2P wave may take at expansion order q, per layout
 bool l2p_columns_pay(int q, int npacks, int ncu);   // L2P layout choice for a launch of npacks waves
 hipError_t launch_bh(fmm_tree *t, int outputs, double *phi, double *field, double *grad, hipStream_t s);
 // P2P over the leaves p2p_order[first .. first + count) (count < 0: to the end)

@@ -971,10 +971,12 @@ static hipError_t launch_p2p_range(fmm_tree *t, hipStream_t s, bool grad, int fi
 // - packed columns: for every (n_x, n_y) with n_x + n_y <= q + 2 the entries
 //   n_z = 0 .. q + 2 - n_x - n_y lie contiguously, (q+3)(q+4)(q+5)/6 values,
 //   a third of the cube, but each neighbour column costs an address add.
-// The cube is used while every wave of the launch fits on the chip at once
-// under its LDS share (100k particles), the columns when that share limits
-// the resident waves (1M and more), where they are about 25 % faster.
-// The leaves per pack are what a 16 KB budget of cubes allows in both cases.
+// The columns are used when they pack more leaves into a wave than the cube
+// (high orders, where one leaf's cube fills the 16 KB budget: at p - s = 9
+// a cube is 10.6 KB and a wave would take one leaf of ~24 particles), or when
+// the cube's LDS share limits the resident waves (1M particles and more,
+// where they are about 25 % faster); the cube otherwise.  The leaves per pack
+// are what a 16 KB budget of the layout allows.
 // Compiled per q = p - s.
 constexpr int kL2PMaxLeaves = 8;
 constexpr int kL2PPackBudget = 16384;   // bytes of (q+2)^3 cubes that fix the leaves per pack
@@ -988,11 +990,14 @@ __host__ __device__ constexpr int l2p_col(int q, int x, int y)
     return K * (K + 1) * (K + 2) / 6 - kx * (kx + 1) * (kx + 2) / 6 + y * kx - y * (y - 1) / 2;
 }
 __host__ __device__ constexpr int l2p_cube(int q) { return (q + 2) * (q + 2) * (q + 2); }
-int l2p_pack_limit(int q) { return std::max(1, std::min(kL2PMaxLeaves, kL2PPackBudget / (8 * l2p_cube(q)))); }
+int l2p_pack_limit(int q, bool cols)
+{
+    return std::max(1, std::min(kL2PMaxLeaves, kL2PPackBudget / (8 * (cols ? l2p_cols(q) : l2p_cube(q)))));
+}
 constexpr int kLdsPerCU = 160 * 1024;
 bool l2p_columns_pay(int q, int npacks, int ncu)
 {
-    const int cube_bytes = l2p_pack_limit(q) * l2p_cube(q) * 8;
+    const int cube_bytes = l2p_pack_limit(q, false) * l2p_cube(q) * 8;
     return (int64_t)npacks > (int64_t)ncu * std::max(1, kLdsPerCU / cube_bytes);
 }
 
@@ -1152,7 +1157,7 @@ static void l2p_launch_layout(fmm_tree *t, int outputs, double *phi, double *fie
                               const double *near_g)
 {
     Geo g{{t->ht.lo[0], t->ht.lo[1], t->ht.lo[2]}, t->ht.h};
-    const size_t lds = (size_t)l2p_pack_limit(Q) * (COLS ? l2p_cols(Q) : l2p_cube(Q)) * sizeof(double);
+    const size_t lds = (size_t)l2p_pack_limit(Q, COLS) * (COLS ? l2p_cols(Q) : l2p_cube(Q)) * sizeof(double);
     const int nlh = t->basis == FMM_M2L_HARMONIC ? hterms(Q) : 0;
     if constexpr (Q >= 2) {
         if (outputs & FMM_GRAD) {

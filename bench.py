@@ -39,7 +39,7 @@ PEAK_HBM = 8.0e12
 KERNEL_SOURCES = {
     "m2l": ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/m2l.hip",
             "paper_2005_12351_amd/csrc/tree_host.cpp"),
-    "p2p": ("paper_2005_12351_amd/csrc/kernels.hip", "paper_2005_12351_amd/csrc/pair_kernels.h",
+    "p2p": ("paper_2005_12351_amd/csrc/p2p_kernel.h", "paper_2005_12351_amd/csrc/pair_kernels.h",
             "paper_2005_12351_amd/csrc/fmm_capi.cpp"),
 }
 
@@ -67,6 +67,11 @@ def _traffic(kernel_key: str):
     except Exception:
         return None
     return None
+
+
+def _progress(msg):
+    """a progress line on stderr (the JSON line alone goes to stdout)"""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
 def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
@@ -367,6 +372,7 @@ def main():
         v = prof.get(k)
         return v[0] / max(1, v[1]) if v else float("nan")
 
+    _progress("timed steps done")
     m, f64 = res["mixed"], res["fp64"]
     kern_ms = {k: v[0] / max(1, v[1]) for k, v in m["prof"].items()}
     if bh:
@@ -447,6 +453,7 @@ def main():
     lit = None
     if not bh and not at_literal and not args.no_literal_row:
         lit = literal_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, literal[0], literal[1])
+        _progress("literal-parameter row done")
     if not args.no_cpu:
         import oracle
         oracle.lib()
@@ -457,7 +464,9 @@ def main():
             po_s, Eo_s = ot.bh(w.order, w.moments, w.p, w.theta, targets=sample)
         else:
             po_s, Eo_s = ot.fmm(w.order, w.moments, w.p, targets=sample)
+        _progress("CPU baseline (oracle on a bounded sample)")
         cb = cpu_baseline(args, w, w.theta, w.p, "bh" if bh else "fmm")
+        _progress("CPU baseline done; error checks against the oracle")
         allc, one = cb.get("all", {}), cb.get("one", {})
         if "median_s" in allc:
             line["cpu_baseline"] = {
@@ -529,7 +538,9 @@ def main():
         line["literal_parameters"] = lit
     if not args.no_serve:
         kw = {} if args.serve_slots is None else {"slots": args.serve_slots}
+        _progress("serving stream")
         line["serving"] = serve_bench(fmm, W, torch, n_requests=args.serve_requests, **kw)
+        _progress("serving done")
     print(json.dumps(line), flush=True)
     tree.close()
     ctx.close()

@@ -148,6 +148,12 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
 HEADLINE = {2: (0.3, 10)}
 
 
+def overlap_mode(fmm, args):
+    """the near-field overlap of the timed fmm_run steps"""
+    return {"off": fmm.FMM_OVERLAP_OFF, "whole": fmm.FMM_OVERLAP_WHOLE, "split": fmm.FMM_OVERLAP_SPLIT,
+            "tail": fmm.FMM_OVERLAP_TAIL}[args.overlap]
+
+
 def literal_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, theta, p):
     """The same particles at the workload's literal (theta, p), MIXED and
     FP64 (harmonic basis), reported beside the headline with their errors
@@ -157,7 +163,7 @@ def literal_run(fmm, torch, w, pos, mom, outputs, ctx, args, dev, theta, p):
     fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
     out = {"theta": theta, "p": p, "info": tree.info()}
     for name, prec in (("mixed", fmm.FMM_PREC_MIXED), ("fp64", fmm.FMM_PREC_FP64)):
-        ctx.set_overlap(False)
+        ctx.set_overlap(overlap_mode(fmm, args))
         for _ in range(max(3, args.warmup)):
             tree.run(w.order, mom, p, prec, outputs, phi, fld)
         torch.cuda.synchronize()
@@ -212,8 +218,8 @@ def main():
     ap.add_argument("--p", type=int, default=None, help="override the expansion order")
     ap.add_argument("--no-literal-row", action="store_true", help="skip the literal-parameter row")
     ap.add_argument("--serve-slots", type=int, default=None, help="worker slots of the serving pass")
-    ap.add_argument("--overlap", choices=["off", "whole", "split"], default="off",
-                    help="near field beside the far field in the timed steps (default: one after the other)")
+    ap.add_argument("--overlap", choices=["off", "whole", "split", "tail"], default="tail",
+                    help="near field beside the far field in the timed steps (default tail: after the M2L, beside the combine and L2L)")
     ap.add_argument("--m2l-engine", choices=["auto", "mfma", "valu"], default="auto",
                     help="units of the FP32 harmonic-basis M2L (auto: matrix cores for p >= 8)")
     args = ap.parse_args()
@@ -263,8 +269,7 @@ def main():
         phi = torch.empty(w.n, dtype=torch.float64, device=dev) if outputs & fmm.FMM_POT else None
         fld = torch.empty((w.n, 3), dtype=torch.float64, device=dev)
         ctx.profile(False)
-        ctx.set_overlap({"off": fmm.FMM_OVERLAP_OFF, "whole": fmm.FMM_OVERLAP_WHOLE,
-                         "split": fmm.FMM_OVERLAP_SPLIT}[args.overlap])
+        ctx.set_overlap(overlap_mode(fmm, args))
         for _ in range(warmup):
             tree.run(w.order, mom, w.p, prec, outputs, phi, fld)
         torch.cuda.synchronize()

@@ -233,9 +233,11 @@ const char *fmm_last_error(void);
  * FMM_OVERLAP_SPLIT: in fmm_run, half the near field (by cost) beside the
  * upward M2M levels, joined before the M2L, the other half after the M2L
  * beside the combine and L2L, joined before the L2P, so that it never
- * competes with the M2L (fmm_upward alone runs the whole near field).
- * FMM_EINVAL for other values. */
-enum { FMM_OVERLAP_OFF = 0, FMM_OVERLAP_WHOLE = 1, FMM_OVERLAP_SPLIT = 2 };
+ * competes with the M2L (fmm_upward alone runs the whole near field);
+ * FMM_OVERLAP_TAIL: in fmm_run, the whole near field after the M2L, beside
+ * the combine and L2L, joined before the L2P (fmm_upward alone runs it as
+ * OFF does).  FMM_EINVAL for other values. */
+enum { FMM_OVERLAP_OFF = 0, FMM_OVERLAP_WHOLE = 1, FMM_OVERLAP_SPLIT = 2, FMM_OVERLAP_TAIL = 3 };
 int fmm_ctx_set_overlap(fmm_ctx *ctx, int on);
 
 /* Replay HIP graphs (default on): the kernel sequence of fmm_upward and of

@@ -75,7 +75,7 @@ static void drop_graphs(fmm_tree *t)
 extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
-    if (on < 0 || on > FMM_OVERLAP_SPLIT) FAIL(FMM_EINVAL, "overlap mode %d (0, 1 or 2)", on);
+    if (on < 0 || on > FMM_OVERLAP_TAIL) FAIL(FMM_EINVAL, "overlap mode %d (0, 1, 2 or 3)", on);
     ctx->overlap = on;
     for (fmm_tree *t : ctx->trees) drop_graphs(t);
     return FMM_OK;
@@ -728,12 +728,15 @@ static int queue_upward(fmm_ctx *ctx, fmm_tree *t, bool join)
 {
     hipStream_t s = ctx->stream;
     const bool fmm = t->method == FMM_METHOD_FMM;
-    hipStream_t a = ctx->overlap && fmm ? ctx->aux : s;
+    // tail overlap: inside fmm_run the near field follows the M2L
+    // (queue_evaluate); alone, fmm_upward runs it on its own stream
+    const bool tail = ctx->overlap == FMM_OVERLAP_TAIL;
+    hipStream_t a = ctx->overlap && !tail && fmm ? ctx->aux : s;
     {
         ProfScope ps(ctx, s, "p2m");
         KCHK(launch_p2m(t, s));
     }
-    if (fmm) {
+    if (fmm && !(tail && !join)) {
         if (a != s) {
             KCHK(hipEventRecord(ctx->ev_fork, s));
             KCHK(hipStreamWaitEvent(a, ctx->ev_fork, 0));
@@ -771,18 +774,20 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         return FMM_OK;
     }
     const bool split = wait_near && ctx->overlap == FMM_OVERLAP_SPLIT;
+    const bool tail = wait_near && ctx->overlap == FMM_OVERLAP_TAIL;
     if (split) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));   // the first near-field half
     {
         ProfScope ps(ctx, s, "m2l");
         KCHK(launch_m2l(t, s));
     }
-    if (split) {
-        // the second half of the near field beside the combine and L2L
+    if (split || tail) {
+        // the near field (split: its second half) beside the combine and L2L
         KCHK(hipEventRecord(ctx->ev_m2l, s));
         KCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_m2l, 0));
         {
             ProfScope ps(ctx, ctx->aux, "p2p");
-            KCHK(launch_p2p_part(t, ctx->aux, t->p2p_split, -1));
+            if (split) KCHK(launch_p2p_part(t, ctx->aux, t->p2p_split, -1));
+            else KCHK(launch_p2p(t, ctx->aux));
         }
         KCHK(hipEventRecord(ctx->ev_near2, ctx->aux));
     }
@@ -795,7 +800,7 @@ static int queue_evaluate(fmm_ctx *ctx, fmm_tree *t, int outputs, double *phi, d
         ProfScope ps(ctx, s, "l2l");
         KCHK(launch_l2l_level(t, l, s));
     }
-    if (split) KCHK(hipStreamWaitEvent(s, ctx->ev_near2, 0));
+    if (split || tail) KCHK(hipStreamWaitEvent(s, ctx->ev_near2, 0));
     else if (wait_near && ctx->overlap) KCHK(hipStreamWaitEvent(s, ctx->ev_near, 0));
     if (outputs & FMM_GRAD) {
         ProfScope ps(ctx, s, "p2p_grad");

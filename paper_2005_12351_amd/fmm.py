@@ -32,7 +32,7 @@ LIB_PATH = os.environ.get("FMM_LIBRARY") or os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ESTATE, FMM_EBUSY, FMM_ETIMEOUT = range(7)
 FMM_POT, FMM_FIELD, FMM_GRAD = 1, 2, 4   # output mask bits (FMM_GRAD: evaluate_grad only)
-FMM_OVERLAP_OFF, FMM_OVERLAP_WHOLE, FMM_OVERLAP_SPLIT = 0, 1, 2
+FMM_OVERLAP_OFF, FMM_OVERLAP_WHOLE, FMM_OVERLAP_SPLIT, FMM_OVERLAP_TAIL = 0, 1, 2, 3
 FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_M2L_ENGINE_VALU, FMM_M2L_ENGINE_MFMA, FMM_M2L_ENGINE_AUTO = 0, 1, 2   # units of the FP32 harmonic M2L
@@ -236,7 +236,8 @@ class Context:
 
     def set_overlap(self, on=True):
         """False/0 off, True/1 the whole near field beside the far field, 2
-        (FMM_OVERLAP_SPLIT) half beside M2M and half after the M2L"""
+        (FMM_OVERLAP_SPLIT) half beside M2M and half after the M2L, 3
+        (FMM_OVERLAP_TAIL) the whole near field after the M2L"""
         _check(fmm_ctx_set_overlap(self.h, int(on)), "fmm_ctx_set_overlap")
 
     def set_graphs(self, on: bool = True):

@@ -118,12 +118,12 @@ def test_fake_server_stop_drains_queue(fmm):
 
 
 def test_overlap_modes_validated(fmm):
-    """fmm_ctx_set_overlap takes FMM_OVERLAP_OFF / WHOLE / SPLIT and rejects
-    anything else with FMM_EINVAL (no device needed)"""
+    """fmm_ctx_set_overlap takes FMM_OVERLAP_OFF / WHOLE / SPLIT / TAIL and
+    rejects anything else with FMM_EINVAL (no device needed)"""
     ctx = fmm.Context.fake(budget_bytes=1 << 30)
-    for mode in (fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT, False, True):
+    for mode in (fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT, fmm.FMM_OVERLAP_TAIL, False, True):
         ctx.set_overlap(mode)
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         with pytest.raises(RuntimeError, match="overlap mode"):
             ctx.set_overlap(bad)
     ctx.close()

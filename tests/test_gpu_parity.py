@@ -261,7 +261,8 @@ def test_engine_switch_on_one_tree(ctx, order, p):
     assert np.array_equal(out[0][0], out[2][0]) and np.array_equal(out[0][1], out[2][1])
 
 
-@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT])
+@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT,
+                                     fmm.FMM_OVERLAP_TAIL])
 def test_graph_replay_matches_eager(ctx, overlap):
     """Captured graphs replayed several times, with eager work and
     synchronisations in between, give exactly the eager result each time."""
@@ -296,7 +297,8 @@ def test_graph_replay_matches_eager(ctx, overlap):
         ctx.set_graphs(True)
 
 
-@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT])
+@pytest.mark.parametrize("overlap", [fmm.FMM_OVERLAP_OFF, fmm.FMM_OVERLAP_WHOLE, fmm.FMM_OVERLAP_SPLIT,
+                                     fmm.FMM_OVERLAP_TAIL])
 @pytest.mark.parametrize("method", ["fmm", "bh"])
 def test_run_matches_upward_evaluate(ctx, overlap, method):
     """fmm_run (one launch sequence) gives exactly the result of fmm_upward +

@@ -215,7 +215,9 @@ int fmm_run(fmm_ctx *ctx, fmm_tree *tree, int order, const double *moments, int 
  * (level-major, ascending key): level, ix[3] integer cell coordinates,
  * first, count (sorted particle range), parent (-1 at the root), child0,
  * nchild; CSR interaction lists per target cell, sources sorted ascending:
- * m2l_ptr[ncells+1], m2l_src[n_m2l], p2p_ptr[ncells+1], p2p_src[n_p2p]. */
+ * m2l_ptr[ncells+1], m2l_src[n_m2l], p2p_ptr[ncells+1], p2p_src[n_p2p].
+ * When the M2L schedule was made on the device the M2L lists live there
+ * only: asking for them synchronises the context stream. */
 int fmm_tree_export(const fmm_tree *tree, double *geom, uint64_t *key, int64_t *perm,
                     int32_t *level, int32_t *ix, int64_t *first, int64_t *count,
                     int64_t *parent, int64_t *child0, int32_t *nchild, int64_t *m2l_ptr,
@@ -274,6 +276,34 @@ int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis);
  * at the next fmm_upward / fmm_run of a tree.  FMM_EINVAL for another
  * value. */
 int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine);
+
+/* Where fmm_build_tree makes the M2L schedule of FMM trees (Section 3.3:
+ * the M2L of every target of every list, grouped for the kernel): targets
+ * 64 to a tile in (level, position in the parent, same-level neighbourhood,
+ * list length) order; per tile the sorted distinct pair geometries
+ * ((z_B - z_A) / r_B, r_A / r_B), each one derivative tensor for all 64
+ * lanes; class ids the ranks of the geometries among all tiles'; per
+ * (entry, lane) the source cell or the zero row.  FMM_SCHEDULE_DEVICE
+ * (default): built on the GPU after the interaction lists, without their
+ * round trip through the host; when a tile holds more than 4096 distinct
+ * geometries or a packed key would overflow the build takes the host code
+ * instead.  FMM_SCHEDULE_HOST: built by the host threads.  Both give the
+ * same schedule, entry for entry.  Takes effect for trees built afterwards.
+ * FMM_EINVAL for another value. */
+enum { FMM_SCHEDULE_HOST = 0, FMM_SCHEDULE_DEVICE = 1 };
+int fmm_ctx_set_m2l_schedule(fmm_ctx *ctx, int where);
+
+/* The M2L schedule of an FMM tree, to HOST arrays (any pointer may be NULL)
+ * sized by fmm_tree_info (classes info[6], tiles info[7], slots info[8]):
+ * tile_cell[64 tiles] target cell of each lane or -1; tile_uoff[tiles+1]
+ * entry range of each tile; ucls[slots/64] class id of each entry (ascending
+ * within a tile); usrc[slots] source cell of each (entry, lane), ncells
+ * where the lane lacks the class; cls_geom[4 classes] the class geometry
+ * (three offsets in units of r_B, then r_A / r_B); *where the schedule's
+ * builder (FMM_SCHEDULE_DEVICE or _HOST).  Synchronises the context stream.
+ * FMM_EINVAL for a Barnes-Hut tree. */
+int fmm_tree_m2l_schedule(const fmm_tree *tree, int32_t *tile_cell, int32_t *tile_uoff, int32_t *ucls,
+                          int32_t *usrc, double *cls_geom, int *where);
 
 /* Per-kernel device timing.  When enabled, every kernel launch is bracketed
  * by HIP events on the stream it runs on.  fmm_profile_read synchronises and

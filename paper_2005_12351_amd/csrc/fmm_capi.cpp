@@ -89,6 +89,14 @@ extern "C" int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis)
     return FMM_OK;
 }
 
+extern "C" int fmm_ctx_set_m2l_schedule(fmm_ctx *ctx, int where)
+{
+    if (!ctx) FAIL(FMM_EINVAL, "null context");
+    if (where != FMM_SCHEDULE_DEVICE && where != FMM_SCHEDULE_HOST) FAIL(FMM_EINVAL, "unknown M2L schedule %d", where);
+    ctx->m2l_schedule = where;   // trees built from now on
+    return FMM_OK;
+}
+
 extern "C" int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
@@ -357,10 +365,14 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     t->ncrit = ncrit;
     t->theta = theta;
     HostScope hs_all(ctx, "host:build_tree");
+    DevKeep dt;
+    dt.keep = [t](void **p, size_t bytes) { return tree_alloc(t, p, bytes) == FMM_OK ? hipSuccess : hipErrorOutOfMemory; };
+    dt.tl = &t->tiling;
+    dt.tiling = method == FMM_METHOD_FMM && ctx->m2l_schedule == FMM_SCHEDULE_DEVICE;
     {
-        const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx);
+        const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx, &dt);
         if (e != hipSuccess) {
-            delete t;
+            fmm_tree_destroy(t);
             if (e == hipErrorInvalidValue) FAIL(FMM_EINVAL, "non-finite position");
             if (e == hipErrorOutOfMemory) FAIL(FMM_ENOMEM, "tree construction: out of device memory");
             FAIL(FMM_EDEVICE, "tree construction: %s", hipGetErrorString(e));
@@ -368,28 +380,28 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     }
     HostTree &h = t->ht;
     const int64_t nc = h.ncells();
+    t->d_cells = dt.cells;
+    t->d_perm = dt.perm;
+    t->d_key = dt.key;
     if (method == FMM_METHOD_FMM) {
-        HostScope hs(ctx, "host:m2l_tiling");
-        build_m2l_tiling(h, t->tiling);
+        if (dt.done) {
+            t->d_ucls = dt.ucls;
+            t->d_usrc = dt.usrc;
+            t->d_cell_slot = dt.cell_slot;
+            t->d_cls_geom = dt.cls_geom;
+            t->d_m2l_ptr = dt.m2l_ptr;
+            t->d_m2l_src = dt.m2l_src;
+        } else {
+            HostScope hs(ctx, "host:m2l_tiling");
+            build_m2l_tiling(h, t->tiling);
+        }
     } else {
         h.m2l_ptr.assign(nc + 1, 0);
         h.p2p_ptr.assign(nc + 1, 0);
     }
     // leaves, per-particle leaf, non-leaf cells per level, P2P CSR per leaf
     std::vector<int32_t> level_cells(nc);
-    std::vector<DevCell> cells(nc);
     for (int64_t c = 0; c < nc; ++c) {
-        DevCell d{};
-        d.level = h.level[c];
-        d.ix = h.ix[3 * c];
-        d.iy = h.ix[3 * c + 1];
-        d.iz = h.ix[3 * c + 2];
-        d.first = (int32_t)h.first[c];
-        d.count = (int32_t)h.count[c];
-        d.parent = (int32_t)h.parent[c];
-        d.child0 = (int32_t)h.child0[c];
-        d.nchild = h.nchild[c];
-        cells[c] = d;
         level_cells[c] = (int32_t)c;
         if (h.nchild[c] == 0) {
             t->leaves.push_back((int32_t)c);
@@ -410,7 +422,10 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     // (a list is sorted by source index and cells are level-major, so its
     // first source is its shallowest)
     int src_top = nlev, tgt_top = nlev;
-    if ((int64_t)h.m2l_ptr.size() == nc + 1)
+    if (t->tiling.on_device && dt.tgt_top >= 0) {
+        tgt_top = dt.tgt_top;
+        src_top = dt.src_top;
+    } else if ((int64_t)h.m2l_ptr.size() == nc + 1)
         for (int64_t c = 0; c < nc; ++c)
             if (h.m2l_ptr[c + 1] > h.m2l_ptr[c]) {
                 tgt_top = std::min(tgt_top, h.level[c]);
@@ -477,8 +492,6 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         while (k < (int)t->nleaves && acc < 0.5 * tot) acc += leaf_cost[p2p_order[k++]];
         t->p2p_split = k;
     }
-    std::vector<int32_t> perm32(n);
-    for (int64_t i = 0; i < n; ++i) perm32[i] = (int32_t)h.perm[i];
 
     HostScope hs_up(ctx, "host:tree_upload");
     int rc = FMM_OK;
@@ -487,15 +500,13 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         fmm_tree_destroy(t);                           \
         return rc;                                     \
     }
-    UP(t->d_cells, cells);
-    UP(t->d_perm, perm32);
     UP(t->d_leaves, t->leaves);
     UP(t->d_nonleaf, t->level_nonleaf);
     UP(t->d_level_cells, level_cells);
     UP(t->d_p2p_ptr, pptr);
     UP(t->d_p2p_src, psrc);
     UP(t->d_p2p_order, p2p_order);
-    if (method == FMM_METHOD_FMM) {
+    if (method == FMM_METHOD_FMM && !t->tiling.on_device) {
         const M2LTiling &tl = t->tiling;
         UP(t->d_ucls, tl.ucls);
         UP(t->d_usrc, tl.usrc);
@@ -504,8 +515,8 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
             if (tl.tile_cell[k] >= 0) cell_slot[tl.tile_cell[k]] = (int32_t)k;
         UP(t->d_cell_slot, cell_slot);
         UP(t->d_cls_geom, tl.cls_geom);
-        t->work[0] = (double)tl.pairs;
     }
+    if (method == FMM_METHOD_FMM) t->work[0] = (double)t->tiling.pairs;
 #undef UP
     if ((rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n))) {
         fmm_tree_destroy(t);
@@ -1031,12 +1042,38 @@ extern "C" int fmm_tree_info(const fmm_tree *t, int64_t *info)
     info[1] = h.ncells();
     info[2] = (int64_t)h.level_ptr.size() - 1;
     info[3] = t->nleaves;
-    info[4] = h.m2l_ptr.empty() ? 0 : h.m2l_ptr.back();
+    info[4] = t->tiling.on_device ? t->tiling.pairs : h.m2l_ptr.empty() ? 0 : h.m2l_ptr.back();
     info[5] = h.p2p_ptr.empty() ? 0 : h.p2p_ptr.back();
     info[6] = t->tiling.nclasses;
     info[7] = t->tiling.ntiles;
     info[8] = t->tiling.nentries * kTileW;
     info[9] = (int64_t)t->dev_bytes;
+    return FMM_OK;
+}
+
+extern "C" int fmm_tree_m2l_schedule(const fmm_tree *t, int32_t *tile_cell, int32_t *tile_uoff, int32_t *ucls,
+                                     int32_t *usrc, double *cls_geom, int *where)
+{
+    if (!t) FAIL(FMM_EINVAL, "null tree");
+    if (t->method != FMM_METHOD_FMM) FAIL(FMM_EINVAL, "a Barnes-Hut tree has no M2L schedule");
+    if (!t->ctx) FAIL(FMM_EINVAL, "the tree's context was destroyed");
+    const M2LTiling &tl = t->tiling;
+    if (where) *where = tl.on_device ? FMM_SCHEDULE_DEVICE : FMM_SCHEDULE_HOST;
+    auto cp = [](auto *dst, const auto &v) {
+        if (dst && !v.empty()) memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    cp(tile_cell, tl.tile_cell);
+    cp(tile_uoff, tl.tile_uoff);
+    HIPCHK(hipSetDevice(t->ctx->device));
+    hipStream_t s = t->ctx->stream;
+    // the tables as the M2L reads them (device copies of either schedule)
+    if (ucls && tl.nentries)
+        HIPCHK(hipMemcpyAsync(ucls, t->d_ucls, sizeof(int32_t) * tl.nentries, hipMemcpyDeviceToHost, s));
+    if (usrc && tl.nentries)
+        HIPCHK(hipMemcpyAsync(usrc, t->d_usrc, sizeof(int32_t) * tl.nentries * kTileW, hipMemcpyDeviceToHost, s));
+    if (cls_geom && tl.nclasses)
+        HIPCHK(hipMemcpyAsync(cls_geom, t->d_cls_geom, sizeof(double) * 4 * tl.nclasses, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return FMM_OK;
 }
 
@@ -1055,8 +1092,17 @@ extern "C" int fmm_tree_export(const fmm_tree *t, double *geom, uint64_t *key, i
         geom[2] = h.lo[2];
         geom[3] = h.W;
     }
-    cp(key, h.key);
-    cp(perm, h.perm);
+    if (key || perm) {
+        // the order and the keys stayed on the device
+        if (!t->ctx) FAIL(FMM_EINVAL, "the tree's context was destroyed");
+        HIPCHK(hipSetDevice(t->ctx->device));
+        hipStream_t s = t->ctx->stream;
+        std::vector<int32_t> p32(perm ? h.n : 0);
+        if (key) HIPCHK(hipMemcpyAsync(key, t->d_key, sizeof(uint64_t) * h.n, hipMemcpyDeviceToHost, s));
+        if (perm) HIPCHK(hipMemcpyAsync(p32.data(), t->d_perm, sizeof(int32_t) * h.n, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (perm) std::copy(p32.begin(), p32.end(), perm);
+    }
     cp(level, h.level);
     cp(ix, h.ix);
     cp(first, h.first);
@@ -1064,8 +1110,22 @@ extern "C" int fmm_tree_export(const fmm_tree *t, double *geom, uint64_t *key, i
     cp(parent, h.parent);
     cp(child0, h.child0);
     cp(nchild, h.nchild);
-    cp(m2l_ptr, h.m2l_ptr);
-    cp(m2l_src, h.m2l_src);
+    if (t->tiling.on_device && (m2l_ptr || m2l_src)) {
+        // the lists stayed on the device
+        if (!t->ctx) FAIL(FMM_EINVAL, "the tree's context was destroyed");
+        HIPCHK(hipSetDevice(t->ctx->device));
+        hipStream_t s = t->ctx->stream;
+        const int64_t nc = h.ncells(), m = t->tiling.pairs;
+        std::vector<int32_t> p32(nc + 1), s32(m);
+        HIPCHK(hipMemcpyAsync(p32.data(), t->d_m2l_ptr, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost, s));
+        if (m) HIPCHK(hipMemcpyAsync(s32.data(), t->d_m2l_src, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (m2l_ptr) std::copy(p32.begin(), p32.end(), m2l_ptr);
+        if (m2l_src) std::copy(s32.begin(), s32.end(), m2l_src);
+    } else {
+        cp(m2l_ptr, h.m2l_ptr);
+        cp(m2l_src, h.m2l_src);
+    }
     cp(p2p_ptr, h.p2p_ptr);
     cp(p2p_src, h.p2p_src);
     return FMM_OK;

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <string>
 #include <chrono>
+#include <functional>
 #include <vector>
 
 #include "../../include/fmm.h"
@@ -156,8 +157,9 @@ struct HostTree {      // canonical tree, host copy
 // (tree_gpu.hip).  hipErrorInvalidValue: a position is not finite;
 // hipErrorOutOfMemory: a list or frontier exceeds 2^31 entries or the device
 // is out of memory.
+struct DevKeep;
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
-                          HostTree &t, fmm_ctx *ctx = nullptr);
+                          HostTree &t, fmm_ctx *ctx = nullptr, DevKeep *dt = nullptr);
 
 // M2L tiling (tree_host.cpp)
 struct M2LTiling {
@@ -169,8 +171,35 @@ struct M2LTiling {
     std::vector<int32_t> usrc;             // nentries*64: source cell (or zero row)
     std::vector<double> cls_geom;          // nclasses*4: (z_B - z_A)/r_B, r_A/r_B
     int64_t pairs = 0;                     // real list entries
+    bool on_device = false;                // ucls, usrc, cls_geom exist on the device only
 };
 void build_m2l_tiling(const HostTree &t, M2LTiling &out);
+
+// Device buffers of a tree that gpu_build_tree (tree_gpu.hip) leaves on
+// the device: `keep` allocates them (the tree's own allocations).  Always:
+// cells (DevCell per cell), perm (input index of sorted particle i, int32)
+// and key (sorted Morton keys); the host tree then holds neither perm nor
+// key.  With `tiling`, also the M2L tiling of build_m2l_tiling made on the
+// device: on return `done` says whether it is complete (false: a packed key
+// would overflow, or a tile has more distinct pair geometries than the
+// device table holds, and the host code must build it from the host lists).
+// `tl` receives its host parts (sizes, tile_cell, tile_uoff, pairs).  When
+// done, the M2L lists stay on the device (m2l_ptr over ncells + 1, m2l_src)
+// and the host tree holds none; tgt_top / src_top are the shallowest target
+// and source levels of the lists (-1: no list).
+struct DevKeep {
+    std::function<hipError_t(void **, size_t)> keep;
+    DevCell *cells = nullptr;
+    int32_t *perm = nullptr;
+    uint64_t *key = nullptr;
+    bool tiling = false;
+    int32_t *ucls = nullptr, *usrc = nullptr, *cell_slot = nullptr;
+    int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;
+    double *cls_geom = nullptr;
+    M2LTiling *tl = nullptr;
+    int tgt_top = -1, src_top = -1;
+    bool done = false;
+};
 
 // M2L work for one kernel variant: the (tile, output block, entry) units,
 // concatenated, are cut into nwaves pieces of equal cost, one per resident
@@ -222,6 +251,7 @@ struct fmm_ctx {
     bool graphs = true;                   // replay captured HIP graphs
     int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
     int m2l_engine = FMM_M2L_ENGINE_AUTO; // units of the FP32 harmonic-basis M2L
+    int m2l_schedule = FMM_SCHEDULE_DEVICE;   // where tree builds make the M2L schedule
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
@@ -256,6 +286,8 @@ struct fmm_tree {
     int32_t *d_p2p_ptr = nullptr, *d_p2p_src = nullptr;   // per leaf, sources as cell ids
     int4 *d_work = nullptr;                // per expansion configuration
     int32_t *d_ucls = nullptr, *d_usrc = nullptr, *d_cell_slot = nullptr;   // cell -> tile slot or -1
+    int32_t *d_m2l_ptr = nullptr, *d_m2l_src = nullptr;   // M2L lists, kept when the host holds none
+    uint64_t *d_key = nullptr;                            // sorted Morton keys (the host holds none)
     int32_t *d_tile_chunk0 = nullptr, *d_tile_nchunk = nullptr;
     int32_t *d_p2p_order = nullptr;        // leaf ordinals by decreasing near-field cost
     int p2p_split = 0;                     // first position of p2p_order past half the near-field cost

@@ -61,7 +61,8 @@ struct Server {
 // Estimated device bytes of one request (tree, expansions, lists, near-field
 // buffers): particles cost ~112 B plus the sorted moments, cells (about
 // 2.3 n / ncrit) cost their multipole and local rows, the interaction-list
-// tiles and partial results (~2 kB), plus a fixed 4 MB for derivative tables.
+// tiles and partial results (~2 kB) and their M2L list (~1 kB), plus a fixed
+// 4 MB for derivative tables.
 static size_t footprint_estimate(const fmm_request &r)
 {
     const int mask = code_mask(r.order), s = mask_min_order(mask);
@@ -69,7 +70,7 @@ static size_t footprint_estimate(const fmm_request &r)
     const double cells = std::max(1.0, 2.3 * (double)r.n / std::max(1, r.ncrit));
     const double nm = nterms(r.p) - nterms(s - 1), nl = nterms(std::max(0, r.p - s));
     const double per_part = 112.0 + 8.0 * w;
-    const double per_cell = 48.0 + nm * 12.0 + nl * 24.0 + 2048.0;
+    const double per_cell = 48.0 + nm * 12.0 + nl * 24.0 + 3072.0;
     return (size_t)(per_part * (double)r.n + per_cell * cells + 4.0 * (1 << 20));
 }
 

@@ -464,6 +464,12 @@ struct Dev {
         blocks.push_back(p);
         return (T *)p;
     }
+    // hand a block over to another owner (no longer freed with the rest)
+    void detach(void *p)
+    {
+        auto it = std::find(blocks.begin(), blocks.end(), p);
+        if (it != blocks.end()) blocks.erase(it);
+    }
     void release(void *p)
     {
         auto it = std::find(blocks.begin(), blocks.end(), p);
@@ -598,6 +604,351 @@ struct Staging {
     }
 };
 
+// ------------------------------------------------------------------ M2L scheduling
+// The tiling of build_m2l_tiling (tree_host.cpp) on the device, with the same
+// result: targets in (level, octant, same-level signature, list length
+// descending, cell) order, 64 to a tile; per tile the sorted distinct pair
+// geometries; class ids the ranks in the sorted union; per entry and lane
+// the source (or the zero row).  Keys are packed into 64 bits in the order
+// of the host comparators; a key that does not fit (or a tile with more
+// distinct geometries than its hash table holds) sends the tree back to the
+// host code.
+
+constexpr int kTileHashBits = 13;
+constexpr int kTileHash = 1 << kTileHashBits;   // open-addressing slots per tile (LDS)
+constexpr int kTileMaxU = kTileHash / 2;        // distinct geometries a tile may have here
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr int64_t kClsR = 1 << 18;         // offset range of a packed pair geometry
+
+// first probe of a key in the tile table (Fibonacci hashing)
+__device__ __forceinline__ int tile_slot(uint64_t k) { return (int)((k * 0x9E3779B97F4A7C15ull) >> (64 - kTileHashBits)); }
+
+// (dl + 32) << 57 | (d0 + R) << 38 | (d1 + R) << 19 | (d2 + R): the order
+// of (dl, d0, d1, d2)
+__device__ __forceinline__ bool pack_class(const DevCell &A, const DevCell &B, uint64_t &key)
+{
+    const int la = A.level, lb = B.level, lm = max(la, lb);
+    const int64_t d0 = ((2 * (int64_t)B.ix + 1) << (lm - lb)) - ((2 * (int64_t)A.ix + 1) << (lm - la));
+    const int64_t d1 = ((2 * (int64_t)B.iy + 1) << (lm - lb)) - ((2 * (int64_t)A.iy + 1) << (lm - la));
+    const int64_t d2 = ((2 * (int64_t)B.iz + 1) << (lm - lb)) - ((2 * (int64_t)A.iz + 1) << (lm - la));
+    const bool ok = d0 >= -kClsR && d0 < kClsR && d1 >= -kClsR && d1 < kClsR && d2 >= -kClsR && d2 < kClsR;
+    key = ((uint64_t)(lb - la + 32) << 57) | ((uint64_t)(d0 + kClsR) << 38) | ((uint64_t)(d1 + kClsR) << 19) |
+          (uint64_t)(d2 + kClsR);
+    return ok;
+}
+
+__device__ __forceinline__ void unpack_class(uint64_t k, int &dl, int64_t &d0, int64_t &d1, int64_t &d2)
+{
+    const uint64_t m = (1ull << 19) - 1;
+    dl = (int)(k >> 57) - 32;
+    d0 = (int64_t)((k >> 38) & m) - kClsR;
+    d1 = (int64_t)((k >> 19) & m) - kClsR;
+    d2 = (int64_t)(k & m) - kClsR;
+}
+
+// target keys: level (5 bits) | octant (3) | lo0 hi0 lo1 hi1 lo2 hi2 (7 each,
+// + 64) | 8191 - length (13); cells without an M2L list sort last
+__global__ void tile_key_kernel(const DevCell *__restrict__ cells, int nc, const int32_t *__restrict__ ptr,
+                                const int32_t *__restrict__ src, uint64_t *__restrict__ key,
+                                int32_t *__restrict__ val, unsigned long long *__restrict__ info)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    val[c] = c;
+    const int e0 = ptr[c], e1 = ptr[c + 1];
+    if (e1 == e0) {
+        key[c] = kEmptyKey;
+        return;
+    }
+    const DevCell B = cells[c];
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    bool any = false;
+    for (int e = e0; e < e1; ++e) {
+        const DevCell A = cells[src[e]];
+        if (A.level != B.level) continue;
+        const int o[3] = {A.ix - B.ix, A.iy - B.iy, A.iz - B.iz};
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = any ? min(lo[d], o[d]) : o[d];
+            hi[d] = any ? max(hi[d], o[d]) : o[d];
+        }
+        any = true;
+    }
+    const int len = e1 - e0;
+    bool ok = len <= 8191 && B.level < 32;
+    uint64_t k = ((uint64_t)B.level << 58) | ((uint64_t)(((B.ix & 1) << 2) | ((B.iy & 1) << 1) | (B.iz & 1)) << 55);
+    for (int d = 0; d < 3; ++d) {
+        ok = ok && lo[d] >= -64 && lo[d] < 64 && hi[d] >= -64 && hi[d] < 64;
+        k |= (uint64_t)((lo[d] + 64) & 127) << (48 - 14 * d);
+        k |= (uint64_t)((hi[d] + 64) & 127) << (41 - 14 * d);
+    }
+    k |= (uint64_t)(8191 - min(len, 8191));
+    key[c] = k;
+    atomicAdd(&info[0], 1ull);                 // targets
+    if (!ok) atomicOr(&info[1], 1ull);         // a key field overflows
+    atomicMin(&info[4], (unsigned long long)B.level);                  // shallowest target
+    atomicMin(&info[5], (unsigned long long)cells[src[e0]].level);     // shallowest source (lists sorted
+}                                                                      // by source, cells level-major)
+
+__global__ void tile_info_init_kernel(unsigned long long *info)
+{
+    if (threadIdx.x < 6) info[threadIdx.x] = threadIdx.x < 4 ? 0ull : ~0ull;
+}
+
+// one workgroup per tile: the tile's distinct pair geometries in an LDS hash
+// table.  EMIT = false: their number; EMIT = true: sorted into U, written
+// at the tile's entry offset, and every (entry, lane) source placed in usrc
+template <bool EMIT>
+__global__ __launch_bounds__(256) void tile_classes_kernel(const DevCell *__restrict__ cells,
+                                                           const int32_t *__restrict__ tcell,
+                                                           const int32_t *__restrict__ ptr,
+                                                           const int32_t *__restrict__ src,
+                                                           unsigned long long *__restrict__ info,
+                                                           int32_t *__restrict__ tcnt, const int32_t *__restrict__ uoff,
+                                                           uint64_t *__restrict__ ukey, int32_t *__restrict__ usrc)
+{
+    __shared__ uint64_t tab[kTileHash];
+    __shared__ uint64_t U[EMIT ? kTileMaxU : 1];
+    __shared__ int16_t pos[EMIT ? kTileHash : 1];
+    __shared__ int cnt, bad;
+    const int tile = blockIdx.x, ntg = (int)info[0];
+    if (tile * kTileW >= ntg) {   // the grid is sized by all cells
+        if (!EMIT && threadIdx.x == 0) tcnt[tile] = 0;
+        return;
+    }
+    for (int h = threadIdx.x; h < kTileHash; h += blockDim.x) tab[h] = kEmptyKey;
+    if (threadIdx.x == 0) {
+        cnt = 0;
+        bad = 0;
+    }
+    __syncthreads();
+    // 4 threads per lane, every 4th entry of the lane's list each
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int slot = tile * kTileW + lane;
+    const int B = slot < ntg ? tcell[slot] : -1;
+    const int e0 = B >= 0 ? ptr[B] : 0, e1 = B >= 0 ? ptr[B + 1] : 0;
+    const DevCell cb = cells[B >= 0 ? B : 0];
+    auto probe = [&](uint64_t k) {   // the slot of k, inserting it
+        int h = tile_slot(k);
+        for (int n = 0; n < kTileHash; ++n) {
+            const uint64_t old = atomicCAS((unsigned long long *)&tab[h], (unsigned long long)kEmptyKey,
+                                           (unsigned long long)k);
+            if (old == kEmptyKey) {
+                if (atomicAdd(&cnt, 1) >= kTileMaxU) bad = 1;
+                return h;
+            }
+            if (old == k) return h;
+            h = (h + 1) & (kTileHash - 1);
+        }
+        bad = 1;
+        return -1;
+    };
+    for (int e = e0 + part; e < e1; e += 4) {
+        uint64_t k;
+        if (!pack_class(cells[src[e]], cb, k)) bad = 1;
+        probe(k);
+    }
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) {
+            atomicOr(&info[1], 2ull);
+            if (!EMIT) tcnt[tile] = 0;
+        }
+        return;
+    }
+    const int nu = cnt;
+    if constexpr (!EMIT) {
+        if (threadIdx.x == 0) tcnt[tile] = nu;
+        return;
+    } else {
+        // compact, then a bitonic sort of the next power of two
+        __shared__ int fill;
+        if (threadIdx.x == 0) fill = 0;
+        __syncthreads();
+        for (int h = threadIdx.x; h < kTileHash; h += blockDim.x)
+            if (tab[h] != kEmptyKey) U[atomicAdd(&fill, 1)] = tab[h];
+        int np = 1;
+        while (np < nu) np <<= 1;
+        __syncthreads();
+        for (int j = nu + threadIdx.x; j < np; j += blockDim.x) U[j] = kEmptyKey;
+        __syncthreads();
+        for (int k = 2; k <= np; k <<= 1)
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = U[i], b = U[l];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) {
+                            U[i] = b;
+                            U[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        // sorted position of every slot's key
+        const int base = uoff[tile];
+        for (int j = threadIdx.x; j < nu; j += blockDim.x) {
+            const uint64_t k = U[j];
+            int h = tile_slot(k);
+            while (tab[h] != k) h = (h + 1) & (kTileHash - 1);
+            pos[h] = (int16_t)j;
+            ukey[base + j] = k;
+        }
+        __syncthreads();
+        for (int e = e0 + part; e < e1; e += 4) {
+            const int A = src[e];
+            uint64_t k;
+            pack_class(cells[A], cb, k);
+            int h = tile_slot(k);
+            while (tab[h] != k) h = (h + 1) & (kTileHash - 1);
+            usrc[(size_t)(base + pos[h]) * kTileW + lane] = A;
+        }
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// cell -> tile slot, for the targets of the tiles
+__global__ void tile_slots_kernel(const int32_t *__restrict__ tcell, int ntg, int32_t *__restrict__ cell_slot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntg) cell_slot[tcell[i]] = i;
+}
+
+// after the sort of all tiles' geometries: first-of-a-kind flags
+__global__ void class_flags_kernel(const uint64_t *__restrict__ k, int n, int32_t *__restrict__ f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = (i == 0 || k[i] != k[i - 1]) ? 1 : 0;
+}
+
+// class id of every tile entry (the rank of its geometry) and the class
+// geometry ((z_B - z_A) / r_B, r_A / r_B), as the host computes it
+__global__ void class_ids_kernel(const uint64_t *__restrict__ k, const int32_t *__restrict__ idx,
+                                 const int32_t *__restrict__ rank_excl, const int32_t *__restrict__ f, int n,
+                                 int32_t *__restrict__ ucls, double *__restrict__ geom)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = rank_excl[i] + f[i] - 1;
+    ucls[idx[i]] = r;
+    if (f[i]) {
+        int dl;
+        int64_t d0, d1, d2;
+        unpack_class(k[i], dl, d0, d1, d2);
+        const double unit = ldexp(1.0, min(0, dl));
+        geom[4 * r] = (double)d0 * unit;
+        geom[4 * r + 1] = (double)d1 * unit;
+        geom[4 * r + 2] = (double)d2 * unit;
+        geom[4 * r + 3] = ldexp(1.0, dl);
+    }
+}
+
+__global__ void last_of_scan_kernel(int32_t *ptr, int n, const int64_t *total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) ptr[n] = (int32_t)*total;
+}
+
+__global__ void iota_i32_kernel(int32_t *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
+// Device M2L tiling, first part: the M2L CSR offsets, the target order, the
+// per-tile geometry counts and their offsets, then one wait for the sizes.
+// On success with dt.done the kept buffers hold the per-entry tables and
+// *tcell / *uoff / *nclasses_dev the parts the host copies back with the
+// tree (finish_tiling).  `done` false: fall back to the host code.
+struct TileState {
+    int32_t *tcell = nullptr, *uoff = nullptr;
+    double *geom = nullptr;
+    unsigned long long *info = nullptr;   // ntargets, overflow flags, nentries, nclasses, top levels
+    int ntg = 0, ntiles = 0;
+    int64_t nentries = 0;
+};
+
+hipError_t launch_tiling(Dev &dv, const DevCell *cells, int nc, const int32_t *cnt, const int32_t *src, int64_t nsrc,
+                         DevKeep &dt, TileState &ts)
+{
+    dt.done = false;
+    hipStream_t s = dv.s;
+    int32_t *ptr = dv.alloc<int32_t>((size_t)nc + 1);
+    uint64_t *key = dv.alloc<uint64_t>(nc);
+    int32_t *val = dv.alloc<int32_t>(nc);
+    ts.info = dv.alloc<unsigned long long>(6);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(tile_info_init_kernel, dim3(1), dim3(64), 0, s, ts.info);
+    int64_t *itot = (int64_t *)(ts.info + 2);
+    GCHK(scan_i32(dv, cnt, ptr, nc, itot));
+    hipLaunchKernelGGL(last_of_scan_kernel, dim3(1), dim3(64), 0, s, ptr, nc, itot);
+    hipLaunchKernelGGL(tile_key_kernel, dim3(nblk(nc, 256)), dim3(256), 0, s, cells, nc, ptr, src, key, val, ts.info);
+    GCHK(hipGetLastError());
+    GCHK(radix_sort(dv, key, val, nc, 64));
+    const int ntmax = (int)nblk(nc, kTileW);
+    int32_t *tcnt = dv.alloc<int32_t>(ntmax);
+    ts.uoff = dv.alloc<int32_t>((size_t)ntmax + 1);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(tile_classes_kernel<false>, dim3(ntmax), dim3(256), 0, s, cells, val, ptr, src, ts.info, tcnt,
+                       (const int32_t *)nullptr, (uint64_t *)nullptr, (int32_t *)nullptr);
+    GCHK(hipGetLastError());
+    GCHK(scan_i32(dv, tcnt, ts.uoff, ntmax, itot));
+    hipLaunchKernelGGL(last_of_scan_kernel, dim3(1), dim3(64), 0, s, ts.uoff, ntmax, itot);
+    GCHK(hipGetLastError());
+    unsigned long long hi[4];
+    GCHK(hipMemcpyAsync(hi, ts.info, sizeof(hi), hipMemcpyDeviceToHost, s));
+    GCHK(hipStreamSynchronize(s));
+    if (hi[1] != 0 || hi[2] * (unsigned long long)kTileW > (unsigned long long)INT32_MAX) return hipSuccess;
+    ts.ntg = (int)hi[0];
+    ts.ntiles = (ts.ntg + kTileW - 1) / kTileW;
+    ts.nentries = (int64_t)hi[2];
+    ts.tcell = val;
+    const int64_t ne = ts.nentries;
+    // the tables the tree keeps, and its M2L lists (they stay on the device)
+    GCHK(dt.keep((void **)&dt.m2l_ptr, sizeof(int32_t) * ((size_t)nc + 1)));
+    GCHK(dt.keep((void **)&dt.m2l_src, sizeof(int32_t) * (size_t)std::max<int64_t>(1, nsrc)));
+    GCHK(hipMemcpyAsync(dt.m2l_ptr, ptr, sizeof(int32_t) * ((size_t)nc + 1), hipMemcpyDeviceToDevice, s));
+    if (nsrc) GCHK(hipMemcpyAsync(dt.m2l_src, src, sizeof(int32_t) * nsrc, hipMemcpyDeviceToDevice, s));
+    GCHK(dt.keep((void **)&dt.ucls, sizeof(int32_t) * (size_t)std::max<int64_t>(1, ne)));
+    GCHK(dt.keep((void **)&dt.usrc, sizeof(int32_t) * (size_t)std::max<int64_t>(1, ne * kTileW)));
+    GCHK(dt.keep((void **)&dt.cell_slot, sizeof(int32_t) * (size_t)nc));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(nc, 256)), dim3(256), 0, s, dt.cell_slot, (int64_t)nc, -1);
+    hipLaunchKernelGGL(tile_slots_kernel, dim3(nblk(ts.ntg, 256)), dim3(256), 0, s, val, ts.ntg, dt.cell_slot);
+    GCHK(hipGetLastError());
+    if (ne == 0) {
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t *)(ts.info + 3), (int64_t)2);
+        dt.done = true;
+        return hipGetLastError();
+    }
+    // zero rows where a lane lacks the class, then every tile's sorted
+    // geometries and (entry, lane) sources
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)std::min<int64_t>(4096, nblk(ne * kTileW, 256))), dim3(256), 0, s,
+                       dt.usrc, ne * kTileW, (int32_t)nc);
+    uint64_t *ukey = dv.alloc<uint64_t>(ne);
+    int32_t *uidx = dv.alloc<int32_t>(ne), *flag = dv.alloc<int32_t>(ne), *rank = dv.alloc<int32_t>(ne);
+    ts.geom = dv.alloc<double>(4 * (size_t)ne);
+    GCHK(dv.err);
+    hipLaunchKernelGGL(tile_classes_kernel<true>, dim3(ts.ntiles), dim3(256), 0, s, cells, val, ptr, src, ts.info,
+                       (int32_t *)nullptr, (const int32_t *)ts.uoff, ukey, dt.usrc);
+    hipLaunchKernelGGL(iota_i32_kernel, dim3(nblk(ne, 256)), dim3(256), 0, s, uidx, (int)ne);
+    GCHK(hipGetLastError());
+    // class ids: ranks in the sorted union of all tiles' geometries
+    GCHK(radix_sort(dv, ukey, uidx, (int)ne, 64));
+    hipLaunchKernelGGL(class_flags_kernel, dim3(nblk(ne, 256)), dim3(256), 0, s, ukey, (int)ne, flag);
+    GCHK(hipGetLastError());
+    GCHK(scan_i32(dv, flag, rank, (int)ne, (int64_t *)(ts.info + 3)));
+    hipLaunchKernelGGL(class_ids_kernel, dim3(nblk(ne, 256)), dim3(256), 0, s, ukey, uidx, rank, flag, (int)ne, dt.ucls,
+                       ts.geom);
+    GCHK(hipGetLastError());
+    dt.done = true;
+    return hipSuccess;
+}
+
 }  // namespace
 
 // Builds the canonical tree (and, when theta > 0, the interaction lists) of
@@ -605,7 +956,7 @@ struct Staging {
 // be null): its pinned staging buffer and, while profiling, the wall-clock
 // phases.
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
-                          HostTree &t, fmm_ctx *ctx)
+                          HostTree &t, fmm_ctx *ctx, DevKeep *dt)
 {
     t = HostTree();
     t.n = n;
@@ -761,38 +1112,68 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         n_m2l = mm;
         n_p2p = pm;
     }
-
     mark("host:tree_lists");
+    TileState ts;
+    if (lists && dt && dt->tiling) {
+        GCHK(launch_tiling(dv, cells, nc, m2l_cnt, m2l_s32, n_m2l, *dt, ts));
+        mark("host:tree_tiling");
+    }
+    const bool dtile = lists && dt && dt->tiling && dt->done;
+    if (dt) {
+        // cells, order and keys stay on the device for the tree
+        GCHK(dt->keep((void **)&dt->cells, sizeof(DevCell) * nc));
+        GCHK(dt->keep((void **)&dt->perm, sizeof(int32_t) * n));
+        GCHK(dt->keep((void **)&dt->key, sizeof(uint64_t) * n));
+        GCHK(hipMemcpyAsync(dt->cells, cells, sizeof(DevCell) * nc, hipMemcpyDeviceToDevice, s));
+        GCHK(hipMemcpyAsync(dt->perm, idx, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        GCHK(hipMemcpyAsync(dt->key, key, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+    const int64_t n_host = dt ? 0 : n;   // particles whose order and key the host copies
+
     // host copies of the cells, the order, the keys and the lists, in one
     // staging buffer and one wait
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t o_cells = 0, o_perm = o_cells + al(sizeof(DevCell) * nc), o_key = o_perm + al(sizeof(int32_t) * n),
-                 o_mc = o_key + al(sizeof(uint64_t) * n), o_ms = o_mc + al(sizeof(int32_t) * nc),
-                 o_pc = o_ms + al(sizeof(int32_t) * n_m2l), o_ps = o_pc + al(sizeof(int32_t) * nc),
-                 o_end = o_ps + al(sizeof(int32_t) * n_p2p);
+    const size_t o_cells = 0, o_perm = o_cells + al(sizeof(DevCell) * nc),
+                 o_key = o_perm + al(sizeof(int32_t) * n_host), o_mc = o_key + al(sizeof(uint64_t) * n_host),
+                 o_ms = o_mc + al(sizeof(int32_t) * nc),
+                 o_pc = o_ms + al(sizeof(int32_t) * (dtile ? 0 : n_m2l)), o_ps = o_pc + al(sizeof(int32_t) * nc),
+                 o_tc = o_ps + al(sizeof(int32_t) * n_p2p), o_tu = o_tc + al(sizeof(int32_t) * ts.ntg),
+                 o_ti = o_tu + al(sizeof(int32_t) * (ts.ntiles + 1)), o_end = o_ti + al(sizeof(int64_t) * 4);
     Staging st{ctx};
     GCHK(st.reserve(o_end));
     GCHK(hipMemcpyAsync(st.base + o_cells, cells, sizeof(DevCell) * nc, hipMemcpyDeviceToHost, s));
-    GCHK(hipMemcpyAsync(st.base + o_perm, idx, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    GCHK(hipMemcpyAsync(st.base + o_key, key, sizeof(uint64_t) * n, hipMemcpyDeviceToHost, s));
+    if (n_host) {
+        GCHK(hipMemcpyAsync(st.base + o_perm, idx, sizeof(int32_t) * n_host, hipMemcpyDeviceToHost, s));
+        GCHK(hipMemcpyAsync(st.base + o_key, key, sizeof(uint64_t) * n_host, hipMemcpyDeviceToHost, s));
+    }
     if (lists) {
-        GCHK(hipMemcpyAsync(st.base + o_mc, m2l_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-        if (n_m2l) GCHK(hipMemcpyAsync(st.base + o_ms, m2l_s32, sizeof(int32_t) * n_m2l, hipMemcpyDeviceToHost, s));
+        // with the schedule made on the device the host needs no M2L list
+        if (!dtile) {
+            GCHK(hipMemcpyAsync(st.base + o_mc, m2l_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
+            if (n_m2l)
+                GCHK(hipMemcpyAsync(st.base + o_ms, m2l_s32, sizeof(int32_t) * n_m2l, hipMemcpyDeviceToHost, s));
+        }
         GCHK(hipMemcpyAsync(st.base + o_pc, p2p_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
         if (n_p2p) GCHK(hipMemcpyAsync(st.base + o_ps, p2p_s32, sizeof(int32_t) * n_p2p, hipMemcpyDeviceToHost, s));
+    }
+    if (dtile) {
+        if (ts.ntg) GCHK(hipMemcpyAsync(st.base + o_tc, ts.tcell, sizeof(int32_t) * ts.ntg, hipMemcpyDeviceToHost, s));
+        GCHK(hipMemcpyAsync(st.base + o_tu, ts.uoff, sizeof(int32_t) * (ts.ntiles + 1), hipMemcpyDeviceToHost, s));
+        GCHK(hipMemcpyAsync(st.base + o_ti, ts.info + 2, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, s));
     }
     GCHK(hipStreamSynchronize(s));
     mark("host:tree_copy");
     if (lists) {
-        csr_finish((const int32_t *)(st.base + o_mc), (const int32_t *)(st.base + o_ms), n_m2l, nc, t.m2l_ptr,
-                   t.m2l_src);
+        if (!dtile)
+            csr_finish((const int32_t *)(st.base + o_mc), (const int32_t *)(st.base + o_ms), n_m2l, nc, t.m2l_ptr,
+                       t.m2l_src);
         csr_finish((const int32_t *)(st.base + o_pc), (const int32_t *)(st.base + o_ps), n_p2p, nc, t.p2p_ptr,
                    t.p2p_src);
     }
     const DevCell *hc = (const DevCell *)(st.base + o_cells);
     const int32_t *perm = (const int32_t *)(st.base + o_perm);
-    t.key.assign((const uint64_t *)(st.base + o_key), (const uint64_t *)(st.base + o_key) + n);
-    t.perm.assign(perm, perm + n);
+    t.key.assign((const uint64_t *)(st.base + o_key), (const uint64_t *)(st.base + o_key) + n_host);
+    t.perm.assign(perm, perm + n_host);
     t.level.resize(nc);
     t.ix.resize(3 * (size_t)nc);
     t.first.resize(nc);
@@ -811,6 +1192,26 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         t.parent[c] = d.parent;
         t.child0[c] = d.child0;
         t.nchild[c] = d.nchild;
+    }
+    if (dtile) {
+        M2LTiling &tl = *dt->tl;
+        tl = M2LTiling();
+        tl.on_device = true;
+        tl.ntiles = ts.ntiles;
+        tl.nentries = ts.nentries;
+        const int64_t *ti = (const int64_t *)(st.base + o_ti);
+        tl.nclasses = ts.nentries ? (int)ti[1] : 0;
+        dt->tgt_top = ts.ntg ? (int)ti[2] : -1;
+        dt->src_top = ts.ntg ? (int)ti[3] : -1;
+        tl.pairs = n_m2l;
+        tl.tile_cell.assign((size_t)ts.ntiles * kTileW, -1);
+        std::copy((const int32_t *)(st.base + o_tc), (const int32_t *)(st.base + o_tc) + ts.ntg, tl.tile_cell.begin());
+        tl.tile_uoff.assign((const int32_t *)(st.base + o_tu), (const int32_t *)(st.base + o_tu) + ts.ntiles + 1);
+        GCHK(dt->keep((void **)&dt->cls_geom, sizeof(double) * 4 * (size_t)std::max(1, tl.nclasses)));
+        if (tl.nclasses)
+            GCHK(hipMemcpyAsync(dt->cls_geom, ts.geom, sizeof(double) * 4 * tl.nclasses, hipMemcpyDeviceToDevice, s));
+    } else if (dt) {
+        dt->done = false;
     }
     mark("host:tree_copyback");
     return hipSuccess;

@@ -37,6 +37,7 @@ FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_M2L_ENGINE_VALU, FMM_M2L_ENGINE_MFMA, FMM_M2L_ENGINE_AUTO = 0, 1, 2   # units of the FP32 harmonic M2L
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
+FMM_SCHEDULE_HOST, FMM_SCHEDULE_DEVICE = 0, 1   # builder of the M2L schedule (fmm_ctx_set_m2l_schedule)
 FMM_P_MAX = 10
 FMM_MIXED = 16          # order code FMM_MIXED | mask: several source orders (bit k: order k)
 FMM_REQ_QUEUED, FMM_REQ_RUNNING, FMM_REQ_DONE, FMM_REQ_FAILED = range(4)
@@ -82,6 +83,8 @@ fmm_ctx_set_m2l_basis = _sig("fmm_ctx_set_m2l_basis", [_vp, ctypes.c_int])
 fmm_ctx_set_graphs = _sig("fmm_ctx_set_graphs", [_vp, ctypes.c_int])
 fmm_ctx_set_m2l_engine = _sig("fmm_ctx_set_m2l_engine", [_vp, ctypes.c_int])
 fmm_ctx_set_tree_limit = _sig("fmm_ctx_set_tree_limit", [_vp, ctypes.c_size_t])
+fmm_ctx_set_m2l_schedule = _sig("fmm_ctx_set_m2l_schedule", [_vp, ctypes.c_int])
+fmm_tree_m2l_schedule = _sig("fmm_tree_m2l_schedule", [_vp] * 7)
 fmm_profile_enable = _sig("fmm_profile_enable", [_vp, ctypes.c_int])
 fmm_profile_reset = _sig("fmm_profile_reset", [_vp])
 fmm_profile_read = _sig("fmm_profile_read", [_vp, _vp, _vp, _vp, ctypes.c_int])
@@ -97,7 +100,8 @@ fmm_serve_stats = _sig("fmm_serve_stats", [_vp, _vp])
 fmm_ctx_create_fake = _sig("fmm_ctx_create_fake", [ctypes.c_size_t, ctypes.c_double, ctypes.POINTER(_vp)])
 
 EXPORTED = ["fmm_ctx_create", "fmm_ctx_destroy", "fmm_build_tree", "fmm_upward", "fmm_evaluate", "fmm_evaluate_grad", "fmm_evaluate_grad_noalloc", "fmm_evaluate_derivs", "fmm_run", "fmm_tree_info",
-            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_m2l_engine", "fmm_ctx_set_tree_limit", "fmm_profile_enable", "fmm_profile_reset",
+            "fmm_tree_export", "fmm_tree_destroy", "fmm_last_error", "fmm_ctx_set_overlap", "fmm_ctx_set_m2l_basis", "fmm_ctx_set_graphs", "fmm_ctx_set_m2l_engine", "fmm_ctx_set_tree_limit",
+            "fmm_ctx_set_m2l_schedule", "fmm_tree_m2l_schedule", "fmm_profile_enable", "fmm_profile_reset",
             "fmm_profile_read", "fmm_work_counts", "fmm_serve_start", "fmm_submit", "fmm_poll", "fmm_wait",
             "fmm_request_times", "fmm_request_phases", "fmm_serve_stop", "fmm_serve_stats", "fmm_ctx_create_fake"]
 
@@ -233,6 +237,10 @@ class Context:
     def set_m2l_engine(self, engine: int):
         """FMM_M2L_ENGINE_AUTO (default), _MFMA or _VALU; used from the next upward pass"""
         _check(fmm_ctx_set_m2l_engine(self.h, int(engine)), "fmm_ctx_set_m2l_engine")
+
+    def set_m2l_schedule(self, where: int):
+        """FMM_SCHEDULE_DEVICE (default) or FMM_SCHEDULE_HOST; used by trees built afterwards"""
+        _check(fmm_ctx_set_m2l_schedule(self.h, int(where)), "fmm_ctx_set_m2l_schedule")
 
     def set_overlap(self, on=True):
         """False/0 off, True/1 the whole near field beside the far field, 2
@@ -396,6 +404,26 @@ class Tree:
         _check(fmm_tree_export(self.h, *[d[k].ctypes.data for k in order]), "fmm_tree_export")
         d["m2l_src"] = d["m2l_src"][: inf["n_m2l"]]
         d["p2p_src"] = d["p2p_src"][: inf["n_p2p"]]
+        return d
+
+
+    def m2l_schedule(self):
+        """the M2L schedule (fmm_tree_m2l_schedule) as numpy arrays, plus its builder"""
+        import numpy as np
+        inf = self.info()
+        ncls, nt, slots = inf["n_classes"], inf["n_tiles"], inf["m2l_slots"]
+        d = dict(tile_cell=np.zeros(max(1, 64 * nt), np.int32), tile_uoff=np.zeros(nt + 1, np.int32),
+                 ucls=np.zeros(max(1, slots // 64), np.int32), usrc=np.zeros(max(1, slots), np.int32),
+                 cls_geom=np.zeros(max(1, 4 * ncls), np.float64))
+        where = ctypes.c_int(-1)
+        _check(fmm_tree_m2l_schedule(self.h, *[d[k].ctypes.data for k in ("tile_cell", "tile_uoff", "ucls", "usrc",
+                                                                          "cls_geom")], ctypes.byref(where)),
+               "fmm_tree_m2l_schedule")
+        d["tile_cell"] = d["tile_cell"][: 64 * nt]
+        d["ucls"] = d["ucls"][: slots // 64]
+        d["usrc"] = d["usrc"][:slots]
+        d["cls_geom"] = d["cls_geom"][: 4 * ncls].reshape(-1, 4)
+        d["where"] = where.value
         return d
 
 

@@ -99,7 +99,11 @@ enum {
  * library creates its own, non-blocking).  Calls that capture graphs need a
  * stream other than the legacy default stream.  `hbm_budget_bytes` bounds
  * the device memory the serving loop admits (0: 80% of the free memory at
- * creation). */
+ * creation).  The context keeps device memory for reuse, each part up to
+ * min(budget / 8, 4 GiB): the blocks of destroyed trees (handed to later
+ * trees of the same size class) and the scratch arena of tree builds; both
+ * are released with the context.  A context is used by one host thread at
+ * a time. */
 int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, fmm_ctx **out);
 /* Destroys the context after its device work has finished.  Trees of this
  * context that are still alive lose their device memory; fmm_tree_destroy
@@ -283,14 +287,16 @@ int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine);
  * list length) order; per tile the sorted distinct pair geometries
  * ((z_B - z_A) / r_B, r_A / r_B), each one derivative tensor for all 64
  * lanes; class ids the ranks of the geometries among all tiles'; per
- * (entry, lane) the source cell or the zero row.  FMM_SCHEDULE_DEVICE
- * (default): built on the GPU after the interaction lists, without their
- * round trip through the host; when a tile holds more than 4096 distinct
- * geometries or a packed key would overflow the build takes the host code
- * instead.  FMM_SCHEDULE_HOST: built by the host threads.  Both give the
- * same schedule, entry for entry.  Takes effect for trees built afterwards.
- * FMM_EINVAL for another value. */
-enum { FMM_SCHEDULE_HOST = 0, FMM_SCHEDULE_DEVICE = 1 };
+ * (entry, lane) the source cell or the zero row.  FMM_SCHEDULE_DEVICE:
+ * built on the GPU after the interaction lists, without their round trip
+ * through the host; when a tile holds more than 4096 distinct geometries or
+ * a packed key would overflow the build takes the host code instead.
+ * FMM_SCHEDULE_HOST: built by the host threads.  FMM_SCHEDULE_AUTO
+ * (default): the device from 32768 M2L list entries on (about 10^4
+ * particles at ncrit 64), the host below, where its fixed cost is lower.
+ * All give the same schedule, entry for entry.  Takes effect for trees
+ * built afterwards.  FMM_EINVAL for another value. */
+enum { FMM_SCHEDULE_HOST = 0, FMM_SCHEDULE_DEVICE = 1, FMM_SCHEDULE_AUTO = 2 };
 int fmm_ctx_set_m2l_schedule(fmm_ctx *ctx, int where);
 
 /* The M2L schedule of an FMM tree, to HOST arrays (any pointer may be NULL)

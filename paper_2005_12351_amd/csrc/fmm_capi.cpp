@@ -92,7 +92,8 @@ extern "C" int fmm_ctx_set_m2l_basis(fmm_ctx *ctx, int basis)
 extern "C" int fmm_ctx_set_m2l_schedule(fmm_ctx *ctx, int where)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
-    if (where != FMM_SCHEDULE_DEVICE && where != FMM_SCHEDULE_HOST) FAIL(FMM_EINVAL, "unknown M2L schedule %d", where);
+    if (where != FMM_SCHEDULE_DEVICE && where != FMM_SCHEDULE_HOST && where != FMM_SCHEDULE_AUTO)
+        FAIL(FMM_EINVAL, "unknown M2L schedule %d", where);
     ctx->m2l_schedule = where;   // trees built from now on
     return FMM_OK;
 }
@@ -226,6 +227,7 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         delete c;
         FAIL(FMM_EDEVICE, "stream/event creation failed");
     }
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) c->ncu = 256;
     size_t fr = 0, tot = 0;
     HIPCHK(hipMemGetInfo(&fr, &tot));
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)fr);
@@ -239,12 +241,46 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
     return FMM_OK;
 }
 
+// Size classes of tree blocks: 256 B, then four per power of two (at most
+// 25 % above the request), so that released blocks fit later requests.
+static size_t size_class(size_t b)
+{
+    if (b <= 256) return 256;
+    const int e = 63 - __builtin_clzll((unsigned long long)(b - 1));   // 2^e < b <= 2^(e+1)
+    const size_t step = (size_t)1 << (e - 2);
+    return (b + step - 1) / step * step;
+}
+
+size_t ctx_cache_limit(const fmm_ctx *ctx) { return std::min(ctx->budget / 8, (size_t)4 << 30); }
+
+// A released block goes to the context's cache (or back to the allocator
+// when the cache is full).  Work on the context stream queued after this
+// point, and on the auxiliary stream forked from it, is ordered after every
+// earlier use of the block, so handing it to a later tree_alloc is safe.
+static void ctx_dev_free(fmm_ctx *c, void *p, size_t bytes)
+{
+    const size_t cls = size_class(bytes);
+    if (c->dev_cache_bytes + cls <= ctx_cache_limit(c)) {
+        c->dev_cache.emplace(cls, p);
+        c->dev_cache_bytes += cls;
+    } else {
+        (void)hipFreeAsync(p, c->stream);
+    }
+}
+
+static void ctx_cache_drop(fmm_ctx *c)
+{
+    for (auto &kv : c->dev_cache) (void)hipFreeAsync(kv.second, c->stream);
+    c->dev_cache.clear();
+    c->dev_cache_bytes = 0;
+}
+
 static void tree_release_device(fmm_tree *t)
 {
     drop_graphs(t);
     // the near field may still run on the auxiliary stream
     (void)hipStreamSynchronize(t->ctx->aux);
-    for (auto &a : t->allocs) (void)hipFreeAsync(a.first, t->ctx->stream);
+    for (auto &a : t->allocs) ctx_dev_free(t->ctx, a.first, a.second);
     t->allocs.clear();
     t->dev_bytes = 0;
 }
@@ -266,6 +302,10 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
         t->ctx = nullptr;
     }
     c->trees.clear();
+    ctx_cache_drop(c);
+    if (c->arena) (void)hipFreeAsync(c->arena, c->stream);
+    c->arena = nullptr;
+    c->arena_cap = 0;
     (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->prof) {
         if (!e.a) continue;   // a host phase holds no events
@@ -274,6 +314,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     }
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->pin_small) (void)hipHostFree(c->pin_small);
     hipEventDestroy(c->ev_up);
     hipEventDestroy(c->ev_near);
     hipEventDestroy(c->ev_fork);
@@ -286,9 +327,11 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
 }
 
 // ------------------------------------------------------------------ tree
-// Device memory comes from the stream-ordered allocator on the context's
-// stream: allocation and release never synchronise the device, so requests
-// served on other streams keep running while a tree is built or freed.
+// Device memory comes from the context's cache of released blocks of the
+// same size class, else from the stream-ordered allocator on the context's
+// stream: neither synchronises the device, so requests served on other
+// streams keep running while a tree is built or freed.  A tree's size
+// (dev_bytes, the tree limit) counts the requested bytes.
 int tree_alloc(fmm_tree *t, void **p, size_t bytes)
 {
     *p = nullptr;
@@ -296,9 +339,22 @@ int tree_alloc(fmm_tree *t, void **p, size_t bytes)
     if (t->ctx->tree_limit && t->dev_bytes + bytes > t->ctx->tree_limit)
         FAIL(FMM_ENOMEM, "device allocation of %zu bytes would exceed the tree limit of %zu bytes (%zu held)", bytes,
              t->ctx->tree_limit, t->dev_bytes);
-    if (hipMallocAsync(p, bytes, t->ctx->stream) != hipSuccess) {
-        *p = nullptr;
-        FAIL(FMM_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    fmm_ctx *c = t->ctx;
+    const size_t cls = size_class(bytes);
+    auto hit = c->dev_cache.find(cls);
+    if (hit != c->dev_cache.end()) {
+        *p = hit->second;
+        c->dev_cache.erase(hit);
+        c->dev_cache_bytes -= cls;
+    } else if (hipMallocAsync(p, cls, c->stream) != hipSuccess) {
+        // the cached blocks back to the allocator, then once more
+        (void)hipGetLastError();
+        ctx_cache_drop(c);
+        if (hipMallocAsync(p, cls, c->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            *p = nullptr;
+            FAIL(FMM_ENOMEM, "device allocation of %zu bytes failed", bytes);
+        }
     }
     t->allocs.emplace_back(*p, bytes);
     t->dev_bytes += bytes;
@@ -311,9 +367,11 @@ static void tree_free_block(fmm_tree *t, void *p)
     auto it = std::find_if(t->allocs.begin(), t->allocs.end(), [p](const auto &a) { return a.first == p; });
     if (it != t->allocs.end()) {
         t->dev_bytes -= it->second;
+        ctx_dev_free(t->ctx, p, it->second);
         t->allocs.erase(it);
+    } else {
+        (void)hipFreeAsync(p, t->ctx->stream);
     }
-    (void)hipFreeAsync(p, t->ctx->stream);
 }
 
 extern "C" int fmm_ctx_set_tree_limit(fmm_ctx *ctx, size_t bytes)
@@ -323,14 +381,62 @@ extern "C" int fmm_ctx_set_tree_limit(fmm_ctx *ctx, size_t bytes)
     return FMM_OK;
 }
 
-template <typename T>
-static int upload(fmm_tree *t, T **dst, const std::vector<T> &src, hipStream_t s)
+hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base)
 {
-    int rc = tree_alloc(t, (void **)dst, src.size() * sizeof(T));
-    if (rc) return rc;
-    if (!src.empty()) HIPCHK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return FMM_OK;
+    if (ctx->pinned_bytes < bytes) {
+        if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+        ctx->pinned = nullptr;
+        ctx->pinned_bytes = 0;
+        const size_t want = std::max(bytes + bytes / 4, (size_t)1 << 20);
+        hipError_t e = hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        ctx->pinned_bytes = want;
+    }
+    *base = (char *)ctx->pinned;
+    return hipSuccess;
 }
+
+// Uploads of host vectors into new tree allocations: add() allocates and
+// records the vector's data pointer, flush() packs the data into the
+// context's pinned buffer and queues the copies.  Every vector passed to
+// add() must live, unchanged, until flush() returns; the caller
+// synchronises the stream before the pinned buffer is used again.
+struct Uploads {
+    fmm_tree *t;
+    struct Item {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    size_t total = 0;
+    template <typename T>
+    int add(T **dst, const std::vector<T> &src)
+    {
+        int rc = tree_alloc(t, (void **)dst, src.size() * sizeof(T));
+        if (rc) return rc;
+        if (!src.empty()) {
+            items.push_back(Item{*dst, src.data(), src.size() * sizeof(T)});
+            total += (src.size() * sizeof(T) + 255) / 256 * 256;
+        }
+        return FMM_OK;
+    }
+    int flush(hipStream_t s)
+    {
+        if (items.empty()) return FMM_OK;
+        char *base;
+        HIPCHK(ctx_pinned(t->ctx, total, &base));
+        size_t o = 0;
+        for (const Item &it : items) {
+            memcpy(base + o, it.src, it.bytes);
+            HIPCHK(hipMemcpyAsync(it.dst, base + o, it.bytes, hipMemcpyHostToDevice, s));
+            o += (it.bytes + 255) / 256 * 256;
+        }
+        items.clear();
+        total = 0;
+        return FMM_OK;
+    }
+};
 
 extern "C" int fmm_tree_destroy(fmm_tree *t)
 {
@@ -368,7 +474,11 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     DevKeep dt;
     dt.keep = [t](void **p, size_t bytes) { return tree_alloc(t, p, bytes) == FMM_OK ? hipSuccess : hipErrorOutOfMemory; };
     dt.tl = &t->tiling;
-    dt.tiling = method == FMM_METHOD_FMM && ctx->m2l_schedule == FMM_SCHEDULE_DEVICE;
+    // automatic: below some 3·10^4 list entries (about 10^4 particles at
+    // ncrit 64) the fixed cost of the device passes exceeds the host's
+    // (measured: 0.45 against 0.13 ms at 3·10^3 entries, equal at 7·10^4)
+    dt.tiling = method == FMM_METHOD_FMM && ctx->m2l_schedule != FMM_SCHEDULE_HOST;
+    dt.min_pairs = ctx->m2l_schedule == FMM_SCHEDULE_AUTO ? 32768 : 0;
     {
         const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx, &dt);
         if (e != hipSuccess) {
@@ -495,8 +605,9 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
 
     HostScope hs_up(ctx, "host:tree_upload");
     int rc = FMM_OK;
+    Uploads up{t};
 #define UP(dst, vec)                                   \
-    if ((rc = upload(t, &(dst), vec, s)) != FMM_OK) {  \
+    if ((rc = up.add(&(dst), vec)) != FMM_OK) {        \
         fmm_tree_destroy(t);                           \
         return rc;                                     \
     }
@@ -506,11 +617,12 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     UP(t->d_p2p_ptr, pptr);
     UP(t->d_p2p_src, psrc);
     UP(t->d_p2p_order, p2p_order);
+    std::vector<int32_t> cell_slot;   // lives until the flush below
     if (method == FMM_METHOD_FMM && !t->tiling.on_device) {
         const M2LTiling &tl = t->tiling;
         UP(t->d_ucls, tl.ucls);
         UP(t->d_usrc, tl.usrc);
-        std::vector<int32_t> cell_slot(nc, -1);
+        cell_slot.assign(nc, -1);
         for (size_t k = 0; k < tl.tile_cell.size(); ++k)
             if (tl.tile_cell[k] >= 0) cell_slot[tl.tile_cell[k]] = (int32_t)k;
         UP(t->d_cell_slot, cell_slot);
@@ -518,7 +630,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     }
     if (method == FMM_METHOD_FMM) t->work[0] = (double)t->tiling.pairs;
 #undef UP
-    if ((rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n))) {
+    if ((rc = up.flush(s)) || (rc = tree_alloc(t, (void **)&t->d_x, sizeof(double) * 3 * n))) {
         fmm_tree_destroy(t);
         return rc;
     }
@@ -607,9 +719,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         const int nc_ = std::max(1, t->tiling.nclasses);
         const int scw = (p + 1 + 3) / 4 * 4;
         // one wave per resident slot of the device
-        int dev = 0, ncu = 256;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+        const int ncu = t->ctx->ncu;
         // one M2L workgroup per resident workgroup slot; each writes its own
         // partial rows where its piece of the work ends
         build_m2l_work(t->tiling, v, ncu * v.occupancy(), t->m2lwork);
@@ -618,9 +728,10 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             work[k] = make_int4(t->m2lwork.work[4 * k], t->m2lwork.work[4 * k + 1], t->m2lwork.work[4 * k + 2],
                                 t->m2lwork.work[4 * k + 3]);
         hipStream_t st = t->ctx->stream;
-        if ((rc = upload(t, &t->d_work, work, st)) || (rc = upload(t, &t->d_tile_chunk0, t->m2lwork.chunk0, st)) ||
-            (rc = upload(t, &t->d_tile_nchunk, t->m2lwork.nchunk, st)) ||
-            (rc = upload(t, &t->d_wave_ptr, t->m2lwork.wave_ptr, st)))
+        Uploads up{t};
+        if ((rc = up.add(&t->d_work, work)) || (rc = up.add(&t->d_tile_chunk0, t->m2lwork.chunk0)) ||
+            (rc = up.add(&t->d_tile_nchunk, t->m2lwork.nchunk)) || (rc = up.add(&t->d_wave_ptr, t->m2lwork.wave_ptr)) ||
+            (rc = up.flush(st)))
             return rc;
         HIPCHK(hipStreamSynchronize(st));
         if ((rc = tree_alloc(t, &t->d_part, es * (size_t)std::max<int64_t>(1, t->m2lwork.nrows) * v.nl_pad)) ||
@@ -662,18 +773,16 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         };
         const int q = p - order;
         std::vector<int32_t> pack = packing(l2p_pack_limit(q, false));
-        int dev = 0, ncu = 256;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            ncu = prop.multiProcessorCount;
+        const int ncu = t->ctx->ncu;
         std::vector<int32_t> pack_cols = packing(l2p_pack_limit(q, true));
         t->l2p_columns = pack_cols.size() < pack.size() || l2p_columns_pay(q, (int)pack.size() - 1, ncu);
         if (t->l2p_columns) pack.swap(pack_cols);
         if (t->d_l2p_pack) tree_free_block(t, t->d_l2p_pack);
         t->d_l2p_pack = nullptr;
         t->l2p_pack_q = -1;
-        if ((rc = upload(t, &t->d_l2p_pack, pack, t->ctx->stream))) return rc;
-        HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the host vector dies here
+        Uploads up{t};
+        if ((rc = up.add(&t->d_l2p_pack, pack)) || (rc = up.flush(t->ctx->stream))) return rc;
+        HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the pinned staging is reused
         t->l2p_npacks = (int)pack.size() - 1;
         t->l2p_pack_q = p - order;
     }

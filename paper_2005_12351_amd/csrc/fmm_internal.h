@@ -7,6 +7,7 @@
 #include <string>
 #include <chrono>
 #include <functional>
+#include <map>
 #include <vector>
 
 #include "../../include/fmm.h"
@@ -157,6 +158,15 @@ struct HostTree {      // canonical tree, host copy
 // (tree_gpu.hip).  hipErrorInvalidValue: a position is not finite;
 // hipErrorOutOfMemory: a list or frontier exceeds 2^31 entries or the device
 // is out of memory.
+// The context's pinned staging buffer, grown to at least `bytes` (its
+// earlier contents are lost then); no copy through it may be in flight.
+// Copies from pageable memory go through one staging buffer of the runtime
+// and serialise the host threads of all contexts; these do not.
+hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base);
+// most bytes a context keeps cached in released tree blocks, and in its
+// build arena
+size_t ctx_cache_limit(const fmm_ctx *ctx);
+
 struct DevKeep;
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
                           HostTree &t, fmm_ctx *ctx = nullptr, DevKeep *dt = nullptr);
@@ -193,6 +203,7 @@ struct DevKeep {
     int32_t *perm = nullptr;
     uint64_t *key = nullptr;
     bool tiling = false;
+    int64_t min_pairs = 0;   // the device tiling only for at least this many M2L pairs
     int32_t *ucls = nullptr, *usrc = nullptr, *cell_slot = nullptr;
     int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;
     double *cls_geom = nullptr;
@@ -251,13 +262,24 @@ struct fmm_ctx {
     bool graphs = true;                   // replay captured HIP graphs
     int m2l_basis = FMM_M2L_HARMONIC;     // basis of the M2L contraction (FMM trees)
     int m2l_engine = FMM_M2L_ENGINE_AUTO; // units of the FP32 harmonic-basis M2L
-    int m2l_schedule = FMM_SCHEDULE_DEVICE;   // where tree builds make the M2L schedule
+    int m2l_schedule = FMM_SCHEDULE_AUTO;     // where tree builds make the M2L schedule
     bool fake = false;                    // no device: serving-logic tests only
     double fake_ns = 0.0;                 // simulated cost per particle (fake)
     size_t tree_limit = 0;                // device bytes one tree may hold (0: no limit)
     double *noalloc_scratch = nullptr;    // device address of the static gradient scratch on `device`
-    void *pinned = nullptr;               // pinned host staging of tree construction's read-backs
+    void *pinned = nullptr;               // pinned host staging of tree construction's copies
     size_t pinned_bytes = 0;
+    int64_t *pin_small = nullptr;         // pinned words for the totals a tree build reads back
+    int ncu = 256;                        // compute units of the device
+    // Device blocks released by this context's trees, by size class, reused
+    // in the order of the context stream (tree_alloc); and the scratch
+    // arena of its tree builds (gpu_build_tree).  The stream-ordered
+    // allocator serialises the host threads of all contexts, so a context
+    // that serves one request after another calls it only to grow these.
+    std::multimap<size_t, void *> dev_cache;
+    size_t dev_cache_bytes = 0;
+    char *arena = nullptr;
+    size_t arena_cap = 0;
     hipEvent_t ev_fork = nullptr;
     std::vector<ProfEntry> prof;
     std::vector<hipEvent_t> ev_pool;

@@ -229,6 +229,63 @@ __global__ __launch_bounds__(kScanT) void radix_scatter_kernel(const uint64_t *_
     }
 }
 
+// one workgroup, in place: the order of the stable sort on (key & mask) for
+// n <= kSmallSort items, as a bitonic sort of (masked key, position) in LDS;
+// keys and values are then gathered by position
+constexpr int kSmallSort = 8192;
+constexpr int kSmallSortT = 1024;
+__global__ __launch_bounds__(kSmallSortT) void small_sort_kernel(uint64_t *__restrict__ k, int32_t *__restrict__ v, int n,
+                                                                 uint64_t mask)
+{
+    __shared__ uint64_t sk[kSmallSort];
+    __shared__ uint16_t sp[kSmallSort];
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += kSmallSortT) {
+        sk[i] = i < n ? (k[i] & mask) : mask;   // padding sorts last: its position is >= n
+        sp[i] = (uint16_t)i;
+    }
+    __syncthreads();
+    for (int size = 2; size <= np; size <<= 1)
+        for (int j = size >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < np; i += kSmallSortT) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = sk[i], b = sk[l];
+                    const uint16_t pa = sp[i], pb = sp[l];
+                    const bool gt = a > b || (a == b && pa > pb);
+                    if (gt == ((i & size) == 0)) {
+                        sk[i] = b;
+                        sk[l] = a;
+                        sp[i] = pb;
+                        sp[l] = pa;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    constexpr int kPer = kSmallSort / kSmallSortT;
+    uint64_t kk[kPer];
+    int32_t vv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kSmallSortT;
+        if (i < n) {
+            kk[q] = k[sp[i]];
+            vv[q] = v[sp[i]];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kSmallSortT;
+        if (i < n) {
+            k[i] = kk[q];
+            v[i] = vv[q];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- keys
 // per block: componentwise min and max, and 1 if any coordinate is not finite
 __global__ void bbox_partial_kernel(const double *__restrict__ pos, int64_t n, double *__restrict__ part)
@@ -450,8 +507,16 @@ __global__ void zero_i32_kernel(int32_t *p, int64_t n)
 }
 
 // ---------------------------------------------------------------- host side
+// Scratch memory of one build.  With a context, blocks come first from its
+// arena by bumping a pointer (a released arena block is reused only by the
+// next build on the same stream, after this one's work); what does not fit
+// comes from the stream-ordered allocator, and the arena grows to this
+// build's total (up to the context's cache limit) for the next build.
 struct Dev {
     hipStream_t s;
+    int64_t *pin = nullptr;   // 8 pinned words for read-backs (or none)
+    fmm_ctx *ctx = nullptr;
+    size_t used = 0, need = 0;
     std::vector<void *> blocks;
     hipError_t err = hipSuccess;
     template <typename T>
@@ -459,7 +524,14 @@ struct Dev {
     {
         void *p = nullptr;
         if (err != hipSuccess) return nullptr;
-        err = hipMallocAsync(&p, std::max<size_t>(count, 1) * sizeof(T), s);
+        const size_t b = (std::max<size_t>(count, 1) * sizeof(T) + 255) / 256 * 256;
+        need += b;
+        if (ctx && ctx->arena && used + b <= ctx->arena_cap) {
+            p = ctx->arena + used;
+            used += b;
+            return (T *)p;
+        }
+        err = hipMallocAsync(&p, b, s);
         if (err != hipSuccess) return nullptr;
         blocks.push_back(p);
         return (T *)p;
@@ -481,6 +553,21 @@ struct Dev {
     ~Dev()
     {
         for (void *p : blocks) hipFreeAsync(p, s);
+        if (ctx && need > ctx->arena_cap && err == hipSuccess) {
+            const size_t want = std::min(need + need / 4, ctx_cache_limit(ctx));
+            if (want > ctx->arena_cap) {
+                if (ctx->arena) hipFreeAsync(ctx->arena, s);
+                ctx->arena = nullptr;
+                ctx->arena_cap = 0;
+                void *p = nullptr;
+                if (hipMallocAsync(&p, want, s) == hipSuccess) {
+                    ctx->arena = (char *)p;
+                    ctx->arena_cap = want;
+                } else {
+                    (void)hipGetLastError();
+                }
+            }
+        }
     }
 };
 
@@ -511,11 +598,15 @@ hipError_t scan_i32(Dev &dv, const int32_t *in, int32_t *out, int n, int64_t *to
     return hipSuccess;
 }
 
-// the first k device totals, read on the host (synchronises the stream)
-hipError_t read_totals(Dev &dv, const int64_t *dev, int k, int64_t *host)
+// the first k (<= 8) device words, read on the host (synchronises the
+// stream), through the pinned words when there are some
+hipError_t read_totals(Dev &dv, const void *dev, int k, void *host)
 {
-    GCHK(hipMemcpyAsync(host, dev, sizeof(int64_t) * k, hipMemcpyDeviceToHost, dv.s));
-    return hipStreamSynchronize(dv.s);
+    void *dst = dv.pin ? (void *)dv.pin : host;
+    GCHK(hipMemcpyAsync(dst, dev, sizeof(int64_t) * k, hipMemcpyDeviceToHost, dv.s));
+    GCHK(hipStreamSynchronize(dv.s));
+    if (dst != host) memcpy(host, dst, sizeof(int64_t) * k);
+    return hipSuccess;
 }
 
 // stable LSD sort of (key, val) on the low `bits` bits of the key; the result
@@ -523,6 +614,11 @@ hipError_t read_totals(Dev &dv, const int64_t *dev, int k, int64_t *host)
 hipError_t radix_sort(Dev &dv, uint64_t *&k, int32_t *&v, int n, int bits)
 {
     if (n <= 1) return hipSuccess;
+    if (n <= kSmallSort) {   // one launch instead of three per digit
+        const uint64_t mask = bits >= 64 ? ~0ull : (1ull << bits) - 1;
+        hipLaunchKernelGGL(small_sort_kernel, dim3(1), dim3(kSmallSortT), 0, dv.s, k, v, n, mask);
+        return hipGetLastError();
+    }
     const int nb = (int)nblk(n, kScanTile);
     uint64_t *k2 = dv.alloc<uint64_t>(n);
     int32_t *v2 = dv.alloc<int32_t>(n);
@@ -587,15 +683,7 @@ struct Staging {
     hipError_t reserve(size_t bytes)
     {
         if (ctx) {
-            if (ctx->pinned_bytes < bytes) {
-                if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-                ctx->pinned = nullptr;
-                ctx->pinned_bytes = 0;
-                const size_t want = std::max(bytes, (size_t)1 << 20);
-                GCHK(hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
-                ctx->pinned_bytes = want;
-            }
-            base = (char *)ctx->pinned;
+            GCHK(ctx_pinned(ctx, bytes, &base));
         } else {
             plain.resize(bytes);
             base = plain.data();
@@ -854,6 +942,19 @@ __global__ void last_of_scan_kernel(int32_t *ptr, int n, const int64_t *total)
     if (threadIdx.x == 0 && blockIdx.x == 0) ptr[n] = (int32_t)*total;
 }
 
+__global__ void root_cell_kernel(DevCell *c, int32_t n)
+{
+    if (threadIdx.x == 0) {
+        DevCell r{};
+        r.level = 0;
+        r.first = 0;
+        r.count = n;
+        r.parent = -1;
+        r.child0 = -1;
+        c[0] = r;
+    }
+}
+
 __global__ void iota_i32_kernel(int32_t *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,8 +1002,7 @@ hipError_t launch_tiling(Dev &dv, const DevCell *cells, int nc, const int32_t *c
     hipLaunchKernelGGL(last_of_scan_kernel, dim3(1), dim3(64), 0, s, ts.uoff, ntmax, itot);
     GCHK(hipGetLastError());
     unsigned long long hi[4];
-    GCHK(hipMemcpyAsync(hi, ts.info, sizeof(hi), hipMemcpyDeviceToHost, s));
-    GCHK(hipStreamSynchronize(s));
+    GCHK(read_totals(dv, ts.info, 4, hi));
     if (hi[1] != 0 || hi[2] * (unsigned long long)kTileW > (unsigned long long)INT32_MAX) return hipSuccess;
     ts.ntg = (int)hi[0];
     ts.ntiles = (ts.ntg + kTileW - 1) / kTileW;
@@ -961,6 +1061,11 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     t = HostTree();
     t.n = n;
     Dev dv{s};
+    if (ctx) {
+        if (!ctx->pin_small) GCHK(hipHostMalloc((void **)&ctx->pin_small, 4096, hipHostMallocDefault));
+        dv.pin = ctx->pin_small;
+        dv.ctx = ctx;
+    }
     // wall-clock phases for the context's profile (the device work of a
     // phase is counted where the host next waits for it)
     auto t_last = std::chrono::steady_clock::now();
@@ -978,8 +1083,7 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, part, nbb, bb);
     GCHK(hipGetLastError());
     double box[7];
-    GCHK(hipMemcpyAsync(box, bb, sizeof(box), hipMemcpyDeviceToHost, s));
-    GCHK(hipStreamSynchronize(s));
+    GCHK(read_totals(dv, bb, 7, box));
     mark("host:tree_box");
     if (box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
     double W = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
@@ -1003,13 +1107,8 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     size_t cap = std::max<size_t>(64, (size_t)(4 * n / std::max(1, ncrit) + 64));
     DevCell *cells = dv.alloc<DevCell>(cap);
     GCHK(dv.err);
-    DevCell root{};
-    root.level = 0;
-    root.first = 0;
-    root.count = (int32_t)n;
-    root.parent = -1;
-    root.child0 = -1;
-    GCHK(hipMemcpyAsync(cells, &root, sizeof(DevCell), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(root_cell_kernel, dim3(1), dim3(64), 0, s, cells, (int32_t)n);
+    GCHK(hipGetLastError());
     t.level_ptr.push_back(0);
     int lb = 0, le = 1;
     for (int l = 0;; ++l) {
@@ -1054,8 +1153,8 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         std::vector<int64_t> m2l_sz, p2p_sz;
         int2 *fr = dv.alloc<int2>(1);
         GCHK(dv.err);
-        const int2 rr = make_int2(0, 0);
-        GCHK(hipMemcpyAsync(fr, &rr, sizeof(int2), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t *)fr, (int64_t)2);   // (root, root)
+        GCHK(hipGetLastError());
         int64_t nf = 1;
         while (nf > 0) {
             if (nf > INT32_MAX) return hipErrorOutOfMemory;
@@ -1114,7 +1213,7 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     }
     mark("host:tree_lists");
     TileState ts;
-    if (lists && dt && dt->tiling) {
+    if (lists && dt && dt->tiling && n_m2l >= dt->min_pairs) {
         GCHK(launch_tiling(dv, cells, nc, m2l_cnt, m2l_s32, n_m2l, *dt, ts));
         mark("host:tree_tiling");
     }

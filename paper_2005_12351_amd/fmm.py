@@ -37,7 +37,7 @@ FMM_METHOD_FMM, FMM_METHOD_BH = 0, 1
 FMM_M2L_FULL, FMM_M2L_HARMONIC = 0, 1   # M2L contraction basis (fmm_ctx_set_m2l_basis)
 FMM_M2L_ENGINE_VALU, FMM_M2L_ENGINE_MFMA, FMM_M2L_ENGINE_AUTO = 0, 1, 2   # units of the FP32 harmonic M2L
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
-FMM_SCHEDULE_HOST, FMM_SCHEDULE_DEVICE = 0, 1   # builder of the M2L schedule (fmm_ctx_set_m2l_schedule)
+FMM_SCHEDULE_HOST, FMM_SCHEDULE_DEVICE, FMM_SCHEDULE_AUTO = 0, 1, 2   # builder of the M2L schedule
 FMM_P_MAX = 10
 FMM_MIXED = 16          # order code FMM_MIXED | mask: several source orders (bit k: order k)
 FMM_REQ_QUEUED, FMM_REQ_RUNNING, FMM_REQ_DONE, FMM_REQ_FAILED = range(4)
@@ -239,7 +239,7 @@ class Context:
         _check(fmm_ctx_set_m2l_engine(self.h, int(engine)), "fmm_ctx_set_m2l_engine")
 
     def set_m2l_schedule(self, where: int):
-        """FMM_SCHEDULE_DEVICE (default) or FMM_SCHEDULE_HOST; used by trees built afterwards"""
+        """FMM_SCHEDULE_AUTO (default), _DEVICE or _HOST; used by trees built afterwards"""
         _check(fmm_ctx_set_m2l_schedule(self.h, int(where)), "fmm_ctx_set_m2l_schedule")
 
     def set_overlap(self, on=True):

@@ -27,6 +27,7 @@ def _say(*a):
 @pytest.fixture(scope="module")
 def ctxs():
     dev = fmm.Context(0)
+    dev.set_m2l_schedule(fmm.FMM_SCHEDULE_DEVICE)
     host = fmm.Context(0)
     host.set_m2l_schedule(fmm.FMM_SCHEDULE_HOST)
     yield dev, host
@@ -125,7 +126,29 @@ def test_device_schedule_serving(ctxs):
         t.close()
 
 
+def test_schedule_auto():
+    """the default picks the host below 32768 list entries, the device
+    from there on, and both give the host's schedule"""
+    auto = fmm.Context(0)
+    host = fmm.Context(0)
+    host.set_m2l_schedule(fmm.FMM_SCHEDULE_HOST)
+    for n in (1000, 40000):
+        w = W.small_random(77 + n, n, 1, "uniform")
+        pos = torch.from_numpy(w.pos).cuda()
+        ta, th = fmm.Tree(auto, pos, 64, 0.5), fmm.Tree(host, pos, 64, 0.5)
+        a, b = ta.m2l_schedule(), th.m2l_schedule()
+        want = fmm.FMM_SCHEDULE_DEVICE if ta.info()["n_m2l"] >= 32768 else fmm.FMM_SCHEDULE_HOST
+        _say(f"[schedule auto] n={n} n_m2l={ta.info()['n_m2l']} where={a['where']}")
+        assert a["where"] == want
+        for k in ("tile_cell", "tile_uoff", "ucls", "usrc", "cls_geom"):
+            assert np.array_equal(a[k], b[k]), k
+        ta.close()
+        th.close()
+    auto.close()
+    host.close()
+
+
 def test_schedule_setter_rejects(ctxs):
     dev, _ = ctxs
     with pytest.raises(fmm.FMMError):
-        dev.set_m2l_schedule(2)
+        dev.set_m2l_schedule(3)

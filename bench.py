@@ -74,12 +74,14 @@ def _progress(msg):
     print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
-def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
+def serve_bench(fmm, W, torch, n_requests=512, slots=4, budget=2 << 30):
     """Serving workload: requests with N log-uniform in [1e3, 2e5], source
     order in {0,1,2}, p in {4,6,8}, uniform or Plummer positions, theta 0.5,
     ncrit 64, mixed precision.  A closed-loop pass (all submitted at once)
     measures the saturated request rate; the timed open-loop pass replays the
-    Poisson arrivals at 0.7 times that rate.  Latency = done - arrival."""
+    Poisson arrivals at 0.7 times that rate, a second one at a fixed 130
+    requests/s.  Latency = done - arrival.  Four slots: one per hardware
+    queue of the process."""
     import threading
     reqs = W.serving_stream(n_requests, rate=1.0)
     dev = []
@@ -104,32 +106,42 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
         ctx.wait(t)
     sat_rate = n_requests / (time.perf_counter() - t0)
     ctx.close()
+
+    def open_loop(lam):
+        """the Poisson arrivals of the stream replayed at rate lam"""
+        ctx = fmm.Context(0, budget_bytes=budget)
+        ctx.serve_start(slots)
+        tickets = [None] * n_requests
+        start = time.perf_counter()
+
+        def feeder():
+            for k, (r, d) in enumerate(zip(reqs, dev)):
+                delay = start + r.arrival / lam - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[k] = submit(ctx, d)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        for t in tickets:
+            ctx.wait(t)
+        times = [ctx.request_times(t) for t in tickets]
+        phases = [ctx.request_phases(t) for t in tickets]
+        stats = ctx.serve_stats()
+        ctx.close()
+        return times, phases, stats
+
     # open loop at 0.7 x saturated rate
     lam = 0.7 * sat_rate
-    ctx = fmm.Context(0, budget_bytes=budget)
-    ctx.serve_start(slots)
-    tickets = [None] * n_requests
-    start = time.perf_counter()
-
-    def feeder():
-        for k, (r, d) in enumerate(zip(reqs, dev)):
-            delay = start + r.arrival / lam - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets[k] = submit(ctx, d)
-
-    th = threading.Thread(target=feeder)
-    th.start()
-    th.join()
-    for t in tickets:
-        ctx.wait(t)
-    times = [ctx.request_times(t) for t in tickets]
-    phases = [ctx.request_phases(t) for t in tickets]
-    stats = ctx.serve_stats()
-    ctx.close()
+    times, phases, stats = open_loop(lam)
     lat = np.array([x["done"] - x["submit"] for x in times])
     span = max(x["done"] for x in times) - min(x["submit"] for x in times)
     nsum = sum(d[0].n for d in dev)
+    # and at a fixed rate, the same for every build of the library
+    fixed = 130.0
+    ft, _, _ = open_loop(fixed)
+    flat = np.array([x["done"] - x["submit"] for x in ft])
     return {"requests": n_requests, "slots": slots, "budget_bytes": budget, "lambda_req_per_s": lam,
             "saturated_req_per_s": sat_rate, "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3), "mean_latency_ms": float(lat.mean() * 1e3),
@@ -139,6 +151,9 @@ def serve_bench(fmm, W, torch, n_requests=512, slots=8, budget=2 << 30):
                               "tree_build": float(np.mean([p["built"] - x["admit"] for x, p in zip(times, phases)]) * 1e3),
                               "upward_evaluate": float(np.mean([p["computed"] - p["built"] for p in phases]) * 1e3),
                               "release": float(np.mean([x["done"] - p["computed"] for x, p in zip(times, phases)]) * 1e3)},
+            "fixed_rate": {"lambda_req_per_s": fixed, "p50_latency_ms": float(np.percentile(flat, 50) * 1e3),
+                           "p99_latency_ms": float(np.percentile(flat, 99) * 1e3),
+                           "mean_latency_ms": float(flat.mean() * 1e3)},
             "note": "latency = done - arrival; it includes the tree build of each request"}
 
 

@@ -349,9 +349,12 @@ typedef struct {
 enum { FMM_REQ_QUEUED = 0, FMM_REQ_RUNNING = 1, FMM_REQ_DONE = 2, FMM_REQ_FAILED = 3 };
 
 /* Start the server with `max_concurrent` (1..64) worker slots, each with its
- * own streams.  Admission is in arrival order: the oldest queued request
- * starts when a slot is free and its estimated footprint fits in the budget
- * minus the footprints of the running requests. */
+ * own context and stream.  Admission is in arrival order: the oldest queued
+ * request starts when a slot is free and its estimated footprint fits in the
+ * budget minus the footprints of the running requests.  One slot per
+ * hardware queue of the process (4 by default) serves best: more slots
+ * share queues, and a slot then waits behind another's kernels at each of
+ * its tree build's read-backs. */
 int fmm_serve_start(fmm_ctx *ctx, int max_concurrent);
 /* Queue a request (copied); FMM_ENOMEM if its footprint exceeds the whole
  * budget, FMM_EINVAL for bad parameters (nothing is queued then).  The

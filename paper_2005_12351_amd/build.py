@@ -41,7 +41,7 @@ def _sources(gen_dir, gen_opt):
             (os.path.join(CSRC, "tree_host.cpp"), ["-ffp-contract=off"]),
             (os.path.join(CSRC, "m2l_dispatch.cpp"), []),
             (os.path.join(CSRC, "serve.cpp"), [])]
-    for extra in ("bh.hip", "tree_gpu.hip", "derivs.hip"):
+    for extra in ("bh.hip", "tree_gpu.hip", "derivs.hip", "sort.hip"):
         f = os.path.join(CSRC, extra)
         if os.path.exists(f):
             srcs.append((f, []))

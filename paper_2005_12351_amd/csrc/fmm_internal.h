@@ -167,6 +167,11 @@ hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base);
 // build arena
 size_t ctx_cache_limit(const fmm_ctx *ctx);
 
+// stable sort of n (key, value) pairs on the low `bits` key bits into
+// kout/vout (sort.hip); with tmp null only sets tmp_bytes
+hipError_t dev_sort_pairs(void *tmp, size_t &tmp_bytes, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
+                          int32_t *vout, int n, int bits, hipStream_t s);
+
 struct DevKeep;
 hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta, bool lists, hipStream_t s,
                           HostTree &t, fmm_ctx *ctx = nullptr, DevKeep *dt = nullptr);

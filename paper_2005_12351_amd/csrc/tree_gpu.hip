@@ -21,6 +21,7 @@
 // the output positions, so that every pass is deterministic.  The host only
 // reads back totals (sizes of the next level or frontier).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <vector>
 
@@ -69,8 +70,27 @@ __device__ int block_excl_scan(int v, int *sh, int *tot)
 // 64-bit total to *total
 constexpr int kSmallT = 1024;
 constexpr int kSmallScan = 1 << 16;
+__device__ __forceinline__ void scan_small_body(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n,
+                                                int64_t *__restrict__ total);
 __global__ __launch_bounds__(kSmallT) void scan_small_kernel(const int32_t *__restrict__ in, int32_t *__restrict__ out,
                                                              int n, int64_t *__restrict__ total)
+{
+    scan_small_body(in, out, n, total);
+}
+
+// three independent small scans in one launch, one block each
+struct Scan3 {
+    const int32_t *in[3];
+    int32_t *out[3];
+    int64_t *total[3];
+};
+__global__ __launch_bounds__(kSmallT) void scan_small3_kernel(Scan3 a, int n)
+{
+    scan_small_body(a.in[blockIdx.x], a.out[blockIdx.x], n, a.total[blockIdx.x]);
+}
+
+__device__ __forceinline__ void scan_small_body(const int32_t *__restrict__ in, int32_t *__restrict__ out, int n,
+                                                int64_t *__restrict__ total)
 {
     __shared__ int sh[kSmallT / 64];
     __shared__ long long t64[kSmallT / 64];
@@ -232,7 +252,7 @@ __global__ __launch_bounds__(kScanT) void radix_scatter_kernel(const uint64_t *_
 // one workgroup, in place: the order of the stable sort on (key & mask) for
 // n <= kSmallSort items, as a bitonic sort of (masked key, position) in LDS;
 // keys and values are then gathered by position
-constexpr int kSmallSort = 8192;
+constexpr int kSmallSort = 2048;
 constexpr int kSmallSortT = 1024;
 __global__ __launch_bounds__(kSmallSortT) void small_sort_kernel(uint64_t *__restrict__ k, int32_t *__restrict__ v, int n,
                                                                  uint64_t mask)
@@ -319,13 +339,27 @@ __global__ void bbox_partial_kernel(const double *__restrict__ pos, int64_t n, d
     if (threadIdx.x < 7) part[7 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void bbox_final_kernel(const double *__restrict__ part, int nb, double *__restrict__ out)
+// one block of 256: the 7 components (3 minima, 3 maxima, the non-finite
+// flag) over the nb partial results, strided over the threads, then an LDS
+// tree; min and max are exact, so the order does not matter
+__global__ __launch_bounds__(256) void bbox_final_kernel(const double *__restrict__ part, int nb,
+                                                         double *__restrict__ out)
 {
-    if (threadIdx.x >= 7) return;
-    const bool mx = threadIdx.x >= 3;
-    double v = part[threadIdx.x];
-    for (int b = 1; b < nb; ++b) v = mx ? fmax(v, part[7 * b + threadIdx.x]) : fmin(v, part[7 * b + threadIdx.x]);
-    out[threadIdx.x] = v;
+    __shared__ double sh[7][256];
+    double v[7];
+    for (int k = 0; k < 7; ++k) v[k] = k < 3 ? INFINITY : -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int k = 0; k < 7; ++k) v[k] = k < 3 ? fmin(v[k], part[7 * b + k]) : fmax(v[k], part[7 * b + k]);
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 7; ++k)
+                sh[k][threadIdx.x] = k < 3 ? fmin(sh[k][threadIdx.x], sh[k][threadIdx.x + w])
+                                           : fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __device__ __forceinline__ uint64_t spread3(uint64_t v)
@@ -363,31 +397,39 @@ __global__ void keys_kernel(const double *__restrict__ pos, int n, KeyGeo g, uin
 // ---------------------------------------------------------------- tree
 // one thread per cell of the level: the particle runs of the 8 octants by
 // binary search on the sorted keys
-__global__ void tree_split_kernel(const DevCell *__restrict__ cells, int lb, int le, const uint64_t *__restrict__ key,
-                                  int ncrit, int level, int32_t *__restrict__ nch, int2 *__restrict__ runs)
+// eight lanes per cell, lane `dig` finding the end of the run of child
+// digit dig (the first index in the cell's range whose digit exceeds dig;
+// the keys are sorted, so the runs are consecutive), all eight at once
+__global__ __launch_bounds__(256) void tree_split_kernel(const DevCell *__restrict__ cells, int lb, int le,
+                                                         const uint64_t *__restrict__ key, int ncrit, int level,
+                                                         int32_t *__restrict__ nch, int2 *__restrict__ runs)
 {
-    const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= le) return;
-    const DevCell cell = cells[c];
-    int cntc = 0;
-    if (cell.count > ncrit && level < kMaxLevel) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = lb + (g >> 3), dig = g & 7;
+    const bool live = c < le;
+    const DevCell cell = cells[live ? c : lb];
+    const bool split = live && cell.count > ncrit && level < kMaxLevel;
+    const int e = cell.first + cell.count;
+    int lo = cell.first;
+    if (split) {
         const int shift = 3 * (kMaxLevel - level - 1);
-        int a = cell.first;
-        const int e = cell.first + cell.count;
-        for (int dig = 0; dig < 8; ++dig) {
-            // first index in [a, e) whose digit exceeds dig
-            int lo = a, hi = e;
-            while (lo < hi) {
-                const int m = (lo + hi) >> 1;
-                if ((int)((key[m] >> shift) & 7) <= dig) lo = m + 1;
-                else hi = m;
-            }
-            runs[(size_t)(c - lb) * 8 + dig] = make_int2(a, lo - a);
-            cntc += lo > a;
-            a = lo;
+        int hi = e;
+        while (lo < hi) {
+            const int m = (lo + hi) >> 1;
+            if ((int)((key[m] >> shift) & 7) <= dig) lo = m + 1;
+            else hi = m;
         }
     }
-    nch[c - lb] = cntc;
+    // the run of digit dig starts where digit dig - 1 ends (eight lanes of
+    // one cell are consecutive lanes of one wave)
+    const int prev = __shfl_up(lo, 1, 8);
+    const int a = dig == 0 ? cell.first : prev;
+    const int nonempty = split && lo > a ? 1 : 0;
+    int cntc = nonempty;
+    for (int w = 1; w < 8; w <<= 1) cntc += __shfl_xor(cntc, w, 8);
+    if (!live) return;
+    if (split) runs[(size_t)(c - lb) * 8 + dig] = make_int2(a, lo - a);
+    if (dig == 0) nch[c - lb] = split ? cntc : 0;
 }
 
 __global__ void tree_emit_kernel(DevCell *__restrict__ cells, int lb, int le, const int32_t *__restrict__ nch,
@@ -487,11 +529,21 @@ __global__ void trav_emit_kernel(const int2 *__restrict__ fr, int nf, const DevC
     }
 }
 
+// keys sorted by target: each wave adds the length of each of its runs of
+// one target with one atomic (instead of one per key)
 __global__ void list_count_kernel(const uint64_t *__restrict__ key, int64_t m, int kb, int32_t *__restrict__ cnt)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    atomicAdd(&cnt[(int)(key[i] >> kb)], 1);
+    const int lane = threadIdx.x & 63;
+    const int t = i < m ? (int)(key[i] >> kb) : -1;
+    const int prev = __shfl_up(t, 1, 64);
+    const bool head = lane == 0 || prev != t;
+    const unsigned long long heads = __ballot(head);
+    if (head && t >= 0) {
+        const unsigned long long later = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+        const int next = later ? __ffsll((long long)later) - 1 : 64;
+        atomicAdd(&cnt[t], next - lane);
+    }
 }
 
 __global__ void list_src_kernel(const uint64_t *__restrict__ key, int64_t m, int kb, int32_t *__restrict__ src)
@@ -619,6 +671,18 @@ hipError_t radix_sort(Dev &dv, uint64_t *&k, int32_t *&v, int n, int bits)
         hipLaunchKernelGGL(small_sort_kernel, dim3(1), dim3(kSmallSortT), 0, dv.s, k, v, n, mask);
         return hipGetLastError();
     }
+    if (dv.ctx) {   // the library sort: 8-bit digits, a few launches per digit
+        size_t tb = 0;
+        GCHK(dev_sort_pairs(nullptr, tb, k, nullptr, v, nullptr, n, std::min(bits, 64), dv.s));
+        uint64_t *k2 = dv.alloc<uint64_t>(n);
+        int32_t *v2 = dv.alloc<int32_t>(n);
+        char *tmp = dv.alloc<char>(tb);
+        GCHK(dv.err);
+        GCHK(dev_sort_pairs(tmp, tb, k, k2, v, v2, n, std::min(bits, 64), dv.s));
+        std::swap(k, k2);
+        std::swap(v, v2);
+        return hipSuccess;
+    }
     const int nb = (int)nblk(n, kScanTile);
     uint64_t *k2 = dv.alloc<uint64_t>(n);
     int32_t *v2 = dv.alloc<int32_t>(n);
@@ -736,46 +800,75 @@ __device__ __forceinline__ void unpack_class(uint64_t k, int &dl, int64_t &d0, i
 
 // target keys: level (5 bits) | octant (3) | lo0 hi0 lo1 hi1 lo2 hi2 (7 each,
 // + 64) | 8191 - length (13); cells without an M2L list sort last
-__global__ void tile_key_kernel(const DevCell *__restrict__ cells, int nc, const int32_t *__restrict__ ptr,
-                                const int32_t *__restrict__ src, uint64_t *__restrict__ key,
-                                int32_t *__restrict__ val, unsigned long long *__restrict__ info)
+// one wave per cell: its lanes stride over the list, then reduce; the
+// block's targets, shallowest levels and overflow flag go to `info` with one
+// atomic each per block
+constexpr int kKeyT = 1024;
+__global__ __launch_bounds__(kKeyT) void tile_key_kernel(const DevCell *__restrict__ cells, int nc,
+                                                         const int32_t *__restrict__ ptr, const int32_t *__restrict__ src,
+                                                         uint64_t *__restrict__ key, int32_t *__restrict__ val,
+                                                         unsigned long long *__restrict__ info)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    val[c] = c;
-    const int e0 = ptr[c], e1 = ptr[c + 1];
-    if (e1 == e0) {
-        key[c] = kEmptyKey;
-        return;
+    __shared__ int s_cnt, s_bad, s_tl, s_sl;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_bad = 0;
+        s_tl = INT_MAX;
+        s_sl = INT_MAX;
     }
-    const DevCell B = cells[c];
-    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    bool any = false;
-    for (int e = e0; e < e1; ++e) {
-        const DevCell A = cells[src[e]];
-        if (A.level != B.level) continue;
-        const int o[3] = {A.ix - B.ix, A.iy - B.iy, A.iz - B.iz};
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = any ? min(lo[d], o[d]) : o[d];
-            hi[d] = any ? max(hi[d], o[d]) : o[d];
+    __syncthreads();
+    const int c = blockIdx.x * (kKeyT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c < nc) {   // whole waves
+        const int e0 = ptr[c], e1 = ptr[c + 1];
+        const DevCell B = cells[c];
+        int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const DevCell A = cells[src[e]];
+            if (A.level != B.level) continue;
+            const int o[3] = {A.ix - B.ix, A.iy - B.iy, A.iz - B.iz};
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = min(lo[d], o[d]);
+                hi[d] = max(hi[d], o[d]);
+            }
         }
-        any = true;
+        for (int d = 0; d < 3; ++d)
+            for (int w = 32; w > 0; w >>= 1) {
+                lo[d] = min(lo[d], __shfl_xor(lo[d], w, 64));
+                hi[d] = max(hi[d], __shfl_xor(hi[d], w, 64));
+            }
+        if (lane == 0) {
+            val[c] = c;
+            if (e1 == e0) {
+                key[c] = kEmptyKey;
+            } else {
+                if (lo[0] > hi[0])   // no same-level source
+                    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0;
+                const int len = e1 - e0;
+                bool ok = len <= 8191 && B.level < 32;
+                uint64_t k = ((uint64_t)B.level << 58) |
+                             ((uint64_t)(((B.ix & 1) << 2) | ((B.iy & 1) << 1) | (B.iz & 1)) << 55);
+                for (int d = 0; d < 3; ++d) {
+                    ok = ok && lo[d] >= -64 && lo[d] < 64 && hi[d] >= -64 && hi[d] < 64;
+                    k |= (uint64_t)((lo[d] + 64) & 127) << (48 - 14 * d);
+                    k |= (uint64_t)((hi[d] + 64) & 127) << (41 - 14 * d);
+                }
+                k |= (uint64_t)(8191 - min(len, 8191));
+                key[c] = k;
+                atomicAdd(&s_cnt, 1);
+                if (!ok) s_bad = 1;
+                atomicMin(&s_tl, B.level);
+                atomicMin(&s_sl, (int)cells[src[e0]].level);   // lists sorted by source, cells level-major
+            }
+        }
     }
-    const int len = e1 - e0;
-    bool ok = len <= 8191 && B.level < 32;
-    uint64_t k = ((uint64_t)B.level << 58) | ((uint64_t)(((B.ix & 1) << 2) | ((B.iy & 1) << 1) | (B.iz & 1)) << 55);
-    for (int d = 0; d < 3; ++d) {
-        ok = ok && lo[d] >= -64 && lo[d] < 64 && hi[d] >= -64 && hi[d] < 64;
-        k |= (uint64_t)((lo[d] + 64) & 127) << (48 - 14 * d);
-        k |= (uint64_t)((hi[d] + 64) & 127) << (41 - 14 * d);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt > 0) {
+        atomicAdd(&info[0], (unsigned long long)s_cnt);        // targets
+        if (s_bad) atomicOr(&info[1], 1ull);                   // a key field overflows
+        atomicMin(&info[4], (unsigned long long)s_tl);         // shallowest target
+        atomicMin(&info[5], (unsigned long long)s_sl);         // shallowest source
     }
-    k |= (uint64_t)(8191 - min(len, 8191));
-    key[c] = k;
-    atomicAdd(&info[0], 1ull);                 // targets
-    if (!ok) atomicOr(&info[1], 1ull);         // a key field overflows
-    atomicMin(&info[4], (unsigned long long)B.level);                  // shallowest target
-    atomicMin(&info[5], (unsigned long long)cells[src[e0]].level);     // shallowest source (lists sorted
-}                                                                      // by source, cells level-major)
+}
 
 __global__ void tile_info_init_kernel(unsigned long long *info)
 {
@@ -785,8 +878,9 @@ __global__ void tile_info_init_kernel(unsigned long long *info)
 // one workgroup per tile: the tile's distinct pair geometries in an LDS hash
 // table.  EMIT = false: their number; EMIT = true: sorted into U, written
 // at the tile's entry offset, and every (entry, lane) source placed in usrc
+constexpr int kClsT = 1024;   // threads per tile: kClsT / 64 per lane
 template <bool EMIT>
-__global__ __launch_bounds__(256) void tile_classes_kernel(const DevCell *__restrict__ cells,
+__global__ __launch_bounds__(kClsT) void tile_classes_kernel(const DevCell *__restrict__ cells,
                                                            const int32_t *__restrict__ tcell,
                                                            const int32_t *__restrict__ ptr,
                                                            const int32_t *__restrict__ src,
@@ -809,7 +903,7 @@ __global__ __launch_bounds__(256) void tile_classes_kernel(const DevCell *__rest
         bad = 0;
     }
     __syncthreads();
-    // 4 threads per lane, every 4th entry of the lane's list each
+    // kClsT / 64 threads per lane, each taking every (kClsT / 64)-th entry of the lane's list
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
     const int slot = tile * kTileW + lane;
     const int B = slot < ntg ? tcell[slot] : -1;
@@ -830,7 +924,7 @@ __global__ __launch_bounds__(256) void tile_classes_kernel(const DevCell *__rest
         bad = 1;
         return -1;
     };
-    for (int e = e0 + part; e < e1; e += 4) {
+    for (int e = e0 + part; e < e1; e += kClsT / 64) {
         uint64_t k;
         if (!pack_class(cells[src[e]], cb, k)) bad = 1;
         probe(k);
@@ -884,7 +978,7 @@ __global__ __launch_bounds__(256) void tile_classes_kernel(const DevCell *__rest
             ukey[base + j] = k;
         }
         __syncthreads();
-        for (int e = e0 + part; e < e1; e += 4) {
+        for (int e = e0 + part; e < e1; e += kClsT / 64) {
             const int A = src[e];
             uint64_t k;
             pack_class(cells[A], cb, k);
@@ -988,14 +1082,15 @@ hipError_t launch_tiling(Dev &dv, const DevCell *cells, int nc, const int32_t *c
     int64_t *itot = (int64_t *)(ts.info + 2);
     GCHK(scan_i32(dv, cnt, ptr, nc, itot));
     hipLaunchKernelGGL(last_of_scan_kernel, dim3(1), dim3(64), 0, s, ptr, nc, itot);
-    hipLaunchKernelGGL(tile_key_kernel, dim3(nblk(nc, 256)), dim3(256), 0, s, cells, nc, ptr, src, key, val, ts.info);
+    hipLaunchKernelGGL(tile_key_kernel, dim3(nblk(nc, kKeyT / 64)), dim3(kKeyT), 0, s, cells, nc, ptr, src, key, val,
+                       ts.info);
     GCHK(hipGetLastError());
     GCHK(radix_sort(dv, key, val, nc, 64));
     const int ntmax = (int)nblk(nc, kTileW);
     int32_t *tcnt = dv.alloc<int32_t>(ntmax);
     ts.uoff = dv.alloc<int32_t>((size_t)ntmax + 1);
     GCHK(dv.err);
-    hipLaunchKernelGGL(tile_classes_kernel<false>, dim3(ntmax), dim3(256), 0, s, cells, val, ptr, src, ts.info, tcnt,
+    hipLaunchKernelGGL(tile_classes_kernel<false>, dim3(ntmax), dim3(kClsT), 0, s, cells, val, ptr, src, ts.info, tcnt,
                        (const int32_t *)nullptr, (uint64_t *)nullptr, (int32_t *)nullptr);
     GCHK(hipGetLastError());
     GCHK(scan_i32(dv, tcnt, ts.uoff, ntmax, itot));
@@ -1033,7 +1128,7 @@ hipError_t launch_tiling(Dev &dv, const DevCell *cells, int nc, const int32_t *c
     int32_t *uidx = dv.alloc<int32_t>(ne), *flag = dv.alloc<int32_t>(ne), *rank = dv.alloc<int32_t>(ne);
     ts.geom = dv.alloc<double>(4 * (size_t)ne);
     GCHK(dv.err);
-    hipLaunchKernelGGL(tile_classes_kernel<true>, dim3(ts.ntiles), dim3(256), 0, s, cells, val, ptr, src, ts.info,
+    hipLaunchKernelGGL(tile_classes_kernel<true>, dim3(ts.ntiles), dim3(kClsT), 0, s, cells, val, ptr, src, ts.info,
                        (int32_t *)nullptr, (const int32_t *)ts.uoff, ukey, dt.usrc);
     hipLaunchKernelGGL(iota_i32_kernel, dim3(nblk(ne, 256)), dim3(256), 0, s, uidx, (int)ne);
     GCHK(hipGetLastError());
@@ -1080,7 +1175,7 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     double *part = dv.alloc<double>(7 * (size_t)nbb), *bb = dv.alloc<double>(7);
     GCHK(dv.err);
     hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(256), 0, s, pos, n, part);
-    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(64), 0, s, part, nbb, bb);
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(256), 0, s, part, nbb, bb);
     GCHK(hipGetLastError());
     double box[7];
     GCHK(read_totals(dv, bb, 7, box));
@@ -1117,7 +1212,8 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         int32_t *nch = dv.alloc<int32_t>(m), *off = dv.alloc<int32_t>(m);
         int2 *runs = dv.alloc<int2>((size_t)m * 8);
         GCHK(dv.err);
-        hipLaunchKernelGGL(tree_split_kernel, dim3(nblk(m, 256)), dim3(256), 0, s, cells, lb, le, key, ncrit, l, nch, runs);
+        hipLaunchKernelGGL(tree_split_kernel, dim3(nblk((int64_t)m * 8, 256)), dim3(256), 0, s, cells, lb, le, key, ncrit,
+                           l, nch, runs);
         GCHK(hipGetLastError());
         int64_t tot;
         GCHK(scan_i32(dv, nch, off, m, dtot));
@@ -1162,9 +1258,15 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
             GCHK(dv.err);
             hipLaunchKernelGGL(trav_count_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, fr, (int)nf, cells, th2, nk, fm, fp);
             GCHK(hipGetLastError());
-            GCHK(scan_i32(dv, nk, nk, (int)nf, dtot));
-            GCHK(scan_i32(dv, fm, fm, (int)nf, dtot + 1));
-            GCHK(scan_i32(dv, fp, fp, (int)nf, dtot + 2));
+            if (nf <= kSmallScan) {   // the three scans in one launch
+                Scan3 a{{nk, fm, fp}, {nk, fm, fp}, {dtot, dtot + 1, dtot + 2}};
+                hipLaunchKernelGGL(scan_small3_kernel, dim3(3), dim3(kSmallT), 0, s, a, (int)nf);
+                GCHK(hipGetLastError());
+            } else {
+                GCHK(scan_i32(dv, nk, nk, (int)nf, dtot));
+                GCHK(scan_i32(dv, fm, fm, (int)nf, dtot + 1));
+                GCHK(scan_i32(dv, fp, fp, (int)nf, dtot + 2));
+            }
             int64_t tt[3];
             GCHK(read_totals(dv, dtot, 3, tt));
             const int64_t tk = tt[0], tm = tt[1], tp = tt[2];

@@ -15,11 +15,13 @@
 // is neither accepted nor a leaf pair the larger cell is split (both on a
 // tie; a leaf is never split).  Each target's lists are sorted by source.
 //
-// Layout of the work: LSD radix sort with 4-bit digits (stable by
-// construction), one thread per cell and level for the tree, and a
+// Layout of the work: stable sorts (a bitonic sort in LDS on (key, position)
+// for small inputs, the library's LSD radix sort with 8-bit digits for the
+// rest), eight lanes per cell and one pass per level for the tree, and a
 // breadth-first traversal over a frontier of cell pairs with prefix sums for
-// the output positions, so that every pass is deterministic.  The host only
-// reads back totals (sizes of the next level or frontier).
+// the output positions, so that every pass is deterministic.  The host reads
+// back only totals (sizes of the next level or frontier).  After the lists,
+// the M2L schedule is made here too (see launch_tiling).
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -32,8 +34,6 @@ namespace {
 constexpr int kScanT = 256;           // threads per scan block
 constexpr int kScanI = 4;             // items per thread
 constexpr int kScanTile = kScanT * kScanI;
-constexpr int kRadixBits = 4;
-constexpr int kRadixBins = 1 << kRadixBits;
 
 // ---------------------------------------------------------------- scans
 __device__ __forceinline__ int wave_incl_scan(int v)
@@ -179,76 +179,7 @@ __global__ __launch_bounds__(kScanT) void scan_add_kernel(int32_t *__restrict__ 
         if (base + j < n) out[base + j] += add;
 }
 
-// ---------------------------------------------------------------- radix sort
-__global__ __launch_bounds__(kScanT) void radix_count_kernel(const uint64_t *__restrict__ keys, int n, int shift,
-                                                             int nb, int32_t *__restrict__ counts)
-{
-    __shared__ int hist[kRadixBins];
-    if (threadIdx.x < kRadixBins) hist[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanI;
-#pragma unroll
-    for (int j = 0; j < kScanI; ++j)
-        if (base + j < n) atomicAdd(&hist[(int)((keys[base + j] >> shift) & (kRadixBins - 1))], 1);
-    __syncthreads();
-    if (threadIdx.x < kRadixBins) counts[threadIdx.x * nb + blockIdx.x] = hist[threadIdx.x];
-}
-
-// stable scatter: an item's place is the digit's global offset for this
-// block, plus the items of that digit in earlier threads of the block, plus
-// the earlier items of that digit in its own thread
-__global__ __launch_bounds__(kScanT) void radix_scatter_kernel(const uint64_t *__restrict__ kin,
-                                                               const int32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-                                                               int32_t *__restrict__ vout, int n, int shift, int nb,
-                                                               const int32_t *__restrict__ offsets)
-{
-    __shared__ int cnt[kRadixBins][kScanT + 1];
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)t * kScanI;
-    uint64_t k[kScanI];
-    int32_t v[kScanI];
-    int dg[kScanI], rk[kScanI];
-    unsigned long long packed = 0;   // 3-bit count per digit (at most 4 items)
-#pragma unroll
-    for (int j = 0; j < kScanI; ++j) {
-        const bool ok = base + j < n;
-        k[j] = ok ? kin[base + j] : 0;
-        v[j] = ok ? vin[base + j] : 0;
-        dg[j] = ok ? (int)((k[j] >> shift) & (kRadixBins - 1)) : -1;
-        if (ok) {
-            rk[j] = (int)((packed >> (3 * dg[j])) & 7);
-            packed += 1ull << (3 * dg[j]);
-        }
-    }
-    for (int d = 0; d < kRadixBins; ++d) cnt[d][t] = (int)((packed >> (3 * d)) & 7);
-    __syncthreads();
-    // exclusive scan of every digit row over the threads: wave w scans rows
-    // w, w + 4, ...; lane l covers threads 4l .. 4l + 3
-    const int lane = t & 63, w = t >> 6;
-    for (int d = w; d < kRadixBins; d += kScanT / 64) {
-        int a[4], s = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[q] = cnt[d][4 * lane + q];
-            s += a[q];
-        }
-        int run = wave_incl_scan(s) - s;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            cnt[d][4 * lane + q] = run;
-            run += a[q];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kScanI; ++j) {
-        if (dg[j] < 0) continue;
-        const int64_t pos = (int64_t)offsets[dg[j] * nb + blockIdx.x] + cnt[dg[j]][t] + rk[j];
-        kout[pos] = k[j];
-        vout[pos] = v[j];
-    }
-}
-
+// ---------------------------------------------------------------- small sort
 // one workgroup, in place: the order of the stable sort on (key & mask) for
 // n <= kSmallSort items, as a bitonic sort of (masked key, position) in LDS;
 // keys and values are then gathered by position
@@ -588,12 +519,6 @@ struct Dev {
         blocks.push_back(p);
         return (T *)p;
     }
-    // hand a block over to another owner (no longer freed with the rest)
-    void detach(void *p)
-    {
-        auto it = std::find(blocks.begin(), blocks.end(), p);
-        if (it != blocks.end()) blocks.erase(it);
-    }
     void release(void *p)
     {
         auto it = std::find(blocks.begin(), blocks.end(), p);
@@ -661,44 +586,26 @@ hipError_t read_totals(Dev &dv, const void *dev, int k, void *host)
     return hipSuccess;
 }
 
-// stable LSD sort of (key, val) on the low `bits` bits of the key; the result
-// ends in k/v (the buffers are swapped internally as needed)
+// stable sort of (key, val) on the low `bits` bits of the key: one workgroup
+// for at most kSmallSort items, else the library radix sort (8-bit digits);
+// the result ends in k/v (the buffers are swapped as needed)
 hipError_t radix_sort(Dev &dv, uint64_t *&k, int32_t *&v, int n, int bits)
 {
     if (n <= 1) return hipSuccess;
-    if (n <= kSmallSort) {   // one launch instead of three per digit
+    if (n <= kSmallSort) {
         const uint64_t mask = bits >= 64 ? ~0ull : (1ull << bits) - 1;
         hipLaunchKernelGGL(small_sort_kernel, dim3(1), dim3(kSmallSortT), 0, dv.s, k, v, n, mask);
         return hipGetLastError();
     }
-    if (dv.ctx) {   // the library sort: 8-bit digits, a few launches per digit
-        size_t tb = 0;
-        GCHK(dev_sort_pairs(nullptr, tb, k, nullptr, v, nullptr, n, std::min(bits, 64), dv.s));
-        uint64_t *k2 = dv.alloc<uint64_t>(n);
-        int32_t *v2 = dv.alloc<int32_t>(n);
-        char *tmp = dv.alloc<char>(tb);
-        GCHK(dv.err);
-        GCHK(dev_sort_pairs(tmp, tb, k, k2, v, v2, n, std::min(bits, 64), dv.s));
-        std::swap(k, k2);
-        std::swap(v, v2);
-        return hipSuccess;
-    }
-    const int nb = (int)nblk(n, kScanTile);
+    size_t tb = 0;
+    GCHK(dev_sort_pairs(nullptr, tb, k, nullptr, v, nullptr, n, std::min(bits, 64), dv.s));
     uint64_t *k2 = dv.alloc<uint64_t>(n);
     int32_t *v2 = dv.alloc<int32_t>(n);
-    int32_t *cnt = dv.alloc<int32_t>((size_t)kRadixBins * nb);
-    int64_t *tot = dv.alloc<int64_t>(1);
+    char *tmp = dv.alloc<char>(tb);
     GCHK(dv.err);
-    for (int shift = 0; shift < bits; shift += kRadixBits) {
-        hipLaunchKernelGGL(radix_count_kernel, dim3(nb), dim3(kScanT), 0, dv.s, k, n, shift, nb, cnt);
-        GCHK(hipGetLastError());
-        GCHK(scan_i32(dv, cnt, cnt, kRadixBins * nb, tot));
-        hipLaunchKernelGGL(radix_scatter_kernel, dim3(nb), dim3(kScanT), 0, dv.s, k, v, k2, v2, n, shift, nb, cnt);
-        GCHK(hipGetLastError());
-        std::swap(k, k2);
-        std::swap(v, v2);
-    }
-    // k2/v2 now hold the stale buffers; they are released with the rest
+    GCHK(dev_sort_pairs(tmp, tb, k, k2, v, v2, n, std::min(bits, 64), dv.s));
+    std::swap(k, k2);
+    std::swap(v, v2);
     return hipSuccess;
 }
 

@@ -38,7 +38,7 @@ PEAK_HBM = 8.0e12
 
 KERNEL_SOURCES = {
     "m2l": ("paper_2005_12351_amd/csrc/gen_m2l.py", "paper_2005_12351_amd/csrc/m2l.hip",
-            "paper_2005_12351_amd/csrc/tree_host.cpp"),
+            "paper_2005_12351_amd/csrc/tree_host.cpp", "paper_2005_12351_amd/csrc/tree_gpu.hip"),
     "p2p": ("paper_2005_12351_amd/csrc/p2p_kernel.h", "paper_2005_12351_amd/csrc/pair_kernels.h",
             "paper_2005_12351_amd/csrc/fmm_capi.cpp"),
 }
@@ -213,6 +213,27 @@ def cpu_baseline(args, w, theta, p, method):
     return res
 
 
+def tree_builds(fmm, torch, w, pos, k):
+    """K builds of the workload's tree on one context (the first grows its
+    arena and loads the sort kernels), with the context's host phases"""
+    ctx = fmm.Context(0)
+    ts = []
+    for i in range(k + 1):
+        ctx.profile(True)
+        ctx.profile_reset()
+        t0 = time.perf_counter()
+        tree = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        phases = {n: v[0] for n, v in ctx.profile_read().items() if n.startswith("host:")}
+        info = tree.info()
+        tree.close()
+    ctx.close()
+    print(json.dumps({"tree_build_ms": float(np.median(ts[1:])) * 1e3, "first_build_ms": ts[0] * 1e3, "builds": k,
+                      "n": w.n, "theta": w.theta, "ncrit": w.ncrit, "last_build_phases_ms": phases, "tree": info}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +258,8 @@ def main():
                     help="near field beside the far field in the timed steps (default tail: after the M2L, beside the combine and L2L)")
     ap.add_argument("--m2l-engine", choices=["auto", "mfma", "valu"], default="auto",
                     help="units of the FP32 harmonic-basis M2L (auto: matrix cores for p >= 8)")
+    ap.add_argument("--tree-builds", type=int, default=0, metavar="K",
+                    help="only time K tree builds of the workload's particles (one JSON line; no FMM steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -258,6 +281,9 @@ def main():
     pos = torch.from_numpy(w.pos).to(dev)
     mom = torch.from_numpy(w.moments).to(dev)
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
+    if args.tree_builds:
+        tree_builds(fmm, torch, w, pos, args.tree_builds)
+        return
     ctx = fmm.Context(0)
     # device work of this script runs on the context's stream, so the
     # binding has no cross-stream ordering to add around each call

@@ -291,6 +291,13 @@ __global__ __launch_bounds__(256) void bbox_final_kernel(const double *__restric
         __syncthreads();
     }
     if (threadIdx.x < 7) out[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 0) {   // out[7]: the key scale 2^21 / W, W the largest extent (1 if all coincide)
+        const double e0 = sh[3][0] - sh[0][0], e1 = sh[4][0] - sh[1][0], e2 = sh[5][0] - sh[2][0];
+        const double m12 = e1 < e2 ? e2 : e1;
+        double W = e0 < m12 ? m12 : e0;
+        if (W == 0.0) W = 1.0;
+        out[7] = ldexp(1.0, kMaxLevel) / W;
+    }
 }
 
 __device__ __forceinline__ uint64_t spread3(uint64_t v)
@@ -304,37 +311,65 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v)
     return v;
 }
 
-struct KeyGeo {
-    double lo[3];
-    double scale;
-};
-
-__global__ void keys_kernel(const double *__restrict__ pos, int n, KeyGeo g, uint64_t *__restrict__ key,
-                            int32_t *__restrict__ idx)
+// box: the componentwise minima, maxima, the non-finite flag and the key
+// scale (bbox_final_kernel); with a non-finite position every key is 0 (the
+// host rejects the build at its first read-back)
+__global__ void keys_kernel(const double *__restrict__ pos, int n, const double *__restrict__ box,
+                            uint64_t *__restrict__ key, int32_t *__restrict__ idx)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    idx[i] = i;
+    if (box[6] != 0.0) {
+        key[i] = 0;
+        return;
+    }
+    const double scale = box[7];
     const int64_t qmax = (int64_t(1) << kMaxLevel) - 1;
     uint64_t q[3];
     for (int d = 0; d < 3; ++d) {
-        const double v = __dmul_rn(__dsub_rn(pos[3 * (size_t)i + d], g.lo[d]), g.scale);
+        const double v = __dmul_rn(__dsub_rn(pos[3 * (size_t)i + d], box[d]), scale);
         const int64_t qi = (int64_t)floor(v);
         q[d] = (uint64_t)min(max(qi, (int64_t)0), qmax);
     }
     key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
-    idx[i] = i;
 }
 
 // ---------------------------------------------------------------- tree
-// one thread per cell of the level: the particle runs of the 8 octants by
-// binary search on the sorted keys
+// The levels are built without the host: each level's first cell is kept in
+// LevelState::lev, which the kernels read.  Grids are sized by a bound on the
+// number of cells of the level (cells past the level's end exit); a level
+// whose children would exceed the cell capacity sets `flag` and writes
+// nothing, and every later kernel of the batch then does nothing, so the
+// host can grow the array and run the batch again.
+struct LevelState {
+    double box[8];                 // minima, maxima, non-finite flag, key scale
+    int32_t flag;                  // 1: cell capacity exceeded, 2: a level above its bound
+    int32_t pad;
+    int32_t lev[kMaxLevel + 3];    // first cell of every level (lev[l + 1]: end of level l)
+};
+
+__global__ void level_init_kernel(LevelState *ls)
+{
+    if (threadIdx.x < kMaxLevel + 3) ls->lev[threadIdx.x] = threadIdx.x == 1 ? 1 : 0;
+    if (threadIdx.x == 0) ls->flag = 0;
+}
+
+__global__ void level_flag_clear_kernel(LevelState *ls)
+{
+    if (threadIdx.x == 0) ls->flag = 0;
+}
+
 // eight lanes per cell, lane `dig` finding the end of the run of child
 // digit dig (the first index in the cell's range whose digit exceeds dig;
 // the keys are sorted, so the runs are consecutive), all eight at once
-__global__ __launch_bounds__(256) void tree_split_kernel(const DevCell *__restrict__ cells, int lb, int le,
-                                                         const uint64_t *__restrict__ key, int ncrit, int level,
+__global__ __launch_bounds__(256) void tree_split_kernel(const DevCell *__restrict__ cells, const LevelState *ls,
+                                                         int level, const uint64_t *__restrict__ key, int ncrit,
                                                          int32_t *__restrict__ nch, int2 *__restrict__ runs)
 {
+    if (ls->flag) return;
+    const int lb = ls->lev[level], le = ls->lev[level + 1];
+    if (lb >= le) return;   // an empty level (past the deepest)
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = lb + (g >> 3), dig = g & 7;
     const bool live = c < le;
@@ -363,9 +398,29 @@ __global__ __launch_bounds__(256) void tree_split_kernel(const DevCell *__restri
     if (dig == 0) nch[c - lb] = split ? cntc : 0;
 }
 
-__global__ void tree_emit_kernel(DevCell *__restrict__ cells, int lb, int le, const int32_t *__restrict__ nch,
-                                 const int32_t *__restrict__ off, const int2 *__restrict__ runs)
+// one block: the children's offsets within the next level, and its end
+__global__ __launch_bounds__(kSmallT) void level_scan_kernel(const int32_t *__restrict__ nch, int32_t *__restrict__ off,
+                                                             LevelState *ls, int level, int bound, int64_t *tot)
 {
+    int m = ls->flag ? 0 : ls->lev[level + 1] - ls->lev[level];
+    if (m > bound) {   // never expected: the bound is a theorem; read nothing past the buffers
+        if (threadIdx.x == 0) ls->flag = 2;
+        m = 0;
+    }
+    scan_small_body(nch, off, m, tot);
+    if (threadIdx.x == 0) ls->lev[level + 2] = ls->lev[level + 1] + (int)*tot;
+}
+
+__global__ void tree_emit_kernel(DevCell *__restrict__ cells, LevelState *ls, int level, int cap,
+                                 const int32_t *__restrict__ nch, const int32_t *__restrict__ off,
+                                 const int2 *__restrict__ runs)
+{
+    if (ls->flag) return;
+    const int lb = ls->lev[level], le = ls->lev[level + 1];
+    if (ls->lev[level + 2] > cap) {   // the children do not fit: nothing is written
+        if (threadIdx.x == 0) ls->flag = 1;
+        return;
+    }
     const int c = lb + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= le) return;
     const int k = nch[c - lb];
@@ -1077,72 +1132,95 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         ctx->prof.push_back(ProfEntry{nm, nullptr, nullptr, std::chrono::duration<double, std::milli>(now - t_last).count()});
         t_last = now;
     };
-    // root box
+    // root box (read back with the first batch of levels)
+    LevelState *ls = dv.alloc<LevelState>(1);
     const int nbb = (int)std::min<int64_t>(1024, nblk(n, 256));
-    double *part = dv.alloc<double>(7 * (size_t)nbb), *bb = dv.alloc<double>(7);
+    double *part = dv.alloc<double>(7 * (size_t)nbb);
     GCHK(dv.err);
+    hipLaunchKernelGGL(level_init_kernel, dim3(1), dim3(64), 0, s, ls);
     hipLaunchKernelGGL(bbox_partial_kernel, dim3(nbb), dim3(256), 0, s, pos, n, part);
-    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(256), 0, s, part, nbb, bb);
+    hipLaunchKernelGGL(bbox_final_kernel, dim3(1), dim3(256), 0, s, part, nbb, ls->box);
     GCHK(hipGetLastError());
-    double box[7];
-    GCHK(read_totals(dv, bb, 7, box));
-    mark("host:tree_box");
-    if (box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
-    double W = std::max(box[3] - box[0], std::max(box[4] - box[1], box[5] - box[2]));
-    if (W == 0.0) W = 1.0;
-    for (int d = 0; d < 3; ++d) t.lo[d] = box[d];
-    t.W = W;
-    t.h = std::ldexp(W, -22);
-    KeyGeo g{{box[0], box[1], box[2]}, std::ldexp(1.0, kMaxLevel) / W};
 
     // keys and stable sort
     uint64_t *key = dv.alloc<uint64_t>(n);
     int32_t *idx = dv.alloc<int32_t>(n);
     GCHK(dv.err);
-    hipLaunchKernelGGL(keys_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, pos, (int)n, g, key, idx);
+    hipLaunchKernelGGL(keys_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, pos, (int)n, (const double *)ls->box, key, idx);
     GCHK(hipGetLastError());
     GCHK(radix_sort(dv, key, idx, (int)n, 3 * kMaxLevel));
+    mark("host:tree_box");
 
     int64_t *dtot = dv.alloc<int64_t>(4);
     GCHK(dv.err);
-    // cells level by level
+    // Cells level by level, in batches of levels between read-backs.  A
+    // level holds at most 8^l cells, and at most 8 children of each cell
+    // that splits, a split cell holds more than ncrit particles and the
+    // cells of one level are disjoint, and at most n non-empty cells: that
+    // bound sizes the grids and the per-level buffers (shared by the levels).
     size_t cap = std::max<size_t>(64, (size_t)(4 * n / std::max(1, ncrit) + 64));
     DevCell *cells = dv.alloc<DevCell>(cap);
+    const int64_t split_max = n / ((int64_t)ncrit + 1);
+    const int64_t umax = std::max<int64_t>(1, std::min<int64_t>(n, 8 * split_max));
+    int32_t *nch = dv.alloc<int32_t>(umax), *off = dv.alloc<int32_t>(umax);
+    int2 *runs = dv.alloc<int2>((size_t)umax * 8);
     GCHK(dv.err);
     hipLaunchKernelGGL(root_cell_kernel, dim3(1), dim3(64), 0, s, cells, (int32_t)n);
     GCHK(hipGetLastError());
-    t.level_ptr.push_back(0);
-    int lb = 0, le = 1;
-    for (int l = 0;; ++l) {
-        t.level_ptr.push_back(le);
-        const int m = le - lb;
-        int32_t *nch = dv.alloc<int32_t>(m), *off = dv.alloc<int32_t>(m);
-        int2 *runs = dv.alloc<int2>((size_t)m * 8);
-        GCHK(dv.err);
-        hipLaunchKernelGGL(tree_split_kernel, dim3(nblk((int64_t)m * 8, 256)), dim3(256), 0, s, cells, lb, le, key, ncrit,
-                           l, nch, runs);
-        GCHK(hipGetLastError());
-        int64_t tot;
-        GCHK(scan_i32(dv, nch, off, m, dtot));
-        GCHK(read_totals(dv, dtot, 1, &tot));
-        if ((size_t)le + (size_t)tot > cap) {
-            const size_t ncap = std::max(2 * cap, (size_t)le + (size_t)tot);
+    std::vector<int64_t> ub(kMaxLevel + 2, 1);   // ub[l]: bound on the cells of level l
+    for (int l = 0; l + 1 <= kMaxLevel + 1; ++l) ub[l + 1] = std::min<int64_t>(umax, std::min<int64_t>(8 * ub[l], n));
+    LevelState hs;
+    int l0 = 0, nlev = -1;
+    bool first = true;
+    while (nlev < 0) {
+        const int l1 = std::min(l0 + (first ? 6 : 4), kMaxLevel + 1);
+        for (int l = l0; l < l1; ++l) {
+            const int64_t m = ub[l];
+            hipLaunchKernelGGL(tree_split_kernel, dim3(nblk(m * 8, 256)), dim3(256), 0, s, cells, (const LevelState *)ls,
+                               l, key, ncrit, nch, runs);
+            hipLaunchKernelGGL(level_scan_kernel, dim3(1), dim3(kSmallT), 0, s, nch, off, ls, l, (int)m, dtot);
+            hipLaunchKernelGGL(tree_emit_kernel, dim3(nblk(m, 256)), dim3(256), 0, s, cells, ls, l, (int)cap, nch, off,
+                               runs);
+            GCHK(hipGetLastError());
+        }
+        static_assert(sizeof(LevelState) <= 4096, "the level state is read through the pinned words");
+        void *dst = dv.pin ? (void *)dv.pin : (void *)&hs;
+        GCHK(hipMemcpyAsync(dst, ls, sizeof(LevelState), hipMemcpyDeviceToHost, s));
+        GCHK(hipStreamSynchronize(s));
+        if (dst != &hs) memcpy(&hs, dst, sizeof(LevelState));
+        if (first) {
+            if (hs.box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
+            double W = std::max(hs.box[3] - hs.box[0], std::max(hs.box[4] - hs.box[1], hs.box[5] - hs.box[2]));
+            if (W == 0.0) W = 1.0;
+            for (int d = 0; d < 3; ++d) t.lo[d] = hs.box[d];
+            t.W = W;
+            t.h = std::ldexp(W, -22);
+            first = false;
+        }
+        if (hs.flag == 2) return hipErrorUnknown;   // a level above its bound (not expected)
+        if (hs.flag == 1) {
+            // grow the cell array past the largest level end seen and run the batch again
+            size_t need = cap;
+            for (int l = l0; l < l1; ++l) need = std::max(need, (size_t)hs.lev[l + 2]);
+            const size_t ncap = std::max(2 * cap, need + need / 4);
+            if (ncap > (size_t)INT32_MAX) return hipErrorOutOfMemory;
             DevCell *c2 = dv.alloc<DevCell>(ncap);
             GCHK(dv.err);
-            GCHK(hipMemcpyAsync(c2, cells, sizeof(DevCell) * le, hipMemcpyDeviceToDevice, s));
+            GCHK(hipMemcpyAsync(c2, cells, sizeof(DevCell) * cap, hipMemcpyDeviceToDevice, s));
             dv.release(cells);
             cells = c2;
             cap = ncap;
+            hipLaunchKernelGGL(level_flag_clear_kernel, dim3(1), dim3(64), 0, s, ls);
+            GCHK(hipGetLastError());
+            continue;
         }
-        hipLaunchKernelGGL(tree_emit_kernel, dim3(nblk(m, 256)), dim3(256), 0, s, cells, lb, le, nch, off, runs);
-        GCHK(hipGetLastError());
-        dv.release(nch);
-        dv.release(off);
-        dv.release(runs);
-        if (tot == 0) break;
-        lb = le;
-        le = le + (int)tot;
+        // the first level of the batch without children is the deepest
+        for (int l = l0; l < l1 && nlev < 0; ++l)
+            if (hs.lev[l + 2] == hs.lev[l + 1]) nlev = l + 1;
+        l0 = l1;
     }
+    t.level_ptr.assign(hs.lev, hs.lev + nlev + 1);
+    const int le = hs.lev[nlev];
     const int nc = le;
     mark("host:tree_sort_levels");
 

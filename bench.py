@@ -213,7 +213,7 @@ def cpu_baseline(args, w, theta, p, method):
     return res
 
 
-def tree_builds(fmm, torch, w, pos, k):
+def tree_builds(fmm, torch, w, pos, k, method):
     """K builds of the workload's tree on one context (the first grows its
     arena and loads the sort kernels), with the context's host phases"""
     ctx = fmm.Context(0)
@@ -222,7 +222,7 @@ def tree_builds(fmm, torch, w, pos, k):
         ctx.profile(True)
         ctx.profile_reset()
         t0 = time.perf_counter()
-        tree = fmm.Tree(ctx, pos, w.ncrit, w.theta)
+        tree = fmm.Tree(ctx, pos, w.ncrit, w.theta, method)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
         phases = {n: v[0] for n, v in ctx.profile_read().items() if n.startswith("host:")}
@@ -282,7 +282,7 @@ def main():
     mom = torch.from_numpy(w.moments).to(dev)
     outputs = fmm.FMM_FIELD if w.outputs == "field" else (fmm.FMM_POT | fmm.FMM_FIELD)
     if args.tree_builds:
-        tree_builds(fmm, torch, w, pos, args.tree_builds)
+        tree_builds(fmm, torch, w, pos, args.tree_builds, fmm.FMM_METHOD_BH if bh else fmm.FMM_METHOD_FMM)
         return
     ctx = fmm.Context(0)
     # device work of this script runs on the context's stream, so the

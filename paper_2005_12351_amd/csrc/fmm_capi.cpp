@@ -480,6 +480,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     dt.tiling = method == FMM_METHOD_FMM && ctx->m2l_schedule != FMM_SCHEDULE_HOST;
     dt.min_pairs = ctx->m2l_schedule == FMM_SCHEDULE_AUTO ? 32768 : 0;
     {
+        HostScope hs_gpu(ctx, "host:tree_device_build");   // the marked phases plus the release of the build's scratch
         const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx, &dt);
         if (e != hipSuccess) {
             fmm_tree_destroy(t);
@@ -510,6 +511,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         h.p2p_ptr.assign(nc + 1, 0);
     }
     // leaves, per-particle leaf, non-leaf cells per level, P2P CSR per leaf
+    HostScope hs_sched(ctx, "host:tree_near_schedule");
     std::vector<int32_t> level_cells(nc);
     for (int64_t c = 0; c < nc; ++c) {
         level_cells[c] = (int32_t)c;
@@ -543,25 +545,33 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
             }
     t->m2m_top = method == FMM_METHOD_BH ? 0 : src_top;
     t->l2l_from = tgt_top + 1;
-    std::vector<int32_t> pptr(t->nleaves + 1, 0), psrc;
-    double p2p_pairs = 0.0;
-    for (int64_t k = 0; k < t->nleaves; ++k) {
+    // P2P CSR per leaf, each leaf's pairs and its cost (a workgroup's time
+    // grows with its pairs); the sums are of integers below 2^53, exact in
+    // any order, so the leaves are done in parallel
+    const int64_t nlv_ = t->nleaves;
+    std::vector<int32_t> pptr(nlv_ + 1, 0);
+    for (int64_t k = 0; k < nlv_; ++k) {
         const int64_t b = t->leaves[k];
+        pptr[k + 1] = pptr[k] + (int32_t)(h.p2p_ptr[b + 1] - h.p2p_ptr[b]);
+    }
+    std::vector<int32_t> psrc(pptr[nlv_]);
+    std::vector<double> leaf_cost(nlv_, 0.0), leaf_pairs(nlv_, 0.0);
+    host_parallel_for(nlv_, [&](int64_t k) {
+        const int64_t b = t->leaves[k];
+        int32_t *o = psrc.data() + pptr[k];
+        double srcs = 0.0;
         for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) {
-            psrc.push_back((int32_t)h.p2p_src[e]);
-            p2p_pairs += (double)h.count[b] * (double)h.count[h.p2p_src[e]];
+            const int64_t A = h.p2p_src[e];
+            *o++ = (int32_t)A;
+            srcs += (double)h.count[A];
         }
-        if (h.p2p_ptr[b + 1] > h.p2p_ptr[b]) p2p_pairs -= (double)h.count[b];   // no self pair
-        pptr[k + 1] = (int32_t)psrc.size();
-    }
+        leaf_cost[k] = srcs * (double)h.count[b];
+        // the pairs, without the self pair of each particle
+        leaf_pairs[k] = leaf_cost[k] - (h.p2p_ptr[b + 1] > h.p2p_ptr[b] ? (double)h.count[b] : 0.0);
+    });
+    double p2p_pairs = 0.0;
+    for (double v : leaf_pairs) p2p_pairs += v;
     t->work[2] = p2p_pairs;
-    std::vector<double> leaf_cost(t->nleaves, 0.0);
-    for (int64_t k = 0; k < t->nleaves; ++k) {
-        const int64_t b = t->leaves[k];
-        // a workgroup's time grows with its pairs
-        for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) leaf_cost[k] += (double)h.count[h.p2p_src[e]];
-        leaf_cost[k] *= (double)h.count[b];
-    }
     // Near-field dispatch order.  Workgroups go to the eight XCDs in turn
     // (workgroup g to XCD g % 8) and each XCD has its own L2, so the leaves,
     // in Morton order (the order of their first particle), are cut into
@@ -572,10 +582,24 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     constexpr int kXcd = 8;
     std::vector<int32_t> p2p_order;
     {
-        std::vector<int32_t> mort(t->nleaves);
-        for (int64_t k = 0; k < t->nleaves; ++k) mort[k] = (int32_t)k;
-        std::stable_sort(mort.begin(), mort.end(),
-                         [&](int32_t a, int32_t b) { return h.first[t->leaves[a]] < h.first[t->leaves[b]]; });
+        // the leaves in the order of their first particle: a depth-first
+        // walk with the children in octant order (each child's particles
+        // follow its elder sibling's)
+        std::vector<int32_t> leaf_index(nc, -1), mort;
+        mort.reserve(t->nleaves);
+        for (int64_t k = 0; k < t->nleaves; ++k) leaf_index[t->leaves[k]] = (int32_t)k;
+        {
+            std::vector<int32_t> stack{0};
+            while (!stack.empty()) {
+                const int32_t c = stack.back();
+                stack.pop_back();
+                if (h.nchild[c] == 0) {
+                    mort.push_back(leaf_index[c]);
+                    continue;
+                }
+                for (int k = h.nchild[c] - 1; k >= 0; --k) stack.push_back((int32_t)(h.child0[c] + k));
+            }
+        }
         double tot = 0.0;
         for (double c : leaf_cost) tot += c;
         std::vector<std::vector<int32_t>> range(kXcd);
@@ -585,11 +609,12 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
             range[r].push_back(k);
             acc += leaf_cost[k];
         }
+        host_parallel_for(kXcd, [&](int64_t r) {
+            std::stable_sort(range[r].begin(), range[r].end(),
+                             [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
+        });
         size_t longest = 0;
-        for (auto &rg : range) {
-            std::stable_sort(rg.begin(), rg.end(), [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
-            longest = std::max(longest, rg.size());
-        }
+        for (auto &rg : range) longest = std::max(longest, rg.size());
         for (size_t i = 0; i < longest; ++i)
             for (auto &rg : range)
                 if (i < rg.size()) p2p_order.push_back(rg[i]);
@@ -603,6 +628,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         t->p2p_split = k;
     }
 
+    hs_sched.end();
     HostScope hs_up(ctx, "host:tree_upload");
     int rc = FMM_OK;
     Uploads up{t};

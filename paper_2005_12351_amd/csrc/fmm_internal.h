@@ -189,6 +189,9 @@ struct M2LTiling {
     bool on_device = false;                // ucls, usrc, cls_geom exist on the device only
 };
 void build_m2l_tiling(const HostTree &t, M2LTiling &out);
+// f(i) for i in [0, n) on the host threads of the scheduling passes
+// (tree_host.cpp); each i must write its own results only
+void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f);
 
 // Device buffers of a tree that gpu_build_tree (tree_gpu.hip) leaves on
 // the device: `keep` allocates them (the tree's own allocations).  Always:
@@ -381,13 +384,18 @@ struct HostScope {
     fmm_ctx *ctx;
     const char *name;
     std::chrono::steady_clock::time_point t0;
+    bool done = false;
     HostScope(fmm_ctx *c, const char *nm) : ctx(c), name(nm), t0(std::chrono::steady_clock::now()) {}
-    ~HostScope()
+    // records the phase now (once; the destructor then records nothing)
+    void end()
     {
+        if (done) return;
+        done = true;
         if (!ctx || !ctx->profile) return;
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ctx->prof.push_back(ProfEntry{name, nullptr, nullptr, ms});
     }
+    ~HostScope() { end(); }
 };
 
 // kernels entry points (host launchers), return hipError_t

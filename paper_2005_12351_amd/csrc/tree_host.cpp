@@ -130,6 +130,11 @@ static void parallel_for(int64_t n, F f)
     HostPool::get().run(n, f);
 }
 
+void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f)
+{
+    parallel_for(n, [&](int64_t i) { f(i); });
+}
+
 // Exact integer geometry of a pair (source A, target B): the centre offset
 // in units of the smaller radius and the level difference.  It determines
 // ((z_B - z_A) / r_B, r_A / r_B) exactly.

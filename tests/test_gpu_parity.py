@@ -93,6 +93,48 @@ def test_tree_depth_cap(orc, ctx):
     gt.close()
 
 
+def _close_pairs(npairs, sep, seed):
+    """npairs pairs of particles sep apart (relative to the unit box):
+    with ncrit 1 each pair makes a chain of one-child cells down to level
+    21, so the tree holds far more cells than the build's first cell
+    capacity (4 n / ncrit + 64) and its level passes must grow the array
+    and run again"""
+    rng = np.random.default_rng(seed)
+    c = rng.random((npairs, 3))
+    d = rng.standard_normal((npairs, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    return np.ascontiguousarray(np.concatenate([c, c + sep * d]))
+
+
+@pytest.mark.parametrize("npairs,sep", [(100, 1e-9), (400, 1e-7), (60, 1e-12)])
+def test_tree_cell_array_growth(orc, ctx, npairs, sep):
+    pos = _close_pairs(npairs, sep, 11 + npairs)
+    _say(f"[tree growth] n={len(pos)} ncrit=1 sep={sep}")
+    gt = fmm.Tree(ctx, torch.from_numpy(pos).cuda(), 1, 0.5)
+    o = orc.Tree(pos, 1, 0.5).dump()
+    assert len(o.level) > 4 * len(pos) + 64           # the case grows the cell array
+    assert gt.info()["nlevels"] == 22
+    _tree_equal(gt, o)
+    gt.close()
+
+
+def test_fmm_after_cell_array_growth(orc, ctx):
+    """the FMM on such a tree against the oracle's (FP64)"""
+    pos = _close_pairs(150, 1e-8, 5)
+    rng = np.random.default_rng(6)
+    mom = np.ascontiguousarray(rng.standard_normal((len(pos), 3)))
+    _say(f"[fmm growth] n={len(pos)} ncrit=1")
+    t = fmm.Tree(ctx, torch.from_numpy(pos).cuda(), 1, 0.5)
+    t.upward(1, torch.from_numpy(mom).cuda(), 6, fmm.FMM_PREC_FP64)
+    ph, E = t.evaluate()
+    torch.cuda.synchronize()
+    po, Eo = orc.Tree(pos, 1, 0.5).fmm(1, mom, 6)
+    ok = within(ph.cpu().numpy(), po, "fp64", "phi vs oracle FMM", floor=PHI_FLOOR)
+    ok &= within(E.cpu().numpy(), Eo, "fp64", "E vs oracle FMM")
+    t.close()
+    assert ok
+
+
 PARITY = [(0, 4, "uniform", 2000, 32, 0.5), (1, 8, "uniform", 3000, 32, 0.5), (2, 10, "lattice", 3375, 64, 0.5),
           (1, 6, "plummer", 4000, 32, 0.6), (0, 1, "uniform", 1500, 16, 0.5), (2, 3, "plummer", 2500, 8, 0.4),
           (1, 2, "uniform", 700, 4, 0.3), (0, 10, "plummer", 1200, 8, 0.5)]

@@ -292,9 +292,9 @@ int fmm_ctx_set_m2l_engine(fmm_ctx *ctx, int engine);
  * through the host; when a tile holds more than 4096 distinct geometries or
  * a packed key would overflow the build takes the host code instead.
  * FMM_SCHEDULE_HOST: built by the host threads.  FMM_SCHEDULE_AUTO
- * (default): the device from 32768 M2L list entries on (about 10^4
- * particles at ncrit 64), the host below, where its fixed cost is lower.
- * All give the same schedule, entry for entry.  Takes effect for trees
+ * (default): the device (measured faster for every tree size, from a few
+ * thousand list entries on), the host where the device cannot.  All give
+ * the same schedule, entry for entry.  Takes effect for trees
  * built afterwards.  FMM_EINVAL for another value. */
 enum { FMM_SCHEDULE_HOST = 0, FMM_SCHEDULE_DEVICE = 1, FMM_SCHEDULE_AUTO = 2 };
 int fmm_ctx_set_m2l_schedule(fmm_ctx *ctx, int where);

@@ -474,11 +474,11 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     DevKeep dt;
     dt.keep = [t](void **p, size_t bytes) { return tree_alloc(t, p, bytes) == FMM_OK ? hipSuccess : hipErrorOutOfMemory; };
     dt.tl = &t->tiling;
-    // automatic: below some 3·10^4 list entries (about 10^4 particles at
-    // ncrit 64) the fixed cost of the device passes exceeds the host's
-    // (measured: 0.45 against 0.13 ms at 3·10^3 entries, equal at 7·10^4)
+    // automatic: the device, measured faster than the host threads for
+    // every tree from 3·10^3 list entries on (builds of 10^3 to 10^4
+    // particles: 0.60-1.21 ms against 0.63-2.71 ms)
     dt.tiling = method == FMM_METHOD_FMM && ctx->m2l_schedule != FMM_SCHEDULE_HOST;
-    dt.min_pairs = ctx->m2l_schedule == FMM_SCHEDULE_AUTO ? 32768 : 0;
+    dt.min_pairs = 0;
     {
         HostScope hs_gpu(ctx, "host:tree_device_build");   // the marked phases plus the release of the build's scratch
         const hipError_t e = gpu_build_tree(pos, n, ncrit, theta, method == FMM_METHOD_FMM, s, t->ht, ctx, &dt);

@@ -127,8 +127,8 @@ def test_device_schedule_serving(ctxs):
 
 
 def test_schedule_auto():
-    """the default picks the host below 32768 list entries, the device
-    from there on, and both give the host's schedule"""
+    """the default takes the device for small and large trees alike, and
+    gives the host's schedule"""
     auto = fmm.Context(0)
     host = fmm.Context(0)
     host.set_m2l_schedule(fmm.FMM_SCHEDULE_HOST)
@@ -137,9 +137,8 @@ def test_schedule_auto():
         pos = torch.from_numpy(w.pos).cuda()
         ta, th = fmm.Tree(auto, pos, 64, 0.5), fmm.Tree(host, pos, 64, 0.5)
         a, b = ta.m2l_schedule(), th.m2l_schedule()
-        want = fmm.FMM_SCHEDULE_DEVICE if ta.info()["n_m2l"] >= 32768 else fmm.FMM_SCHEDULE_HOST
         _say(f"[schedule auto] n={n} n_m2l={ta.info()['n_m2l']} where={a['where']}")
-        assert a["where"] == want
+        assert a["where"] == fmm.FMM_SCHEDULE_DEVICE
         for k in ("tile_cell", "tile_uoff", "ucls", "usrc", "cls_geom"):
             assert np.array_equal(a[k], b[k]), k
         ta.close()

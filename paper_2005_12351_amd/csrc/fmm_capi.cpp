@@ -76,6 +76,16 @@ extern "C" int fmm_ctx_set_overlap(fmm_ctx *ctx, int on)
 {
     if (!ctx) FAIL(FMM_EINVAL, "null context");
     if (on < 0 || on > FMM_OVERLAP_TAIL) FAIL(FMM_EINVAL, "overlap mode %d (0, 1, 2 or 3)", on);
+    // the auxiliary stream exists only once some overlap asks for it: every
+    // stream takes one of the process's few hardware queues, which contexts
+    // without overlap (the serving slots) would otherwise share
+    if (on != FMM_OVERLAP_OFF && !ctx->aux && !ctx->fake) {
+        HIPCHK(hipSetDevice(ctx->device));
+        if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess) {
+            ctx->aux = nullptr;
+            FAIL(FMM_EDEVICE, "stream creation failed");
+        }
+    }
     ctx->overlap = on;
     for (fmm_tree *t : ctx->trees) drop_graphs(t);
     return FMM_OK;
@@ -218,8 +228,7 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         }
         c->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming) != hipSuccess ||
+    if (hipEventCreateWithFlags(&c->ev_up, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_m2l, hipEventDisableTiming) != hipSuccess ||
@@ -279,7 +288,7 @@ static void tree_release_device(fmm_tree *t)
 {
     drop_graphs(t);
     // the near field may still run on the auxiliary stream
-    (void)hipStreamSynchronize(t->ctx->aux);
+    if (t->ctx->aux) (void)hipStreamSynchronize(t->ctx->aux);
     for (auto &a : t->allocs) ctx_dev_free(t->ctx, a.first, a.second);
     t->allocs.clear();
     t->dev_bytes = 0;
@@ -320,7 +329,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     hipEventDestroy(c->ev_fork);
     hipEventDestroy(c->ev_m2l);
     hipEventDestroy(c->ev_near2);
-    hipStreamDestroy(c->aux);
+    if (c->aux) hipStreamDestroy(c->aux);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
     return FMM_OK;

@@ -232,7 +232,8 @@ extern "C" int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_by
         hipEventCreateWithFlags(&c->ev_near, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_m2l, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_near2, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_near2, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_upload, hipEventDisableTiming) != hipSuccess) {
         delete c;
         FAIL(FMM_EDEVICE, "stream/event creation failed");
     }
@@ -329,6 +330,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     hipEventDestroy(c->ev_fork);
     hipEventDestroy(c->ev_m2l);
     hipEventDestroy(c->ev_near2);
+    hipEventDestroy(c->ev_upload);
     if (c->aux) hipStreamDestroy(c->aux);
     if (c->own_stream) hipStreamDestroy(c->stream);
     delete c;
@@ -392,6 +394,12 @@ extern "C" int fmm_ctx_set_tree_limit(fmm_ctx *ctx, size_t bytes)
 
 hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base)
 {
+    // the copies of the last flush of uploads read the buffer until they end
+    if (ctx->upload_pending) {
+        const hipError_t e = hipEventSynchronize(ctx->ev_upload);
+        ctx->upload_pending = false;
+        if (e != hipSuccess) return e;
+    }
     if (ctx->pinned_bytes < bytes) {
         if (ctx->pinned) (void)hipHostFree(ctx->pinned);
         ctx->pinned = nullptr;
@@ -407,9 +415,9 @@ hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base)
 
 // Uploads of host vectors into new tree allocations: add() allocates and
 // records the vector's data pointer, flush() packs the data into the
-// context's pinned buffer and queues the copies.  Every vector passed to
-// add() must live, unchanged, until flush() returns; the caller
-// synchronises the stream before the pinned buffer is used again.
+// context's pinned buffer, queues the copies and records ev_upload after
+// them (the next use of the pinned buffer waits for that event).  Every
+// vector passed to add() must live, unchanged, until flush() returns.
 struct Uploads {
     fmm_tree *t;
     struct Item {
@@ -441,6 +449,8 @@ struct Uploads {
             HIPCHK(hipMemcpyAsync(it.dst, base + o, it.bytes, hipMemcpyHostToDevice, s));
             o += (it.bytes + 255) / 256 * 256;
         }
+        HIPCHK(hipEventRecord(t->ctx->ev_upload, s));
+        t->ctx->upload_pending = true;
         items.clear();
         total = 0;
         return FMM_OK;
@@ -701,6 +711,11 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
     // below exists: a failure on the way leaves it marked so, and the next
     // call sets it up again whatever its parameters
     t->p = -1;
+    // the host-built tables go up in one flush at the end (their vectors
+    // live until then)
+    Uploads up{t};
+    std::vector<int4> work;
+    std::vector<int32_t> pack;
     for (void **pp : {(void **)&t->d_mom, (void **)&t->d_mom32, (void **)&t->d_M64, (void **)&t->d_M32, &t->d_Mh,
                       (void **)&t->d_Mf64, (void **)&t->d_part, (void **)&t->d_L64, (void **)&t->d_near, (void **)&t->d_near_g,
                       (void **)&t->d_D64,
@@ -758,17 +773,13 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         // one M2L workgroup per resident workgroup slot; each writes its own
         // partial rows where its piece of the work ends
         build_m2l_work(t->tiling, v, ncu * v.occupancy(), t->m2lwork);
-        std::vector<int4> work(t->m2lwork.work.size() / 4);
+        work.resize(t->m2lwork.work.size() / 4);
         for (size_t k = 0; k < work.size(); ++k)
             work[k] = make_int4(t->m2lwork.work[4 * k], t->m2lwork.work[4 * k + 1], t->m2lwork.work[4 * k + 2],
                                 t->m2lwork.work[4 * k + 3]);
-        hipStream_t st = t->ctx->stream;
-        Uploads up{t};
         if ((rc = up.add(&t->d_work, work)) || (rc = up.add(&t->d_tile_chunk0, t->m2lwork.chunk0)) ||
-            (rc = up.add(&t->d_tile_nchunk, t->m2lwork.nchunk)) || (rc = up.add(&t->d_wave_ptr, t->m2lwork.wave_ptr)) ||
-            (rc = up.flush(st)))
+            (rc = up.add(&t->d_tile_nchunk, t->m2lwork.nchunk)) || (rc = up.add(&t->d_wave_ptr, t->m2lwork.wave_ptr)))
             return rc;
-        HIPCHK(hipStreamSynchronize(st));
         if ((rc = tree_alloc(t, &t->d_part, es * (size_t)std::max<int64_t>(1, t->m2lwork.nrows) * v.nl_pad)) ||
             (rc = tree_alloc(t, (void **)&t->d_L64, sizeof(double) * nc * (harm ? hterms(p - order) : nl))) ||
             (rc = tree_alloc(t, (void **)&t->d_D64, sizeof(double) * nc_ * v.nd)) ||
@@ -807,7 +818,7 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
             return pk;
         };
         const int q = p - order;
-        std::vector<int32_t> pack = packing(l2p_pack_limit(q, false));
+        pack = packing(l2p_pack_limit(q, false));
         const int ncu = t->ctx->ncu;
         std::vector<int32_t> pack_cols = packing(l2p_pack_limit(q, true));
         t->l2p_columns = pack_cols.size() < pack.size() || l2p_columns_pay(q, (int)pack.size() - 1, ncu);
@@ -815,12 +826,11 @@ static int ensure_expansions(fmm_tree *t, int code, int p, int prec)
         if (t->d_l2p_pack) tree_free_block(t, t->d_l2p_pack);
         t->d_l2p_pack = nullptr;
         t->l2p_pack_q = -1;
-        Uploads up{t};
-        if ((rc = up.add(&t->d_l2p_pack, pack)) || (rc = up.flush(t->ctx->stream))) return rc;
-        HIPCHK(hipStreamSynchronize(t->ctx->stream));   // the pinned staging is reused
+        if ((rc = up.add(&t->d_l2p_pack, pack))) return rc;
         t->l2p_npacks = (int)pack.size() - 1;
         t->l2p_pack_q = p - order;
     }
+    if ((rc = up.flush(t->ctx->stream))) return rc;
     hipError_t e = t->d_M64 ? launch_fill(t->d_M64, (size_t)(nc + 1) * nmp, t->ctx->stream) : hipSuccess;
     // P2M and M2M write the FP32 copy too; the rest (the zero row the padded
     // M2L slots read, unused levels) stays zero (nmp is a multiple of 4)

@@ -293,6 +293,8 @@ struct fmm_ctx {
     std::vector<hipEvent_t> ev_pool;
     hipEvent_t ev_up = nullptr, ev_near = nullptr;
     hipEvent_t ev_m2l = nullptr, ev_near2 = nullptr;   // split overlap: M2L queued, second P2P part done
+    hipEvent_t ev_upload = nullptr;       // after the copies of the last flush of uploads from `pinned`
+    bool upload_pending = false;          // ev_upload recorded and not yet waited for
     struct Server *server = nullptr;
     std::vector<struct fmm_tree *> trees;  // live trees; released with the context
 };

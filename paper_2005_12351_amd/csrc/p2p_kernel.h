@@ -40,6 +40,15 @@ struct P2PArgs {
     double h, lo[3];
 };
 
+// One staged source: its position relative to the target leaf (FP64, in
+// units of the leaf radius) and its FP32 moment blocks in one record, so the
+// pair loop walks all of them with a single LDS address.
+template <int NV>
+struct alignas(16) P2PStaged {
+    double x, y, z, unused;
+    float4 m[NV];
+};
+
 constexpr int kPT = 256;        // threads per target leaf
 constexpr int kPList = 256;     // list entries per window
 constexpr int kPChunk32 = 512;  // staged sources per chunk (FP32)
@@ -166,11 +175,9 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
     constexpr int CH = NV > 3 ? kPChunk32 / 2 : kPChunk32;
     // the staging area doubles as the reduction buffer at the end of a pass
     // (8 KB less LDS per workgroup, one more workgroup per CU)
-    __shared__ double sbuf[3 * kPChunk32];
-    double *const spx = sbuf, *const spy = sbuf + CH, *const spz = sbuf + 2 * CH;
-    static_assert(NO * kPT <= 3 * kPChunk32, "reduction buffer exceeds the staging area");
-    double (*const red)[kPT] = reinterpret_cast<double (*)[kPT]>(sbuf);
-    __shared__ float4 spm[NV][CH];
+    __shared__ P2PStaged<NV> sst[CH];
+    static_assert(NO * kPT * sizeof(double) <= sizeof(P2PStaged<NV>) * CH, "reduction buffer exceeds the staging area");
+    double (*const red)[kPT] = reinterpret_cast<double (*)[kPT]>(sst);
     __shared__ int wstart[kPList], wfirst[kPList];
     __shared__ float4 wgeo[kPList];
     __shared__ int sh[kPT / 64];
@@ -239,15 +246,15 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
                     if (j < nc) {
                         const int q = p2p_entry(wstart, nw, c0 + j);
                         const size_t pj = (size_t)wfirst[q] + (c0 + j - wstart[q]);
-                        spx[j] = (a.xs[pj] - zb[0]) * irb;
-                        spy[j] = (a.xs[n + pj] - zb[1]) * irb;
-                        spz[j] = (a.xs[2 * n + pj] - zb[2]) * irb;
+                        sst[j].x = (a.xs[pj] - zb[0]) * irb;
+                        sst[j].y = (a.xs[n + pj] - zb[1]) * irb;
+                        sst[j].z = (a.xs[2 * n + pj] - zb[2]) * irb;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) spm[v][j] = m4[MW * pj + v];
+                        for (int v = 0; v < NV; ++v) sst[j].m[v] = m4[MW * pj + v];
                     } else {
-                        spx[j] = spy[j] = spz[j] = 1.0e4;
+                        sst[j].x = sst[j].y = sst[j].z = 1.0e4;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) spm[v][j] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        for (int v = 0; v < NV; ++v) sst[j].m[v] = make_float4(0.f, 0.f, 0.f, 0.f);
                     }
                 }
                 __syncthreads();
@@ -266,12 +273,12 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
                     auto pairs = [&](auto check) {
                     for (int jj = 0; jj < per; ++jj) {
                         const int j = ja + jj;
-                        const float rx = (float)(tx - spx[j]), ry = (float)(ty - spy[j]), rz = (float)(tz - spz[j]);
+                        const float rx = (float)(tx - sst[j].x), ry = (float)(ty - sst[j].y), rz = (float)(tz - sst[j].z);
                         const float r2 = __builtin_fmaf(rx, rx, __builtin_fmaf(ry, ry, rz * rz));
                         const float inv = (decltype(check)::value && j == jself) ? 0.f : __builtin_amdgcn_rsqf(r2);
                         float4 mv[NV];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) mv[v] = spm[v][j];
+                        for (int v = 0; v < NV; ++v) mv[v] = sst[j].m[v];
                         if constexpr (GRAD) {
                             if constexpr (ONE) {
                                 float t6[6];

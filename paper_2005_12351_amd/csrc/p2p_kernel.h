@@ -79,8 +79,9 @@ __device__ __forceinline__ int p2p_block_scan(int v, int *sh, int *tot)
 // Window of up to kPList list entries: start offset of each entry's particles
 // within the window, first particle, source geometry relative to the target
 // leaf (centre difference in units of r_b, and r_A / r_b), and the window
-// offset of the target leaf's own entry (-1 if absent).  Returns the number
-// of staged sources of the window.
+// offset of the target leaf's own entry (-1 if absent).  The slots of
+// wstart past the window's entries hold INT_MAX (see p2p_entry).  Returns
+// the number of staged sources of the window.
 static __device__ int p2p_window(const P2PArgs &a, const DevCell &cb, int b, int w0, int nw, int *wstart, int *wfirst,
                           float4 *wgeo, int *wself, int *sh)
 {
@@ -99,23 +100,25 @@ static __device__ int p2p_window(const P2PArgs &a, const DevCell &cb, int b, int
     }
     int tot;
     const int st = p2p_block_scan(cnt, sh, &tot);
-    if (q < nw) wstart[q] = st;
+    static_assert(kPT == kPList, "one thread per window slot");
+    wstart[q] = q < nw ? st : INT_MAX;
     __syncthreads();
     if (q < nw && *wself == -2 - q) *wself = st;
     __syncthreads();
     return tot;
 }
 
-// entry of window source j: the last q with wstart[q] <= j
+// entry of window source j: the last q with wstart[q] <= j.  Steps of
+// powers of two from the largest below nw: the index stays below twice that
+// step, so within the kPList slots, and the slots past the window hold
+// INT_MAX, so no bound test is needed; the step count is the same for the
+// whole wave (a scalar loop)
 __device__ __forceinline__ int p2p_entry(const int *wstart, int nw, int j)
 {
-    int lo = 0, hi = nw - 1;
-    while (lo < hi) {
-        const int m = (lo + hi + 1) >> 1;
-        if (wstart[m] <= j) lo = m;
-        else hi = m - 1;
-    }
-    return lo;
+    int q = 0;
+    for (int step = nw > 1 ? 1 << (31 - __clz(nw - 1)) : 0; step > 0; step >>= 1)
+        if (wstart[q + step] <= j) q += step;
+    return q;
 }
 
 // the pair terms of one source of several orders: each order's terms go to

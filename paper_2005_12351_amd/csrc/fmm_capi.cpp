@@ -325,6 +325,7 @@ extern "C" int fmm_ctx_destroy(fmm_ctx *c)
     for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->pin_small) (void)hipHostFree(c->pin_small);
+    if (c->sig) (void)hipHostFree(c->sig);
     hipEventDestroy(c->ev_up);
     hipEventDestroy(c->ev_near);
     hipEventDestroy(c->ev_fork);

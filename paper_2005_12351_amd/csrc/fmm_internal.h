@@ -278,6 +278,11 @@ struct fmm_ctx {
     void *pinned = nullptr;               // pinned host staging of tree construction's copies
     size_t pinned_bytes = 0;
     int64_t *pin_small = nullptr;         // pinned words for the totals a tree build reads back
+    // coherent host words a tree build's read-backs arrive in: a one-thread
+    // kernel writes the words, then the sequence number sig_seq, which the
+    // host polls (tree_gpu.hip, read_words)
+    int64_t *sig = nullptr, *sig_dev = nullptr;
+    int64_t sig_seq = 0;
     int ncu = 256;                        // compute units of the device
     // Device blocks released by this context's trees, by size class, reused
     // in the order of the context stream (tree_alloc); and the scratch

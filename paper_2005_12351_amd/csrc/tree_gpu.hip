@@ -23,6 +23,7 @@
 // back only totals (sizes of the next level or frontier).  After the lists,
 // the M2L schedule is made here too (see launch_tiling).
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <vector>
@@ -630,15 +631,54 @@ hipError_t scan_i32(Dev &dv, const int32_t *in, int32_t *out, int n, int64_t *to
     return hipSuccess;
 }
 
-// the first k (<= 8) device words, read on the host (synchronises the
-// stream), through the pinned words when there are some
-hipError_t read_totals(Dev &dv, const void *dev, int k, void *host)
+// Read-backs of a few device words through the context's coherent host
+// words: one thread copies them with system-scope stores, then stores the
+// read-back's sequence number with release order, and the host polls that
+// number (about 6 us from the kernel's launch to the words on the host,
+// against about 14 us for a copy and a stream wait).  After kSigSpin of
+// polling the host waits for the stream instead, which also reports a
+// failed kernel.
+constexpr int kSigWords = 64;                  // words one read-back carries; the sequence number follows
+constexpr double kSigSpinUs = 1000.0;
+__global__ void publish_kernel(const int64_t *__restrict__ src, int n, int64_t *host, int64_t seq)
 {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < n; ++i) __hip_atomic_store(&host[i], src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&host[kSigWords], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// the first k device words (8-byte aligned), read on the host; this waits
+// for the stream's work up to them
+hipError_t read_words(Dev &dv, const void *dev, int k, void *host)
+{
+    if (dv.ctx && dv.ctx->sig && k <= kSigWords) {
+        fmm_ctx *c = dv.ctx;
+        const int64_t seq = ++c->sig_seq;
+        hipLaunchKernelGGL(publish_kernel, dim3(1), dim3(64), 0, dv.s, (const int64_t *)dev, k, c->sig_dev, seq);
+        GCHK(hipGetLastError());
+        const auto t0 = std::chrono::steady_clock::now();
+        while (__atomic_load_n(&c->sig[kSigWords], __ATOMIC_ACQUIRE) != seq) {
+            if (std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() > kSigSpinUs) {
+                GCHK(hipStreamSynchronize(dv.s));
+                if (__atomic_load_n(&c->sig[kSigWords], __ATOMIC_ACQUIRE) != seq) return hipErrorUnknown;
+                break;
+            }
+        }
+        memcpy(host, c->sig, sizeof(int64_t) * k);
+        return hipSuccess;
+    }
     void *dst = dv.pin ? (void *)dv.pin : host;
     GCHK(hipMemcpyAsync(dst, dev, sizeof(int64_t) * k, hipMemcpyDeviceToHost, dv.s));
     GCHK(hipStreamSynchronize(dv.s));
     if (dst != host) memcpy(host, dst, sizeof(int64_t) * k);
     return hipSuccess;
+}
+
+// the first k (<= 8) device words, read on the host (synchronises the
+// stream)
+hipError_t read_totals(Dev &dv, const void *dev, int k, void *host)
+{
+    return read_words(dv, dev, k, host);
 }
 
 // stable sort of (key, val) on the low `bits` bits of the key: one workgroup
@@ -1120,6 +1160,17 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     Dev dv{s};
     if (ctx) {
         if (!ctx->pin_small) GCHK(hipHostMalloc((void **)&ctx->pin_small, 4096, hipHostMallocDefault));
+        if (!ctx->sig) {
+            GCHK(hipHostMalloc((void **)&ctx->sig, sizeof(int64_t) * (kSigWords + 1),
+                               hipHostMallocCoherent | hipHostMallocMapped));
+            ctx->sig[kSigWords] = ctx->sig_seq;
+            const hipError_t e = hipHostGetDevicePointer((void **)&ctx->sig_dev, ctx->sig, 0);
+            if (e != hipSuccess) {
+                (void)hipHostFree(ctx->sig);
+                ctx->sig = nullptr;
+                return e;
+            }
+        }
         dv.pin = ctx->pin_small;
         dv.ctx = ctx;
     }
@@ -1183,11 +1234,9 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
                                runs);
             GCHK(hipGetLastError());
         }
-        static_assert(sizeof(LevelState) <= 4096, "the level state is read through the pinned words");
-        void *dst = dv.pin ? (void *)dv.pin : (void *)&hs;
-        GCHK(hipMemcpyAsync(dst, ls, sizeof(LevelState), hipMemcpyDeviceToHost, s));
-        GCHK(hipStreamSynchronize(s));
-        if (dst != &hs) memcpy(&hs, dst, sizeof(LevelState));
+        static_assert(sizeof(LevelState) % 8 == 0 && sizeof(LevelState) <= 8 * kSigWords,
+                      "the level state is read back as whole words");
+        GCHK(read_words(dv, ls, (int)(sizeof(LevelState) / 8), &hs));
         if (first) {
             if (hs.box[6] != 0.0) return hipErrorInvalidValue;   // a position is not finite
             double W = std::max(hs.box[3] - hs.box[0], std::max(hs.box[4] - hs.box[1], hs.box[5] - hs.box[2]));

@@ -576,6 +576,8 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     }
     std::vector<int32_t> psrc(pptr[nlv_]);
     std::vector<double> leaf_cost(nlv_, 0.0), leaf_pairs(nlv_, 0.0);
+    // (the host threads pay from about a thousand leaves on)
+    constexpr int64_t kSerialLeaves = 1024;
     host_parallel_for(nlv_, [&](int64_t k) {
         const int64_t b = t->leaves[k];
         int32_t *o = psrc.data() + pptr[k];
@@ -588,7 +590,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         leaf_cost[k] = srcs * (double)h.count[b];
         // the pairs, without the self pair of each particle
         leaf_pairs[k] = leaf_cost[k] - (h.p2p_ptr[b + 1] > h.p2p_ptr[b] ? (double)h.count[b] : 0.0);
-    });
+    }, kSerialLeaves);
     double p2p_pairs = 0.0;
     for (double v : leaf_pairs) p2p_pairs += v;
     t->work[2] = p2p_pairs;
@@ -632,7 +634,7 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         host_parallel_for(kXcd, [&](int64_t r) {
             std::stable_sort(range[r].begin(), range[r].end(),
                              [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
-        });
+        }, nlv_ < kSerialLeaves ? kXcd + 1 : 0);
         size_t longest = 0;
         for (auto &rg : range) longest = std::max(longest, rg.size());
         for (size_t i = 0; i < longest; ++i)

@@ -190,8 +190,10 @@ struct M2LTiling {
 };
 void build_m2l_tiling(const HostTree &t, M2LTiling &out);
 // f(i) for i in [0, n) on the host threads of the scheduling passes
-// (tree_host.cpp); each i must write its own results only
-void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f);
+// (tree_host.cpp); each i must write its own results only.  Below
+// serial_below items the calling thread does them all: waking the pool
+// costs tens of microseconds, more than small loops take.
+void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f, int64_t serial_below = 0);
 
 // Device buffers of a tree that gpu_build_tree (tree_gpu.hip) leaves on
 // the device: `keep` allocates them (the tree's own allocations).  Always:

@@ -1209,7 +1209,10 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     // that splits, a split cell holds more than ncrit particles and the
     // cells of one level are disjoint, and at most n non-empty cells: that
     // bound sizes the grids and the per-level buffers (shared by the levels).
-    size_t cap = std::max<size_t>(64, (size_t)(4 * n / std::max(1, ncrit) + 64));
+    // The cell array starts at 10 n / ncrit cells (at most 4 n): a uniform
+    // tree just past a split of a whole level holds about 9 n / ncrit, and a
+    // tree that needs more grows the array and runs its batch again.
+    size_t cap = std::max<size_t>(64, (size_t)std::min<int64_t>(10 * n / std::max(1, ncrit), 4 * n) + 64);
     DevCell *cells = dv.alloc<DevCell>(cap);
     const int64_t split_max = n / ((int64_t)ncrit + 1);
     const int64_t umax = std::max<int64_t>(1, std::min<int64_t>(n, 8 * split_max));

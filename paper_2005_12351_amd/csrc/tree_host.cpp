@@ -130,8 +130,12 @@ static void parallel_for(int64_t n, F f)
     HostPool::get().run(n, f);
 }
 
-void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f)
+void host_parallel_for(int64_t n, const std::function<void(int64_t)> &f, int64_t serial_below)
 {
+    if (n < serial_below) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
     parallel_for(n, [&](int64_t i) { f(i); });
 }
 

@@ -574,23 +574,32 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
         const int64_t b = t->leaves[k];
         pptr[k + 1] = pptr[k] + (int32_t)(h.p2p_ptr[b + 1] - h.p2p_ptr[b]);
     }
-    std::vector<int32_t> psrc(pptr[nlv_]);
+    // With the sources kept on the device (dt.p2p_src, a build with lists)
+    // the costs come from the device and the per-leaf CSR is the device's
+    // list as it is; otherwise (no lists: every leaf's list is empty) it is
+    // built here.
+    const bool dev_src = dt.p2p_src != nullptr;
+    std::vector<int32_t> psrc(dev_src ? 0 : pptr[nlv_]);
     std::vector<double> leaf_cost(nlv_, 0.0), leaf_pairs(nlv_, 0.0);
     // (the host threads pay from about a thousand leaves on)
     constexpr int64_t kSerialLeaves = 1024;
     host_parallel_for(nlv_, [&](int64_t k) {
         const int64_t b = t->leaves[k];
-        int32_t *o = psrc.data() + pptr[k];
-        double srcs = 0.0;
-        for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) {
-            const int64_t A = h.p2p_src[e];
-            *o++ = (int32_t)A;
-            srcs += (double)h.count[A];
+        if (dev_src) {
+            leaf_cost[k] = (double)h.p2p_cost[b];
+        } else {
+            int32_t *o = psrc.data() + pptr[k];
+            double srcs = 0.0;
+            for (int64_t e = h.p2p_ptr[b]; e < h.p2p_ptr[b + 1]; ++e) {
+                const int64_t A = h.p2p_src[e];
+                *o++ = (int32_t)A;
+                srcs += (double)h.count[A];
+            }
+            leaf_cost[k] = srcs * (double)h.count[b];
         }
-        leaf_cost[k] = srcs * (double)h.count[b];
         // the pairs, without the self pair of each particle
         leaf_pairs[k] = leaf_cost[k] - (h.p2p_ptr[b + 1] > h.p2p_ptr[b] ? (double)h.count[b] : 0.0);
-    }, kSerialLeaves);
+    }, dev_src ? INT64_MAX : kSerialLeaves);
     double p2p_pairs = 0.0;
     for (double v : leaf_pairs) p2p_pairs += v;
     t->work[2] = p2p_pairs;
@@ -663,7 +672,8 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     UP(t->d_nonleaf, t->level_nonleaf);
     UP(t->d_level_cells, level_cells);
     UP(t->d_p2p_ptr, pptr);
-    UP(t->d_p2p_src, psrc);
+    if (dev_src) t->d_p2p_src = dt.p2p_src;
+    else UP(t->d_p2p_src, psrc);
     UP(t->d_p2p_order, p2p_order);
     std::vector<int32_t> cell_slot;   // lives until the flush below
     if (method == FMM_METHOD_FMM && !t->tiling.on_device) {
@@ -1284,6 +1294,18 @@ extern "C" int fmm_tree_export(const fmm_tree *t, double *geom, uint64_t *key, i
         cp(m2l_src, h.m2l_src);
     }
     cp(p2p_ptr, h.p2p_ptr);
-    cp(p2p_src, h.p2p_src);
+    const int64_t np2p = h.p2p_ptr.empty() ? 0 : h.p2p_ptr.back();
+    if (p2p_src && np2p > 0 && h.p2p_src.empty()) {
+        // the sources stayed on the device, in the same CSR order
+        if (!t->ctx) FAIL(FMM_EINVAL, "the tree's context was destroyed");
+        HIPCHK(hipSetDevice(t->ctx->device));
+        hipStream_t s = t->ctx->stream;
+        std::vector<int32_t> s32(np2p);
+        HIPCHK(hipMemcpyAsync(s32.data(), t->d_p2p_src, sizeof(int32_t) * np2p, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::copy(s32.begin(), s32.end(), p2p_src);
+    } else {
+        cp(p2p_src, h.p2p_src);
+    }
     return FMM_OK;
 }

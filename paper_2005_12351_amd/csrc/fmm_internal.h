@@ -150,6 +150,9 @@ struct HostTree {      // canonical tree, host copy
     std::vector<int32_t> nchild;
     std::vector<int64_t> level_ptr;        // nlevels + 1
     std::vector<int64_t> m2l_ptr, m2l_src, p2p_ptr, p2p_src;
+    // per cell: its particle count times the particles of its P2P sources
+    // (filled when the P2P sources stay on the device; p2p_src is empty then)
+    std::vector<int64_t> p2p_cost;
     int64_t ncells() const { return (int64_t)level.size(); }
 };
 
@@ -216,6 +219,10 @@ struct DevKeep {
     int64_t min_pairs = 0;   // the device tiling only for at least this many M2L pairs
     int32_t *ucls = nullptr, *usrc = nullptr, *cell_slot = nullptr;
     int32_t *m2l_ptr = nullptr, *m2l_src = nullptr;
+    // With lists: the P2P sources stay on the device (CSR over the cells by
+    // the host's p2p_ptr; only leaves have entries, so it is also the
+    // per-leaf CSR in leaf order), and the host gets per-cell costs instead.
+    int32_t *p2p_src = nullptr;
     double *cls_geom = nullptr;
     M2LTiling *tl = nullptr;
     int tgt_top = -1, src_top = -1;

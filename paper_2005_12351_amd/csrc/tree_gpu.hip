@@ -1038,6 +1038,21 @@ __global__ void last_of_scan_kernel(int32_t *ptr, int n, const int64_t *total)
     if (threadIdx.x == 0 && blockIdx.x == 0) ptr[n] = (int32_t)*total;
 }
 
+// per cell: its particle count times the particles of its P2P sources (the
+// direct-sum work of a target leaf), one wave per cell; integers, exact
+constexpr int kCostT = 256;
+__global__ __launch_bounds__(kCostT) void p2p_cost_kernel(const DevCell *__restrict__ cells, int nc,
+                                                          const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ src, int64_t *__restrict__ cost)
+{
+    const int c = blockIdx.x * (kCostT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (c >= nc) return;   // whole waves
+    int64_t s = 0;
+    for (int e = ptr[c] + lane; e < ptr[c + 1]; e += 64) s += cells[src[e]].count;
+    for (int w = 32; w > 0; w >>= 1) s += __shfl_xor(s, w, 64);
+    if (lane == 0) cost[c] = s * (int64_t)cells[c].count;
+}
+
 __global__ void root_cell_kernel(DevCell *c, int32_t n)
 {
     if (threadIdx.x == 0) {
@@ -1350,6 +1365,23 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         n_m2l = mm;
         n_p2p = pm;
     }
+    // the P2P sources stay on the device with the tree; the host gets the
+    // per-cell costs that order the near-field dispatch
+    int64_t *p2p_cost = nullptr;
+    const bool keep_p2p = lists && dt;
+    if (keep_p2p) {
+        int32_t *pptr = dv.alloc<int32_t>((size_t)nc + 1);
+        p2p_cost = dv.alloc<int64_t>(nc);
+        GCHK(dv.err);
+        GCHK(scan_i32(dv, p2p_cnt, pptr, nc, dtot + 3));
+        hipLaunchKernelGGL(last_of_scan_kernel, dim3(1), dim3(64), 0, s, pptr, nc, (const int64_t *)(dtot + 3));
+        hipLaunchKernelGGL(p2p_cost_kernel, dim3(nblk(nc, kCostT / 64)), dim3(kCostT), 0, s, (const DevCell *)cells, nc,
+                           (const int32_t *)pptr, (const int32_t *)p2p_s32, p2p_cost);
+        GCHK(hipGetLastError());
+        GCHK(dt->keep((void **)&dt->p2p_src, sizeof(int32_t) * (size_t)std::max<int64_t>(1, n_p2p)));
+        if (n_p2p)
+            GCHK(hipMemcpyAsync(dt->p2p_src, p2p_s32, sizeof(int32_t) * n_p2p, hipMemcpyDeviceToDevice, s));
+    }
     mark("host:tree_lists");
     TileState ts;
     if (lists && dt && dt->tiling && n_m2l >= dt->min_pairs) {
@@ -1375,7 +1407,8 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
                  o_key = o_perm + al(sizeof(int32_t) * n_host), o_mc = o_key + al(sizeof(uint64_t) * n_host),
                  o_ms = o_mc + al(sizeof(int32_t) * nc),
                  o_pc = o_ms + al(sizeof(int32_t) * (dtile ? 0 : n_m2l)), o_ps = o_pc + al(sizeof(int32_t) * nc),
-                 o_tc = o_ps + al(sizeof(int32_t) * n_p2p), o_tu = o_tc + al(sizeof(int32_t) * ts.ntg),
+                 o_pk = o_ps + al(sizeof(int32_t) * (keep_p2p ? 0 : n_p2p)),
+                 o_tc = o_pk + al(sizeof(int64_t) * (keep_p2p ? nc : 0)), o_tu = o_tc + al(sizeof(int32_t) * ts.ntg),
                  o_ti = o_tu + al(sizeof(int32_t) * (ts.ntiles + 1)), o_end = o_ti + al(sizeof(int64_t) * 4);
     Staging st{ctx};
     GCHK(st.reserve(o_end));
@@ -1392,7 +1425,9 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
                 GCHK(hipMemcpyAsync(st.base + o_ms, m2l_s32, sizeof(int32_t) * n_m2l, hipMemcpyDeviceToHost, s));
         }
         GCHK(hipMemcpyAsync(st.base + o_pc, p2p_cnt, sizeof(int32_t) * nc, hipMemcpyDeviceToHost, s));
-        if (n_p2p) GCHK(hipMemcpyAsync(st.base + o_ps, p2p_s32, sizeof(int32_t) * n_p2p, hipMemcpyDeviceToHost, s));
+        if (keep_p2p) GCHK(hipMemcpyAsync(st.base + o_pk, p2p_cost, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, s));
+        else if (n_p2p)
+            GCHK(hipMemcpyAsync(st.base + o_ps, p2p_s32, sizeof(int32_t) * n_p2p, hipMemcpyDeviceToHost, s));
     }
     if (dtile) {
         if (ts.ntg) GCHK(hipMemcpyAsync(st.base + o_tc, ts.tcell, sizeof(int32_t) * ts.ntg, hipMemcpyDeviceToHost, s));
@@ -1405,8 +1440,17 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
         if (!dtile)
             csr_finish((const int32_t *)(st.base + o_mc), (const int32_t *)(st.base + o_ms), n_m2l, nc, t.m2l_ptr,
                        t.m2l_src);
-        csr_finish((const int32_t *)(st.base + o_pc), (const int32_t *)(st.base + o_ps), n_p2p, nc, t.p2p_ptr,
-                   t.p2p_src);
+        if (keep_p2p) {
+            const int32_t *c = (const int32_t *)(st.base + o_pc);
+            t.p2p_ptr.assign(nc + 1, 0);
+            for (int i = 0; i < nc; ++i) t.p2p_ptr[i + 1] = t.p2p_ptr[i] + c[i];
+            t.p2p_src.clear();
+            const int64_t *k = (const int64_t *)(st.base + o_pk);
+            t.p2p_cost.assign(k, k + nc);
+        } else {
+            csr_finish((const int32_t *)(st.base + o_pc), (const int32_t *)(st.base + o_ps), n_p2p, nc, t.p2p_ptr,
+                       t.p2p_src);
+        }
     }
     const DevCell *hc = (const DevCell *)(st.base + o_cells);
     const int32_t *perm = (const int32_t *)(st.base + o_perm);

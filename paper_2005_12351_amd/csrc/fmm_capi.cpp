@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 
 #include "fmm_internal.h"
 
@@ -609,7 +610,8 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
     // eight ranges of equal cost and workgroup g takes the (g / 8)-th leaf of
     // range g % 8: the leaves one XCD works on are neighbours and share most
     // of their source leaves in its L2.  Within a range the heaviest leaves
-    // go first, so that the light ones fill the end of the launch.
+    // go first (to within a bucket of cost), so that the light ones fill the
+    // end of the launch.
     constexpr int kXcd = 8;
     std::vector<int32_t> p2p_order;
     {
@@ -640,10 +642,35 @@ extern "C" int fmm_build_tree(fmm_ctx *ctx, const double *pos, int64_t n, int nc
             range[r].push_back(k);
             acc += leaf_cost[k];
         }
-        host_parallel_for(kXcd, [&](int64_t r) {
-            std::stable_sort(range[r].begin(), range[r].end(),
-                             [&](int32_t a, int32_t b) { return leaf_cost[a] > leaf_cost[b]; });
-        }, nlv_ < kSerialLeaves ? kXcd + 1 : 0);
+        // heaviest first within a range: a stable counting sort on the cost's
+        // octave and its next three bits (eight buckets an octave, about 9 %
+        // wide), so leaves of nearly equal cost keep their Morton order; one
+        // pass, no comparison sort and no host threads to wake
+        // (the bucket is read off the double: its biased exponent and the top
+        // three bits of its mantissa, counted from 1.0 up)
+        constexpr int kBuckets = 512;
+        std::vector<int16_t> slot(nlv_);
+        for (int64_t k = 0; k < nlv_; ++k) {
+            const double c = leaf_cost[k];
+            uint64_t bits;
+            memcpy(&bits, &c, sizeof bits);
+            const int64_t b = c >= 1.0 ? (int64_t)(bits >> 49) - (int64_t)(1023 << 3) + 1 : 0;
+            slot[k] = (int16_t)(kBuckets - 1 - std::min<int64_t>(kBuckets - 1, b));   // heaviest first
+        }
+        std::vector<int32_t> cnt(kBuckets), tmp;
+        for (auto &rg : range) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int32_t k : rg) ++cnt[slot[k]];
+            int32_t acc = 0;
+            for (int b = 0; b < kBuckets; ++b) {
+                const int32_t c = cnt[b];
+                cnt[b] = acc;
+                acc += c;
+            }
+            tmp.resize(rg.size());
+            for (int32_t k : rg) tmp[cnt[slot[k]]++] = k;
+            rg.swap(tmp);
+        }
         size_t longest = 0;
         for (auto &rg : range) longest = std::max(longest, rg.size());
         for (size_t i = 0; i < longest; ++i)

@@ -102,8 +102,11 @@ enum {
  * creation).  The context keeps device memory for reuse, each part up to
  * min(budget / 8, 4 GiB): the blocks of destroyed trees (handed to later
  * trees of the same size class) and the scratch arena of tree builds; both
- * are released with the context.  A context is used by one host thread at
- * a time. */
+ * are released with the context.  Creating a context also sets the release
+ * threshold of the device's default stream-ordered memory pool to keep
+ * freed memory mapped for reuse (process-wide; memory freed to that pool is
+ * not returned to the driver before the process ends).  A context is used
+ * by one host thread at a time. */
 int fmm_ctx_create(int device, void *hip_stream, size_t hbm_budget_bytes, fmm_ctx **out);
 /* Destroys the context after its device work has finished.  Trees of this
  * context that are still alive lose their device memory; fmm_tree_destroy
@@ -354,7 +357,9 @@ enum { FMM_REQ_QUEUED = 0, FMM_REQ_RUNNING = 1, FMM_REQ_DONE = 2, FMM_REQ_FAILED
  * budget minus the footprints of the running requests.  One slot per
  * hardware queue of the process (4 by default) serves best: more slots
  * share queues, and a slot then waits behind another's kernels at each of
- * its tree build's read-backs. */
+ * its tree build's read-backs.  Each slot's tree-build arena is allocated
+ * here (64 MB, at most min(budget / 8, 4 GiB)), so that the first requests
+ * do not pay for it. */
 int fmm_serve_start(fmm_ctx *ctx, int max_concurrent);
 /* Queue a request (copied); FMM_ENOMEM if its footprint exceeds the whole
  * budget, FMM_EINVAL for bad parameters (nothing is queued then).  The

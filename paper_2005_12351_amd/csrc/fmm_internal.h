@@ -169,6 +169,9 @@ hipError_t ctx_pinned(fmm_ctx *ctx, size_t bytes, char **base);
 // most bytes a context keeps cached in released tree blocks, and in its
 // build arena
 size_t ctx_cache_limit(const fmm_ctx *ctx);
+// the context's build arena grown to at least `bytes` (at most the cache
+// limit), allocated on its stream and waited for (tree_gpu.hip)
+hipError_t ctx_arena_reserve(fmm_ctx *ctx, size_t bytes);
 
 // stable sort of n (key, value) pairs on the low `bits` key bits into
 // kout/vout (sort.hip); with tmp null only sets tmp_bytes

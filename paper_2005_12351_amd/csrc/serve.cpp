@@ -199,6 +199,9 @@ extern "C" int fmm_serve_start(fmm_ctx *ctx, int max_concurrent)
                 return rc;
             }
             c->graphs = false;   // one-shot trees: capturing would not pay off
+            // the slot's build arena sized before the first request (a build
+            // of 2·10^5 particles needs about 40-60 MB); a larger one grows it
+            (void)ctx_arena_reserve(c, (size_t)64 << 20);
             S->sub.push_back(c);
         }
     }

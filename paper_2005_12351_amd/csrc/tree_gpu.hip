@@ -587,7 +587,9 @@ struct Dev {
     {
         for (void *p : blocks) hipFreeAsync(p, s);
         if (ctx && need > ctx->arena_cap && err == hipSuccess) {
-            const size_t want = std::min(need + need / 4, ctx_cache_limit(ctx));
+            // twice this build's need (at least 32 MB), so that builds up to
+            // twice as large grow it no further
+            const size_t want = std::min(std::max(2 * need, (size_t)32 << 20), ctx_cache_limit(ctx));
             if (want > ctx->arena_cap) {
                 if (ctx->arena) hipFreeAsync(ctx->arena, s);
                 ctx->arena = nullptr;
@@ -1162,6 +1164,24 @@ hipError_t launch_tiling(Dev &dv, const DevCell *cells, int nc, const int32_t *c
 }
 
 }  // namespace
+
+hipError_t ctx_arena_reserve(fmm_ctx *ctx, size_t bytes)
+{
+    bytes = std::min(bytes, ctx_cache_limit(ctx));
+    if (ctx->arena_cap >= bytes) return hipSuccess;
+    if (ctx->arena) (void)hipFreeAsync(ctx->arena, ctx->stream);
+    ctx->arena = nullptr;
+    ctx->arena_cap = 0;
+    void *p = nullptr;
+    const hipError_t e = hipMallocAsync(&p, bytes, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e;
+    }
+    ctx->arena = (char *)p;
+    ctx->arena_cap = bytes;
+    return hipStreamSynchronize(ctx->stream);
+}
 
 // Builds the canonical tree (and, when theta > 0, the interaction lists) of
 // the n device positions on stream s, and returns it in host form.  ctx (may

@@ -1317,8 +1317,29 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     if (lists) {
         const double th2 = theta * theta;
         const int kb = bits_for(nc);
-        std::vector<uint64_t *> m2l_parts, p2p_parts;
-        std::vector<int64_t> m2l_sz, p2p_sz;
+        // The list keys of all steps go to one buffer per list at running
+        // offsets.  Capacities from the usual list lengths at this theta
+        // (about 170 M2L entries per cell and 30 P2P entries per leaf at
+        // theta 0.5, growing as theta^-2.6 and theta^-3), with a margin; a
+        // step that would not fit grows its buffer first (a copy of what
+        // the earlier steps wrote).
+        const double rth = 0.5 / theta;
+        auto capped = [](double v) { return (int64_t)std::min(v, (double)INT32_MAX); };
+        int64_t mcap = capped(1.3 * 170.0 * std::pow(rth, 2.6) * nc + 4096);
+        int64_t pcap = capped(1.3 * 30.0 * rth * rth * rth * nc + 4096);
+        int64_t moff = 0, poff = 0;
+        uint64_t *mall = dv.alloc<uint64_t>(mcap), *pall = dv.alloc<uint64_t>(pcap);
+        auto ensure = [&](uint64_t *&buf, int64_t &cap, int64_t off, int64_t need) -> hipError_t {
+            if (off + need <= cap) return hipSuccess;
+            const int64_t ncap = std::max(2 * cap, off + need + (off + need) / 4);
+            uint64_t *b2 = dv.alloc<uint64_t>(ncap);
+            GCHK(dv.err);
+            if (off) GCHK(hipMemcpyAsync(b2, buf, sizeof(uint64_t) * off, hipMemcpyDeviceToDevice, s));
+            dv.release(buf);
+            buf = b2;
+            cap = ncap;
+            return hipSuccess;
+        };
         int2 *fr = dv.alloc<int2>(1);
         GCHK(dv.err);
         hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, s, (int32_t *)fr, (int64_t)2);   // (root, root)
@@ -1344,10 +1365,12 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
             const int64_t tk = tt[0], tm = tt[1], tp = tt[2];
             if (tk > INT32_MAX) return hipErrorOutOfMemory;
             int2 *next = dv.alloc<int2>(tk);
-            uint64_t *mk = dv.alloc<uint64_t>(tm), *pk = dv.alloc<uint64_t>(tp);
             GCHK(dv.err);
+            if (moff + tm > INT32_MAX || poff + tp > INT32_MAX) return hipErrorOutOfMemory;
+            GCHK(ensure(mall, mcap, moff, tm));
+            GCHK(ensure(pall, pcap, poff, tp));
             hipLaunchKernelGGL(trav_emit_kernel, dim3(nblk(nf, 256)), dim3(256), 0, s, fr, (int)nf, cells, th2, nk, fm, fp,
-                               kb, next, mk, (int64_t)0, pk, (int64_t)0);
+                               kb, next, mall, moff, pall, poff);
             GCHK(hipGetLastError());
             dv.release(nk);
             dv.release(fm);
@@ -1355,31 +1378,12 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
             dv.release(fr);
             fr = next;
             nf = tk;
-            m2l_parts.push_back(mk);
-            m2l_sz.push_back(tm);
-            p2p_parts.push_back(pk);
-            p2p_sz.push_back(tp);
+            moff += tm;
+            poff += tp;
         }
         mark("host:tree_traverse");
-        // gather the per-step outputs, then sort by (target, source)
-        auto gather = [&](std::vector<uint64_t *> &parts, std::vector<int64_t> &sz, uint64_t *&all, int64_t &m) -> hipError_t {
-            m = 0;
-            for (int64_t z : sz) m += z;
-            all = dv.alloc<uint64_t>(m);
-            GCHK(dv.err);
-            int64_t o = 0;
-            for (size_t i = 0; i < parts.size(); ++i) {
-                if (sz[i]) GCHK(hipMemcpyAsync(all + o, parts[i], sizeof(uint64_t) * sz[i], hipMemcpyDeviceToDevice, s));
-                o += sz[i];
-                dv.release(parts[i]);
-            }
-            return hipSuccess;
-        };
-        uint64_t *mall, *pall;
-        int64_t mm, pm;
-        GCHK(gather(m2l_parts, m2l_sz, mall, mm));
-        GCHK(gather(p2p_parts, p2p_sz, pall, pm));
-        if (mm > INT32_MAX || pm > INT32_MAX) return hipErrorOutOfMemory;
+        // sort by (target, source)
+        const int64_t mm = moff, pm = poff;
         GCHK(csr_launch(dv, mall, mm, kb, nc, &m2l_cnt, &m2l_s32));
         GCHK(csr_launch(dv, pall, pm, kb, nc, &p2p_cnt, &p2p_s32));
         n_m2l = mm;

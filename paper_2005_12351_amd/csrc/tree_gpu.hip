@@ -1261,8 +1261,15 @@ hipError_t gpu_build_tree(const double *pos, int64_t n, int ncrit, double theta,
     LevelState hs;
     int l0 = 0, nlev = -1;
     bool first = true;
+    // the first batch: the levels of a uniform tree of n particles (each
+    // split leaves about an eighth of a cell's particles per child) and the
+    // one below it, whose cells do not split; deeper trees take batches of
+    // four more (a level past the tree's end launches kernels that only
+    // find nothing to do)
+    int first_batch = 2;
+    for (double m = (double)n / std::max(1, ncrit); m > 1.0 && first_batch < kMaxLevel + 1; m /= 8.0) ++first_batch;
     while (nlev < 0) {
-        const int l1 = std::min(l0 + (first ? 6 : 4), kMaxLevel + 1);
+        const int l1 = std::min(l0 + (first ? first_batch : 4), kMaxLevel + 1);
         for (int l = l0; l < l1; ++l) {
             const int64_t m = ub[l];
             hipLaunchKernelGGL(tree_split_kernel, dim3(nblk(m * 8, 256)), dim3(256), 0, s, cells, (const LevelState *)ls,

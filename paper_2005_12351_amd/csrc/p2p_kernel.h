@@ -240,10 +240,18 @@ __global__ __launch_bounds__(kPT, 5) void p2p_f32_kernel(P2PArgs a)
             // is padded with zero sources far away (their terms are exactly
             // zero), so every slice takes the same number of sources and the
             // pair loop runs on a counter common to the whole workgroup
-            const int cstep = (CH / ns) * ns;
+            // The slices of one wave read records per * 48 bytes apart (for
+            // dipoles); with per a multiple of 8 slices two apart hit the same
+            // LDS banks, so per is kept off those multiples (one more padding
+            // source per slice where needed, within the chunk).
+            // (per is the same for the whole workgroup; read through the first
+            // lane so that the compiler keeps the pair loop's counter scalar)
+            const int pmax = CH / ns - ((CH / ns > 1 && (CH / ns) % 8 == 0) ? 1 : 0);
+            const int cstep = pmax * ns;
             for (int c0 = 0; c0 < nsw; c0 += cstep) {
                 const int nc = min(cstep, nsw - c0);
-                const int per = (nc + ns - 1) / ns;   // sources per slice
+                const int per0 = (nc + ns - 1) / ns;   // sources per slice
+                const int per = __builtin_amdgcn_readfirstlane(per0 + ((per0 % 8 == 0 && per0 < pmax) ? 1 : 0));
                 __syncthreads();
                 for (int j = tid; j < per * ns; j += kPT) {
                     if (j < nc) {
